@@ -1,0 +1,322 @@
+"""Python access to the FP64 CPU oracle (test infrastructure only).
+
+Only tests/, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product library never calls it.
+
+Functions mirror the paper's objects: F(eta, chi), h, g (Appendix A), T_pm,
+p_f, k (Appendix B), the look-up tables of Sec. 3, Philox4x64-10, and the
+Monte-Carlo step of Sec. 3 run over whole particle families.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import build as _build
+
+_LIB = None
+
+FLAG_EMIT = 1
+FLAG_PAIRS = 2
+FLAG_PROPAGATE = 4
+
+FIELD_UNIFORM = 0
+FIELD_LP_PULSE = 1
+FIELD_CP_WAVE = 2
+FIELD_CP_STANDING = 3
+FIELD_GRID_CP_STANDING = 4
+
+SPECIES = ("electron", "positron", "photon")
+
+
+class _TableParams(C.Structure):
+    _fields_ = [("n_eta", C.c_int32), ("eta_min", C.c_double), ("eta_max", C.c_double),
+                ("n_chi", C.c_int32), ("cutoff_energy_frac", C.c_double),
+                ("n_chi_pair", C.c_int32), ("chi_pair_min", C.c_double), ("chi_pair_max", C.c_double),
+                ("n_f", C.c_int32)]
+
+
+class _Config(C.Structure):
+    _fields_ = [("field_kind", C.c_int32), ("field", C.c_double * 16),
+                ("grid_nx", C.c_int32), ("grid_ny", C.c_int32),
+                ("grid_dx", C.c_double), ("grid_dy", C.c_double),
+                ("grid_x0", C.c_double), ("grid_y0", C.c_double),
+                ("dims", C.c_int32), ("dt", C.c_double), ("t0", C.c_double),
+                ("step0", C.c_int64), ("n_steps", C.c_int64),
+                ("seed", C.c_uint64), ("instance", C.c_uint64), ("flags", C.c_uint32),
+                ("draw_initial_tau", C.c_int32), ("lambda_L", C.c_double)]
+
+
+class _Tables(C.Structure):
+    _fields_ = [("n_eta", C.c_int32), ("eta_min", C.c_double), ("eta_max", C.c_double),
+                ("h", C.POINTER(C.c_double)),
+                ("n_chi", C.c_int32), ("lnchi_min", C.POINTER(C.c_double)),
+                ("dlnchi", C.POINTER(C.c_double)), ("P_chi", C.POINTER(C.c_double)),
+                ("n_chi_pair", C.c_int32), ("chi_pair_min", C.c_double), ("chi_pair_max", C.c_double),
+                ("T", C.POINTER(C.c_double)), ("n_f", C.c_int32),
+                ("f_grid", C.POINTER(C.c_double)), ("P_f", C.POINTER(C.c_double))]
+
+
+_DP = C.POINTER(C.c_double)
+
+
+class _Species(C.Structure):
+    _fields_ = [("x", _DP), ("y", _DP), ("z", _DP), ("ux", _DP), ("uy", _DP), ("uz", _DP),
+                ("tau", _DP), ("margin", _DP), ("uid", C.POINTER(C.c_uint64)),
+                ("count", C.c_int64), ("capacity", C.c_int64)]
+
+
+class _Ledger(C.Structure):
+    _fields_ = [("energy0", C.c_double * 3), ("energy", C.c_double * 3), ("count", C.c_int64 * 3),
+                ("work", C.c_double), ("defect_emit", C.c_double), ("defect_pair", C.c_double),
+                ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
+                ("n_range", C.c_int64), ("n_nonfinite", C.c_int64)]
+
+
+def lib():
+    """Load oracle/liboracle.so, compiling it first if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        path = _build.LIB
+        if not os.path.exists(path):
+            _build.build()
+        L = C.CDLL(path)
+        for name in ("oracle_bessel_k", "oracle_bessel_k_tail"):
+            getattr(L, name).argtypes = [C.c_double, C.c_double]
+            getattr(L, name).restype = C.c_double
+        for name in ("oracle_F", "oracle_energy_below", "oracle_cutoff_chi", "oracle_pf"):
+            getattr(L, name).argtypes = [C.c_double, C.c_double]
+            getattr(L, name).restype = C.c_double
+        for name in ("oracle_h", "oracle_g", "oracle_T", "oracle_pair_k"):
+            getattr(L, name).argtypes = [C.c_double]
+            getattr(L, name).restype = C.c_double
+        L.oracle_philox.argtypes = [C.POINTER(C.c_uint64)] * 3
+        L.oracle_philox.restype = None
+        L.oracle_gauss_legendre.argtypes = [C.c_int, _DP, _DP]
+        L.oracle_build_tables.argtypes = [C.POINTER(_TableParams)] + [_DP] * 8
+        L.oracle_build_tables.restype = C.c_int
+        L.oracle_run.argtypes = [C.POINTER(_Config), C.POINTER(_Tables), C.POINTER(_Species),
+                                 C.POINTER(_Species), C.POINTER(_Ledger)]
+        L.oracle_run.restype = C.c_int
+        L.oracle_num_threads.restype = C.c_int
+        _LIB = L
+    return _LIB
+
+
+def _vec(fn, *args):
+    b = np.broadcast_arrays(*[np.asarray(a, dtype=np.float64) for a in args])
+    out = np.empty(b[0].shape)
+    for idx in np.ndindex(out.shape):
+        out[idx] = fn(*[float(x[idx]) for x in b])
+    return out if out.shape else float(out)
+
+
+# ---- special functions -------------------------------------------------------
+def bessel_k(nu, y):
+    return _vec(lib().oracle_bessel_k, nu, y)
+
+
+def bessel_k_tail(nu, y):
+    """int_y^inf K_nu(t) dt"""
+    return _vec(lib().oracle_bessel_k_tail, nu, y)
+
+
+def F(eta, chi):
+    """Quantum synchrotron function (Appendix A)."""
+    return _vec(lib().oracle_F, eta, chi)
+
+
+def h(eta):
+    return _vec(lib().oracle_h, eta)
+
+
+def g(eta):
+    return _vec(lib().oracle_g, eta)
+
+
+def energy_below(eta, chi):
+    """int_0^chi F(eta, chi') dchi'"""
+    return _vec(lib().oracle_energy_below, eta, chi)
+
+
+def cutoff_chi(eta, frac=1e-9):
+    return _vec(lib().oracle_cutoff_chi, eta, frac)
+
+
+def T(chi):
+    """Pair emissivity T_pm(chi) (Appendix B)."""
+    return _vec(lib().oracle_T, chi)
+
+
+def pair_k(chi):
+    return _vec(lib().oracle_pair_k, chi)
+
+
+def pf(f, chi):
+    """Normalised pair energy-split density p_f(f, chi) (Appendix B)."""
+    return _vec(lib().oracle_pf, f, chi)
+
+
+def gauss_legendre(n):
+    x = np.empty(n)
+    w = np.empty(n)
+    lib().oracle_gauss_legendre(n, x.ctypes.data_as(_DP), w.ctypes.data_as(_DP))
+    return x, w
+
+
+def philox(counter, key):
+    """One Philox4x64-10 block for a 4-word counter and a 2-word key."""
+    c = np.ascontiguousarray(counter, dtype=np.uint64)
+    k = np.ascontiguousarray(key, dtype=np.uint64)
+    o = np.empty(4, dtype=np.uint64)
+    P = C.POINTER(C.c_uint64)
+    lib().oracle_philox(c.ctypes.data_as(P), k.ctypes.data_as(P), o.ctypes.data_as(P))
+    return o
+
+
+# ---- tables ------------------------------------------------------------------
+DEFAULT_TABLE_PARAMS = dict(n_eta=256, eta_min=1e-4, eta_max=1e2, n_chi=256, cutoff_energy_frac=1e-9,
+                            n_chi_pair=256, chi_pair_min=1e-2, chi_pair_max=1e2, n_f=256)
+
+
+def build_tables(**overrides) -> dict:
+    """The look-up tables of Sec. 3 (h, T_pm, P_chi, P_f) as numpy arrays."""
+    p = dict(DEFAULT_TABLE_PARAMS)
+    p.update(overrides)
+    tp = _TableParams(**p)
+    ne, nc, npair, nf = p["n_eta"], p["n_chi"], p["n_chi_pair"], p["n_f"]
+    t = dict(params=p,
+             h=np.empty(ne), lnchi_min=np.empty(ne), dlnchi=np.empty(ne), P_chi=np.empty((ne, nc)),
+             T=np.empty(npair), f_grid=np.empty(nf), P_f=np.empty((npair, nf)), k_norm=np.empty(npair))
+    rc = lib().oracle_build_tables(C.byref(tp), *[t[k].ctypes.data_as(_DP) for k in
+                                                  ("h", "lnchi_min", "dlnchi", "P_chi", "T", "f_grid",
+                                                   "P_f", "k_norm")])
+    if rc != 0:
+        raise ValueError("oracle_build_tables rejected its parameters")
+    return t
+
+
+# ---- Monte-Carlo run -----------------------------------------------------------
+@dataclass
+class RunConfig:
+    field_kind: int
+    field: tuple
+    dt: float
+    n_steps: int
+    t0: float = 0.0
+    step0: int = 0
+    seed: int = 1
+    instance: int = 0
+    flags: int = FLAG_EMIT | FLAG_PAIRS | FLAG_PROPAGATE
+    dims: int = 3
+    draw_initial_tau: bool = True
+    lambda_L: float = 1e-6
+    grid: tuple = (0, 0, 0.0, 0.0, 0.0, 0.0)  # nx, ny, dx, dy, x0, y0
+
+
+def _species_in(d):
+    if d is None:
+        return _Species(count=0, capacity=0), []
+    keep = []
+
+    def arr(name, dtype=np.float64):
+        a = d.get(name)
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dtype)
+        keep.append(a)
+        return a
+
+    n = len(d["uid"])
+    s = _Species(count=n, capacity=n)
+    for name in ("x", "y", "z", "ux", "uy", "uz", "tau"):
+        a = arr(name)
+        if a is not None:
+            setattr(s, name, a.ctypes.data_as(_DP))
+    u = arr("uid", np.uint64)
+    s.uid = u.ctypes.data_as(C.POINTER(C.c_uint64))
+    return s, keep
+
+
+def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=None, capacity=None):
+    """Advance every family rooted at the given particles; return (species dict, ledger dict).
+
+    Each species input is a dict of arrays x, y, z, ux, uy, uz, uid (and tau when
+    ``cfg.draw_initial_tau`` is False).  Outputs hold the live particles of each
+    species, family by family, plus ``margin``: the smallest |tau| a particle
+    showed after a decrement (small values flag threshold straddles).
+    """
+    L = lib()
+    p = tables["params"]
+    tab = _Tables(n_eta=p["n_eta"], eta_min=p["eta_min"], eta_max=p["eta_max"],
+                  h=tables["h"].ctypes.data_as(_DP), n_chi=p["n_chi"],
+                  lnchi_min=tables["lnchi_min"].ctypes.data_as(_DP),
+                  dlnchi=tables["dlnchi"].ctypes.data_as(_DP),
+                  P_chi=tables["P_chi"].ctypes.data_as(_DP), n_chi_pair=p["n_chi_pair"],
+                  chi_pair_min=p["chi_pair_min"], chi_pair_max=p["chi_pair_max"],
+                  T=tables["T"].ctypes.data_as(_DP), n_f=p["n_f"],
+                  f_grid=tables["f_grid"].ctypes.data_as(_DP), P_f=tables["P_f"].ctypes.data_as(_DP))
+    conf = _Config()
+    conf.field_kind = cfg.field_kind
+    fp = list(cfg.field) + [0.0] * (16 - len(cfg.field))
+    conf.field = (C.c_double * 16)(*fp)
+    conf.grid_nx, conf.grid_ny, conf.grid_dx, conf.grid_dy, conf.grid_x0, conf.grid_y0 = cfg.grid
+    conf.dims = cfg.dims
+    conf.dt = cfg.dt
+    conf.t0 = cfg.t0
+    conf.step0 = cfg.step0
+    conf.n_steps = cfg.n_steps
+    conf.seed = cfg.seed
+    conf.instance = cfg.instance
+    conf.flags = cfg.flags
+    conf.draw_initial_tau = 1 if cfg.draw_initial_tau else 0
+    conf.lambda_L = cfg.lambda_L
+
+    ins = (_Species * 3)()
+    keep = []
+    for i, d in enumerate((electrons, positrons, photons)):
+        s, k = _species_in(d)
+        ins[i] = s
+        keep += k
+    n_in = sum(int(ins[i].count) for i in range(3))
+    cap = capacity if capacity is not None else [max(16, 4 * n_in)] * 3
+
+    for attempt in range(2):
+        outs = (_Species * 3)()
+        bufs = []
+        for i in range(3):
+            b = {k: np.empty(cap[i]) for k in ("x", "y", "z", "ux", "uy", "uz", "tau", "margin")}
+            b["uid"] = np.empty(cap[i], dtype=np.uint64)
+            bufs.append(b)
+            o = _Species(count=0, capacity=cap[i])
+            for k in ("x", "y", "z", "ux", "uy", "uz", "tau", "margin"):
+                setattr(o, k, b[k].ctypes.data_as(_DP))
+            o.uid = b["uid"].ctypes.data_as(C.POINTER(C.c_uint64))
+            outs[i] = o
+        led = _Ledger()
+        rc = L.oracle_run(C.byref(conf), C.byref(tab), ins, outs, C.byref(led))
+        if rc == 0:
+            break
+        # outputs did not fit: retry with the sizes the oracle reported (same result, deterministic)
+        cap = [int(outs[i].count) + 1 for i in range(3)]
+    else:
+        raise RuntimeError("oracle output sizing failed")
+
+    res = {}
+    for i, name in enumerate(SPECIES):
+        n = int(outs[i].count)
+        res[name] = {k: v[:n].copy() for k, v in bufs[i].items()}
+        if cfg.dims == 2:
+            res[name].pop("z")
+    ledger = dict(energy0=list(led.energy0), energy=list(led.energy), count=list(led.count),
+                  work=led.work, defect_emit=led.defect_emit, defect_pair=led.defect_pair,
+                  n_emit=led.n_emit, n_null=led.n_null, n_pair=led.n_pair, n_range=led.n_range,
+                  n_nonfinite=led.n_nonfinite)
+    return res, ledger
+
+
+def num_threads() -> int:
+    return int(lib().oracle_num_threads())
