@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Throughput of the QED Monte-Carlo step (push + emission + pairs) on one MI355X.
+
+Workload (default): the head-on collision of 1e6 electrons (gamma ~ N(2000, 10%),
+sigma = 2 um) with a linearly polarised a0 = 200, lambda = 1 um, 30 fs sin^2 pulse,
+dt = lambda/(200 c), 20000 steps, photon emission and pair creation on, dead photons
+compacted every 100 steps, FP64.  `warmup` untimed steps, then exactly `steps` timed
+steps of the same run.  value = particle-steps (every electron, positron and photon
+slot present at the start of a step) per second of the timed region.
+
+Also printed on the same JSON line: the roofline of the dominant kernel (algorithmic
+bytes per launch / its mean HIP-event duration over the timed region, against 8 TB/s),
+and the FP64 oracle timed on the host cores over a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particle-steps/s (push+QED MC) FP64 vs FP32-mixed vs batched; % HBM peak"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(form, kind, led0, led1):
+    """Algorithmic HBM bytes of one kernel class over the timed region.
+
+    Per particle-step, FP64 form: lepton 56 B read (x, u, tau) + 56 B written; photon 52 B read
+    (birth position, birth step, k) + 16 B more when its pair rate is non-zero (tau read and
+    written).  Per event: the emitter's uid (8 B) and the child's record (photon 68 B; pair
+    2 x 64 B).  FP32-mixed: lepton 56 + 56 (hi/lo position and momentum, tau); photon 28 (+16);
+    photon child 44 B; pair 2 x 64 B."""
+    d = lambda k, i=None: (led1[k][i] - led0[k][i]) if i is not None else (led1[k] - led0[k])
+    if kind == "lepton":
+        steps = d("particle_steps", 0) + d("particle_steps", 1)
+        per, child = (112, 68) if form == "fp64" else (112, 44)
+        return steps * per + (d("n_emit") + d("n_null")) * 8 + d("n_emit") * child
+    steps = d("particle_steps", 2)
+    base = 52 if form == "fp64" else 28
+    return steps * base + d("photon_steps_in_field") * 16 + d("n_pair") * (8 + 128)
+
+
+def source_hash():
+    h = hashlib.sha1()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_1311_5551_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_1311_5551_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:12]
+
+
+def measured_traffic(kernel, form):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
+    the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, form))
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def run_form(form, args, tables):
+    import torch
+    from paper_1311_5551_amd import capi, workloads as W
+    from paper_1311_5551_amd.sim import Run
+
+    total = args.warmup + args.steps
+    if form in ("fp64", "fp32"):
+        w = W.collision_config2(n=args.electrons, n_steps=max(total, 20000))
+        ws = [w]
+        workload = ("collision_lp_a200: %d electrons gamma~N(2000,10%%) sigma 2um vs LP a0=200 lambda 1um "
+                    "30fs sin^2, dt=lambda/200c, steps %d..%d of 20000, emission+pairs, compaction every %d"
+                    % (w.n, args.warmup, total, args.compact_every))
+    else:
+        ws = W.batched_config5(n_steps=4000)
+        for w in ws:
+            w.capacity = dict(electron=3 * w.n + 4096, positron=2 * w.n + 4096,
+                              photon=int(w.n * (40 + 0.5 * float(w.notes.split()[0].split("=")[1]))) + 8192)
+        workload = ("batched_collisions: 256 instances, N_i=10^U(3,6) (total %d electrons), a0~U(50,500), "
+                    "gamma0 log-U[500,5000], steps %d..%d of a 4000-step window centred on the collisions"
+                    % (sum(w.n for w in ws), args.warmup, total))
+    prec = capi.QED_FP64 if form == "fp64" else capi.QED_FP32_MIXED
+    log("%s: allocating and binding (%s)" % (form, workload[:60]))
+    run = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
+    step = 0
+    log("%s: %d warmup steps" % (form, args.warmup))
+    for _ in range(args.warmup):
+        run.step(1)
+        step += 1
+        if step % args.compact_every == 0:
+            run.compact()
+    led0 = run.ledger()
+    run.profile(True)
+    run.synchronize()
+    log("%s: timing %d steps" % (form, args.steps))
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        run.step(1)
+        step += 1
+        if step % args.compact_every == 0:
+            run.compact()
+        if i and i % 2000 == 0:
+            log("%s: step %d" % (form, step))
+    run.synchronize()
+    t1 = time.perf_counter()
+    ms, launches = run.profile_read()
+    run.profile(False)
+    led1 = run.ledger()
+    n_inst = len(ws)
+    agg0 = _aggregate(led0)
+    agg1 = _aggregate(led1)
+    psteps = sum(agg1["particle_steps"]) - sum(agg0["particle_steps"])
+    status = sorted(set(l["status"] for l in led1))
+    res = dict(form=form, workload=workload, n_inst=n_inst, seconds=t1 - t0, particle_steps=int(psteps),
+               value=psteps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / args.steps,
+               kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2]),
+               launches=dict(setup=launches[0], lepton=launches[1], photon=launches[2]),
+               photons_end=int(agg1["count"][2]), pairs=int(agg1["n_pair"] - agg0["n_pair"]),
+               emissions=int(agg1["n_emit"] - agg0["n_emit"]), drift_max=max(l["drift"] for l in led1),
+               status=status)
+    kind = "photon" if ms[2] >= ms[1] else "lepton"
+    byts = kernel_bytes(form, kind, agg0, agg1)
+    n_l = launches[2] if kind == "photon" else launches[1]
+    avg_s = (ms[2] if kind == "photon" else ms[1]) / max(n_l, 1) * 1e-3
+    achieved = byts / max(n_l, 1) / avg_s / 1e9
+    traffic = measured_traffic(kind, form)
+    res["roofline"] = {"kernel": "k_%s_%s" % (kind, "f64" if form == "fp64" else "f32"), "bound": "hbm",
+                       "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                       "traffic": traffic, "algorithmic_bytes_per_launch": byts / max(n_l, 1),
+                       "mean_launch_us": avg_s * 1e6}
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+    return res
+
+
+def _aggregate(leds):
+    out = {"particle_steps": [0, 0, 0], "count": [0, 0, 0]}
+    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field"):
+        out[k] = sum(l[k] for l in leds)
+    for i in range(3):
+        out["particle_steps"][i] = sum(l["particle_steps"][i] for l in leds)
+        out["count"][i] = sum(l["count"][i] for l in leds)
+    return out
+
+
+def cpu_baseline(args):
+    """The FP64 oracle on the host cores over the first `families` electrons of the same
+    workload (their whole families, all 20000 steps)."""
+    import oracle
+    from paper_1311_5551_amd import workloads as W
+    tables = oracle.build_tables()
+    w = W.subset(W.collision_config2(n=args.electrons), range(args.cpu_families))
+    cfg = oracle.RunConfig(field_kind=w.field_kind, field=w.field, dt=w.dt, n_steps=w.n_steps, flags=w.flags,
+                           seed=w.seed, instance=w.instance)
+    log("cpu baseline: oracle on %d families x %d steps, %d threads" % (w.n, w.n_steps, oracle.num_threads()))
+    t0 = time.perf_counter()
+    _, led = oracle.run(cfg, tables, electrons=w.electrons)
+    t1 = time.perf_counter()
+    return {"value": led["particle_steps"] / (t1 - t0), "unit": "particle-steps/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "first %d electrons of the 1e6-electron collision and all their descendants, all 20000 steps "
+                      "(%d particle-steps, %.1f s); oracle tables built beforehand" % (w.n, led["particle_steps"],
+                                                                                         t1 - t0)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=19800)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--electrons", type=int, default=1_000_000)
+    ap.add_argument("--compact-every", type=int, default=100)
+    ap.add_argument("--block", type=int, default=256)
+    ap.add_argument("--ppt", type=int, default=4)
+    ap.add_argument("--forms", default="fp64", help="comma list of fp64, fp32, batched; the first is `value`")
+    ap.add_argument("--cpu-families", type=int, default=500)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the QED step shards by particle family with no per-step "
+              "communication, so only the single-GPU throughput is measured here (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1311_5551_amd.sim import Tables
+    torch.cuda.set_device(0)
+    log("building tables on the GPU")
+    tables = Tables.build()
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    results = [run_form(f, args, tables) for f in forms]
+    main_r = results[0]
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args)
+    out = {
+        "metric": METRIC,
+        "value": main_r["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if main_r["form"] == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": main_r["workload"], "form": main_r["form"], "instances": main_r["n_inst"],
+                   "launch": {"block": args.block, "particles_per_thread": args.ppt}},
+        "roofline": main_r["roofline"],
+        "cpu_baseline": cpu,
+        "detail": {r["form"]: {k: v for k, v in r.items() if k not in ("workload",)} for r in results},
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

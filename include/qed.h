@@ -1,0 +1,231 @@
+/*
+ * qed.h -- C ABI of libqed: the per-particle QED Monte-Carlo emission step of
+ * Ridgers et al., "Modelling gamma-ray photon emission and pair production in
+ * high-intensity laser-matter interactions" (arXiv:1311.5551), on MI355X (gfx950).
+ *
+ * Pointers named *_dev are device memory on the device that was current when the
+ * handle they are used with was created; other pointers are host memory.  Nothing
+ * here takes ownership of caller memory.  Every call returns a qed_status and never
+ * throws, aborts or exits; after a non-OK return qed_last_error() describes it.
+ *
+ * Code units (both sides of this interface):
+ *   time t' = w t with w = 2 pi c / lambda_L;  length x' = w x / c;
+ *   lepton momentum u = p/(m c), gamma = sqrt(1 + |u|^2);
+ *   photon momentum k = p/(m c), energy |k| m c^2;
+ *   fields E' = E/E_s and B' = c B/E_s (E_s the Schwinger field).
+ */
+#ifndef QED_H
+#define QED_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* qed_stream; /* a hipStream_t; NULL = the null stream */
+
+typedef enum {
+  QED_OK = 0,
+  QED_ERR_ARG = -1,       /* invalid argument; nothing was enqueued */
+  QED_ERR_HIP = -2,       /* HIP runtime failure; qed_last_error() has the HIP message */
+  QED_ERR_CAPACITY = -3,  /* children were dropped because a species buffer was full */
+  QED_ERR_NONFINITE = -4, /* a particle state became non-finite */
+  QED_ERR_STATE = -5,     /* call order violated (e.g. a step before qed_bind) */
+  QED_ERR_DEVICE = -6     /* the current device is not a gfx950 GPU */
+} qed_status;
+
+typedef enum { QED_FP64 = 0, QED_FP32_MIXED = 1 } qed_precision;
+
+/* step flags */
+enum {
+  QED_EMIT = 1u,      /* leptons emit photons (Sec. 3: optical depth, P_chi sampling, recoil) */
+  QED_PAIRS = 2u,     /* photons create pairs (Sec. 3: optical depth with T_pm, P_f sampling) */
+  QED_PROPAGATE = 4u  /* photons are stepped; without it emitted photons are only recorded (Sec. 3.1) */
+};
+
+/* field kinds; p[] parameters in code units */
+enum {
+  QED_FIELD_UNIFORM = 0,         /* p = {Ex, Ey, Ez, Bx, By, Bz} */
+  QED_FIELD_LP_PULSE = 1,        /* p = {E0, Psi, psi0, phase}: psi = t - x - psi0,
+                                    E_y = B_z = E0 sin^2(pi psi/Psi) cos(psi + phase) on 0 <= psi <= Psi */
+  QED_FIELD_CP_WAVE = 2,         /* p = {E0, phase}: psi = t - x + phase, E = E0 (0, cos psi, sin psi),
+                                    B = x_hat x E (Sec. 2.4 test configuration) */
+  QED_FIELD_CP_STANDING = 3,     /* p = {E0}: two counter-propagating CP waves, E_y = 2E0 cos t cos x,
+                                    E_z = 2E0 sin t cos x, B_y = 2E0 cos t sin x, B_z = 2E0 sin t sin x */
+  QED_FIELD_GRID_CP_STANDING = 4 /* the standing wave written each step onto a 2-D Yee grid (FP32) and
+                                    gathered with first-order (cloud-in-cell) weights (Sec. 3.2) */
+};
+
+/* ---------------------------------------------------------------------------
+ * Look-up tables (Sec. 3): h(eta) and T(chi) are read by linear interpolation between
+ * tabulated nodes, and photon chi and pair split f are drawn by inverting the tabulated
+ * cumulative probabilities P_chi(eta, chi) and P_f(f, chi).  Built on the device from
+ * the integrals of Appendix A and B.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  int32_t n_eta;              /* rows of h and P_chi, log-spaced eta in [eta_min, eta_max]; 2..1024 */
+  double eta_min, eta_max;
+  int32_t n_chi;              /* columns of P_chi: log-spaced chi from chi_min(eta) to eta/2; >= 2 */
+  double cutoff_energy_frac;  /* chi_min(eta): photons below it carry this share of the energy (1e-9) */
+  int32_t n_chi_pair;         /* rows of T and P_f, log-spaced chi in [chi_pair_min, chi_pair_max]; 2..1024 */
+  double chi_pair_min, chi_pair_max;
+  int32_t n_f;                /* columns of P_f: f_l = sin^2(pi l / 2(n_f - 1)); >= 3 */
+} qed_table_params;
+
+typedef struct qed_tables qed_tables; /* opaque, immutable after creation, shareable across streams */
+
+/* Host copies of the tables (valid until qed_tables_destroy):
+ *   h[n_eta]                      h(eta_i) = int_0^{eta_i/2} F/chi dchi  (Appendix A)
+ *   lnchi_min[n_eta], dlnchi[n_eta]  row grids: ln chi_ij = lnchi_min[i] + j dlnchi[i]
+ *   P_chi[n_eta][n_chi]           P(eta_i, chi_ij); column 0 is the share below the cut, last is 1
+ *   T[n_chi_pair]                 T_pm(chi_k) = 0.16 K_{1/3}^2(2/(3 chi_k)) / chi_k  (Appendix B)
+ *   f_grid[n_f], P_f[n_chi_pair][n_f], k_norm[n_chi_pair]   cumulative p_f and its normaliser */
+typedef struct {
+  qed_table_params params;
+  const double *h, *lnchi_min, *dlnchi, *P_chi, *T, *f_grid, *P_f, *k_norm;
+} qed_table_view;
+
+/* Builds all tables on the current device (FP64 quadrature of the Appendix A/B integrals) and
+ * keeps device and host copies.  Synchronous.  QED_ERR_ARG on out-of-range parameters. */
+qed_status qed_build_tables(const qed_table_params* params, qed_tables** out);
+
+/* Wraps tables supplied as host arrays (e.g. published tables), laid out as in qed_table_view;
+ * k_norm may be NULL.  Copies them; the caller keeps its arrays. */
+qed_status qed_tables_from_host(const qed_table_params* params, const double* h, const double* lnchi_min,
+                                const double* dlnchi, const double* P_chi, const double* T,
+                                const double* f_grid, const double* P_f, const double* k_norm,
+                                qed_tables** out);
+
+qed_status qed_tables_view(const qed_tables* tables, qed_table_view* out);
+void qed_tables_destroy(qed_tables* tables);
+
+/* ---------------------------------------------------------------------------
+ * Particles: one structure-of-arrays per species, caller-owned device memory.
+ * Species order inside an instance: 0 electrons (charge -1), 1 positrons (+1), 2 photons.
+ * Element type of x..uz: double in QED_FP64; float in QED_FP32_MIXED.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+  void *x_dev, *y_dev, *z_dev;      /* leptons: position; photons: position at birth.  z NULL in 2-D */
+  void *ux_dev, *uy_dev, *uz_dev;   /* leptons: u; photons: k */
+  float *x_lo_dev, *y_lo_dev, *z_lo_dev;    /* QED_FP32_MIXED leptons: low words of compensated */
+  float *ux_lo_dev, *uy_lo_dev, *uz_lo_dev; /* position and momentum (value = hi + lo); else NULL */
+  int32_t* birth_step_dev;          /* photons: step at whose start the photon sits at its birth
+                                       position; it moves ballistically: x(step n) = x_b + (n - b) dt k/|k| */
+  double* tau_dev;                  /* remaining optical depth (FP64 in both precisions); a photon with
+                                       tau < 0 has been converted to a pair and awaits qed_compact */
+  uint64_t* uid_dev;                /* particle id; keys the random stream of the particle */
+  int64_t* count_dev;               /* number of particles in [0, count); device-resident, updated by the
+                                       library as children are appended and photons compacted */
+  int64_t capacity;                 /* length of every array above */
+} qed_species;
+
+typedef struct {
+  int32_t kind;                     /* QED_FIELD_* */
+  double p[16];
+  float* grid_dev;                  /* GRID kinds: 6 x ny x nx floats, components Ex, Ey, Ez, Bx, By, Bz,
+                                       x fastest; Yee offsets Ex(i+1/2, j), Ey(i, j+1/2), Ez(i, j),
+                                       Bx(i, j+1/2), By(i+1/2, j), Bz(i+1/2, j+1/2); periodic */
+  int32_t nx, ny;
+  double dx, dy, x0, y0;
+} qed_field;
+
+typedef struct {
+  qed_species s[3];
+  qed_field field;
+  double weight;                    /* real particles per macro-particle (children inherit it, Sec. 3.2) */
+  uint64_t seed;                    /* Philox4x64-10 key = (seed, key_instance) */
+  uint64_t key_instance;
+  int32_t dims;                     /* 3, or 2 for x-y motion (z_dev NULL) */
+} qed_instance;
+
+typedef struct {
+  double t0;          /* code time of step 0: step n runs from t0 + n dt to t0 + (n+1) dt */
+  double dt;
+  double lambda_L;    /* laser wavelength (m) that defines the code units */
+  uint32_t flags;     /* QED_EMIT | QED_PAIRS | QED_PROPAGATE */
+  qed_precision precision;
+} qed_step_params;
+
+typedef struct qed_workspace qed_workspace; /* opaque: device state of bound instances */
+
+/* Workspace for up to max_inst instances on the current device. */
+qed_status qed_workspace_create(int32_t max_inst, qed_workspace** out);
+void qed_workspace_destroy(qed_workspace* ws);
+
+/* Binds instances (host array, copied; the device arrays they point to stay caller-owned and
+ * must outlive all work enqueued on them), checks their shapes, allocates scratch sized to the
+ * capacities, zeroes the event counters and records the initial energy.  Synchronous. */
+qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
+                    const qed_step_params* params);
+
+/* Launch shape of the step kernels: threads per block (64..1024, multiple of 64) and particles
+ * per thread (1..16).  Takes effect from the next step. */
+qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt);
+
+/* Sec. 3: every macro-particle starts with a sampled optical depth, tau = -ln U with U from the
+ * particle's stream at counter (uid, 0, INIT, 0), for every particle in [0, count).  Async. */
+qed_status qed_init_optical_depth(qed_workspace* ws, qed_stream stream);
+
+/* Sets the index of the next step (device-resident clock; graph-capturable).  Async. */
+qed_status qed_set_step(qed_workspace* ws, int64_t step, qed_stream stream);
+
+/* One Monte-Carlo step (Sec. 3; in the PIC coupling of Sec. 3.2 it follows the particle push):
+ * for every lepton present at the start of the step: fields at (x^n, t^n), Boris push, eta,
+ * tau -= lambda_gamma(eta) dt; on tau <= 0 sample chi from P_chi, recoil, append the photon and
+ * redraw tau.  For every photon (QED_PROPAGATE): move at c, chi, tau -= lambda_pm(chi) dt; on
+ * tau <= 0 sample f from P_f, append the pair, mark the photon dead.  Children are first stepped
+ * in the next step.  Never allocates; async on `stream`; device-side conditions (full buffers,
+ * non-finite state) are reported by the next qed_energy_ledger. */
+qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params,
+                    qed_stream stream);
+
+/* n_steps steps; steps are replayed from a HIP graph of graph_steps steps (captured once per
+ * workspace and launch shape; 0 = plain launches).  Async. */
+qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params,
+                   int64_t n_steps, int32_t graph_steps, qed_stream stream);
+
+/* Removes dead photons (tau < 0) from every bound photon species by moving live photons from
+ * the tail into the holes (order is not preserved).  Async. */
+qed_status qed_compact(qed_workspace* ws, qed_stream stream);
+
+/* Energy account of one instance (Sec. 3.1 and Table 2), in m c^2 times the weight. */
+typedef struct {
+  double energy[3];       /* sum of gamma (leptons) and |k| (live photons) now */
+  double energy0;         /* total at qed_bind */
+  double work;            /* field work on leptons in the pushes since qed_bind */
+  double defect_emit;     /* sum over emissions of gamma_after + |k| - gamma_before */
+  double defect_pair;     /* sum over pair creations of gamma_- + gamma_+ - |k| */
+  double dropped_energy;  /* energy of children that did not fit their buffer */
+  int64_t count[3];
+  int64_t n_emit, n_null, n_pair;  /* emissions, draws below the cut-off, pair creations */
+  int64_t n_dropped, n_range, n_nonfinite;
+  int64_t photon_steps_in_field;   /* photon steps that saw a non-zero pair rate */
+  int64_t particle_steps[3];       /* particles present at the start of each step, summed over the
+                                      steps since qed_bind (photons: buffer slots, incl. dead ones
+                                      not yet compacted) */
+  double drift;           /* |sum energy - energy0 - work - defects + dropped| / energy0 */
+} qed_ledger;
+
+/* Fills out[0..n_inst-1] for the bound instances.  Synchronises `stream`.  Returns
+ * QED_ERR_CAPACITY or QED_ERR_NONFINITE (after filling out) if that happened since qed_bind. */
+qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stream);
+
+/* Kernel timing with HIP events recorded around each kernel of qed_step on its stream (not
+ * available inside qed_run's graph replay).  qed_profile_read synchronises, returns the summed
+ * durations in milliseconds and launch counts of [0] step set-up (snapshot, grid refresh),
+ * [1] lepton kernel, [2] photon kernel since qed_profile(ws, 1), and keeps timing. */
+qed_status qed_profile(qed_workspace* ws, int32_t enable);
+qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches);
+
+/* Thread-local description of the last non-OK status. */
+const char* qed_last_error(void);
+
+/* Library build identifier. */
+const char* qed_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QED_H */

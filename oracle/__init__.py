@@ -66,6 +66,7 @@ _DP = C.POINTER(C.c_double)
 class _Species(C.Structure):
     _fields_ = [("x", _DP), ("y", _DP), ("z", _DP), ("ux", _DP), ("uy", _DP), ("uz", _DP),
                 ("tau", _DP), ("margin", _DP), ("uid", C.POINTER(C.c_uint64)),
+                ("birth", C.POINTER(C.c_int64)), ("family", C.POINTER(C.c_int64)),
                 ("count", C.c_int64), ("capacity", C.c_int64)]
 
 
@@ -73,7 +74,7 @@ class _Ledger(C.Structure):
     _fields_ = [("energy0", C.c_double * 3), ("energy", C.c_double * 3), ("count", C.c_int64 * 3),
                 ("work", C.c_double), ("defect_emit", C.c_double), ("defect_pair", C.c_double),
                 ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
-                ("n_range", C.c_int64), ("n_nonfinite", C.c_int64)]
+                ("n_range", C.c_int64), ("n_nonfinite", C.c_int64), ("particle_steps", C.c_int64)]
 
 
 def lib():
@@ -238,6 +239,9 @@ def _species_in(d):
             setattr(s, name, a.ctypes.data_as(_DP))
     u = arr("uid", np.uint64)
     s.uid = u.ctypes.data_as(C.POINTER(C.c_uint64))
+    b = arr("birth_step", np.int64)
+    if b is not None:
+        s.birth = b.ctypes.data_as(C.POINTER(C.c_int64))
     return s, keep
 
 
@@ -245,9 +249,13 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
     """Advance every family rooted at the given particles; return (species dict, ledger dict).
 
     Each species input is a dict of arrays x, y, z, ux, uy, uz, uid (and tau when
-    ``cfg.draw_initial_tau`` is False).  Outputs hold the live particles of each
-    species, family by family, plus ``margin``: the smallest |tau| a particle
-    showed after a decrement (small values flag threshold straddles).
+    ``cfg.draw_initial_tau`` is False; photons may carry ``birth_step``).  Outputs hold
+    the live particles of each species, family by family; photons report the position
+    where they were born and ``birth_step``, the step at whose start they sat there
+    (their position at the start of step n is x + (n - birth_step) dt k/|k|).  Also
+    ``margin``: the smallest |tau| a particle
+    showed after a decrement (small values flag threshold straddles), and ``family``:
+    the index, in input order, of the particle the family grew from.
     """
     L = lib()
     p = tables["params"]
@@ -290,11 +298,15 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
         for i in range(3):
             b = {k: np.empty(cap[i]) for k in ("x", "y", "z", "ux", "uy", "uz", "tau", "margin")}
             b["uid"] = np.empty(cap[i], dtype=np.uint64)
+            b["family"] = np.empty(cap[i], dtype=np.int64)
+            b["birth_step"] = np.empty(cap[i], dtype=np.int64)
             bufs.append(b)
             o = _Species(count=0, capacity=cap[i])
             for k in ("x", "y", "z", "ux", "uy", "uz", "tau", "margin"):
                 setattr(o, k, b[k].ctypes.data_as(_DP))
             o.uid = b["uid"].ctypes.data_as(C.POINTER(C.c_uint64))
+            o.family = b["family"].ctypes.data_as(C.POINTER(C.c_int64))
+            o.birth = b["birth_step"].ctypes.data_as(C.POINTER(C.c_int64))
             outs[i] = o
         led = _Ledger()
         rc = L.oracle_run(C.byref(conf), C.byref(tab), ins, outs, C.byref(led))
@@ -314,7 +326,7 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
     ledger = dict(energy0=list(led.energy0), energy=list(led.energy), count=list(led.count),
                   work=led.work, defect_emit=led.defect_emit, defect_pair=led.defect_pair,
                   n_emit=led.n_emit, n_null=led.n_null, n_pair=led.n_pair, n_range=led.n_range,
-                  n_nonfinite=led.n_nonfinite)
+                  n_nonfinite=led.n_nonfinite, particle_steps=led.particle_steps)
     return res, ledger
 
 

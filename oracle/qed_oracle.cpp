@@ -667,14 +667,16 @@ double sample_f(const Tables& tb, double chi, double u) {
 
 // --- particles and families ------------------------------------------------
 struct Particle {
-  double x, y, z, ux, uy, uz, tau;
+  double x, y, z, ux, uy, uz, tau;  // photons: x, y, z is the position at step `birth`
   uint64_t uid;
+  int64_t birth;  // photons: step at whose start the photon sits at (x, y, z)
   int species;  // 0 electron, 1 positron, 2 photon
   double margin;  // smallest |tau| seen after a decrement (threshold-straddle flag)
   bool alive;
 };
 
 struct Tally {
+  int64_t particle_steps = 0;  // particles advanced, one per particle per step
   double work = 0.0;       // sum of field work on leptons (Boris identity)
   double defect_emit = 0.0;
   double defect_pair = 0.0;
@@ -751,6 +753,7 @@ void step_lepton(Particle& p, const Config& c, const Tables& tb, int64_t n, std:
           ph.uz = k.z;
           ph.tau = optical_depth_draw(r[3]);
           ph.uid = r[2];
+          ph.birth = n + 1;  // first stepped in the next step, from the emitter's new position
           ph.species = 2;
           ph.margin = INFINITY;
           ph.alive = true;
@@ -766,18 +769,18 @@ void step_lepton(Particle& p, const Config& c, const Tables& tb, int64_t n, std:
   if (!std::isfinite(p.tau) || !std::isfinite(p.ux) || !std::isfinite(p.uy) || !std::isfinite(p.uz)) ++tl.n_nonfinite;
 }
 
-// one step of a photon: ballistic move at c, then the pair optical depth (eq. 3)
+// one step of a photon: it moves at c along k (eq. 5: null geodesics), so its position
+// at the start of step n is x_b + (n - birth) dt k/|k|; then the pair optical depth (eq. 3)
 void step_photon(Particle& p, const Config& c, const Tables& tb, int64_t n, std::vector<Particle>& fam,
                  Tally& tl) {
   const double t = c.t0 + (double)n * c.dt;
-  Vec3 E, B;
-  fields_at(c, p.x, p.y, p.z, t, &E, &B);
   const Vec3 k = {p.ux, p.uy, p.uz};
   const double eps = std::sqrt(dot(k, k));
-  const Vec3 nh = (1.0 / eps) * k;
-  p.x += c.dt * nh.x;
-  p.y += c.dt * nh.y;
-  if (c.dims == 3) p.z += c.dt * nh.z;
+  const Vec3 nh = {k.x / eps, k.y / eps, k.z / eps};
+  const double age = (double)(n - p.birth) * c.dt;
+  const Vec3 xn = {p.x + age * nh.x, p.y + age * nh.y, c.dims == 3 ? p.z + age * nh.z : 0.0};
+  Vec3 E, B;
+  fields_at(c, xn.x, xn.y, xn.z, t, &E, &B);
   if (c.flags & FLAG_PAIRS) {
     // chi = (eps/2) sqrt(|E + n x B|^2 - (n.E)^2)
     const Vec3 a = E + cross(nh, B);
@@ -795,10 +798,13 @@ void step_photon(Particle& p, const Config& c, const Tables& tb, int64_t n, std:
         const Vec3 up = f * k;            // positron takes the fraction f
         const Vec3 ue = (1.0 - f) * k;    // electron the rest
         tl.defect_pair += gamma_of(up.x, up.y, up.z) + gamma_of(ue.x, ue.y, ue.z) - eps;
+        // the pair appears where the photon is at the end of the step
+        const double age1 = age + c.dt;
         Particle e, po;
-        e.x = po.x = p.x;
-        e.y = po.y = p.y;
-        e.z = po.z = p.z;
+        e.x = po.x = p.x + age1 * nh.x;
+        e.y = po.y = p.y + age1 * nh.y;
+        e.z = po.z = c.dims == 3 ? p.z + age1 * nh.z : 0.0;
+        e.birth = po.birth = 0;
         e.ux = ue.x;
         e.uy = ue.y;
         e.uz = ue.z;
@@ -861,6 +867,8 @@ typedef struct {
 typedef struct {
   double *x, *y, *z, *ux, *uy, *uz, *tau, *margin;
   uint64_t* uid;
+  int64_t* birth;    // photons: step at whose start the photon sits at (x, y, z) (optional on input)
+  int64_t* family;   // out only (optional): index of the input particle the family grew from
   int64_t count;     // in: number of input particles; out: number written
   int64_t capacity;  // out only: room in the arrays
 } oracle_species;
@@ -871,6 +879,7 @@ typedef struct {
   int64_t count[3];    // live particles at the end
   double work, defect_emit, defect_pair;
   int64_t n_emit, n_null, n_pair, n_range, n_nonfinite;
+  int64_t particle_steps;  // live particles advanced, summed over steps
 } oracle_ledger;
 
 // Runs n_steps steps starting at step0 for every family rooted at an input particle.
@@ -927,6 +936,7 @@ int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_
       p.uy = in[s].uy[i];
       p.uz = in[s].uz[i];
       p.uid = in[s].uid[i];
+      p.birth = in[s].birth ? in[s].birth[i] : 0;
       p.species = s;
       p.margin = INFINITY;
       p.alive = true;
@@ -960,9 +970,13 @@ int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_
         // copy: push_back may reallocate while the particle is being advanced
         Particle p = fam[i];
         if (p.species == 2) {
-          if (c.flags & FLAG_PROPAGATE) step_photon(p, c, tb, n, fam, tl);
+          if (c.flags & FLAG_PROPAGATE) {
+            step_photon(p, c, tb, n, fam, tl);
+            ++tl.particle_steps;
+          }
         } else {
           step_lepton(p, c, tb, n, fam, tl);
+          ++tl.particle_steps;
         }
         fam[i] = p;
       }
@@ -990,6 +1004,7 @@ int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_
     led->n_pair += tl.n_pair;
     led->n_range += tl.n_range;
     led->n_nonfinite += tl.n_nonfinite;
+    led->particle_steps += tl.particle_steps;
   }
   int64_t w[3] = {0, 0, 0};
   for (int64_t f = 0; f < nf; ++f) {
@@ -1009,6 +1024,8 @@ int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_
         out[s].tau[k] = p.tau;
         out[s].uid[k] = p.uid;
         if (out[s].margin) out[s].margin[k] = p.margin;
+        if (out[s].family) out[s].family[k] = f;
+        if (out[s].birth) out[s].birth[k] = p.birth;
       }
     }
   }

@@ -1,0 +1,721 @@
+// C ABI of libqed (declared in include/qed.h): argument checking, device memory that the
+// library owns (tables, workspace), kernel launch sequencing, HIP-graph replay and the
+// energy ledger.  No call here computes physics on the host; every step of the method
+// runs in the kernels of qed_tables.hip, qed_step.hip and qed_mixed.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qed_device.h"
+#include "qed_kernels.h"
+
+using namespace qedk;
+
+namespace {
+
+thread_local std::string g_err;
+
+qed_status fail(qed_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                      \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess) return fail(QED_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+qed_status check_device(int* dev_out, int* cus_out) {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(QED_ERR_DEVICE, "device %d is %s; this library is built for gfx950", dev, prop.gcnArchName);
+  *dev_out = dev;
+  if (cus_out) *cus_out = prop.multiProcessorCount;
+  return QED_OK;
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+// device memory check: `p` must lie in a device allocation with room for `bytes`
+qed_status check_dev_range(const void* p, size_t bytes, const char* what, int inst, int sp) {
+  if (!p) return fail(QED_ERR_ARG, "instance %d species %d: %s is NULL", inst, sp, what);
+  hipPointerAttribute_t attr;
+  if (hipPointerGetAttributes(&attr, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(QED_ERR_ARG, "instance %d species %d: %s is not device memory", inst, sp, what);
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(QED_ERR_ARG, "instance %d species %d: %s is not device memory", inst, sp, what);
+  void* base = nullptr;
+  size_t size = 0;
+  if (hipMemGetAddressRange(&base, &size, const_cast<void*>(p)) == hipSuccess && base) {
+    const char* b = (const char*)base;
+    const char* q = (const char*)p;
+    if (q + bytes > b + size)
+      return fail(QED_ERR_ARG, "instance %d species %d: %s holds %zu bytes past %p, capacity needs %zu", inst, sp,
+                  what, (size_t)(b + size - q), p, bytes);
+  } else {
+    (void)hipGetLastError();
+  }
+  return QED_OK;
+}
+
+}  // namespace
+
+struct qed_tables {
+  qed_table_params p{};
+  int device = 0;
+  double *h = nullptr, *lnchi_min = nullptr, *dlnchi = nullptr, *P = nullptr, *T = nullptr, *fgrid = nullptr,
+         *Pf = nullptr, *knorm = nullptr;
+  float *h32 = nullptr, *T32 = nullptr;
+  std::vector<double> hh, hlnchi, hdlnchi, hP, hT, hf, hPf, hk;
+};
+
+struct qed_workspace {
+  int device = 0;
+  int cus = 256;
+  int max_inst = 0;
+  int n_inst = 0;
+  bool bound = false;
+  qed_precision prec = QED_FP64;
+  int field_kind = 0;
+  bool any_grid = false;
+  std::vector<qed_instance> inst;
+  std::vector<double> e0;
+  qed_instance* d_inst = nullptr;
+  InstAcc* d_acc = nullptr;
+  Glob* d_glob = nullptr;
+  int64_t* d_base = nullptr;  // 3 * max_inst: leptons (2 per instance) then photons
+  int64_t* d_movers = nullptr;
+  size_t movers_len = 0;
+  int block = 256, ppt = 4;
+  // kernel timing: event pairs per kernel class, reused across reads
+  bool profiling = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_marks;
+  // graph cache
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::string graph_key;
+};
+
+namespace {
+
+void free_tables(qed_tables* t) {
+  if (!t) return;
+  hipFree(t->h);
+  hipFree(t->lnchi_min);
+  hipFree(t->dlnchi);
+  hipFree(t->P);
+  hipFree(t->T);
+  hipFree(t->fgrid);
+  hipFree(t->Pf);
+  hipFree(t->knorm);
+  hipFree(t->h32);
+  hipFree(t->T32);
+  delete t;
+}
+
+qed_status check_table_params(const qed_table_params* p) {
+  if (!p) return fail(QED_ERR_ARG, "table params is NULL");
+  if (p->n_eta < 2 || p->n_eta > 1024) return fail(QED_ERR_ARG, "n_eta = %d outside [2, 1024]", p->n_eta);
+  if (p->n_chi < 2 || p->n_chi > 1024) return fail(QED_ERR_ARG, "n_chi = %d outside [2, 1024]", p->n_chi);
+  if (p->n_chi_pair < 2 || p->n_chi_pair > 1024)
+    return fail(QED_ERR_ARG, "n_chi_pair = %d outside [2, 1024]", p->n_chi_pair);
+  if (p->n_f < 3 || p->n_f > 1024) return fail(QED_ERR_ARG, "n_f = %d outside [3, 1024]", p->n_f);
+  if (!finite_pos(p->eta_min) || !finite_pos(p->eta_max) || !(p->eta_max > p->eta_min))
+    return fail(QED_ERR_ARG, "eta range [%g, %g] invalid", p->eta_min, p->eta_max);
+  if (p->eta_min < 1e-8 || p->eta_max > 1e4)
+    return fail(QED_ERR_ARG, "eta range [%g, %g] outside [1e-8, 1e4]", p->eta_min, p->eta_max);
+  if (!finite_pos(p->chi_pair_min) || !finite_pos(p->chi_pair_max) || !(p->chi_pair_max > p->chi_pair_min))
+    return fail(QED_ERR_ARG, "chi_pair range [%g, %g] invalid", p->chi_pair_min, p->chi_pair_max);
+  if (p->chi_pair_min < 1e-3 || p->chi_pair_max > 1e5)
+    return fail(QED_ERR_ARG, "chi_pair range [%g, %g] outside [1e-3, 1e5]", p->chi_pair_min, p->chi_pair_max);
+  if (!(p->cutoff_energy_frac > 1e-15 && p->cutoff_energy_frac < 1e-2))
+    return fail(QED_ERR_ARG, "cutoff_energy_frac = %g outside (1e-15, 1e-2)", p->cutoff_energy_frac);
+  return QED_OK;
+}
+
+template <class T>
+qed_status dalloc(T** p, size_t n) {
+  HIP_TRY(hipMalloc((void**)p, n * sizeof(T)));
+  return QED_OK;
+}
+
+qed_status alloc_tables(qed_tables* t) {
+  const auto& p = t->p;
+  qed_status st;
+  if ((st = dalloc(&t->h, p.n_eta)) || (st = dalloc(&t->lnchi_min, p.n_eta)) || (st = dalloc(&t->dlnchi, p.n_eta)) ||
+      (st = dalloc(&t->P, (size_t)p.n_eta * p.n_chi)) || (st = dalloc(&t->T, p.n_chi_pair)) ||
+      (st = dalloc(&t->fgrid, p.n_f)) || (st = dalloc(&t->Pf, (size_t)p.n_chi_pair * p.n_f)) ||
+      (st = dalloc(&t->knorm, p.n_chi_pair)) || (st = dalloc(&t->h32, p.n_eta)) || (st = dalloc(&t->T32, p.n_chi_pair)))
+    return st;
+  return QED_OK;
+}
+
+// host copies, FP32 copies of h and T, and sanity of the result
+qed_status finish_tables(qed_tables* t, bool from_device) {
+  const auto& p = t->p;
+  if (from_device) {
+    t->hh.resize(p.n_eta);
+    t->hlnchi.resize(p.n_eta);
+    t->hdlnchi.resize(p.n_eta);
+    t->hP.resize((size_t)p.n_eta * p.n_chi);
+    t->hT.resize(p.n_chi_pair);
+    t->hf.resize(p.n_f);
+    t->hPf.resize((size_t)p.n_chi_pair * p.n_f);
+    t->hk.resize(p.n_chi_pair);
+    HIP_TRY(hipMemcpy(t->hh.data(), t->h, p.n_eta * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t->hlnchi.data(), t->lnchi_min, p.n_eta * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t->hdlnchi.data(), t->dlnchi, p.n_eta * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t->hP.data(), t->P, t->hP.size() * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t->hT.data(), t->T, p.n_chi_pair * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t->hf.data(), t->fgrid, p.n_f * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t->hPf.data(), t->Pf, t->hPf.size() * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t->hk.data(), t->knorm, p.n_chi_pair * 8, hipMemcpyDeviceToHost));
+  }
+  // every cumulative row must be finite, non-decreasing, in [0, 1] and end at 1
+  for (int i = 0; i < p.n_eta; ++i) {
+    if (!finite_pos(t->hh[i]) || !std::isfinite(t->hlnchi[i]) || !finite_pos(t->hdlnchi[i]))
+      return fail(QED_ERR_STATE, "table row %d of h / chi grid is not finite", i);
+    const double* P = &t->hP[(size_t)i * p.n_chi];
+    for (int j = 0; j < p.n_chi; ++j)
+      if (!(P[j] >= 0.0 && P[j] <= 1.0) || (j && P[j] < P[j - 1]))
+        return fail(QED_ERR_STATE, "P_chi row %d is not a cumulative distribution at column %d", i, j);
+    if (P[p.n_chi - 1] != 1.0) return fail(QED_ERR_STATE, "P_chi row %d does not end at 1", i);
+  }
+  for (int k = 0; k < p.n_chi_pair; ++k) {
+    if (!(t->hT[k] >= 0.0) || !std::isfinite(t->hT[k])) return fail(QED_ERR_STATE, "T row %d not finite", k);
+    const double* P = &t->hPf[(size_t)k * p.n_f];
+    for (int l = 0; l < p.n_f; ++l)
+      if (!(P[l] >= 0.0 && P[l] <= 1.0) || (l && P[l] < P[l - 1]))
+        return fail(QED_ERR_STATE, "P_f row %d is not a cumulative distribution at column %d", k, l);
+    if (P[0] != 0.0 || P[p.n_f - 1] != 1.0) return fail(QED_ERR_STATE, "P_f row %d does not span [0, 1]", k);
+  }
+  std::vector<float> h32(p.n_eta), T32(p.n_chi_pair);
+  for (int i = 0; i < p.n_eta; ++i) h32[i] = (float)t->hh[i];
+  for (int k = 0; k < p.n_chi_pair; ++k) T32[k] = (float)t->hT[k];
+  HIP_TRY(hipMemcpy(t->h32, h32.data(), p.n_eta * 4, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t->T32, T32.data(), p.n_chi_pair * 4, hipMemcpyHostToDevice));
+  return QED_OK;
+}
+
+Tabs device_tabs(const qed_tables* t) {
+  Tabs tb;
+  const auto& p = t->p;
+  tb.n_eta = p.n_eta;
+  tb.le0 = std::log(p.eta_min);
+  tb.dle = (std::log(p.eta_max) - tb.le0) / (p.n_eta - 1);
+  tb.h = t->h;
+  tb.h32 = t->h32;
+  tb.n_chi = p.n_chi;
+  tb.lnchi_min = t->lnchi_min;
+  tb.dlnchi = t->dlnchi;
+  tb.P = t->P;
+  tb.n_cp = p.n_chi_pair;
+  tb.lc0 = std::log(p.chi_pair_min);
+  tb.dlc = (std::log(p.chi_pair_max) - tb.lc0) / (p.n_chi_pair - 1);
+  tb.T = t->T;
+  tb.T32 = t->T32;
+  tb.n_f = p.n_f;
+  tb.f = t->fgrid;
+  tb.Pf = t->Pf;
+  return tb;
+}
+
+qed_status check_params(const qed_workspace* ws, const qed_step_params* p) {
+  if (!p) return fail(QED_ERR_ARG, "step params is NULL");
+  if (!finite_pos(p->dt)) return fail(QED_ERR_ARG, "dt = %g must be finite and positive", p->dt);
+  if (!std::isfinite(p->t0)) return fail(QED_ERR_ARG, "t0 = %g must be finite", p->t0);
+  if (!finite_pos(p->lambda_L)) return fail(QED_ERR_ARG, "lambda_L = %g must be finite and positive", p->lambda_L);
+  if (p->flags & ~7u) return fail(QED_ERR_ARG, "unknown flag bits 0x%x", p->flags);
+  if ((p->flags & QED_PAIRS) && !(p->flags & QED_PROPAGATE))
+    return fail(QED_ERR_ARG, "QED_PAIRS needs QED_PROPAGATE (pairs come from stepped photons)");
+  if (p->precision != QED_FP64 && p->precision != QED_FP32_MIXED)
+    return fail(QED_ERR_ARG, "unknown precision %d", (int)p->precision);
+  if (ws && ws->bound && p->precision != ws->prec)
+    return fail(QED_ERR_STATE, "precision differs from the one the instances were bound with");
+  return QED_OK;
+}
+
+StepConst step_const(const qed_step_params* p) {
+  StepConst sc;
+  sc.t0 = p->t0;
+  sc.dt = p->dt;
+  sc.kappa = p->lambda_L / kLambdaCompton;
+  sc.a_gamma = std::sqrt(3.0) * kAlpha * sc.kappa / (2.0 * kPi);
+  sc.a_pair = kAlpha * sc.kappa;
+  sc.flags = p->flags;
+  return sc;
+}
+
+hipEvent_t next_event(qed_workspace* ws) {
+  if (ws->ev_used == ws->ev_pool.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ws->ev_pool.push_back(e);
+  }
+  return ws->ev_pool[ws->ev_used++];
+}
+
+// records a start event for kernel class `k`; returns the slot to close with mark_end
+int mark_begin(qed_workspace* ws, int k, hipStream_t s) {
+  if (!ws->profiling) return -1;
+  hipEvent_t a = next_event(ws), b = next_event(ws);
+  if (!a || !b) return -1;
+  hipEventRecord(a, s);
+  ws->ev_marks.push_back({k, {a, b}});
+  return (int)ws->ev_marks.size() - 1;
+}
+
+void mark_end(qed_workspace* ws, int slot, hipStream_t s) {
+  if (slot >= 0) hipEventRecord(ws->ev_marks[slot].second.second, s);
+}
+
+qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
+  const int B = ws->block, ppt = ws->ppt;
+  const int chunk = B * ppt;
+  const StepConst sc = step_const(p);
+  int m = mark_begin(ws, 0, s);
+  launch_step_begin(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_base, ws->d_base + 2 * ws->max_inst, chunk,
+                    chunk, 1, s);
+  if (ws->any_grid) launch_grid_refresh(ws->d_inst, ws->n_inst, ws->d_glob, sc, s);
+  mark_end(ws, m, s);
+  StepArgs a;
+  a.inst = ws->d_inst;
+  a.acc = ws->d_acc;
+  a.glob = ws->d_glob;
+  a.ppt = ppt;
+  a.tb = device_tabs(tb);
+  a.sc = sc;
+  const int grid = ws->cus * (2048 / B > 0 ? 2048 / B : 1);
+  const bool mixed = ws->prec == QED_FP32_MIXED;
+  a.base = ws->d_base;
+  a.n_base = 2 * ws->n_inst;
+  m = mark_begin(ws, 1, s);
+  launch_lepton(ws->field_kind, a, grid, B, mixed, s);
+  mark_end(ws, m, s);
+  if (p->flags & QED_PROPAGATE) {
+    a.base = ws->d_base + 2 * ws->max_inst;
+    a.n_base = ws->n_inst;
+    m = mark_begin(ws, 2, s);
+    launch_photon(ws->field_kind, a, grid, B, mixed, s);
+    mark_end(ws, m, s);
+  }
+  HIP_TRY(hipGetLastError());
+  return QED_OK;
+}
+
+void drop_graph(qed_workspace* ws) {
+  if (ws->exec) hipGraphExecDestroy(ws->exec);
+  if (ws->graph) hipGraphDestroy(ws->graph);
+  ws->exec = nullptr;
+  ws->graph = nullptr;
+  ws->graph_key.clear();
+}
+
+qed_status run_ledger(qed_workspace* ws, std::vector<InstAcc>& acc, hipStream_t s) {
+  launch_ledger(ws->d_inst, ws->n_inst, ws->d_acc, ws->prec == QED_FP32_MIXED, s);
+  HIP_TRY(hipGetLastError());
+  acc.resize(ws->n_inst);
+  HIP_TRY(hipMemcpyAsync(acc.data(), ws->d_acc, ws->n_inst * sizeof(InstAcc), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  return QED_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* qed_last_error(void) { return g_err.c_str(); }
+
+const char* qed_version(void) { return "libqed 1.0 (gfx950, Philox4x64-10, FP64 and FP32-mixed)"; }
+
+qed_status qed_build_tables(const qed_table_params* params, qed_tables** out) {
+  if (!out) return fail(QED_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  qed_status st = check_table_params(params);
+  if (st) return st;
+  int dev;
+  if ((st = check_device(&dev, nullptr))) return st;
+  qed_tables* t = new qed_tables();
+  t->p = *params;
+  t->device = dev;
+  if ((st = alloc_tables(t))) {
+    free_tables(t);
+    return st;
+  }
+  hipError_t e = launch_build_tables(t->p, t->h, t->lnchi_min, t->dlnchi, t->P, t->T, t->fgrid, t->Pf, t->knorm, nullptr);
+  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e != hipSuccess) {
+    free_tables(t);
+    return fail(QED_ERR_HIP, "table build: %s", hipGetErrorString(e));
+  }
+  if ((st = finish_tables(t, true))) {
+    free_tables(t);
+    return st;
+  }
+  *out = t;
+  return QED_OK;
+}
+
+qed_status qed_tables_from_host(const qed_table_params* params, const double* h, const double* lnchi_min,
+                                const double* dlnchi, const double* P_chi, const double* T, const double* f_grid,
+                                const double* P_f, const double* k_norm, qed_tables** out) {
+  if (!out) return fail(QED_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  qed_status st = check_table_params(params);
+  if (st) return st;
+  if (!h || !lnchi_min || !dlnchi || !P_chi || !T || !f_grid || !P_f) return fail(QED_ERR_ARG, "a table array is NULL");
+  int dev;
+  if ((st = check_device(&dev, nullptr))) return st;
+  qed_tables* t = new qed_tables();
+  t->p = *params;
+  t->device = dev;
+  const auto& p = t->p;
+  t->hh.assign(h, h + p.n_eta);
+  t->hlnchi.assign(lnchi_min, lnchi_min + p.n_eta);
+  t->hdlnchi.assign(dlnchi, dlnchi + p.n_eta);
+  t->hP.assign(P_chi, P_chi + (size_t)p.n_eta * p.n_chi);
+  t->hT.assign(T, T + p.n_chi_pair);
+  t->hf.assign(f_grid, f_grid + p.n_f);
+  t->hPf.assign(P_f, P_f + (size_t)p.n_chi_pair * p.n_f);
+  if (k_norm) t->hk.assign(k_norm, k_norm + p.n_chi_pair);
+  else t->hk.assign(p.n_chi_pair, 0.0);
+  auto up = [&](double* d, const std::vector<double>& v) {
+    return hipMemcpy(d, v.data(), v.size() * 8, hipMemcpyHostToDevice);
+  };
+  if ((st = alloc_tables(t))) {
+    free_tables(t);
+    return st;
+  }
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(t->h, t->hh);
+  if (e == hipSuccess) e = up(t->lnchi_min, t->hlnchi);
+  if (e == hipSuccess) e = up(t->dlnchi, t->hdlnchi);
+  if (e == hipSuccess) e = up(t->P, t->hP);
+  if (e == hipSuccess) e = up(t->T, t->hT);
+  if (e == hipSuccess) e = up(t->fgrid, t->hf);
+  if (e == hipSuccess) e = up(t->Pf, t->hPf);
+  if (e == hipSuccess) e = up(t->knorm, t->hk);
+  if (e != hipSuccess) {
+    free_tables(t);
+    return fail(QED_ERR_HIP, "table upload: %s", hipGetErrorString(e));
+  }
+  if ((st = finish_tables(t, false))) {
+    free_tables(t);
+    return st;
+  }
+  *out = t;
+  return QED_OK;
+}
+
+qed_status qed_tables_view(const qed_tables* t, qed_table_view* out) {
+  if (!t || !out) return fail(QED_ERR_ARG, "NULL argument");
+  out->params = t->p;
+  out->h = t->hh.data();
+  out->lnchi_min = t->hlnchi.data();
+  out->dlnchi = t->hdlnchi.data();
+  out->P_chi = t->hP.data();
+  out->T = t->hT.data();
+  out->f_grid = t->hf.data();
+  out->P_f = t->hPf.data();
+  out->k_norm = t->hk.data();
+  return QED_OK;
+}
+
+void qed_tables_destroy(qed_tables* t) { free_tables(t); }
+
+qed_status qed_workspace_create(int32_t max_inst, qed_workspace** out) {
+  if (!out) return fail(QED_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (max_inst < 1 || max_inst > 65535 / 3) return fail(QED_ERR_ARG, "max_inst = %d outside [1, 21845]", max_inst);
+  int dev, cus;
+  qed_status st = check_device(&dev, &cus);
+  if (st) return st;
+  qed_workspace* ws = new qed_workspace();
+  ws->device = dev;
+  ws->cus = cus;
+  ws->max_inst = max_inst;
+  hipError_t e = hipMalloc((void**)&ws->d_inst, max_inst * sizeof(qed_instance));
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->d_acc, max_inst * sizeof(InstAcc));
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->d_glob, sizeof(Glob));
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->d_base, 3 * (size_t)max_inst * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMemset(ws->d_glob, 0, sizeof(Glob));
+  if (e == hipSuccess) e = hipMemset(ws->d_acc, 0, max_inst * sizeof(InstAcc));
+  if (e != hipSuccess) {
+    qed_workspace_destroy(ws);
+    return fail(QED_ERR_HIP, "workspace allocation: %s", hipGetErrorString(e));
+  }
+  *out = ws;
+  return QED_OK;
+}
+
+void qed_workspace_destroy(qed_workspace* ws) {
+  if (!ws) return;
+  drop_graph(ws);
+  for (hipEvent_t e : ws->ev_pool) hipEventDestroy(e);
+  hipFree(ws->d_inst);
+  hipFree(ws->d_acc);
+  hipFree(ws->d_glob);
+  hipFree(ws->d_base);
+  hipFree(ws->d_movers);
+  delete ws;
+}
+
+qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt) {
+  if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
+  if (block < 64 || block > 256 || block % 64) return fail(QED_ERR_ARG, "block = %d: need 64..256, multiple of 64", block);
+  if (ppt < 1 || ppt > 16) return fail(QED_ERR_ARG, "ppt = %d outside [1, 16]", ppt);
+  if (ws->block != block || ws->ppt != ppt) drop_graph(ws);
+  ws->block = block;
+  ws->ppt = ppt;
+  return QED_OK;
+}
+
+qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst, const qed_step_params* params) {
+  if (!ws || !inst) return fail(QED_ERR_ARG, "NULL argument");
+  if (n_inst < 1 || n_inst > ws->max_inst) return fail(QED_ERR_ARG, "n_inst = %d outside [1, %d]", n_inst, ws->max_inst);
+  ws->bound = false;
+  qed_status st = check_params(nullptr, params);
+  if (st) return st;
+  const bool mixed = params->precision == QED_FP32_MIXED;
+  const size_t fe = mixed ? 4 : 8;
+  int cur;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != ws->device) return fail(QED_ERR_STATE, "workspace belongs to device %d, current is %d", ws->device, cur);
+  size_t movers = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const qed_instance& I = inst[i];
+    if (I.dims != 2 && I.dims != 3) return fail(QED_ERR_ARG, "instance %d: dims = %d (2 or 3)", i, I.dims);
+    if (!finite_pos(I.weight)) return fail(QED_ERR_ARG, "instance %d: weight must be finite and positive", i);
+    const qed_field& F = I.field;
+    if (F.kind < QED_FIELD_UNIFORM || F.kind > QED_FIELD_GRID_CP_STANDING)
+      return fail(QED_ERR_ARG, "instance %d: unknown field kind %d", i, F.kind);
+    if (F.kind != inst[0].field.kind)
+      return fail(QED_ERR_ARG, "instance %d: all bound instances must share one field kind", i);
+    for (int k = 0; k < 16; ++k)
+      if (!std::isfinite(F.p[k])) return fail(QED_ERR_ARG, "instance %d: field parameter %d not finite", i, k);
+    if (F.kind == QED_FIELD_LP_PULSE && !finite_pos(F.p[1]))
+      return fail(QED_ERR_ARG, "instance %d: pulse length must be positive", i);
+    if (F.kind == QED_FIELD_GRID_CP_STANDING) {
+      if (F.nx < 2 || F.ny < 2 || !finite_pos(F.dx) || !finite_pos(F.dy) || !std::isfinite(F.x0) || !std::isfinite(F.y0))
+        return fail(QED_ERR_ARG, "instance %d: grid shape invalid", i);
+      if ((st = check_dev_range(F.grid_dev, (size_t)6 * F.nx * F.ny * 4, "grid_dev", i, -1))) return st;
+    }
+    for (int s = 0; s < 3; ++s) {
+      const qed_species& S = I.s[s];
+      if (S.capacity < 0 || S.capacity > ((int64_t)1 << 40)) return fail(QED_ERR_ARG, "instance %d species %d: capacity", i, s);
+      if ((st = check_dev_range(S.count_dev, 8, "count_dev", i, s))) return st;
+      if (S.capacity == 0) continue;
+      const size_t n = (size_t)S.capacity;
+      if ((st = check_dev_range(S.x_dev, n * fe, "x_dev", i, s)) || (st = check_dev_range(S.y_dev, n * fe, "y_dev", i, s)) ||
+          (st = check_dev_range(S.ux_dev, n * fe, "ux_dev", i, s)) ||
+          (st = check_dev_range(S.uy_dev, n * fe, "uy_dev", i, s)) ||
+          (st = check_dev_range(S.uz_dev, n * fe, "uz_dev", i, s)) ||
+          (st = check_dev_range(S.tau_dev, n * 8, "tau_dev", i, s)) ||
+          (st = check_dev_range(S.uid_dev, n * 8, "uid_dev", i, s)))
+        return st;
+      if (I.dims == 3 && (st = check_dev_range(S.z_dev, n * fe, "z_dev", i, s))) return st;
+      if (s == 2 && (st = check_dev_range(S.birth_step_dev, n * 4, "birth_step_dev", i, s))) return st;
+      if (mixed && s < 2) {
+        if ((st = check_dev_range(S.x_lo_dev, n * 4, "x_lo_dev", i, s)) ||
+            (st = check_dev_range(S.y_lo_dev, n * 4, "y_lo_dev", i, s)) ||
+            (st = check_dev_range(S.ux_lo_dev, n * 4, "ux_lo_dev", i, s)) ||
+            (st = check_dev_range(S.uy_lo_dev, n * 4, "uy_lo_dev", i, s)) ||
+            (st = check_dev_range(S.uz_lo_dev, n * 4, "uz_lo_dev", i, s)))
+          return st;
+        if (I.dims == 3 && (st = check_dev_range(S.z_lo_dev, n * 4, "z_lo_dev", i, s))) return st;
+      }
+    }
+    movers += (size_t)I.s[2].capacity;
+  }
+  // every child needs a slot in its species: emission needs photons, pairs need both leptons
+  drop_graph(ws);
+  ws->inst.assign(inst, inst + n_inst);
+  ws->n_inst = n_inst;
+  ws->prec = params->precision;
+  ws->field_kind = inst[0].field.kind;
+  ws->any_grid = inst[0].field.kind == QED_FIELD_GRID_CP_STANDING;
+  // compaction scratch: one mover index per photon slot
+  std::vector<InstAcc> acc0(n_inst);
+  std::memset(acc0.data(), 0, n_inst * sizeof(InstAcc));
+  size_t off = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    acc0[i].mover_off = (int64_t)off;
+    off += (size_t)inst[i].s[2].capacity;
+  }
+  if (movers > ws->movers_len) {
+    hipFree(ws->d_movers);
+    ws->d_movers = nullptr;
+    ws->movers_len = 0;
+    HIP_TRY(hipMalloc((void**)&ws->d_movers, (movers ? movers : 1) * sizeof(int64_t)));
+    ws->movers_len = movers;
+  }
+  HIP_TRY(hipMemcpy(ws->d_inst, inst, n_inst * sizeof(qed_instance), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ws->d_acc, acc0.data(), n_inst * sizeof(InstAcc), hipMemcpyHostToDevice));
+  std::vector<InstAcc> acc;
+  if ((st = run_ledger(ws, acc, nullptr))) return st;
+  ws->e0.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i)
+    ws->e0[i] = (acc[i].led_energy[0] + acc[i].led_energy[1] + acc[i].led_energy[2]) * inst[i].weight;
+  ws->bound = true;
+  return QED_OK;
+}
+
+qed_status qed_init_optical_depth(qed_workspace* ws, qed_stream stream) {
+  if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
+  if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
+  launch_init_tau(ws->d_inst, ws->n_inst, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return QED_OK;
+}
+
+qed_status qed_set_step(qed_workspace* ws, int64_t step, qed_stream stream) {
+  if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
+  if (step < 0 || step > ((int64_t)1 << 31)) return fail(QED_ERR_ARG, "step = %lld outside [0, 2^31]", (long long)step);
+  launch_set_step(ws->d_glob, step, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return QED_OK;
+}
+
+qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params, qed_stream stream) {
+  if (!tables || !ws) return fail(QED_ERR_ARG, "NULL argument");
+  if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
+  if (tables->device != ws->device) return fail(QED_ERR_STATE, "tables and workspace are on different devices");
+  qed_status st = check_params(ws, params);
+  if (st) return st;
+  return enqueue_step(tables, ws, params, (hipStream_t)stream);
+}
+
+qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params, int64_t n_steps,
+                   int32_t graph_steps, qed_stream stream) {
+  if (!tables || !ws) return fail(QED_ERR_ARG, "NULL argument");
+  if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
+  if (tables->device != ws->device) return fail(QED_ERR_STATE, "tables and workspace are on different devices");
+  qed_status st = check_params(ws, params);
+  if (st) return st;
+  if (n_steps < 0) return fail(QED_ERR_ARG, "n_steps < 0");
+  if (graph_steps < 0 || graph_steps > 100000) return fail(QED_ERR_ARG, "graph_steps = %d outside [0, 1e5]", graph_steps);
+  hipStream_t s = (hipStream_t)stream;
+  if (graph_steps > 0 && s == nullptr) return fail(QED_ERR_ARG, "graph replay needs a non-null stream");
+  if (graph_steps > 0 && ws->profiling) return fail(QED_ERR_STATE, "kernel timing is on; graph replay cannot record it");
+  int64_t done = 0;
+  if (graph_steps > 0 && n_steps >= graph_steps) {
+    char key[256];
+    snprintf(key, sizeof(key), "%p|%a|%a|%a|%u|%d|%d|%d|%d", (const void*)tables, params->t0, params->dt,
+             params->lambda_L, params->flags, (int)params->precision, ws->block, ws->ppt, graph_steps);
+    if (ws->graph_key != key) {
+      drop_graph(ws);
+      HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      for (int g = 0; g < graph_steps; ++g) {
+        st = enqueue_step(tables, ws, params, s);
+        if (st) {
+          hipGraph_t junk = nullptr;
+          hipStreamEndCapture(s, &junk);
+          if (junk) hipGraphDestroy(junk);
+          return st;
+        }
+      }
+      HIP_TRY(hipStreamEndCapture(s, &ws->graph));
+      HIP_TRY(hipGraphInstantiate(&ws->exec, ws->graph, nullptr, nullptr, 0));
+      ws->graph_key = key;
+    }
+    for (; done + graph_steps <= n_steps; done += graph_steps) HIP_TRY(hipGraphLaunch(ws->exec, s));
+  }
+  for (; done < n_steps; ++done)
+    if ((st = enqueue_step(tables, ws, params, s))) return st;
+  return QED_OK;
+}
+
+qed_status qed_profile(qed_workspace* ws, int32_t enable) {
+  if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
+  ws->profiling = enable != 0;
+  ws->ev_marks.clear();
+  ws->ev_used = 0;
+  return QED_OK;
+}
+
+qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches) {
+  if (!ws || !ms || !launches) return fail(QED_ERR_ARG, "NULL argument");
+  for (int k = 0; k < 3; ++k) {
+    ms[k] = 0.0;
+    launches[k] = 0;
+  }
+  for (auto& mk : ws->ev_marks) {
+    HIP_TRY(hipEventSynchronize(mk.second.second));
+    float t = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&t, mk.second.first, mk.second.second));
+    ms[mk.first] += t;
+    launches[mk.first] += 1;
+  }
+  ws->ev_marks.clear();
+  ws->ev_used = 0;
+  return QED_OK;
+}
+
+qed_status qed_compact(qed_workspace* ws, qed_stream stream) {
+  if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
+  if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
+  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_movers, ws->prec == QED_FP32_MIXED, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return QED_OK;
+}
+
+qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stream) {
+  if (!ws || !out) return fail(QED_ERR_ARG, "NULL argument");
+  if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
+  std::vector<InstAcc> acc;
+  qed_status st = run_ledger(ws, acc, (hipStream_t)stream);
+  if (st) return st;
+  bool dropped = false, nonfinite = false;
+  for (int i = 0; i < ws->n_inst; ++i) {
+    const double w = ws->inst[i].weight;
+    const InstAcc& A = acc[i];
+    qed_ledger& L = out[i];
+    std::memset(&L, 0, sizeof(L));
+    double tot = 0.0;
+    for (int s = 0; s < 3; ++s) {
+      L.energy[s] = A.led_energy[s] * w;
+      L.count[s] = (int64_t)A.led_count[s];
+      tot += L.energy[s];
+    }
+    L.energy0 = ws->e0[i];
+    L.work = A.work * w;
+    L.defect_emit = A.defect_emit * w;
+    L.defect_pair = A.defect_pair * w;
+    L.dropped_energy = A.dropped_energy * w;
+    L.n_emit = (int64_t)A.n_emit;
+    L.n_null = (int64_t)A.n_null;
+    L.n_pair = (int64_t)A.n_pair;
+    L.n_dropped = (int64_t)A.n_dropped;
+    L.n_range = (int64_t)A.n_range;
+    L.n_nonfinite = (int64_t)A.n_nonfinite;
+    L.photon_steps_in_field = (int64_t)A.n_field;
+    for (int s = 0; s < 3; ++s) L.particle_steps[s] = (int64_t)A.particle_steps[s];
+    const double resid = tot - L.energy0 - L.work - L.defect_emit - L.defect_pair + L.dropped_energy;
+    L.drift = L.energy0 > 0.0 ? std::fabs(resid) / L.energy0 : std::fabs(resid);
+    dropped |= A.n_dropped > 0;
+    nonfinite |= A.n_nonfinite > 0;
+  }
+  if (nonfinite) return fail(QED_ERR_NONFINITE, "a particle state became non-finite");
+  if (dropped) return fail(QED_ERR_CAPACITY, "children were dropped: a species buffer was full");
+  return QED_OK;
+}
+
+}  // extern "C"

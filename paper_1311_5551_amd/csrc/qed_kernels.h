@@ -1,0 +1,34 @@
+// Kernel argument blocks and host-side launchers shared by the kernel files and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qed_device.h"
+
+namespace qedk {
+
+struct StepArgs {
+  const qed_instance* inst;   // bound instances (device)
+  InstAcc* acc;               // per-instance accumulators (device)
+  const Glob* glob;           // device clock and chunk-list lengths
+  const int64_t* base;        // chunk-list prefix for this kernel's species list
+  int n_base;                 // entries in `base`
+  int ppt;                    // particles per thread in a chunk
+  Tabs tb;
+  StepConst sc;
+};
+
+hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnchi_min, double* dlnchi, double* P,
+                               double* T, double* fgrid, double* Pf, double* knorm, hipStream_t s);
+void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, int64_t* base_lep,
+                       int64_t* base_ph, int chunk_lep, int chunk_ph, int advance, hipStream_t s);
+void launch_set_step(Glob* glob, int64_t step, hipStream_t s);
+void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s);
+void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
+void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
+void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s);
+void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s);
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, bool mixed, hipStream_t s);
+
+}  // namespace qedk

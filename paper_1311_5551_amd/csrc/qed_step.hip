@@ -1,0 +1,643 @@
+// Per-step kernels of the QED Monte-Carlo step (Sec. 3 and 3.2 of the paper):
+//   k_step_begin   snapshot of the live counts, chunk lists, device clock
+//   k_grid_refresh analytic refresh of the 2-D Yee grid (grid field kind)
+//   k_lepton       push + eta + optical depth + photon emission (electrons and positrons)
+//   k_photon       ballistic photons + chi + pair optical depth + pair creation
+// and the auxiliary passes: optical-depth initialisation, compaction of dead photons and
+// the energy-ledger reduction.
+//
+// Work decomposition: every species of every bound instance is cut into chunks of
+// blockDim * ppt consecutive particles; a prefix array over (instance, species) maps a
+// global chunk index to its particles.  Blocks stride over the chunk list, so one launch
+// serves one instance or hundreds of instances of very different sizes, and the counts
+// never leave the device (the step sequence can be captured in a HIP graph).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qed_device.h"
+#include "qed_kernels.h"
+#include "qed_mixed.h"
+
+namespace qedk {
+
+// ---------------------------------------------------------------------------
+// snapshot at the start of a step or pass
+// ---------------------------------------------------------------------------
+__global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
+                             Glob* __restrict__ glob, int64_t* __restrict__ base_lep, int64_t* __restrict__ base_ph,
+                             int chunk_lep, int chunk_ph, int advance_clock) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+    for (int s = 0; s < 3; ++s) {
+      const qed_species& S = inst[i].s[s];
+      int64_t c = 0;
+      if (S.count_dev) {
+        c = *S.count_dev;
+        if (c > S.capacity) {
+          // appends past the end were dropped (and counted) by the kernel that made them
+          *S.count_dev = S.capacity;
+          c = S.capacity;
+        }
+        if (c < 0) c = 0;
+      }
+      acc[i].n_start[s] = c;
+      if (advance_clock) acc[i].particle_steps[s] += (unsigned long long)c;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t b = 0;
+    for (int i = 0; i < n_inst; ++i)
+      for (int s = 0; s < 2; ++s) {
+        base_lep[2 * i + s] = b;
+        b += (acc[i].n_start[s] + chunk_lep - 1) / chunk_lep;
+      }
+    glob->n_chunks[0] = b;
+    b = 0;
+    for (int i = 0; i < n_inst; ++i) {
+      base_ph[i] = b;
+      b += (acc[i].n_start[2] + chunk_ph - 1) / chunk_ph;
+    }
+    glob->n_chunks[1] = b;
+    if (advance_clock) {
+      glob->step_cur = glob->step_next;
+      glob->step_next = glob->step_cur + 1;
+    }
+  }
+}
+
+__global__ void k_set_step(Glob* glob, int64_t step) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) glob->step_next = step;
+}
+
+// largest idx with base[idx] <= c (lands on a non-empty entry; see the chunk-list layout)
+__device__ __forceinline__ int find_entry(const int64_t* __restrict__ base, int n, int64_t c) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (base[mid] <= c) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// ---------------------------------------------------------------------------
+// analytic refresh of the grid: the standing wave at t^n, in FP64, stored as FP32
+// ---------------------------------------------------------------------------
+__global__ void k_grid_refresh(const qed_instance* __restrict__ inst, int n_inst, const Glob* __restrict__ glob,
+                               StepConst sc) {
+  const double t = sc.t0 + (double)glob->step_cur * sc.dt;
+  for (int ii = 0; ii < n_inst; ++ii) {
+    const qed_field& F = inst[ii].field;
+    if (F.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    const int64_t plane = (int64_t)F.nx * F.ny;
+    const double ct = cos(t), st = sin(t), e2 = 2.0 * F.p[0];
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < plane; q += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t i = q % F.nx;
+      // components at x offsets 0 (Ey, Ez, Bx) and 1/2 (Ex, By, Bz); the wave is uniform in y
+      const double xa = F.x0 + (double)i * F.dx;
+      const double xb = F.x0 + ((double)i + 0.5) * F.dx;
+      const double ca = cos(xa), cb = sin(xb);
+      float* g = F.grid_dev;
+      g[q] = 0.0f;                                          // Ex
+      g[plane + q] = (float)(e2 * ct * ca);                 // Ey(i, j+1/2)
+      g[2 * plane + q] = (float)(e2 * st * ca);             // Ez(i, j)
+      g[3 * plane + q] = 0.0f;                              // Bx
+      g[4 * plane + q] = (float)(e2 * ct * cb);             // By(i+1/2, j)
+      g[5 * plane + q] = (float)(e2 * st * cb);             // Bz(i+1/2, j+1/2)
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// leptons, FP64 form
+// ---------------------------------------------------------------------------
+template <int FK>
+__global__ __launch_bounds__(256) void k_lepton_f64(StepArgs a) {
+  extern __shared__ double smem[];
+  double* sh = smem;
+  double* sred = smem + a.tb.n_eta;
+  unsigned* sredu = (unsigned*)(sred + 16 * 3);
+  for (int i = threadIdx.x; i < a.tb.n_eta; i += blockDim.x) sh[i] = a.tb.h[i];
+  __syncthreads();
+
+  const int64_t step = a.glob->step_cur;
+  const double t = a.sc.t0 + (double)step * a.sc.dt;
+  const double dt = a.sc.dt;
+  const int64_t nch = a.glob->n_chunks[0];
+  const int B = blockDim.x;
+  const int64_t CH = (int64_t)B * a.ppt;
+  const bool emit = (a.sc.flags & QED_EMIT) != 0;
+
+  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const int idx = find_entry(a.base, a.n_base, c);
+    const int ii = idx >> 1, sp = idx & 1;
+    const qed_instance& I = a.inst[ii];
+    const qed_species& S = I.s[sp];
+    const qed_species& G = I.s[2];
+    const int64_t n = a.acc[ii].n_start[sp];
+    const int64_t k0 = (c - a.base[idx]) * CH;
+    const double q = sp == 0 ? -1.0 : 1.0;
+    const double hq = 0.5 * q * a.sc.kappa * dt;
+    const bool d3 = I.dims == 3;
+    double* X = (double*)S.x_dev;
+    double* Y = (double*)S.y_dev;
+    double* Z = (double*)S.z_dev;
+    double* UX = (double*)S.ux_dev;
+    double* UY = (double*)S.uy_dev;
+    double* UZ = (double*)S.uz_dev;
+
+    double dacc[3] = {0.0, 0.0, 0.0};   // work, defect, dropped energy
+    unsigned uacc[5] = {0, 0, 0, 0, 0};  // emit, null, range, nonfinite, dropped
+
+    for (int j = 0; j < a.ppt; ++j) {
+      const int64_t k = k0 + (int64_t)j * B + threadIdx.x;
+      const bool active = k < n;
+      bool child = false;
+      double cx = 0, cy = 0, cz = 0, ckx = 0, cky = 0, ckz = 0, ctau = 0;
+      uint64_t cuid = 0;
+      if (active) {
+        double x = X[k], y = Y[k], z = d3 ? Z[k] : 0.0;
+        double ux = UX[k], uy = UY[k], uz = UZ[k], tau = S.tau_dev[k];
+        double E[3], Bf[3];
+        field_at<FK>(I.field, x, y, t, E, Bf);
+        // Boris push
+        const double g0 = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
+        const double umx = ux + hq * E[0], umy = uy + hq * E[1], umz = uz + hq * E[2];
+        const double gm = sqrt(1.0 + (umx * umx + umy * umy + umz * umz));
+        const double tx = hq / gm * Bf[0], ty = hq / gm * Bf[1], tz = hq / gm * Bf[2];
+        const double sf = 2.0 / (1.0 + (tx * tx + ty * ty + tz * tz));
+        const double sx = sf * tx, sy = sf * ty, sz = sf * tz;
+        const double upx = umx + (umy * tz - umz * ty), upy = umy + (umz * tx - umx * tz),
+                     upz = umz + (umx * ty - umy * tx);
+        const double ulx = umx + (upy * sz - upz * sy), uly = umy + (upz * sx - upx * sz),
+                     ulz = umz + (upx * sy - upy * sx);
+        const double u1x = ulx + hq * E[0], u1y = uly + hq * E[1], u1z = ulz + hq * E[2];
+        const double g1 = sqrt(1.0 + (u1x * u1x + u1y * u1y + u1z * u1z));
+        dacc[0] += 2.0 * hq * (E[0] * (ulx + umx) + E[1] * (uly + umy) + E[2] * (ulz + umz)) / (g1 + g0);
+        x += dt * u1x / g1;
+        y += dt * u1y / g1;
+        if (d3) z += dt * u1z / g1;
+        ux = u1x;
+        uy = u1y;
+        uz = u1z;
+        if (emit) {
+          const double ax = g1 * E[0] + (u1y * Bf[2] - u1z * Bf[1]);
+          const double ay = g1 * E[1] + (u1z * Bf[0] - u1x * Bf[2]);
+          const double az = g1 * E[2] + (u1x * Bf[1] - u1y * Bf[0]);
+          const double ue = u1x * E[0] + u1y * E[1] + u1z * E[2];
+          const double r2 = (ax * ax + ay * ay + az * az) - ue * ue;
+          const double eta = sqrt(r2 > 0.0 ? r2 : 0.0);
+          if (eta > 0.0) {
+            const double h = lookup_h(sh, a.tb, eta, uacc[2]);
+            tau -= a.sc.a_gamma * (eta / g1) * h * dt;
+            if (tau <= 0.0) {
+              uint64_t r[4];
+              philox4x64_10(S.uid_dev[k], (uint64_t)step, KIND_EMIT, 0, I.seed, I.key_instance, r);
+              double chi;
+              if (sample_chi(a.tb, eta, unit_open(r[0]), &chi)) {
+                const double xi = 2.0 * chi / eta;
+                const double kx = xi * u1x, ky = xi * u1y, kz = xi * u1z;
+                ux = u1x - kx;
+                uy = u1y - ky;
+                uz = u1z - kz;
+                const double g2 = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
+                const double eps = sqrt(kx * kx + ky * ky + kz * kz);
+                dacc[1] += g2 + eps - g1;
+                child = true;
+                cx = x;
+                cy = y;
+                cz = z;
+                ckx = kx;
+                cky = ky;
+                ckz = kz;
+                ctau = optical_depth(r[3]);
+                cuid = r[2];
+                ++uacc[0];
+              } else {
+                ++uacc[1];
+              }
+              tau = optical_depth(r[1]);
+            }
+          }
+        }
+        if (!isfinite(tau) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz)) ++uacc[3];
+        X[k] = x;
+        Y[k] = y;
+        if (d3) Z[k] = z;
+        UX[k] = ux;
+        UY[k] = uy;
+        UZ[k] = uz;
+        S.tau_dev[k] = tau;
+      }
+      // append the photons of this pass, one atomic per wave
+      const long long slot = wave_reserve(child, G.count_dev);
+      if (child) {
+        if (slot < G.capacity) {
+          ((double*)G.x_dev)[slot] = cx;
+          ((double*)G.y_dev)[slot] = cy;
+          if (d3) ((double*)G.z_dev)[slot] = cz;
+          ((double*)G.ux_dev)[slot] = ckx;
+          ((double*)G.uy_dev)[slot] = cky;
+          ((double*)G.uz_dev)[slot] = ckz;
+          G.tau_dev[slot] = ctau;
+          G.uid_dev[slot] = cuid;
+          G.birth_step_dev[slot] = (int32_t)(step + 1);
+        } else {
+          ++uacc[4];
+          dacc[2] += sqrt(ckx * ckx + cky * cky + ckz * ckz);
+        }
+      }
+    }
+    block_sum(dacc, uacc, sred, sredu);
+    if (threadIdx.x == 0) {
+      InstAcc& A = a.acc[ii];
+      if (dacc[0] != 0.0) atomicAdd(&A.work, dacc[0]);
+      if (dacc[1] != 0.0) atomicAdd(&A.defect_emit, dacc[1]);
+      if (dacc[2] != 0.0) atomicAdd(&A.dropped_energy, dacc[2]);
+      if (uacc[0]) atomicAdd(&A.n_emit, (unsigned long long)uacc[0]);
+      if (uacc[1]) atomicAdd(&A.n_null, (unsigned long long)uacc[1]);
+      if (uacc[2]) atomicAdd(&A.n_range, (unsigned long long)uacc[2]);
+      if (uacc[3]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[3]);
+      if (uacc[4]) atomicAdd(&A.n_dropped, (unsigned long long)uacc[4]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// photons, FP64 form.  Position at the start of step n: x_b + (n - b) dt k/|k|.
+// ---------------------------------------------------------------------------
+template <int FK>
+__global__ __launch_bounds__(256) void k_photon_f64(StepArgs a) {
+  extern __shared__ double smem[];
+  double* sT = smem;
+  double* sred = smem + a.tb.n_cp;
+  unsigned* sredu = (unsigned*)(sred + 16 * 3);
+  for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) sT[i] = a.tb.T[i];
+  __syncthreads();
+
+  const int64_t step = a.glob->step_cur;
+  const double t = a.sc.t0 + (double)step * a.sc.dt;
+  const double dt = a.sc.dt;
+  const int64_t nch = a.glob->n_chunks[1];
+  const int B = blockDim.x;
+  const int64_t CH = (int64_t)B * a.ppt;
+  const bool pairs = (a.sc.flags & QED_PAIRS) != 0;
+
+  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const int ii = find_entry(a.base, a.n_base, c);
+    const qed_instance& I = a.inst[ii];
+    const qed_species& S = I.s[2];
+    const qed_species& Se = I.s[0];
+    const qed_species& Sp = I.s[1];
+    const int64_t n = a.acc[ii].n_start[2];
+    const int64_t k0 = (c - a.base[ii]) * CH;
+    const bool d3 = I.dims == 3;
+
+    double dacc[3] = {0.0, 0.0, 0.0};   // defect, dropped energy, unused
+    unsigned uacc[5] = {0, 0, 0, 0, 0};  // pairs, in-field steps, range, nonfinite, dropped
+
+    for (int j = 0; j < a.ppt; ++j) {
+      const int64_t k = k0 + (int64_t)j * B + threadIdx.x;
+      const bool active = k < n;
+      bool born = false;
+      double px = 0, py = 0, pz = 0, ex = 0, ey = 0, ez = 0, etau = 0, ptau = 0, pkx = 0, pky = 0, pkz = 0;
+      uint64_t euid = 0, puid = 0;
+      if (active && pairs) {
+        const double kx = ((const double*)S.ux_dev)[k], ky = ((const double*)S.uy_dev)[k],
+                     kz = ((const double*)S.uz_dev)[k];
+        const double eps = sqrt(kx * kx + ky * ky + kz * kz);
+        const double nx = kx / eps, ny = ky / eps, nz = kz / eps;
+        const double age = (double)(step - (int64_t)S.birth_step_dev[k]) * dt;
+        const double x = ((const double*)S.x_dev)[k] + age * nx;
+        const double y = ((const double*)S.y_dev)[k] + age * ny;
+        double E[3], Bf[3];
+        field_at<FK>(I.field, x, y, t, E, Bf);
+        // chi = (eps/2) sqrt(|E + n x B|^2 - (n.E)^2)
+        const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
+        const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
+        const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
+        const double ne = nx * E[0] + ny * E[1] + nz * E[2];
+        const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
+        const double chi = 0.5 * eps * sqrt(r2 > 0.0 ? r2 : 0.0);
+        const double T = lookup_T(sT, a.tb, chi, uacc[2]);
+        if (T > 0.0) {
+          double tau = S.tau_dev[k];
+          if (!(tau < 0.0)) {  // tau < 0: already converted
+            ++uacc[1];
+            tau -= a.sc.a_pair * chi * T / eps * dt;
+            if (tau <= 0.0) {
+              const uint64_t uid = S.uid_dev[k];
+              uint64_t r0[4], r1[4];
+              philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 0, I.seed, I.key_instance, r0);
+              philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 1, I.seed, I.key_instance, r1);
+              const double f = sample_f(a.tb, chi, unit_open(r0[0]));
+              pkx = f * kx;
+              pky = f * ky;
+              pkz = f * kz;
+              ex = (1.0 - f) * kx;
+              ey = (1.0 - f) * ky;
+              ez = (1.0 - f) * kz;
+              const double gp = sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
+              const double ge = sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
+              dacc[0] += gp + ge - eps;
+              const double age1 = age + dt;
+              px = ((const double*)S.x_dev)[k] + age1 * nx;
+              py = ((const double*)S.y_dev)[k] + age1 * ny;
+              pz = d3 ? ((const double*)S.z_dev)[k] + age1 * nz : 0.0;
+              euid = r0[1];
+              puid = r0[2];
+              etau = optical_depth(r0[3]);
+              ptau = optical_depth(r1[0]);
+              born = true;
+              ++uacc[0];
+              tau = -1.0;  // annihilated
+            }
+            if (!isfinite(tau)) ++uacc[3];
+            S.tau_dev[k] = tau;
+          }
+        }
+      }
+      // append electron and positron, one atomic per wave each
+      const long long se = wave_reserve(born, Se.count_dev);
+      const long long spo = wave_reserve(born, Sp.count_dev);
+      if (born) {
+        if (se < Se.capacity) {
+          ((double*)Se.x_dev)[se] = px;
+          ((double*)Se.y_dev)[se] = py;
+          if (d3) ((double*)Se.z_dev)[se] = pz;
+          ((double*)Se.ux_dev)[se] = ex;
+          ((double*)Se.uy_dev)[se] = ey;
+          ((double*)Se.uz_dev)[se] = ez;
+          Se.tau_dev[se] = etau;
+          Se.uid_dev[se] = euid;
+        } else {
+          ++uacc[4];
+          dacc[1] += sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
+        }
+        if (spo < Sp.capacity) {
+          ((double*)Sp.x_dev)[spo] = px;
+          ((double*)Sp.y_dev)[spo] = py;
+          if (d3) ((double*)Sp.z_dev)[spo] = pz;
+          ((double*)Sp.ux_dev)[spo] = pkx;
+          ((double*)Sp.uy_dev)[spo] = pky;
+          ((double*)Sp.uz_dev)[spo] = pkz;
+          Sp.tau_dev[spo] = ptau;
+          Sp.uid_dev[spo] = puid;
+        } else {
+          ++uacc[4];
+          dacc[1] += sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
+        }
+      }
+    }
+    block_sum(dacc, uacc, sred, sredu);
+    if (threadIdx.x == 0) {
+      InstAcc& A = a.acc[ii];
+      if (dacc[0] != 0.0) atomicAdd(&A.defect_pair, dacc[0]);
+      if (dacc[1] != 0.0) atomicAdd(&A.dropped_energy, dacc[1]);
+      if (uacc[0]) atomicAdd(&A.n_pair, (unsigned long long)uacc[0]);
+      if (uacc[1]) atomicAdd(&A.n_field, (unsigned long long)uacc[1]);
+      if (uacc[2]) atomicAdd(&A.n_range, (unsigned long long)uacc[2]);
+      if (uacc[3]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[3]);
+      if (uacc[4]) atomicAdd(&A.n_dropped, (unsigned long long)uacc[4]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// optical-depth initialisation: tau = -ln U, U from counter (uid, 0, INIT, 0)
+// grid: x strides particles, y = instance * 3 + species
+// ---------------------------------------------------------------------------
+__global__ void k_init_tau(const qed_instance* __restrict__ inst) {
+  const int ii = blockIdx.y / 3, s = blockIdx.y % 3;
+  const qed_instance& I = inst[ii];
+  const qed_species& S = I.s[s];
+  if (!S.count_dev) return;
+  int64_t n = *S.count_dev;
+  if (n > S.capacity) n = S.capacity;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t r[4];
+    philox4x64_10(S.uid_dev[k], 0, KIND_INIT, 0, I.seed, I.key_instance, r);
+    S.tau_dev[k] = optical_depth(r[0]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// energy ledger: sum of gamma (leptons) and |k| (live photons), and counts
+// ---------------------------------------------------------------------------
+__global__ void k_ledger_zero(InstAcc* acc, int n_inst) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+    for (int s = 0; s < 3; ++s) {
+      acc[i].led_energy[s] = 0.0;
+      acc[i].led_count[s] = 0;
+    }
+  }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_ledger(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc) {
+  __shared__ double sred[16 * 1];
+  __shared__ unsigned sredu[16 * 1];
+  const int ii = blockIdx.y / 3, s = blockIdx.y % 3;
+  const qed_species& S = inst[ii].s[s];
+  double d[1] = {0.0};
+  unsigned u[1] = {0};
+  if (S.count_dev) {
+    int64_t n = *S.count_dev;
+    if (n > S.capacity) n = S.capacity;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+      double ux, uy, uz;
+      if (MIXED) {
+        ux = (double)((const float*)S.ux_dev)[k];
+        uy = (double)((const float*)S.uy_dev)[k];
+        uz = (double)((const float*)S.uz_dev)[k];
+        if (s < 2) {
+          ux += (double)S.ux_lo_dev[k];
+          uy += (double)S.uy_lo_dev[k];
+          uz += (double)S.uz_lo_dev[k];
+        }
+      } else {
+        ux = ((const double*)S.ux_dev)[k];
+        uy = ((const double*)S.uy_dev)[k];
+        uz = ((const double*)S.uz_dev)[k];
+      }
+      if (s == 2) {
+        if (S.tau_dev[k] < 0.0) continue;
+        d[0] += sqrt(ux * ux + uy * uy + uz * uz);
+      } else {
+        d[0] += sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
+      }
+      ++u[0];
+    }
+  }
+  block_sum(d, u, sred, sredu);
+  if (threadIdx.x == 0) {
+    if (d[0] != 0.0) atomicAdd(&acc[ii].led_energy[s], d[0]);
+    if (u[0]) atomicAdd(&acc[ii].led_count[s], (unsigned long long)u[0]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// compaction of dead photons (tau < 0): live photons from [n_live, n) fill the holes in [0, n_live)
+// ---------------------------------------------------------------------------
+__global__ void k_compact_prep(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+    const qed_species& S = inst[i].s[2];
+    int64_t n = S.count_dev ? *S.count_dev : 0;
+    if (n > S.capacity) n = S.capacity;
+    if (n < 0) n = 0;
+    if (S.count_dev) *S.count_dev = n;
+    acc[i].n_start[2] = n;
+    acc[i].n_live = 0;
+    acc[i].hole_ctr = 0;
+    acc[i].mover_ctr = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_compact_count(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc) {
+  __shared__ double sred[16];
+  __shared__ unsigned sredu[16];
+  const int ii = blockIdx.y;
+  const qed_species& S = inst[ii].s[2];
+  const int64_t n = acc[ii].n_start[2];
+  double d[1] = {0.0};
+  unsigned u[1] = {0};
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    if (!(S.tau_dev[k] < 0.0)) ++u[0];
+  block_sum(d, u, sred, sredu);
+  if (threadIdx.x == 0 && u[0]) atomicAdd((unsigned long long*)&acc[ii].n_live, (unsigned long long)u[0]);
+}
+
+__global__ __launch_bounds__(256) void k_compact_movers(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
+                                                        int64_t* __restrict__ movers) {
+  const int ii = blockIdx.y;
+  const qed_species& S = inst[ii].s[2];
+  const int64_t n = acc[ii].n_start[2], L = acc[ii].n_live;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // loop bounds are identical across a wave so that every lane reaches the ballot
+  for (int64_t k0 = L + blockIdx.x * (int64_t)blockDim.x; k0 < n; k0 += stride) {
+    const int64_t k = k0 + threadIdx.x;
+    const bool mv = k < n && !(S.tau_dev[k] < 0.0);
+    const long long slot = wave_reserve(mv, (int64_t*)&acc[ii].mover_ctr);
+    if (mv) movers[acc[ii].mover_off + slot] = k;
+  }
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
+                                                      const int64_t* __restrict__ movers) {
+  const int ii = blockIdx.y;
+  const qed_species& S = inst[ii].s[2];
+  const int64_t L = acc[ii].n_live, n = acc[ii].n_start[2];
+  const long long n_movers = (long long)acc[ii].mover_ctr;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool d3 = inst[ii].dims == 3;
+  for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < L; k0 += stride) {
+    const int64_t k = k0 + threadIdx.x;
+    const bool hole = k < L && S.tau_dev[k] < 0.0;
+    const long long slot = wave_reserve(hole, (int64_t*)&acc[ii].hole_ctr);
+    // every hole in [0, L) has a mover in [L, n); the bounds below only guard that invariant
+    if (hole && slot < n_movers) {
+      const int64_t src = movers[acc[ii].mover_off + slot];
+      if (src < L || src >= n) continue;
+      if (MIXED) {
+        ((float*)S.x_dev)[k] = ((const float*)S.x_dev)[src];
+        ((float*)S.y_dev)[k] = ((const float*)S.y_dev)[src];
+        if (d3) ((float*)S.z_dev)[k] = ((const float*)S.z_dev)[src];
+        ((float*)S.ux_dev)[k] = ((const float*)S.ux_dev)[src];
+        ((float*)S.uy_dev)[k] = ((const float*)S.uy_dev)[src];
+        ((float*)S.uz_dev)[k] = ((const float*)S.uz_dev)[src];
+      } else {
+        ((double*)S.x_dev)[k] = ((const double*)S.x_dev)[src];
+        ((double*)S.y_dev)[k] = ((const double*)S.y_dev)[src];
+        if (d3) ((double*)S.z_dev)[k] = ((const double*)S.z_dev)[src];
+        ((double*)S.ux_dev)[k] = ((const double*)S.ux_dev)[src];
+        ((double*)S.uy_dev)[k] = ((const double*)S.uy_dev)[src];
+        ((double*)S.uz_dev)[k] = ((const double*)S.uz_dev)[src];
+      }
+      S.tau_dev[k] = S.tau_dev[src];
+      S.uid_dev[k] = S.uid_dev[src];
+      S.birth_step_dev[k] = S.birth_step_dev[src];
+    }
+  }
+}
+
+__global__ void k_compact_finish(const qed_instance* __restrict__ inst, int n_inst, const InstAcc* __restrict__ acc) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+    const qed_species& S = inst[i].s[2];
+    if (S.count_dev) *S.count_dev = acc[i].n_live;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launchers
+// ---------------------------------------------------------------------------
+template <int FK>
+static void launch_lepton_fk(const StepArgs& a, dim3 grid, dim3 block, size_t shm, hipStream_t s, bool mixed) {
+  if (mixed) hipLaunchKernelGGL(k_lepton_f32<FK>, grid, block, shm, s, a);
+  else hipLaunchKernelGGL(k_lepton_f64<FK>, grid, block, shm, s, a);
+}
+template <int FK>
+static void launch_photon_fk(const StepArgs& a, dim3 grid, dim3 block, size_t shm, hipStream_t s, bool mixed) {
+  if (mixed) hipLaunchKernelGGL(k_photon_f32<FK>, grid, block, shm, s, a);
+  else hipLaunchKernelGGL(k_photon_f64<FK>, grid, block, shm, s, a);
+}
+
+void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, int64_t* base_lep,
+                       int64_t* base_ph, int chunk_lep, int chunk_ph, int advance, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, inst, n_inst, acc, glob, base_lep, base_ph, chunk_lep,
+                     chunk_ph, advance);
+}
+
+void launch_set_step(Glob* glob, int64_t step, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, glob, step);
+}
+
+void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s) {
+  hipLaunchKernelGGL(k_grid_refresh, dim3(2048), dim3(256), 0, s, inst, n_inst, glob, sc);
+}
+
+void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
+  const size_t shm = (size_t)a.tb.n_eta * (mixed ? sizeof(float) : sizeof(double)) + 16 * 3 * sizeof(double) +
+                     16 * 5 * sizeof(unsigned) + 64;
+  const dim3 g(grid), b(block);
+  switch (fk) {
+    case QED_FIELD_UNIFORM: launch_lepton_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_LP_PULSE: launch_lepton_fk<QED_FIELD_LP_PULSE>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_CP_WAVE: launch_lepton_fk<QED_FIELD_CP_WAVE>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_CP_STANDING: launch_lepton_fk<QED_FIELD_CP_STANDING>(a, g, b, shm, s, mixed); break;
+    default: launch_lepton_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, shm, s, mixed); break;
+  }
+}
+
+void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
+  const size_t shm = (size_t)a.tb.n_cp * (mixed ? sizeof(float) : sizeof(double)) + 16 * 3 * sizeof(double) +
+                     16 * 5 * sizeof(unsigned) + 64;
+  const dim3 g(grid), b(block);
+  switch (fk) {
+    case QED_FIELD_UNIFORM: launch_photon_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_LP_PULSE: launch_photon_fk<QED_FIELD_LP_PULSE>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_CP_WAVE: launch_photon_fk<QED_FIELD_CP_WAVE>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_CP_STANDING: launch_photon_fk<QED_FIELD_CP_STANDING>(a, g, b, shm, s, mixed); break;
+    default: launch_photon_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, shm, s, mixed); break;
+  }
+}
+
+void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s) {
+  hipLaunchKernelGGL(k_init_tau, dim3(64, 3 * n_inst), dim3(256), 0, s, inst);
+}
+
+void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s) {
+  hipLaunchKernelGGL(k_ledger_zero, dim3(1), dim3(256), 0, s, acc, n_inst);
+  if (mixed) hipLaunchKernelGGL(k_ledger<true>, dim3(128, 3 * n_inst), dim3(256), 0, s, inst, acc);
+  else hipLaunchKernelGGL(k_ledger<false>, dim3(128, 3 * n_inst), dim3(256), 0, s, inst, acc);
+}
+
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, bool mixed, hipStream_t s) {
+  hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
+  hipLaunchKernelGGL(k_compact_count, dim3(128, n_inst), dim3(256), 0, s, inst, acc);
+  hipLaunchKernelGGL(k_compact_movers, dim3(128, n_inst), dim3(256), 0, s, inst, acc, movers);
+  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, dim3(128, n_inst), dim3(256), 0, s, inst, acc, movers);
+  else hipLaunchKernelGGL(k_compact_fill<false>, dim3(128, n_inst), dim3(256), 0, s, inst, acc, movers);
+  hipLaunchKernelGGL(k_compact_finish, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
+}
+
+}  // namespace qedk

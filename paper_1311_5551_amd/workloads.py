@@ -92,8 +92,13 @@ def uniform_b(n: int, gamma0: float, b: float, dt: float, n_steps: int, flags: i
     """Electrons at the origin with u perpendicular to a uniform B' = b z_hat."""
     zeros = np.zeros(n)
     e = _beam(n, gamma0, (1.0, 0.0, 0.0), (zeros, zeros, zeros), 3)
-    return Workload(name=name, field_kind=FIELD_UNIFORM, field=(0.0, 0.0, 0.0, 0.0, 0.0, b), dt=dt,
-                    n_steps=n_steps, flags=flags, electrons=e, seed=seed)
+    w = Workload(name=name, field_kind=FIELD_UNIFORM, field=(0.0, 0.0, 0.0, 0.0, 0.0, b), dt=dt,
+                 n_steps=n_steps, flags=flags, electrons=e, seed=seed)
+    # at most one emission per particle per step (Sec. 3.1); pairs per photon
+    ph = n * n_steps + 1024
+    w.capacity = dict(electron=n + 2 * ph if flags & FLAG_PAIRS else n + 1024,
+                      positron=2 * ph if flags & FLAG_PAIRS else 1024, photon=ph)
+    return w
 
 
 def dt_qed(field_max: float, h0: float = 5.24) -> float:
@@ -135,8 +140,11 @@ def cp_wave_test2(n: int, dt_over_qed: float = 0.3, seed: int = 1, pairs: bool =
     zeros = np.zeros(n)
     e = _beam(n, 4120.0, (-1.0, 0.0, 0.0), (zeros, zeros, zeros), 3)
     flags = FLAG_EMIT | (FLAG_PAIRS | FLAG_PROPAGATE if pairs else 0)
-    return Workload(name="paper_test2", field_kind=FIELD_CP_WAVE, field=(e0, 0.0), dt=t_end / n_steps,
-                    n_steps=n_steps, flags=flags, electrons=e, seed=seed)
+    w = Workload(name="paper_test2", field_kind=FIELD_CP_WAVE, field=(e0, 0.0), dt=t_end / n_steps,
+                 n_steps=n_steps, flags=flags, electrons=e, seed=seed)
+    ph = n * n_steps + 1024
+    w.capacity = dict(electron=n + 2 * ph, positron=2 * ph, photon=ph)
+    return w
 
 
 # ---------------------------------------------------------------------------
@@ -173,9 +181,12 @@ def collision(n: int, a0: float = 200.0, gamma_mean: float = 2000.0, gamma_rel_s
     beta = math.sqrt(1.0 - 1.0 / (gamma_mean * gamma_mean))
     # envelope argument psi = t - x - psi0; the peak (psi = Psi/2) reaches x = -beta t_m at t_m
     psi0 = t_m + beta * t_m - 0.5 * psi_len
-    return Workload(name=name, field_kind=FIELD_LP_PULSE, field=(e0, psi_len, psi0, 0.0), dt=dt,
-                    n_steps=n_steps, flags=flags, electrons=e, seed=seed, instance=instance,
-                    notes="a0=%g gamma=%g" % (a0, gamma_mean))
+    w = Workload(name=name, field_kind=FIELD_LP_PULSE, field=(e0, psi_len, psi0, 0.0), dt=dt,
+                 n_steps=n_steps, flags=flags, electrons=e, seed=seed, instance=instance,
+                 notes="a0=%g gamma=%g" % (a0, gamma_mean))
+    # room for the emission and pair yield of a0 <= 500, gamma <= 5000 beams
+    w.capacity = dict(electron=3 * n + 4096, positron=2 * n + 4096, photon=160 * n + 8192)
+    return w
 
 
 def collision_config2(n: int = 1_000_000, n_steps: int = 20_000) -> Workload:

@@ -1,0 +1,223 @@
+"""GPU tests of the library's mechanics around the step: edge cases (empty and ragged
+species, full buffers, non-finite state, eta above the table), argument checking,
+compaction, HIP-graph replay, batched instances, restarts and the FP32-mixed form."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1311_5551_amd import capi, workloads as W
+from paper_1311_5551_amd.sim import Run, Tables
+
+from parity import compare_species, oracle_run, record
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def shared_tables(oracle_tables):
+    return Tables.from_arrays(oracle_tables)
+
+
+def _states_equal(ra, rb, ia=0, ib=0, species=("electron", "positron", "photon")):
+    """Bitwise equality of two runs' particles, matched by uid."""
+    for name in species:
+        a, b = ra.species(ia, name), rb.species(ib, name)
+        assert len(a["uid"]) == len(b["uid"]), name
+        oa, ob = np.argsort(a["uid"]), np.argsort(b["uid"])
+        for k in a:
+            np.testing.assert_array_equal(a[k][oa], b[k][ob], err_msg="%s.%s" % (name, k))
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 65, 257, 1025])
+def test_empty_and_ragged_counts(n, shared_tables, oracle_tables):
+    w = W.uniform_b(n, 1000.0, 1e-3, 0.15, 40, W.FLAG_EMIT)
+    r = Run(w, shared_tables, ppt=3)
+    r.step(w.n_steps)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK"
+    o_res, o_led = oracle_run(w, oracle_tables)
+    assert led["n_emit"] == o_led["n_emit"] and led["count"] == o_led["count"]
+    for name in ("electron", "photon"):
+        rep = compare_species(r.species(0, name), o_res[name], photon=name == "photon")
+        assert rep["matched"] == len(o_res[name]["uid"]) == rep["n_gpu"]
+        assert (rep["e_err"] <= 1e-12).all()
+
+
+def test_capacity_overflow_is_reported_and_accounted(shared_tables, oracle_tables):
+    n = 4000
+    w = W.uniform_b(n, 1000.0, 1e-3, 0.15, 1, W.FLAG_EMIT)
+    o_res, o_led = oracle_run(w, oracle_tables)
+    cap = o_led["n_emit"] // 2
+    r = Run(w, shared_tables, capacity=dict(photon=cap))
+    r.step(1)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_ERR_CAPACITY"
+    assert led["n_dropped"] == o_led["n_emit"] - cap
+    assert led["count"][2] == cap
+    # the dropped photons' energy is booked, so the ledger still closes
+    assert led["drift"] < 1e-12
+    assert led["dropped_energy"] > 0
+
+
+def test_nonfinite_state_is_reported(shared_tables):
+    w = W.uniform_b(100, 1000.0, 1e-3, 0.15, 3, W.FLAG_EMIT)
+    w.electrons["ux"][7] = float("nan")
+    r = Run(w, shared_tables)
+    r.step(3)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_ERR_NONFINITE"
+    assert led["n_nonfinite"] >= 1
+    e = r.species(0, "electron")
+    assert np.isfinite(e["ux"][e["uid"] != 7]).all()
+
+
+def test_eta_above_table_is_clamped_and_counted(shared_tables, oracle_tables):
+    # gamma = 2e5 in B' = 1e-3: eta = 200 > eta_max = 100
+    w = W.uniform_b(200, 2e5, 1e-3, 1e-3, 5, W.FLAG_EMIT)
+    r = Run(w, shared_tables)
+    r.step(5)
+    led = r.ledger()[0]
+    o_res, o_led = oracle_run(w, oracle_tables)
+    assert led["n_range"] == o_led["n_range"] > 0
+    rep = compare_species(r.species(0, "electron"), o_res["electron"])
+    assert (rep["e_err"] <= 1e-12).all()
+
+
+def test_invalid_arguments_are_rejected(shared_tables):
+    w = W.uniform_b(10, 1000.0, 1e-3, 0.15, 3, W.FLAG_EMIT)
+    r = Run(w, shared_tables)
+    bad = capi.qed_step_params(t0=0.0, dt=-1.0, lambda_L=1e-6, flags=1, precision=0)
+    with pytest.raises(capi.QEDError) as e:
+        capi.qed_step(shared_tables.handle, r.ws, bad, r._s())
+    assert e.value.status == capi.QED_ERR_ARG
+    bad = capi.qed_step_params(t0=0.0, dt=0.1, lambda_L=1e-6, flags=capi.QED_PAIRS, precision=0)
+    with pytest.raises(capi.QEDError):
+        capi.qed_step(shared_tables.handle, r.ws, bad, r._s())
+    bad = capi.qed_step_params(t0=0.0, dt=0.1, lambda_L=1e-6, flags=1, precision=1)
+    with pytest.raises(capi.QEDError) as e:
+        capi.qed_step(shared_tables.handle, r.ws, bad, r._s())
+    assert e.value.status == capi.QED_ERR_STATE
+    with pytest.raises(capi.QEDError):
+        capi.qed_set_launch(r.ws, 100, 4)
+    # a host pointer, and a capacity larger than the allocation, are refused at bind
+    inst = capi.qed_instance.from_buffer_copy(r.insts[0])
+    host = np.zeros(16)
+    inst.s[0].x_dev = host.ctypes.data
+    with pytest.raises(capi.QEDError) as e:
+        capi.qed_bind(r.ws, [inst], r.params)
+    assert e.value.status == capi.QED_ERR_ARG
+    inst = capi.qed_instance.from_buffer_copy(r.insts[0])
+    inst.s[2].capacity = inst.s[2].capacity * 1000 + 10 ** 8
+    with pytest.raises(capi.QEDError) as e:
+        capi.qed_bind(r.ws, [inst], r.params)
+    assert e.value.status == capi.QED_ERR_ARG
+    tp = capi.qed_table_params(n_eta=1, eta_min=1e-4, eta_max=1e2, n_chi=16, cutoff_energy_frac=1e-9,
+                               n_chi_pair=16, chi_pair_min=1e-2, chi_pair_max=1e2, n_f=16)
+    with pytest.raises(capi.QEDError):
+        capi.qed_build_tables(tp)
+
+
+def _collision_run(tables, n=3000, steps=2600, seed=21, **kw):
+    w = W.collision(n, n_steps=steps, meet_step=steps // 2, seed=seed)
+    return w, Run(w, tables, **kw)
+
+
+def test_compaction_preserves_live_photons(shared_tables):
+    w, ra = _collision_run(shared_tables)
+    _, rb = _collision_run(shared_tables)
+    ra.step(1800)
+    rb.step(1800)
+    before = ra.species(0, "photon", live_only=True)
+    n_slots = ra.count(0, "photon")
+    ra.compact()
+    after = ra.species(0, "photon", live_only=False)
+    assert (after["tau"] >= 0).all()
+    assert len(after["uid"]) == len(before["uid"]) < n_slots
+    oa, ob = np.argsort(after["uid"]), np.argsort(before["uid"])
+    for k in before:
+        np.testing.assert_array_equal(after[k][oa], before[k][ob])
+    # stepping on from the compacted buffer changes nothing per uid
+    ra.step(800)
+    rb.step(800)
+    _states_equal(ra, rb)
+
+
+def test_graph_replay_matches_plain_launches(shared_tables):
+    # plain launches vs steps replayed from a captured HIP graph, with eager work in between
+    w, ra = _collision_run(shared_tables, n=2000)
+    _, rb = _collision_run(shared_tables, n=2000)
+    ra.step(2600)
+    for chunk in (600, 600, 600, 800):
+        rb.run(chunk, graph_steps=50)
+        rb.ledger()  # eager work and a synchronisation between replays
+    _states_equal(ra, rb)
+    la, lb = ra.ledger()[0], rb.ledger()[0]
+    for k in ("n_emit", "n_null", "n_pair", "count"):
+        assert la[k] == lb[k]
+
+
+def test_batched_instances_equal_single_runs(shared_tables):
+    ws = [W.collision(n, a0=a0, gamma_mean=g0, n_steps=2400, meet_step=1200, seed=1, instance=i, uid0=0)
+          for i, (n, a0, g0) in enumerate([(1000, 200.0, 2000.0), (17, 450.0, 800.0), (3001, 60.0, 4500.0),
+                                           (1, 300.0, 1500.0), (650, 120.0, 3000.0)])]
+    rb = Run(ws, shared_tables)
+    rb.step(2400)
+    for i, w in enumerate(ws):
+        rs = Run(w, shared_tables)
+        rs.step(2400)
+        _states_equal(rb, rs, ia=i, ib=0)
+        lb, ls = rb.ledger()[i], rs.ledger()[0]
+        assert lb["n_emit"] == ls["n_emit"] and lb["n_pair"] == ls["n_pair"]
+
+
+def test_restart_from_saved_state_is_exact(shared_tables):
+    w, ra = _collision_run(shared_tables, n=1500)
+    ra.step(2600)
+    _, rb = _collision_run(shared_tables, n=1500)
+    rb.step(1300)
+    st = rb.state()
+    rc = Run(w, shared_tables, initial=st, draw_initial_tau=False, step0=1300)
+    rc.step(1300)
+    _states_equal(ra, rc)
+
+
+def _spectrum(ph, bins):
+    eps = np.sqrt(ph["ux"] ** 2 + ph["uy"] ** 2 + ph["uz"] ** 2)
+    return np.histogram(eps, bins=bins)[0]
+
+
+def test_fp32_mixed_against_fp64(gpu_tables_default):
+    # precision form of the collision: per-bin photon spectrum error, mean energy loss, pair
+    # yield, and ledger closure, against the FP64 form (same random streams)
+    t = gpu_tables_default
+    n, steps = 20000, 2600
+    w = W.collision(n, n_steps=steps, meet_step=steps // 2, seed=31)
+    r64 = Run(w, t)
+    r32 = Run(w, t, precision=capi.QED_FP32_MIXED)
+    r64.step(steps)
+    r32.step(steps)
+    l64, l32 = r64.ledger()[0], r32.ledger()[0]
+    bins = np.logspace(-3, 4, 65)
+    s64, s32 = _spectrum(r64.species(0, "photon"), bins), _spectrum(r32.species(0, "photon"), bins)
+    sel = s64 >= 10000
+    rel = np.abs(s32[sel] - s64[sel]) / s64[sel]
+    g0 = l64["energy0"] / n
+    loss64 = g0 - l64["energy"][0] / n
+    loss32 = g0 - l32["energy"][0] / n
+    rec = dict(bins_used=int(sel.sum()), spectrum_rel_err_max=float(rel.max()),
+               energy_loss_rel_err=abs(loss32 - loss64) / loss64,
+               pair_yield_64=l64["n_pair"] / n, pair_yield_32=l32["n_pair"] / n,
+               photons_64=l64["count"][2], photons_32=l32["count"][2], drift_32=l32["drift"], drift_64=l64["drift"])
+    record("fp32_mixed_vs_fp64", rec)
+    assert l32["status"] == "QED_OK" and l64["status"] == "QED_OK"
+    assert sel.sum() >= 10
+    assert rel.max() <= 1e-3
+    assert rec["energy_loss_rel_err"] <= 1e-3
+    assert l32["drift"] <= 1e-9
+
+
+@pytest.fixture(scope="module")
+def gpu_tables_default():
+    return Tables.build()
