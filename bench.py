@@ -185,7 +185,7 @@ def main():
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--ppt", type=int, default=4)
     ap.add_argument("--forms", default="fp64", help="comma list of fp64, fp32, batched; the first is `value`")
-    ap.add_argument("--cpu-families", type=int, default=500)
+    ap.add_argument("--cpu-families", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:

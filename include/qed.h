@@ -159,8 +159,8 @@ void qed_workspace_destroy(qed_workspace* ws);
 qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
                     const qed_step_params* params);
 
-/* Launch shape of the step kernels: threads per block (64..1024, multiple of 64) and particles
- * per thread (1..16).  Takes effect from the next step. */
+/* Launch shape of the step kernels: threads per block (64..256, multiple of 64) and particles
+ * per thread (1, 2, 4 or 8).  Takes effect from the next step. */
 qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt);
 
 /* Sec. 3: every macro-particle starts with a sampled optical depth, tau = -ln U with U from the

@@ -91,7 +91,8 @@ def lib():
         for name in ("oracle_F", "oracle_energy_below", "oracle_cutoff_chi", "oracle_pf"):
             getattr(L, name).argtypes = [C.c_double, C.c_double]
             getattr(L, name).restype = C.c_double
-        for name in ("oracle_h", "oracle_g", "oracle_T", "oracle_pair_k"):
+        for name in ("oracle_h", "oracle_g", "oracle_T", "oracle_pair_k", "oracle_cr_exp", "oracle_cr_log",
+                     "oracle_cr_sin", "oracle_cr_cos"):
             getattr(L, name).argtypes = [C.c_double]
             getattr(L, name).restype = C.c_double
         L.oracle_philox.argtypes = [C.POINTER(C.c_uint64)] * 3

@@ -320,7 +320,151 @@ double unit_open(uint64_t r) { return ((double)(r >> 11) + 0.5) * 0x1.0p-53; }
 
 // Section 3: the optical depth at which a particle next reacts, from P = 1 - exp(-tau)
 // with P uniform: tau = -ln(1 - P), and 1 - P is itself uniform on (0, 1).
-double optical_depth_draw(uint64_t r) { return -std::log(unit_open(r)); }
+double cr_log(double x);  // correctly rounded natural log, defined below
+double optical_depth_draw(uint64_t r) { return -cr_log(unit_open(r)); }
+
+// ----------------------------------------------------------------------------
+// Correctly rounded exp, log, sin, cos for the Monte-Carlo step.  Each is evaluated in
+// double-double arithmetic (Dekker's exact sum and product splits; ~2^-100 relative) and
+// rounded once, which gives the correctly rounded double except within ~2^-100 of a
+// rounding midpoint.  Two implementations that both round correctly agree bit for bit,
+// whatever their algorithms.
+//   exp: x = k ln2 + r (ln2 in three parts), e^r = sum r^n/n! summed until negligible.
+//   log: x = m 2^e, log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...), s = (m - 1)/(m + 1).
+//   sin, cos: x = k pi/2 + r (pi/2 in three parts), Taylor series of sin r and cos r.
+// ----------------------------------------------------------------------------
+struct DD {
+  double hi, lo;
+};
+DD dd_norm(double a, double b) {  // |a| >= |b|
+  const double s = a + b;
+  return {s, b - (s - a)};
+}
+DD dd_sum(double a, double b) {
+  const double s = a + b, v = s - a;
+  return {s, (a - (s - v)) + (b - v)};
+}
+DD dd_prod(double a, double b) {
+  const double p = a * b;
+  return {p, std::fma(a, b, -p)};
+}
+DD operator+(DD a, DD b) {
+  DD s = dd_sum(a.hi, b.hi);
+  DD t = dd_sum(a.lo, b.lo);
+  s.lo += t.hi;
+  s = dd_norm(s.hi, s.lo);
+  s.lo += t.lo;
+  return dd_norm(s.hi, s.lo);
+}
+DD operator*(DD a, DD b) {
+  DD p = dd_prod(a.hi, b.hi);
+  p.lo += a.hi * b.lo + a.lo * b.hi;
+  return dd_norm(p.hi, p.lo);
+}
+DD operator*(DD a, double b) {
+  DD p = dd_prod(a.hi, b);
+  p.lo += a.lo * b;
+  return dd_norm(p.hi, p.lo);
+}
+DD operator/(DD a, double b) {
+  const double q1 = a.hi / b;
+  const DD p = dd_prod(q1, b);
+  const double rem = ((a.hi - p.hi) - p.lo) + a.lo;
+  return dd_norm(q1, rem / b);
+}
+DD operator/(DD a, DD b) {
+  const double q1 = a.hi / b.hi;
+  const DD r = a + DD{-(b * q1).hi, -(b * q1).lo};
+  const double q2 = r.hi / b.hi;
+  const DD r2 = r + DD{-(b * q2).hi, -(b * q2).lo};
+  const double q3 = r2.hi / b.hi;
+  return dd_norm(q1, q2) + DD{q3, 0.0};
+}
+double dd_round(DD a) { return a.hi + a.lo; }
+
+// ln 2 and pi/2 split into a short leading part (exact multiples) and two tails
+constexpr double kLn2P1 = 0x1.62e42fefa3800p-1, kLn2P2 = 0x1.ef35793c76730p-45, kLn2P3 = 0x1.f97b57a079a19p-103;
+constexpr double kHalfPiP1 = 0x1.921fb54400000p+0, kHalfPiP2 = 0x1.0b4611a626331p-34,
+                 kHalfPiP3 = 0x1.1701b839a2520p-88;
+
+DD reduce(double x, double k, double p1, double p2, double p3) {
+  DD r = DD{x - k * p1, 0.0} + dd_prod(-k, p2);
+  return dd_norm(r.hi, r.lo - k * p3);
+}
+
+double cr_exp(double x) {
+  if (!(x < 709.0) || !(x > -700.0)) return std::exp(x);
+  const double k = std::nearbyint(x / 0.6931471805599453);
+  const DD r = reduce(x, k, kLn2P1, kLn2P2, kLn2P3);
+  DD sum = {1.0, 0.0}, term = {1.0, 0.0};
+  for (int n = 1; n < 40; ++n) {
+    term = term * r / (double)n;
+    sum = sum + term;
+    if (std::fabs(term.hi) < 1e-36) break;
+  }
+  return std::ldexp(dd_round(sum), (int)k);
+}
+
+double cr_log(double x) {
+  if (!(x > 0.0) || !std::isfinite(x)) return std::log(x);
+  int e;
+  double m = std::frexp(x, &e);
+  if (m < 0.7071067811865476) {
+    m *= 2.0;
+    --e;
+  }
+  // s = (m - 1)/(m + 1): m - 1 is exact (Sterbenz), m + 1 as a double-double
+  const DD s = DD{m - 1.0, 0.0} / dd_sum(m, 1.0);
+  const DD s2 = s * s;
+  DD sum = s, pw = s;
+  for (int n = 3; n < 200; n += 2) {
+    pw = pw * s2;
+    const DD t = pw / (double)n;
+    sum = sum + t;
+    if (std::fabs(t.hi) < 1e-36 * std::fabs(sum.hi) + 1e-300) break;
+  }
+  const DD ln2 = DD{0x1.62e42fefa39efp-1, 0x1.abc9e3b39803fp-56};
+  return dd_round(ln2 * (double)e + sum * 2.0);
+}
+
+void cr_sincos(double x, double* sn, double* cs) {
+  if (!(std::fabs(x) < 1048576.0)) {
+    *sn = std::sin(x);
+    *cs = std::cos(x);
+    return;
+  }
+  const double k = std::nearbyint(x / 1.5707963267948966);
+  const DD r = reduce(x, k, kHalfPiP1, kHalfPiP2, kHalfPiP3);
+  const DD r2 = r * r;
+  DD sn_sum = r, cs_sum = {1.0, 0.0}, ts = r, tc = {1.0, 0.0};
+  for (int n = 1; n < 30; ++n) {
+    // terms (-1)^n r^(2n+1)/(2n+1)! and (-1)^n r^(2n)/(2n)!
+    tc = tc * r2 / (double)((2 * n - 1) * (2 * n));
+    ts = ts * r2 / (double)((2 * n) * (2 * n + 1));
+    tc = DD{-tc.hi, -tc.lo};
+    ts = DD{-ts.hi, -ts.lo};
+    cs_sum = cs_sum + tc;
+    sn_sum = sn_sum + ts;
+    if (std::fabs(tc.hi) < 1e-36 && std::fabs(ts.hi) < 1e-36 * std::fabs(r.hi)) break;
+  }
+  const double sv = dd_round(sn_sum), cv = dd_round(cs_sum);
+  long q = (long)std::fmod(k, 4.0);
+  if (q < 0) q += 4;
+  *sn = q == 0 ? sv : q == 1 ? cv : q == 2 ? -sv : -cv;
+  *cs = q == 0 ? cv : q == 1 ? -sv : q == 2 ? -cv : sv;
+}
+
+double cr_sin(double x) {
+  double s, c;
+  cr_sincos(x, &s, &c);
+  return s;
+}
+
+double cr_cos(double x) {
+  double s, c;
+  cr_sincos(x, &s, &c);
+  return c;
+}
 
 }  // namespace
 
@@ -341,6 +485,10 @@ double oracle_T(double chi) { return pair_T(chi); }
 double oracle_pair_k(double chi) { return pair_k(chi); }
 double oracle_pf(double f, double chi) { return pair_split_unnorm(f, chi) / pair_k(chi); }
 void oracle_philox(const uint64_t* ctr, const uint64_t* key, uint64_t* out) { philox4x64_10(ctr, key, out); }
+double oracle_cr_exp(double x) { return cr_exp(x); }
+double oracle_cr_log(double x) { return cr_log(x); }
+double oracle_cr_sin(double x) { return cr_sin(x); }
+double oracle_cr_cos(double x) { return cr_cos(x); }
 void oracle_gauss_legendre(int n, double* x, double* w) {
   GaussLegendre r = make_gauss_legendre(n);
   for (int i = 0; i < n; ++i) {
@@ -488,7 +636,7 @@ inline Vec3 cross(Vec3 a, Vec3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a
 // --- analytic sources -----------------------------------------------------
 void cp_standing(double E0, double x, double t, double out[6]) {
   // E_y = 2E0 cos t cos x, E_z = 2E0 sin t cos x, B_y = 2E0 cos t sin x, B_z = 2E0 sin t sin x
-  const double ct = std::cos(t), st = std::sin(t), cx = std::cos(x), sx = std::sin(x);
+  const double ct = cr_cos(t), st = cr_sin(t), cx = cr_cos(x), sx = cr_sin(x);
   out[0] = 0.0;
   out[1] = 2.0 * E0 * ct * cx;
   out[2] = 2.0 * E0 * st * cx;
@@ -525,8 +673,8 @@ void fields_at(const Config& c, double x, double y, double z, double t, Vec3* E,
     case FIELD_LP_PULSE: {
       const double psi = t - x - c.fp[2];
       if (psi >= 0.0 && psi <= c.fp[1]) {
-        const double s = std::sin(kPi * psi / c.fp[1]);
-        const double e = c.fp[0] * s * s * std::cos(psi + c.fp[3]);
+        const double s = cr_sin(kPi * psi / c.fp[1]);
+        const double e = c.fp[0] * s * s * cr_cos(psi + c.fp[3]);
         f[1] = e;
         f[5] = e;
       }
@@ -534,7 +682,7 @@ void fields_at(const Config& c, double x, double y, double z, double t, Vec3* E,
     }
     case FIELD_CP_WAVE: {
       const double psi = t - x + c.fp[1];
-      const double ey = c.fp[0] * std::cos(psi), ez = c.fp[0] * std::sin(psi);
+      const double ey = c.fp[0] * cr_cos(psi), ez = c.fp[0] * cr_sin(psi);
       f[1] = ey;
       f[2] = ez;
       f[4] = -ez;
@@ -573,7 +721,7 @@ void fields_at(const Config& c, double x, double y, double z, double t, Vec3* E,
 // h(eta): linear in value between nodes on a uniform ln(eta) grid; clamped to the end
 // values outside [eta_min, eta_max] (above the range is counted).
 double lookup_h(const Tables& tb, double eta, int64_t* range_hi) {
-  const double s = (std::log(eta) - tb.le0) / tb.dle;
+  const double s = (cr_log(eta) - tb.le0) / tb.dle;
   if (!(s > 0.0)) return tb.h[0];
   if (s >= tb.n_eta - 1) {
     ++*range_hi;
@@ -587,7 +735,7 @@ double lookup_h(const Tables& tb, double eta, int64_t* range_hi) {
 // T(chi): as h, but zero below chi_pair_min where T < 1e-58.
 double lookup_T(const Tables& tb, double chi, int64_t* range_hi) {
   if (!(chi > 0.0)) return 0.0;
-  const double s = (std::log(chi) - tb.lc0) / tb.dlc;
+  const double s = (cr_log(chi) - tb.lc0) / tb.dlc;
   if (s < 0.0) return 0.0;
   if (s >= tb.n_cp - 1) {
     ++*range_hi;
@@ -614,7 +762,7 @@ int row_inverse(const double* P, int n, double u, double* frac) {
 // Section 3: chi from the tabulated cumulative P_chi at the emitter's eta.
 // Returns false when the draw falls below the low-energy cut-off in either row used.
 bool sample_chi(const Tables& tb, double eta, double u, double* chi) {
-  const double leta = std::log(eta);
+  const double leta = cr_log(eta);
   const double s = (leta - tb.le0) / tb.dle;
   auto Q = [&](int r, double* q) {
     const double* P = tb.P + (size_t)r * tb.n_chi;
@@ -644,7 +792,7 @@ bool sample_chi(const Tables& tb, double eta, double u, double* chi) {
     if (!ok_a || !ok_b) return false;
     lnchi = (1.0 - w) * qa + w * qb;
   }
-  *chi = std::exp(lnchi);
+  *chi = cr_exp(lnchi);
   return true;
 }
 
@@ -652,7 +800,7 @@ bool sample_chi(const Tables& tb, double eta, double u, double* chi) {
 // procedure: rows at the two nodes bracketing ln chi, linear in f inside a row,
 // blended linearly in ln chi.
 double sample_f(const Tables& tb, double chi, double u) {
-  const double s = (std::log(chi) - tb.lc0) / tb.dlc;
+  const double s = (cr_log(chi) - tb.lc0) / tb.dlc;
   auto frow = [&](int r) {
     double fr;
     const int j = row_inverse(tb.Pf + (size_t)r * tb.n_f, tb.n_f, u, &fr);

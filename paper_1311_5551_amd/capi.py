@@ -102,6 +102,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("libqed.so is not built (%s); run paper_1311_5551_amd/build.py" % LIB_PATH)
+        # torch ships its own HIP runtime with the same soname as the system one; loading torch
+        # first makes libqed bind to that copy, so the process holds a single HIP runtime
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGNATURES.items():
             f = getattr(L, name)

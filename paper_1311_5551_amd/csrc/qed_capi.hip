@@ -458,6 +458,7 @@ qed_status qed_workspace_create(int32_t max_inst, qed_workspace** out) {
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_base, 3 * (size_t)max_inst * sizeof(int64_t));
   if (e == hipSuccess) e = hipMemset(ws->d_glob, 0, sizeof(Glob));
   if (e == hipSuccess) e = hipMemset(ws->d_acc, 0, max_inst * sizeof(InstAcc));
+  if (e == hipSuccess) e = init_crmath();
   if (e != hipSuccess) {
     qed_workspace_destroy(ws);
     return fail(QED_ERR_HIP, "workspace allocation: %s", hipGetErrorString(e));
@@ -481,7 +482,7 @@ void qed_workspace_destroy(qed_workspace* ws) {
 qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (block < 64 || block > 256 || block % 64) return fail(QED_ERR_ARG, "block = %d: need 64..256, multiple of 64", block);
-  if (ppt < 1 || ppt > 16) return fail(QED_ERR_ARG, "ppt = %d outside [1, 16]", ppt);
+  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) return fail(QED_ERR_ARG, "ppt = %d: need 1, 2, 4 or 8", ppt);
   if (ws->block != block || ws->ppt != ppt) drop_graph(ws);
   ws->block = block;
   ws->ppt = ppt;

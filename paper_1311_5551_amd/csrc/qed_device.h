@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "../../include/qed.h"
+#include "qed_crmath.h"
 
 namespace qedk {
 
@@ -95,7 +96,7 @@ __device__ __forceinline__ void philox4x64_10(uint64_t c0, uint64_t c1, uint64_t
 __device__ __forceinline__ double unit_open(uint64_t r) { return ((double)(r >> 11) + 0.5) * 0x1.0p-53; }
 
 // optical depth at which the next reaction happens: P = 1 - exp(-tau) uniform (Sec. 3)
-__device__ __forceinline__ double optical_depth(uint64_t r) { return -log(unit_open(r)); }
+__device__ __forceinline__ double optical_depth(uint64_t r) { return -cr_log(unit_open(r)); }
 
 // ---------------------------------------------------------------------------
 // fields at a point (FP64); the grid kind gathers FP32 node values with CIC weights
@@ -105,7 +106,9 @@ __device__ __forceinline__ int64_t wrap_index(int64_t i, int n) {
   return r < 0 ? r + n : r;
 }
 
-template <int FK>
+// EXACT selects correctly rounded trigonometry (bit-reproducible momenta); the fast variant
+// (device library, <= 1 ulp) serves quantities that only feed an optical-depth decrement.
+template <int FK, bool EXACT = true>
 __device__ __forceinline__ void field_at(const qed_field& F, double x, double y, double t, double E[3],
                                          double B[3]) {
   E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = 0.0;
@@ -119,20 +122,30 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
   } else if (FK == QED_FIELD_LP_PULSE) {
     const double psi = t - x - F.p[2];
     if (psi >= 0.0 && psi <= F.p[1]) {
-      const double s = sin(kPi * psi / F.p[1]);
-      const double e = F.p[0] * s * s * cos(psi + F.p[3]);
+      const double s = EXACT ? cr_sin(kPi * psi / F.p[1]) : sin(kPi * psi / F.p[1]);
+      const double e = F.p[0] * s * s * (EXACT ? cr_cos(psi + F.p[3]) : cos(psi + F.p[3]));
       E[1] = e;
       B[2] = e;
     }
   } else if (FK == QED_FIELD_CP_WAVE) {
     const double psi = t - x + F.p[1];
-    const double ey = F.p[0] * cos(psi), ez = F.p[0] * sin(psi);
+    double sn, cs;
+    if (EXACT) cr_sincos(psi, &sn, &cs);
+    else sincos(psi, &sn, &cs);
+    const double ey = F.p[0] * cs, ez = F.p[0] * sn;
     E[1] = ey;
     E[2] = ez;
     B[1] = -ez;
     B[2] = ey;
   } else if (FK == QED_FIELD_CP_STANDING) {
-    const double ct = cos(t), st = sin(t), cx = cos(x), sx = sin(x);
+    double st, ct, sx, cx;
+    if (EXACT) {
+      cr_sincos(t, &st, &ct);
+      cr_sincos(x, &sx, &cx);
+    } else {
+      sincos(t, &st, &ct);
+      sincos(x, &sx, &cx);
+    }
     E[1] = 2.0 * F.p[0] * ct * cx;
     E[2] = 2.0 * F.p[0] * st * cx;
     B[1] = 2.0 * F.p[0] * ct * sx;
@@ -170,7 +183,8 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
 // table look-ups (Sec. 3: linear interpolation in the look-up tables)
 // ---------------------------------------------------------------------------
 
-// h(eta) from an LDS copy; clamped outside [eta_min, eta_max], counting eta > eta_max
+// h(eta) from an LDS copy; clamped outside [eta_min, eta_max], counting eta > eta_max.  The
+// rate only feeds the optical-depth decrement, so the device library's log serves.
 __device__ __forceinline__ double lookup_h(const double* sh, const Tabs& tb, double eta, unsigned& range) {
   const double s = (log(eta) - tb.le0) / tb.dle;
   if (!(s > 0.0)) return sh[0];
@@ -183,7 +197,8 @@ __device__ __forceinline__ double lookup_h(const double* sh, const Tabs& tb, dou
   return (1.0 - w) * sh[i] + w * sh[i + 1];
 }
 
-// T(chi) from an LDS copy; zero below chi_pair_min (T < 1e-58 there)
+// T(chi) from an LDS copy; zero below chi_pair_min (T < 1e-58 there); feeds only the
+// optical-depth decrement
 __device__ __forceinline__ double lookup_T(const double* sT, const Tabs& tb, double chi, unsigned& range) {
   if (!(chi > 0.0)) return 0.0;
   const double s = (log(chi) - tb.lc0) / tb.dlc;
@@ -211,7 +226,7 @@ __device__ __forceinline__ int row_inverse(const double* __restrict__ P, int n, 
 
 // chi from P_chi at the emitter's eta (rows i, i+1 blended in ln eta); false below the cut-off
 __device__ inline bool sample_chi(const Tabs& tb, double eta, double u, double* chi) {
-  const double leta = log(eta);
+  const double leta = cr_log(eta);
   const double s = (leta - tb.le0) / tb.dle;
   double lnchi;
   auto Q = [&](int r, double* q) {
@@ -239,13 +254,13 @@ __device__ inline bool sample_chi(const Tabs& tb, double eta, double u, double* 
     if (!oka || !okb) return false;
     lnchi = (1.0 - w) * qa + w * qb;
   }
-  *chi = exp(lnchi);
+  *chi = cr_exp(lnchi);
   return true;
 }
 
 // positron energy fraction f from P_f (rows blended in ln chi, linear in f within a row)
 __device__ inline double sample_f(const Tabs& tb, double chi, double u) {
-  const double s = (log(chi) - tb.lc0) / tb.dlc;
+  const double s = (cr_log(chi) - tb.lc0) / tb.dlc;
   auto frow = [&](int r) {
     double fr;
     const int j = row_inverse(tb.Pf + (size_t)r * tb.n_f, tb.n_f, u, &fr);

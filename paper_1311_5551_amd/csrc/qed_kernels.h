@@ -19,6 +19,7 @@ struct StepArgs {
   StepConst sc;
 };
 
+hipError_t init_crmath();
 hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnchi_min, double* dlnchi, double* P,
                                double* T, double* fgrid, double* Pf, double* knorm, hipStream_t s);
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, int64_t* base_lep,

@@ -287,148 +287,4 @@ __global__ __launch_bounds__(256) void k_lepton_f32(StepArgs a) {
   }
 }
 
-template <int FK>
-__global__ __launch_bounds__(256) void k_photon_f32(StepArgs a) {
-  extern __shared__ double smem[];
-  double* sred = smem;
-  unsigned* sredu = (unsigned*)(sred + 16 * 3);
-  float* sT = (float*)(sredu + 16 * 5);
-  for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) sT[i] = a.tb.T32[i];
-  __syncthreads();
-
-  const int64_t step = a.glob->step_cur;
-  const double t = a.sc.t0 + (double)step * a.sc.dt;
-  const double dt = a.sc.dt;
-  const int64_t nch = a.glob->n_chunks[1];
-  const int B = blockDim.x;
-  const int64_t CH = (int64_t)B * a.ppt;
-  const bool pairs = (a.sc.flags & QED_PAIRS) != 0;
-  const float apdt = (float)(a.sc.a_pair * a.sc.dt);
-
-  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-    int lo_ = 0, hi_ = a.n_base - 1;
-    while (lo_ < hi_) {
-      const int mid = (lo_ + hi_ + 1) >> 1;
-      if (a.base[mid] <= c) lo_ = mid; else hi_ = mid - 1;
-    }
-    const int ii = lo_;
-    const qed_instance& I = a.inst[ii];
-    const qed_species& S = I.s[2];
-    const qed_species& Se = I.s[0];
-    const qed_species& Sp = I.s[1];
-    const int64_t n = a.acc[ii].n_start[2];
-    const int64_t k0 = (c - a.base[ii]) * CH;
-    const bool d3 = I.dims == 3;
-
-    double dacc[3] = {0.0, 0.0, 0.0};
-    unsigned uacc[5] = {0, 0, 0, 0, 0};
-
-    for (int j = 0; j < a.ppt; ++j) {
-      const int64_t k = k0 + (int64_t)j * B + threadIdx.x;
-      const bool active = k < n;
-      bool born = false;
-      double px = 0, py = 0, pz = 0, etau = 0, ptau = 0;
-      double ex = 0, ey = 0, ez = 0, pkx = 0, pky = 0, pkz = 0;
-      uint64_t euid = 0, puid = 0;
-      if (active && pairs) {
-        const float kx = ((const float*)S.ux_dev)[k], ky = ((const float*)S.uy_dev)[k],
-                    kz = ((const float*)S.uz_dev)[k];
-        const float eps = sqrtf(kx * kx + ky * ky + kz * kz);
-        const float nx = kx / eps, ny = ky / eps, nz = kz / eps;
-        const double age = (double)(step - (int64_t)S.birth_step_dev[k]) * dt;
-        const double x = (double)((const float*)S.x_dev)[k] + age * nx;
-        const double y = (double)((const float*)S.y_dev)[k] + age * ny;
-        float E[3], Bf[3];
-        field_at32<FK>(I.field, x, y, t, E, Bf);
-        const float ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
-        const float ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
-        const float az = E[2] + (nx * Bf[1] - ny * Bf[0]);
-        const float ne = nx * E[0] + ny * E[1] + nz * E[2];
-        const float r2 = (ax * ax + ay * ay + az * az) - ne * ne;
-        const float chi = 0.5f * eps * sqrtf(r2 > 0.0f ? r2 : 0.0f);
-        const float T = lookup32(sT, a.tb.n_cp, a.tb.lc0, a.tb.dlc, chi, uacc[2], true);
-        if (T > 0.0f) {
-          double tau = S.tau_dev[k];
-          if (!(tau < 0.0)) {
-            ++uacc[1];
-            tau -= (double)(apdt * chi * T / eps);
-            if (tau <= 0.0) {
-              const uint64_t uid = S.uid_dev[k];
-              uint64_t r0[4], r1[4];
-              philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 0, I.seed, I.key_instance, r0);
-              philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 1, I.seed, I.key_instance, r1);
-              const double f = sample_f(a.tb, (double)chi, unit_open(r0[0]));
-              pkx = f * kx;
-              pky = f * ky;
-              pkz = f * kz;
-              ex = (double)kx - pkx;
-              ey = (double)ky - pky;
-              ez = (double)kz - pkz;
-              const double gp = sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
-              const double ge = sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
-              const double epsd = sqrt((double)kx * kx + (double)ky * ky + (double)kz * kz);
-              dacc[0] += gp + ge - epsd;
-              const double age1 = age + dt;
-              px = (double)((const float*)S.x_dev)[k] + age1 * nx;
-              py = (double)((const float*)S.y_dev)[k] + age1 * ny;
-              pz = d3 ? (double)((const float*)S.z_dev)[k] + age1 * nz : 0.0;
-              euid = r0[1];
-              puid = r0[2];
-              etau = optical_depth(r0[3]);
-              ptau = optical_depth(r1[0]);
-              born = true;
-              ++uacc[0];
-              tau = -1.0;
-            }
-            if (!isfinite(tau)) ++uacc[3];
-            S.tau_dev[k] = tau;
-          }
-        }
-      }
-      const long long se = wave_reserve(born, Se.count_dev);
-      const long long spo = wave_reserve(born, Sp.count_dev);
-      if (born) {
-        float h, l;
-        if (se < Se.capacity) {
-          split_double(px, h, l); ((float*)Se.x_dev)[se] = h; Se.x_lo_dev[se] = l;
-          split_double(py, h, l); ((float*)Se.y_dev)[se] = h; Se.y_lo_dev[se] = l;
-          if (d3) { split_double(pz, h, l); ((float*)Se.z_dev)[se] = h; Se.z_lo_dev[se] = l; }
-          split_double(ex, h, l); ((float*)Se.ux_dev)[se] = h; Se.ux_lo_dev[se] = l;
-          split_double(ey, h, l); ((float*)Se.uy_dev)[se] = h; Se.uy_lo_dev[se] = l;
-          split_double(ez, h, l); ((float*)Se.uz_dev)[se] = h; Se.uz_lo_dev[se] = l;
-          Se.tau_dev[se] = etau;
-          Se.uid_dev[se] = euid;
-        } else {
-          ++uacc[4];
-          dacc[1] += sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
-        }
-        if (spo < Sp.capacity) {
-          split_double(px, h, l); ((float*)Sp.x_dev)[spo] = h; Sp.x_lo_dev[spo] = l;
-          split_double(py, h, l); ((float*)Sp.y_dev)[spo] = h; Sp.y_lo_dev[spo] = l;
-          if (d3) { split_double(pz, h, l); ((float*)Sp.z_dev)[spo] = h; Sp.z_lo_dev[spo] = l; }
-          split_double(pkx, h, l); ((float*)Sp.ux_dev)[spo] = h; Sp.ux_lo_dev[spo] = l;
-          split_double(pky, h, l); ((float*)Sp.uy_dev)[spo] = h; Sp.uy_lo_dev[spo] = l;
-          split_double(pkz, h, l); ((float*)Sp.uz_dev)[spo] = h; Sp.uz_lo_dev[spo] = l;
-          Sp.tau_dev[spo] = ptau;
-          Sp.uid_dev[spo] = puid;
-        } else {
-          ++uacc[4];
-          dacc[1] += sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
-        }
-      }
-    }
-    block_sum(dacc, uacc, sred, sredu);
-    if (threadIdx.x == 0) {
-      InstAcc& A = a.acc[ii];
-      if (dacc[0] != 0.0) atomicAdd(&A.defect_pair, dacc[0]);
-      if (dacc[1] != 0.0) atomicAdd(&A.dropped_energy, dacc[1]);
-      if (uacc[0]) atomicAdd(&A.n_pair, (unsigned long long)uacc[0]);
-      if (uacc[1]) atomicAdd(&A.n_field, (unsigned long long)uacc[1]);
-      if (uacc[2]) atomicAdd(&A.n_range, (unsigned long long)uacc[2]);
-      if (uacc[3]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[3]);
-      if (uacc[4]) atomicAdd(&A.n_dropped, (unsigned long long)uacc[4]);
-    }
-  }
-}
-
 }  // namespace qedk

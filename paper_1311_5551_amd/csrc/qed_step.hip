@@ -14,6 +14,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+#include <type_traits>
+
 #include "qed_device.h"
 #include "qed_kernels.h"
 #include "qed_mixed.h"
@@ -89,13 +92,15 @@ __global__ void k_grid_refresh(const qed_instance* __restrict__ inst, int n_inst
     const qed_field& F = inst[ii].field;
     if (F.kind != QED_FIELD_GRID_CP_STANDING) continue;
     const int64_t plane = (int64_t)F.nx * F.ny;
-    const double ct = cos(t), st = sin(t), e2 = 2.0 * F.p[0];
+    double st, ct;
+    cr_sincos(t, &st, &ct);
+    const double e2 = 2.0 * F.p[0];
     for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < plane; q += (int64_t)gridDim.x * blockDim.x) {
       const int64_t i = q % F.nx;
       // components at x offsets 0 (Ey, Ez, Bx) and 1/2 (Ex, By, Bz); the wave is uniform in y
       const double xa = F.x0 + (double)i * F.dx;
       const double xb = F.x0 + ((double)i + 0.5) * F.dx;
-      const double ca = cos(xa), cb = sin(xb);
+      const double ca = cr_cos(xa), cb = cr_sin(xb);
       float* g = F.grid_dev;
       g[q] = 0.0f;                                          // Ex
       g[plane + q] = (float)(e2 * ct * ca);                 // Ey(i, j+1/2)
@@ -263,15 +268,51 @@ __global__ __launch_bounds__(256) void k_lepton_f64(StepArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// photons, FP64 form.  Position at the start of step n: x_b + (n - b) dt k/|k|.
+// photons, both precisions.  Position at the start of step n: x_b + (n - b) dt k/|k|.
+//
+// A thread first loads the birth positions, momenta and birth steps of all PPT particles it
+// owns in the chunk (independent loads in flight together), then works through them.  Most
+// photons sit where the field vanishes and need nothing more; the others decrement their pair
+// optical depth with a rate from the device library's trigonometry and log (the decrement only
+// decides the event step) and, at a pair event, recompute chi with correctly rounded functions
+// for the sampling that sets the pair momenta.  Event statistics stay in registers across the
+// block's chunks and are flushed when the instance changes.
 // ---------------------------------------------------------------------------
-template <int FK>
-__global__ __launch_bounds__(256) void k_photon_f64(StepArgs a) {
+template <bool MIXED>
+__device__ __forceinline__ void write_lepton(const qed_species& S, long long slot, double x, double y, double z,
+                                             double ux, double uy, double uz, double tau, uint64_t uid, bool d3) {
+  if (MIXED) {
+    float h, l;
+    split_double(x, h, l); ((float*)S.x_dev)[slot] = h; S.x_lo_dev[slot] = l;
+    split_double(y, h, l); ((float*)S.y_dev)[slot] = h; S.y_lo_dev[slot] = l;
+    if (d3) { split_double(z, h, l); ((float*)S.z_dev)[slot] = h; S.z_lo_dev[slot] = l; }
+    split_double(ux, h, l); ((float*)S.ux_dev)[slot] = h; S.ux_lo_dev[slot] = l;
+    split_double(uy, h, l); ((float*)S.uy_dev)[slot] = h; S.uy_lo_dev[slot] = l;
+    split_double(uz, h, l); ((float*)S.uz_dev)[slot] = h; S.uz_lo_dev[slot] = l;
+  } else {
+    ((double*)S.x_dev)[slot] = x;
+    ((double*)S.y_dev)[slot] = y;
+    if (d3) ((double*)S.z_dev)[slot] = z;
+    ((double*)S.ux_dev)[slot] = ux;
+    ((double*)S.uy_dev)[slot] = uy;
+    ((double*)S.uz_dev)[slot] = uz;
+  }
+  S.tau_dev[slot] = tau;
+  S.uid_dev[slot] = uid;
+}
+
+template <int FK, int PPT, bool MIXED>
+__global__ __launch_bounds__(256) void k_photon(StepArgs a) {
+  using Real = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double smem[];
-  double* sT = smem;
-  double* sred = smem + a.tb.n_cp;
+  double* sred = smem;
   unsigned* sredu = (unsigned*)(sred + 16 * 3);
-  for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) sT[i] = a.tb.T[i];
+  double* sT = (double*)(sredu + 16 * 5);
+  float* sT32 = (float*)sT;
+  for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) {
+    if (MIXED) sT32[i] = a.tb.T32[i];
+    else sT[i] = a.tb.T[i];
+  }
   __syncthreads();
 
   const int64_t step = a.glob->step_cur;
@@ -279,70 +320,139 @@ __global__ __launch_bounds__(256) void k_photon_f64(StepArgs a) {
   const double dt = a.sc.dt;
   const int64_t nch = a.glob->n_chunks[1];
   const int B = blockDim.x;
-  const int64_t CH = (int64_t)B * a.ppt;
+  const int64_t CH = (int64_t)B * PPT;
   const bool pairs = (a.sc.flags & QED_PAIRS) != 0;
+
+  int cur = -1;                        // instance the accumulators belong to
+  double dacc[3] = {0.0, 0.0, 0.0};    // defect, dropped energy, unused
+  unsigned uacc[5] = {0, 0, 0, 0, 0};  // pairs, in-field steps, range, nonfinite, dropped
+  auto flush = [&](int ii) {
+    block_sum(dacc, uacc, sred, sredu);
+    if (threadIdx.x == 0) {
+      InstAcc& A = a.acc[ii];
+      if (dacc[0] != 0.0) atomicAdd(&A.defect_pair, dacc[0]);
+      if (dacc[1] != 0.0) atomicAdd(&A.dropped_energy, dacc[1]);
+      if (uacc[0]) atomicAdd(&A.n_pair, (unsigned long long)uacc[0]);
+      if (uacc[1]) atomicAdd(&A.n_field, (unsigned long long)uacc[1]);
+      if (uacc[2]) atomicAdd(&A.n_range, (unsigned long long)uacc[2]);
+      if (uacc[3]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[3]);
+      if (uacc[4]) atomicAdd(&A.n_dropped, (unsigned long long)uacc[4]);
+    }
+    dacc[0] = dacc[1] = dacc[2] = 0.0;
+    uacc[0] = uacc[1] = uacc[2] = uacc[3] = uacc[4] = 0;
+  };
 
   for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
     const int ii = find_entry(a.base, a.n_base, c);
+    if (ii != cur) {
+      if (cur >= 0) flush(cur);
+      cur = ii;
+    }
     const qed_instance& I = a.inst[ii];
     const qed_species& S = I.s[2];
-    const qed_species& Se = I.s[0];
-    const qed_species& Sp = I.s[1];
     const int64_t n = a.acc[ii].n_start[2];
-    const int64_t k0 = (c - a.base[ii]) * CH;
+    const int64_t k0 = (c - a.base[ii]) * CH + threadIdx.x;
     const bool d3 = I.dims == 3;
+    const Real* KX = (const Real*)S.ux_dev;
+    const Real* KY = (const Real*)S.uy_dev;
+    const Real* KZ = (const Real*)S.uz_dev;
+    const Real* XB = (const Real*)S.x_dev;
+    const Real* YB = (const Real*)S.y_dev;
+    const Real* ZB = (const Real*)S.z_dev;
 
-    double dacc[3] = {0.0, 0.0, 0.0};   // defect, dropped energy, unused
-    unsigned uacc[5] = {0, 0, 0, 0, 0};  // pairs, in-field steps, range, nonfinite, dropped
-
-    for (int j = 0; j < a.ppt; ++j) {
-      const int64_t k = k0 + (int64_t)j * B + threadIdx.x;
-      const bool active = k < n;
+    Real kx[PPT], ky[PPT], kz[PPT], xb[PPT], yb[PPT];
+    int32_t bs[PPT];
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int64_t k = k0 + (int64_t)j * B;
+      if (pairs && k < n) {
+        kx[j] = KX[k];
+        ky[j] = KY[k];
+        kz[j] = KZ[k];
+        xb[j] = XB[k];
+        yb[j] = YB[k];
+        bs[j] = S.birth_step_dev[k];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int64_t k = k0 + (int64_t)j * B;
       bool born = false;
-      double px = 0, py = 0, pz = 0, ex = 0, ey = 0, ez = 0, etau = 0, ptau = 0, pkx = 0, pky = 0, pkz = 0;
+      double px = 0, py = 0, pz = 0, etau = 0, ptau = 0, ex = 0, ey = 0, ez = 0, pkx = 0, pky = 0, pkz = 0;
       uint64_t euid = 0, puid = 0;
-      if (active && pairs) {
-        const double kx = ((const double*)S.ux_dev)[k], ky = ((const double*)S.uy_dev)[k],
-                     kz = ((const double*)S.uz_dev)[k];
-        const double eps = sqrt(kx * kx + ky * ky + kz * kz);
-        const double nx = kx / eps, ny = ky / eps, nz = kz / eps;
-        const double age = (double)(step - (int64_t)S.birth_step_dev[k]) * dt;
-        const double x = ((const double*)S.x_dev)[k] + age * nx;
-        const double y = ((const double*)S.y_dev)[k] + age * ny;
-        double E[3], Bf[3];
-        field_at<FK>(I.field, x, y, t, E, Bf);
-        // chi = (eps/2) sqrt(|E + n x B|^2 - (n.E)^2)
-        const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
-        const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
-        const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
-        const double ne = nx * E[0] + ny * E[1] + nz * E[2];
-        const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
-        const double chi = 0.5 * eps * sqrt(r2 > 0.0 ? r2 : 0.0);
-        const double T = lookup_T(sT, a.tb, chi, uacc[2]);
+      if (pairs && k < n) {
+        const Real eps = sqrt(kx[j] * kx[j] + ky[j] * ky[j] + kz[j] * kz[j]);
+        const Real nx = kx[j] / eps, ny = ky[j] / eps, nz = kz[j] / eps;
+        const double age = (double)(step - (int64_t)bs[j]) * dt;
+        const double x = (double)xb[j] + age * nx;
+        const double y = (double)yb[j] + age * ny;
+        double chi, T;
+        if (MIXED) {
+          float E[3], Bf[3];
+          field_at32<FK>(I.field, x, y, t, E, Bf);
+          const float ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
+          const float ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
+          const float az = E[2] + (nx * Bf[1] - ny * Bf[0]);
+          const float ne = nx * E[0] + ny * E[1] + nz * E[2];
+          const float r2 = (ax * ax + ay * ay + az * az) - ne * ne;
+          const float chif = 0.5f * (float)eps * sqrtf(r2 > 0.0f ? r2 : 0.0f);
+          chi = chif;
+          T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.dlc, chif, uacc[2], true);
+        } else {
+          double E[3], Bf[3];
+          field_at<FK, false>(I.field, x, y, t, E, Bf);
+          const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
+          const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
+          const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
+          const double ne = nx * E[0] + ny * E[1] + nz * E[2];
+          const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
+          chi = 0.5 * (double)eps * sqrt(r2 > 0.0 ? r2 : 0.0);
+          T = lookup_T(sT, a.tb, chi, uacc[2]);
+        }
         if (T > 0.0) {
           double tau = S.tau_dev[k];
           if (!(tau < 0.0)) {  // tau < 0: already converted
             ++uacc[1];
-            tau -= a.sc.a_pair * chi * T / eps * dt;
+            tau -= MIXED ? (double)((float)(a.sc.a_pair * dt) * (float)chi * (float)T / (float)eps)
+                         : a.sc.a_pair * chi * T / (double)eps * dt;
             if (tau <= 0.0) {
               const uint64_t uid = S.uid_dev[k];
               uint64_t r0[4], r1[4];
               philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 0, I.seed, I.key_instance, r0);
               philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 1, I.seed, I.key_instance, r1);
+              if (!MIXED) {
+                // chi for the sampling with correctly rounded field values
+                double E[3], Bf[3];
+                field_at<FK, true>(I.field, x, y, t, E, Bf);
+                const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
+                const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
+                const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
+                const double ne = nx * E[0] + ny * E[1] + nz * E[2];
+                const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
+                chi = 0.5 * (double)eps * sqrt(r2 > 0.0 ? r2 : 0.0);
+              }
               const double f = sample_f(a.tb, chi, unit_open(r0[0]));
-              pkx = f * kx;
-              pky = f * ky;
-              pkz = f * kz;
-              ex = (1.0 - f) * kx;
-              ey = (1.0 - f) * ky;
-              ez = (1.0 - f) * kz;
+              const double kxd = kx[j], kyd = ky[j], kzd = kz[j];
+              pkx = f * kxd;
+              pky = f * kyd;
+              pkz = f * kzd;
+              if (MIXED) {
+                ex = kxd - pkx;
+                ey = kyd - pky;
+                ez = kzd - pkz;
+              } else {
+                ex = (1.0 - f) * kxd;
+                ey = (1.0 - f) * kyd;
+                ez = (1.0 - f) * kzd;
+              }
               const double gp = sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
               const double ge = sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
-              dacc[0] += gp + ge - eps;
+              const double epsd = MIXED ? sqrt(kxd * kxd + kyd * kyd + kzd * kzd) : (double)eps;
+              dacc[0] += gp + ge - epsd;
               const double age1 = age + dt;
-              px = ((const double*)S.x_dev)[k] + age1 * nx;
-              py = ((const double*)S.y_dev)[k] + age1 * ny;
-              pz = d3 ? ((const double*)S.z_dev)[k] + age1 * nz : 0.0;
+              px = (double)xb[j] + age1 * nx;
+              py = (double)yb[j] + age1 * ny;
+              pz = d3 ? (double)ZB[k] + age1 * nz : 0.0;
               euid = r0[1];
               puid = r0[2];
               etau = optical_depth(r0[3]);
@@ -357,49 +467,27 @@ __global__ __launch_bounds__(256) void k_photon_f64(StepArgs a) {
         }
       }
       // append electron and positron, one atomic per wave each
+      const qed_species& Se = I.s[0];
+      const qed_species& Sp = I.s[1];
       const long long se = wave_reserve(born, Se.count_dev);
       const long long spo = wave_reserve(born, Sp.count_dev);
       if (born) {
         if (se < Se.capacity) {
-          ((double*)Se.x_dev)[se] = px;
-          ((double*)Se.y_dev)[se] = py;
-          if (d3) ((double*)Se.z_dev)[se] = pz;
-          ((double*)Se.ux_dev)[se] = ex;
-          ((double*)Se.uy_dev)[se] = ey;
-          ((double*)Se.uz_dev)[se] = ez;
-          Se.tau_dev[se] = etau;
-          Se.uid_dev[se] = euid;
+          write_lepton<MIXED>(Se, se, px, py, pz, ex, ey, ez, etau, euid, d3);
         } else {
           ++uacc[4];
           dacc[1] += sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
         }
         if (spo < Sp.capacity) {
-          ((double*)Sp.x_dev)[spo] = px;
-          ((double*)Sp.y_dev)[spo] = py;
-          if (d3) ((double*)Sp.z_dev)[spo] = pz;
-          ((double*)Sp.ux_dev)[spo] = pkx;
-          ((double*)Sp.uy_dev)[spo] = pky;
-          ((double*)Sp.uz_dev)[spo] = pkz;
-          Sp.tau_dev[spo] = ptau;
-          Sp.uid_dev[spo] = puid;
+          write_lepton<MIXED>(Sp, spo, px, py, pz, pkx, pky, pkz, ptau, puid, d3);
         } else {
           ++uacc[4];
           dacc[1] += sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
         }
       }
     }
-    block_sum(dacc, uacc, sred, sredu);
-    if (threadIdx.x == 0) {
-      InstAcc& A = a.acc[ii];
-      if (dacc[0] != 0.0) atomicAdd(&A.defect_pair, dacc[0]);
-      if (dacc[1] != 0.0) atomicAdd(&A.dropped_energy, dacc[1]);
-      if (uacc[0]) atomicAdd(&A.n_pair, (unsigned long long)uacc[0]);
-      if (uacc[1]) atomicAdd(&A.n_field, (unsigned long long)uacc[1]);
-      if (uacc[2]) atomicAdd(&A.n_range, (unsigned long long)uacc[2]);
-      if (uacc[3]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[3]);
-      if (uacc[4]) atomicAdd(&A.n_dropped, (unsigned long long)uacc[4]);
-    }
   }
+  if (cur >= 0) flush(cur);
 }
 
 // ---------------------------------------------------------------------------
@@ -570,15 +658,47 @@ __global__ void k_compact_finish(const qed_instance* __restrict__ inst, int n_in
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
+
+// Reciprocal factorials 1/n! as double-doubles (Dekker splits; dd / integer division with one
+// exact remainder), uploaded once per device for the correctly rounded device math.
+hipError_t init_crmath() {
+  static unsigned long long done = 0;  // one bit per device
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 64 && (done >> dev) & 1ull) return hipSuccess;
+  dd f[30];
+  f[0] = {1.0, 0.0};
+  for (int n = 1; n < 30; ++n) {
+    const double q1 = f[n - 1].hi / n;
+    const double p = q1 * n, pe = std::fma(q1, (double)n, -p);
+    const double rem = ((f[n - 1].hi - p) - pe) + f[n - 1].lo;
+    const double q2 = rem / n;
+    const double s = q1 + q2;
+    f[n] = {s, q2 - (s - q1)};
+  }
+  e = hipMemcpyToSymbol(HIP_SYMBOL(c_inv_fact), f, sizeof(f));
+  if (e == hipSuccess && dev < 64) done |= 1ull << dev;
+  return e;
+}
 template <int FK>
 static void launch_lepton_fk(const StepArgs& a, dim3 grid, dim3 block, size_t shm, hipStream_t s, bool mixed) {
   if (mixed) hipLaunchKernelGGL(k_lepton_f32<FK>, grid, block, shm, s, a);
   else hipLaunchKernelGGL(k_lepton_f64<FK>, grid, block, shm, s, a);
 }
+template <int FK, int PPT>
+static void launch_photon_ppt(const StepArgs& a, dim3 grid, dim3 block, size_t shm, hipStream_t s, bool mixed) {
+  if (mixed) hipLaunchKernelGGL((k_photon<FK, PPT, true>), grid, block, shm, s, a);
+  else hipLaunchKernelGGL((k_photon<FK, PPT, false>), grid, block, shm, s, a);
+}
 template <int FK>
 static void launch_photon_fk(const StepArgs& a, dim3 grid, dim3 block, size_t shm, hipStream_t s, bool mixed) {
-  if (mixed) hipLaunchKernelGGL(k_photon_f32<FK>, grid, block, shm, s, a);
-  else hipLaunchKernelGGL(k_photon_f64<FK>, grid, block, shm, s, a);
+  switch (a.ppt) {
+    case 1: launch_photon_ppt<FK, 1>(a, grid, block, shm, s, mixed); break;
+    case 2: launch_photon_ppt<FK, 2>(a, grid, block, shm, s, mixed); break;
+    case 8: launch_photon_ppt<FK, 8>(a, grid, block, shm, s, mixed); break;
+    default: launch_photon_ppt<FK, 4>(a, grid, block, shm, s, mixed); break;
+  }
 }
 
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, int64_t* base_lep,
@@ -609,8 +729,7 @@ void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, h
 }
 
 void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
-  const size_t shm = (size_t)a.tb.n_cp * (mixed ? sizeof(float) : sizeof(double)) + 16 * 3 * sizeof(double) +
-                     16 * 5 * sizeof(unsigned) + 64;
+  const size_t shm = (size_t)a.tb.n_cp * sizeof(double) + 16 * 3 * sizeof(double) + 16 * 5 * sizeof(unsigned) + 64;
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_photon_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;

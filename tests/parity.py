@@ -1,18 +1,19 @@
 """Helpers shared by the GPU parity tests: run a workload on the GPU (through the C ABI)
 and on the oracle (CPU), match particles by uid and compare them.
 
-Tolerances (derived from FP64 arithmetic; the oracle and the kernels round differently
-only in libm-vs-device transcendentals, so per-operation differences are ~1 ulp):
-  momenta    max_c |du_c| / max(|u|, 1)  <= 1e-12 for >= 99% of particles, and the energy
-             |d gamma| / gamma <= 1e-12 for all; every particle within U_CAP.  Gyration
-             and strong-field (a0 >> gamma) dynamics turn a 1-ulp difference of exp, log,
-             sin or cos into a phase difference that grows with the number of turns, so
-             the direction of u can differ by more than its magnitude does.
-  positions  |dx| / max(|x|, 1)          <= 1e-10  (incremental vs closed-form photon
-             positions differ by accumulated rounding, <= n_steps * 1.1e-16 relative)
+Both sides evaluate exp, log, sin and cos correctly rounded wherever a result reaches a
+momentum or a sampled chi, and order the FP64 operations of the step the same way, so with
+the oracle's tables loaded into the library the momenta agree to the last bit.  What may
+differ is the optical depth: the kernels decrement it with the device library's log and
+trigonometry, so tau differs by a few ulp per decrement and an event can move by one step
+when tau lands within rounding of zero (a threshold straddle).  Bars:
+  momenta    max_c |du_c| / max(|u|, 1)  <= 1e-12 for >= 99% of particles, every particle
+             within U_CAP, and |d gamma| / gamma <= E_TOL for all
+  positions  |dx| / max(|x|, 1)          <= 1e-10
   tau        |dtau|                      <= 1e-10  (sums of O(1) decrements)
-A particle whose family showed |tau| < 1e-9 after some decrement is a flagged
-threshold straddle: the two sides may legitimately decide its event differently.
+A particle whose family showed |tau| < 1e-9 after some decrement is a flagged threshold
+straddle: the two sides may legitimately decide its event differently.  With tables built
+on the GPU the bars widen (see the end-to-end constants in test_gpu_parity.py).
 """
 from __future__ import annotations
 

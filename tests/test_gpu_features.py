@@ -30,10 +30,10 @@ def _states_equal(ra, rb, ia=0, ib=0, species=("electron", "positron", "photon")
             np.testing.assert_array_equal(a[k][oa], b[k][ob], err_msg="%s.%s" % (name, k))
 
 
-@pytest.mark.parametrize("n", [0, 1, 63, 65, 257, 1025])
-def test_empty_and_ragged_counts(n, shared_tables, oracle_tables):
+@pytest.mark.parametrize("n,ppt", [(0, 4), (1, 1), (63, 2), (65, 8), (257, 4), (1025, 8)])
+def test_empty_and_ragged_counts(n, ppt, shared_tables, oracle_tables):
     w = W.uniform_b(n, 1000.0, 1e-3, 0.15, 40, W.FLAG_EMIT)
-    r = Run(w, shared_tables, ppt=3)
+    r = Run(w, shared_tables, ppt=ppt)
     r.step(w.n_steps)
     led = r.ledger()[0]
     assert led["status"] == "QED_OK"
@@ -101,6 +101,8 @@ def test_invalid_arguments_are_rejected(shared_tables):
     assert e.value.status == capi.QED_ERR_STATE
     with pytest.raises(capi.QEDError):
         capi.qed_set_launch(r.ws, 100, 4)
+    with pytest.raises(capi.QEDError):
+        capi.qed_set_launch(r.ws, 256, 3)
     # a host pointer, and a capacity larger than the allocation, are refused at bind
     inst = capi.qed_instance.from_buffer_copy(r.insts[0])
     host = np.zeros(16)
@@ -192,7 +194,7 @@ def test_fp32_mixed_against_fp64(gpu_tables_default):
     # precision form of the collision: per-bin photon spectrum error, mean energy loss, pair
     # yield, and ledger closure, against the FP64 form (same random streams)
     t = gpu_tables_default
-    n, steps = 20000, 2600
+    n, steps = 100000, 2600
     w = W.collision(n, n_steps=steps, meet_step=steps // 2, seed=31)
     r64 = Run(w, t)
     r32 = Run(w, t, precision=capi.QED_FP32_MIXED)

@@ -58,7 +58,8 @@ def test_tables_full_match_oracle(gpu_tables, oracle_tables):
     _compare_tables(gpu_tables.view(), oracle_tables, TABLE_TOL, "full")
 
 
-def _check_parity(run, w, o_res, o_led, u_tol=U_TOL, label=None, max_mismatch_frac=1e-6):
+def _check_parity(run, w, o_res, o_led, u_tol=U_TOL, label=None, max_mismatch_frac=1e-6, e_tol=E_TOL,
+                  u_cap=U_CAP):
     """Compare every species of instance 0 against the oracle.
 
     Bar: children (event sequences) identical apart from families flagged as threshold
@@ -81,7 +82,7 @@ def _check_parity(run, w, o_res, o_led, u_tol=U_TOL, label=None, max_mismatch_fr
         fam = o["family"][rep["ib"]] if len(rep["ib"]) else np.zeros(0, dtype=np.int64)
         ok_fam = np.array([int(f) not in flagged_fam for f in fam], dtype=bool)
         ue, ee, xe, te = rep["u_err"], rep["e_err"], rep["x_err"], rep["tau_err"]
-        hard = (ee > E_TOL) | (ue > U_CAP) | (xe > X_TOL) | (te > TAU_TOL)
+        hard = (ee > e_tol) | (ue > u_cap) | (xe > X_TOL) | (te > TAU_TOL)
         if name == "photon" and len(rep["ia"]):
             hard |= g["birth_step"][rep["ia"]] != o["birth_step"][rep["ib"]]
         hard &= ok_fam
@@ -116,10 +117,21 @@ def _gpu_run(w, tables, **kw):
 
 
 # End to end (GPU-built tables against oracle-built tables) the sampled chi of every event
-# inherits the tables' own difference: |dP| <~ 1e-14 over segments of dP ~ 1/n_chi moves
-# ln chi by ~1e-12 per event, which a random walk over ~500 events per electron brings to
-# <~ 1e-10 in u.  With the tables shared, the step itself is held to 1e-12.
+# inherits the tables' own difference: a CDF difference |dP| <~ 3e-15 moves the inverse by
+# dP / p, with p the density per unit ln chi; p ~ 1 in the bulk (|d ln chi| ~ 1e-14) but
+# down to ~1e-5 in the tails of the spectrum, where a photon's energy then moves by up to
+# ~1e-10 relative, and the emitter's momentum by that times the photon's share.  A random
+# walk over ~500 events per electron keeps the bulk within 1e-10.  With the tables shared,
+# the step itself is held to the strict bars.
 U_TOL_E2E = 1e-10
+U_CAP_E2E = 1e-8
+E_TOL_E2E = 1e-9
+
+
+def _bars(tables_kind):
+    if tables_kind == "shared":
+        return dict(u_tol=U_TOL, e_tol=E_TOL, u_cap=U_CAP)
+    return dict(u_tol=U_TOL_E2E, e_tol=E_TOL_E2E, u_cap=U_CAP_E2E)
 
 
 @pytest.fixture(scope="module")
@@ -147,8 +159,7 @@ def test_config1_full_parity(tables_kind, gpu_tables, shared_tables, oracle_tabl
     o_res, o_led = oracle_run(w, oracle_tables)
     r = _gpu_run(w, shared_tables if tables_kind == "shared" else gpu_tables)
     led = r.ledger()[0]
-    _check_parity(r, w, o_res, o_led, u_tol=U_TOL if tables_kind == "shared" else U_TOL_E2E,
-                  label="config1_" + tables_kind)
+    _check_parity(r, w, o_res, o_led, label="config1_" + tables_kind, **_bars(tables_kind))
     flagged = len(straddle_uids(o_res))
     assert abs(led["count"][2] - o_led["count"][2]) <= 1000 * flagged
     assert abs(led["n_emit"] - o_led["n_emit"]) <= 1000 * flagged
@@ -170,8 +181,7 @@ def test_collision_parity_with_pairs(tables_kind, gpu_tables, shared_tables, ora
     r = _gpu_run(w, shared_tables if tables_kind == "shared" else gpu_tables)
     led = r.ledger()[0]
     assert o_led["n_pair"] > 20
-    _check_parity(r, w, o_res, o_led, u_tol=U_TOL if tables_kind == "shared" else U_TOL_E2E,
-                  label="collision_" + tables_kind)
+    _check_parity(r, w, o_res, o_led, label="collision_" + tables_kind, **_bars(tables_kind))
     if not straddle_uids(o_res).size:
         assert led["n_pair"] == o_led["n_pair"]
         assert led["n_emit"] == o_led["n_emit"]
