@@ -34,19 +34,22 @@ def log(msg):
 def kernel_bytes(form, kind, led0, led1):
     """Algorithmic HBM bytes of one kernel class over the timed region.
 
-    Per particle-step, FP64 form: lepton 56 B read (x, u, tau) + 56 B written; photon 52 B read
-    (birth position, birth step, k) + 16 B more when its pair rate is non-zero (tau read and
-    written).  Per event: the emitter's uid (8 B) and the child's record (photon 68 B; pair
-    2 x 64 B).  FP32-mixed: lepton 56 + 56 (hi/lo position and momentum, tau); photon 28 (+16);
-    photon child 44 B; pair 2 x 64 B."""
+    Leptons, per particle-step: 56 B read (x, u, tau) + 56 B written in FP64 (FP32-mixed: the
+    same 112 B as hi/lo words of position and momentum plus the FP64 tau); per event the
+    emitter's uid (8 B) and the photon record written (FP64 68 B, FP32-mixed 44 B).
+    Photon sweep, per photon slot-step, with a field that depends on x only (the plane-wave
+    pulse): k (3 words), x at birth (1 word) and the birth step (4 B): 36 B in FP64, 20 B in
+    FP32-mixed; + 16 B (tau read and written) for the photons that see a non-zero pair rate;
+    + 8 B per queued pair event.  The pair pass (separate class) reads the event's photon and
+    writes the two leptons."""
     d = lambda k, i=None: (led1[k][i] - led0[k][i]) if i is not None else (led1[k] - led0[k])
     if kind == "lepton":
         steps = d("particle_steps", 0) + d("particle_steps", 1)
         per, child = (112, 68) if form == "fp64" else (112, 44)
         return steps * per + (d("n_emit") + d("n_null")) * 8 + d("n_emit") * child
     steps = d("particle_steps", 2)
-    base = 52 if form == "fp64" else 28
-    return steps * base + d("photon_steps_in_field") * 16 + d("n_pair") * (8 + 128)
+    base = 36 if form == "fp64" else 20
+    return steps * base + d("photon_steps_in_field") * 16 + d("n_pair") * 8
 
 
 def source_hash():
@@ -124,10 +127,11 @@ def run_form(form, args, tables):
     status = sorted(set(l["status"] for l in led1))
     res = dict(form=form, workload=workload, n_inst=n_inst, seconds=t1 - t0, particle_steps=int(psteps),
                value=psteps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / args.steps,
-               kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2]),
-               launches=dict(setup=launches[0], lepton=launches[1], photon=launches[2]),
+               kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2], pair_events=ms[3]),
+               launches=dict(setup=launches[0], lepton=launches[1], photon=launches[2], pair_events=launches[3]),
                photons_end=int(agg1["count"][2]), pairs=int(agg1["n_pair"] - agg0["n_pair"]),
                emissions=int(agg1["n_emit"] - agg0["n_emit"]), drift_max=max(l["drift"] for l in led1),
+               photon_steps_in_field=int(agg1["photon_steps_in_field"] - agg0["photon_steps_in_field"]),
                status=status)
     kind = "photon" if ms[2] >= ms[1] else "lepton"
     byts = kernel_bytes(form, kind, agg0, agg1)
@@ -135,7 +139,7 @@ def run_form(form, args, tables):
     avg_s = (ms[2] if kind == "photon" else ms[1]) / max(n_l, 1) * 1e-3
     achieved = byts / max(n_l, 1) / avg_s / 1e9
     traffic = measured_traffic(kind, form)
-    res["roofline"] = {"kernel": "k_%s_%s" % (kind, "f64" if form == "fp64" else "f32"), "bound": "hbm",
+    res["roofline"] = {"kernel": "k_%s<%s>" % (kind, form), "bound": "hbm",
                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                        "traffic": traffic, "algorithmic_bytes_per_launch": byts / max(n_l, 1),
                        "mean_launch_us": avg_s * 1e6}

@@ -163,6 +163,12 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
  * per thread (1, 2, 4 or 8).  Takes effect from the next step. */
 qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt);
 
+/* Capacity (entries of 8 bytes, 1..2^32; default 2^20) of the per-step queue through which the
+ * photon pass hands photons whose optical depth reached zero to the pair-creation pass.  A step
+ * with more pair events than this finds the excess by a sweep over all photons: same results,
+ * slower step.  Reallocates (synchronous); drops a captured graph. */
+qed_status qed_set_event_queue(qed_workspace* ws, int64_t capacity);
+
 /* Sec. 3: every macro-particle starts with a sampled optical depth, tau = -ln U with U from the
  * particle's stream at counter (uid, 0, INIT, 0), for every particle in [0, count).  Async. */
 qed_status qed_init_optical_depth(qed_workspace* ws, qed_stream stream);
@@ -212,9 +218,11 @@ typedef struct {
 qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stream);
 
 /* Kernel timing with HIP events recorded around each kernel of qed_step on its stream (not
- * available inside qed_run's graph replay).  qed_profile_read synchronises, returns the summed
- * durations in milliseconds and launch counts of [0] step set-up (snapshot, grid refresh),
- * [1] lepton kernel, [2] photon kernel since qed_profile(ws, 1), and keeps timing. */
+ * available inside qed_run's graph replay).  qed_profile_read synchronises and writes, for the
+ * QED_PROFILE_CLASSES kernel classes [0] step set-up (snapshot, grid refresh), [1] lepton
+ * kernel, [2] photon sweep, [3] pair-creation pass, the summed durations in milliseconds and
+ * the launch counts since qed_profile(ws, 1) or the previous read, and keeps timing. */
+#define QED_PROFILE_CLASSES 4
 qed_status qed_profile(qed_workspace* ws, int32_t enable);
 qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches);
 

@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "QED_OK", -1: "QED_ERR_ARG", -2: "QED_ERR_HIP", -3: "QED_ERR_
                 -4: "QED_ERR_NONFINITE", -5: "QED_ERR_STATE", -6: "QED_ERR_DEVICE"}
 QED_FP64, QED_FP32_MIXED = 0, 1
 QED_EMIT, QED_PAIRS, QED_PROPAGATE = 1, 2, 4
+QED_PROFILE_CLASSES = 4
 QED_FIELD_UNIFORM, QED_FIELD_LP_PULSE, QED_FIELD_CP_WAVE, QED_FIELD_CP_STANDING, QED_FIELD_GRID_CP_STANDING = \
     0, 1, 2, 3, 4
 
@@ -82,6 +83,7 @@ _SIGNATURES = {
     "qed_workspace_destroy": (None, [_vp]),
     "qed_bind": (C.c_int, [_vp, C.POINTER(qed_instance), C.c_int32, C.POINTER(qed_step_params)]),
     "qed_set_launch": (C.c_int, [_vp, C.c_int32, C.c_int32]),
+    "qed_set_event_queue": (C.c_int, [_vp, C.c_int64]),
     "qed_init_optical_depth": (C.c_int, [_vp, _vp]),
     "qed_set_step": (C.c_int, [_vp, C.c_int64, _vp]),
     "qed_step": (C.c_int, [_vp, _vp, C.POINTER(qed_step_params), _vp]),
@@ -170,6 +172,10 @@ def qed_set_launch(ws, block: int, ppt: int):
     return check(lib().qed_set_launch(ws, block, ppt))
 
 
+def qed_set_event_queue(ws, capacity: int):
+    return check(lib().qed_set_event_queue(ws, capacity))
+
+
 def qed_init_optical_depth(ws, stream=None):
     return check(lib().qed_init_optical_depth(ws, stream))
 
@@ -201,8 +207,8 @@ def qed_profile(ws, enable: bool):
 
 
 def qed_profile_read(ws):
-    ms = (C.c_double * 3)()
-    n = (C.c_int64 * 3)()
+    ms = (C.c_double * QED_PROFILE_CLASSES)()
+    n = (C.c_int64 * QED_PROFILE_CLASSES)()
     check(lib().qed_profile_read(ws, ms, n))
     return list(ms), list(n)
 

@@ -85,6 +85,8 @@ struct qed_tables {
   std::vector<double> hh, hlnchi, hdlnchi, hP, hT, hf, hPf, hk;
 };
 
+constexpr int64_t kDefaultEventQueue = int64_t(1) << 20;
+
 struct qed_workspace {
   int device = 0;
   int cus = 256;
@@ -99,6 +101,9 @@ struct qed_workspace {
   qed_instance* d_inst = nullptr;
   InstAcc* d_acc = nullptr;
   Glob* d_glob = nullptr;
+  EvCtl* d_evc = nullptr;
+  uint64_t* d_evq = nullptr;
+  int64_t evq_cap = 0;
   int64_t* d_base = nullptr;  // 3 * max_inst: leptons (2 per instance) then photons
   int64_t* d_movers = nullptr;
   size_t movers_len = 0;
@@ -229,6 +234,7 @@ Tabs device_tabs(const qed_tables* t) {
   tb.P = t->P;
   tb.n_cp = p.n_chi_pair;
   tb.lc0 = std::log(p.chi_pair_min);
+  tb.cp_min = p.chi_pair_min;
   tb.dlc = (std::log(p.chi_pair_max) - tb.lc0) / (p.n_chi_pair - 1);
   tb.T = t->T;
   tb.T32 = t->T32;
@@ -292,7 +298,8 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   const int chunk = B * ppt;
   const StepConst sc = step_const(p);
   int m = mark_begin(ws, 0, s);
-  launch_step_begin(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_base, ws->d_base + 2 * ws->max_inst, chunk,
+  launch_step_begin(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_evc, ws->d_base, ws->d_base + 2 * ws->max_inst,
+                    chunk,
                     chunk, 1, s);
   if (ws->any_grid) launch_grid_refresh(ws->d_inst, ws->n_inst, ws->d_glob, sc, s);
   mark_end(ws, m, s);
@@ -303,6 +310,9 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.ppt = ppt;
   a.tb = device_tabs(tb);
   a.sc = sc;
+  a.q.ctl = ws->d_evc;
+  a.q.ent = ws->d_evq;
+  a.q.cap = ws->evq_cap;
   const int grid = ws->cus * (2048 / B > 0 ? 2048 / B : 1);
   const bool mixed = ws->prec == QED_FP32_MIXED;
   a.base = ws->d_base;
@@ -310,11 +320,16 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   m = mark_begin(ws, 1, s);
   launch_lepton(ws->field_kind, a, grid, B, mixed, s);
   mark_end(ws, m, s);
-  if (p->flags & QED_PROPAGATE) {
+  if (p->flags & QED_PAIRS) {
+    // photons only change state through the pair optical depth: without pair creation their
+    // position is the closed form of their birth record and no pass runs
     a.base = ws->d_base + 2 * ws->max_inst;
     a.n_base = ws->n_inst;
     m = mark_begin(ws, 2, s);
     launch_photon(ws->field_kind, a, grid, B, mixed, s);
+    mark_end(ws, m, s);
+    m = mark_begin(ws, 3, s);
+    launch_pair_events(ws->field_kind, a, ws->cus, 256, mixed, s);
     mark_end(ws, m, s);
   }
   HIP_TRY(hipGetLastError());
@@ -455,6 +470,10 @@ qed_status qed_workspace_create(int32_t max_inst, qed_workspace** out) {
   hipError_t e = hipMalloc((void**)&ws->d_inst, max_inst * sizeof(qed_instance));
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_acc, max_inst * sizeof(InstAcc));
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_glob, sizeof(Glob));
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->d_evc, sizeof(EvCtl));
+  if (e == hipSuccess) e = hipMemset(ws->d_evc, 0, sizeof(EvCtl));
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->d_evq, (size_t)kDefaultEventQueue * sizeof(uint64_t));
+  if (e == hipSuccess) ws->evq_cap = kDefaultEventQueue;
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_base, 3 * (size_t)max_inst * sizeof(int64_t));
   if (e == hipSuccess) e = hipMemset(ws->d_glob, 0, sizeof(Glob));
   if (e == hipSuccess) e = hipMemset(ws->d_acc, 0, max_inst * sizeof(InstAcc));
@@ -474,6 +493,8 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->d_inst);
   hipFree(ws->d_acc);
   hipFree(ws->d_glob);
+  hipFree(ws->d_evc);
+  hipFree(ws->d_evq);
   hipFree(ws->d_base);
   hipFree(ws->d_movers);
   delete ws;
@@ -652,9 +673,24 @@ qed_status qed_profile(qed_workspace* ws, int32_t enable) {
   return QED_OK;
 }
 
+qed_status qed_set_event_queue(qed_workspace* ws, int64_t capacity) {
+  if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
+  if (capacity < 1 || capacity > (int64_t(1) << 32))
+    return fail(QED_ERR_ARG, "event queue capacity = %lld outside [1, 2^32]", (long long)capacity);
+  HIP_TRY(hipSetDevice(ws->device));
+  HIP_TRY(hipDeviceSynchronize());
+  drop_graph(ws);
+  uint64_t* q = nullptr;
+  HIP_TRY(hipMalloc((void**)&q, (size_t)capacity * sizeof(uint64_t)));
+  hipFree(ws->d_evq);
+  ws->d_evq = q;
+  ws->evq_cap = capacity;
+  return QED_OK;
+}
+
 qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches) {
   if (!ws || !ms || !launches) return fail(QED_ERR_ARG, "NULL argument");
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < QED_PROFILE_CLASSES; ++k) {
     ms[k] = 0.0;
     launches[k] = 0;
   }

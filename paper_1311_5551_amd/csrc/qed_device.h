@@ -18,6 +18,41 @@ constexpr double kLambdaCompton = 2.42631023867e-12;   // h/(m_e c) in metres
 
 enum : uint64_t { KIND_INIT = 0, KIND_EMIT = 1, KIND_PAIR = 2 };
 
+// Pointers into global memory.  Pointers read from the instance table are generic to the
+// compiler, which would then address them with flat instructions (which also count against the
+// LDS wait counter); the cast makes their loads and stores global ones.
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+
+// Element at a 32-bit byte offset from a uniform base: the address is formed as a scalar base
+// plus a zero-extended 32-bit lane offset, the form global loads and stores take directly.
+template <class T>
+__device__ __forceinline__ gptr<T> at_off(gptr<T> base, unsigned elem) {
+  return (gptr<T>)((__attribute__((address_space(1))) char*)base + elem * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ gptr<const T> at_off(gptr<const T> base, unsigned elem) {
+  return (gptr<const T>)((__attribute__((address_space(1))) const char*)base + elem * (unsigned)sizeof(T));
+}
+
+// Values that are the same in every lane (loaded from a uniform address), moved to scalar
+// registers so that address arithmetic on them stays scalar.
+__device__ __forceinline__ int uni32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)(uint64_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uni_ptr(T* p) {
+  return (T*)(uintptr_t)uni64((int64_t)(uintptr_t)p);
+}
+__device__ __forceinline__ double uni_f64(double v) { return __longlong_as_double(uni64(__double_as_longlong(v))); }
+
 // Device copy of the tables plus their grid constants.
 struct Tabs {
   int n_eta;
@@ -30,6 +65,7 @@ struct Tabs {
   const double* P;             // [n_eta][n_chi]
   int n_cp;
   double lc0, dlc;             // ln chi_pair_min, ln-spacing of the pair rows
+  double cp_min;               // chi_pair_min
   const double* T;
   const float* T32;
   int n_f;
@@ -64,6 +100,24 @@ struct Glob {
   int64_t step_cur, step_next;   // device clock: index of the running / next step
   int64_t n_chunks[2];           // chunk-list lengths: 0 leptons, 1 photons
 };
+
+// Pair-event queue of one step: the photon sweep appends (instance << 40 | slot) of every photon
+// whose optical depth reached zero; the event pass converts them.  When more events occur than
+// the queue holds, `overflow` is set and the event pass finds them by a sweep over the photons.
+struct EvCtl {
+  int64_t count;
+  int32_t overflow;
+  int32_t pad;
+};
+struct EvQueue {
+  EvCtl* ctl;
+  uint64_t* ent;
+  int64_t cap;
+};
+constexpr int kEvSlotBits = 40;
+// state of a photon's optical depth: >= 0 live, [kTauPendingMin, 0] converting this step, -1 gone
+constexpr double kTauGone = -1.0;
+constexpr double kTauPendingMin = -0.5;
 
 // ---------------------------------------------------------------------------
 // Philox4x64-10 (Salmon et al., SC'11): counter (uid, step, kind, sub), key (seed, instance)
@@ -108,6 +162,96 @@ __device__ __forceinline__ int64_t wrap_index(int64_t i, int n) {
 
 // EXACT selects correctly rounded trigonometry (bit-reproducible momenta); the fast variant
 // (device library, <= 1 ulp) serves quantities that only feed an optical-depth decrement.
+// ---------------------------------------------------------------------------
+// Compact sin/cos and log for values that only set optical-depth decrements (the step decided
+// by a decrement is insensitive to their last bits; momenta always use the correctly rounded
+// functions).  Written out so that the kernels carry no large-argument reduction code: fewer
+// instructions and registers than the general library routines.
+// ---------------------------------------------------------------------------
+namespace fastm {
+constexpr double f2 = 1.0 / 2.0, f3 = 1.0 / 6.0, f4 = 1.0 / 24.0, f5 = 1.0 / 120.0, f6 = 1.0 / 720.0,
+                 f7 = 1.0 / 5040.0, f8 = 1.0 / 40320.0, f9 = 1.0 / 362880.0, f10 = 1.0 / 3628800.0,
+                 f11 = 1.0 / 39916800.0, f12 = 1.0 / 479001600.0, f13 = 1.0 / 6227020800.0,
+                 f14 = 1.0 / 87178291200.0, f15 = 1.0 / 1307674368000.0, f16 = 1.0 / 20922789888000.0,
+                 f17 = 1.0 / 355687428096000.0, f18 = 1.0 / 6402373705728000.0;
+}  // namespace fastm
+
+// sin and cos of x, |x| < 2^20: x = k pi/2 + r by Cody-Waite reduction (pi/2 in three parts, the
+// first with 33 bits so that k times it is exact), |r| <= pi/4, Taylor polynomials to r^17 and
+// r^18 (truncation below 1e-19); quadrant from k mod 4.  Error a few ulp.
+__device__ __forceinline__ void fast_sincos(double x, double* sn, double* cs) {
+  using namespace fastm;
+  const double k = rint(x * kTwoOverPi);
+  const double r = ((x - k * kPio2A) - k * kPio2B) - k * kPio2C;
+  const double r2 = r * r;
+  double ps = f17;
+  ps = ps * r2 - f15;
+  ps = ps * r2 + f13;
+  ps = ps * r2 - f11;
+  ps = ps * r2 + f9;
+  ps = ps * r2 - f7;
+  ps = ps * r2 + f5;
+  ps = ps * r2 - f3;
+  const double sv = r + r * (r2 * ps);
+  double pc = f18;
+  pc = pc * r2 - f16;
+  pc = pc * r2 + f14;
+  pc = pc * r2 - f12;
+  pc = pc * r2 + f10;
+  pc = pc * r2 - f8;
+  pc = pc * r2 + f6;
+  pc = pc * r2 - f4;
+  const double cv = (1.0 - f2 * r2) - r2 * (r2 * pc);
+  const int q = (int)(int64_t)k & 3;
+  *sn = q == 0 ? sv : q == 1 ? cv : q == 2 ? -sv : -cv;
+  *cs = q == 0 ? cv : q == 1 ? -sv : q == 2 ? -cv : sv;
+}
+
+// natural log of a finite x > 0: x = m 2^e with m in [1/sqrt2, sqrt2), log m = 2 atanh(s),
+// s = (m - 1)/(m + 1), |s| <= 0.172, by its odd series to s^25 (truncation below 1e-19).
+__device__ __forceinline__ double fast_log(double x) {
+  int e;
+  double m = frexp(x, &e);
+  if (m < 0.70710678118654752) {
+    m += m;
+    e -= 1;
+  }
+  const double f = m - 1.0;
+  const double s = f / (2.0 + f);
+  const double s2 = s * s;
+  double p = 2.0 / 25.0;
+  p = p * s2 + 2.0 / 23.0;
+  p = p * s2 + 2.0 / 21.0;
+  p = p * s2 + 2.0 / 19.0;
+  p = p * s2 + 2.0 / 17.0;
+  p = p * s2 + 2.0 / 15.0;
+  p = p * s2 + 2.0 / 13.0;
+  p = p * s2 + 2.0 / 11.0;
+  p = p * s2 + 2.0 / 9.0;
+  p = p * s2 + 2.0 / 7.0;
+  p = p * s2 + 2.0 / 5.0;
+  p = p * s2 + 2.0 / 3.0;
+  const double ed = (double)e;
+  return ed * kLn2Hi + (ed * kLn2Lo + (2.0 * s + s * (s2 * p)));
+}
+
+// FP32 sin and cos of |x| <= 4 (phases already reduced in FP64): Cody-Waite by pi/2 in two FP32
+// parts, Taylor polynomials to r^11 and r^10.
+__device__ __forceinline__ void fast_sincosf(float x, float* sn, float* cs) {
+  const float k = rintf(x * 0.636619772f);
+  const float r = (x - k * 1.57079637f) - k * -4.37113883e-8f;
+  const float r2 = r * r;
+  const float ps = ((((-2.50521084e-8f * r2 + 2.75573192e-6f) * r2 - 1.98412698e-4f) * r2 + 8.33333333e-3f) * r2 -
+                    1.66666667e-1f);
+  const float sv = r + r * (r2 * ps);
+  const float pc = ((((2.08767570e-9f * r2 - 2.75573192e-7f) * r2 + 2.48015873e-5f) * r2 - 1.38888889e-3f) * r2 +
+                    4.16666667e-2f);
+  const float cv = (1.0f - 0.5f * r2) + r2 * (r2 * pc);
+  const int q = (int)k & 3;
+  *sn = q == 0 ? sv : q == 1 ? cv : q == 2 ? -sv : -cv;
+  *cs = q == 0 ? cv : q == 1 ? -sv : q == 2 ? -cv : sv;
+}
+
 template <int FK, bool EXACT = true>
 __device__ __forceinline__ void field_at(const qed_field& F, double x, double y, double t, double E[3],
                                          double B[3]) {
@@ -122,8 +266,15 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
   } else if (FK == QED_FIELD_LP_PULSE) {
     const double psi = t - x - F.p[2];
     if (psi >= 0.0 && psi <= F.p[1]) {
-      const double s = EXACT ? cr_sin(kPi * psi / F.p[1]) : sin(kPi * psi / F.p[1]);
-      const double e = F.p[0] * s * s * (EXACT ? cr_cos(psi + F.p[3]) : cos(psi + F.p[3]));
+      double s, c, d;
+      if (EXACT) {
+        s = cr_sin(kPi * psi / F.p[1]);
+        c = cr_cos(psi + F.p[3]);
+      } else {
+        fast_sincos(kPi * psi / F.p[1], &s, &d);
+        fast_sincos(psi + F.p[3], &d, &c);
+      }
+      const double e = F.p[0] * s * s * c;
       E[1] = e;
       B[2] = e;
     }
@@ -131,7 +282,7 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
     const double psi = t - x + F.p[1];
     double sn, cs;
     if (EXACT) cr_sincos(psi, &sn, &cs);
-    else sincos(psi, &sn, &cs);
+    else fast_sincos(psi, &sn, &cs);
     const double ey = F.p[0] * cs, ez = F.p[0] * sn;
     E[1] = ey;
     E[2] = ez;
@@ -143,8 +294,8 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
       cr_sincos(t, &st, &ct);
       cr_sincos(x, &sx, &cx);
     } else {
-      sincos(t, &st, &ct);
-      sincos(x, &sx, &cx);
+      fast_sincos(t, &st, &ct);
+      fast_sincos(x, &sx, &cx);
     }
     E[1] = 2.0 * F.p[0] * ct * cx;
     E[2] = 2.0 * F.p[0] * st * cx;
@@ -165,7 +316,7 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
       const int64_t i0 = (int64_t)fx, j0 = (int64_t)fy;
       const int64_t ia = wrap_index(i0, F.nx), ib = wrap_index(i0 + 1, F.nx);
       const int64_t ja = wrap_index(j0, F.ny), jb = wrap_index(j0 + 1, F.ny);
-      const float* g = F.grid_dev + c * plane;
+      gptr<const float> g = as_global((const float*)F.grid_dev + c * plane);
       const double g00 = g[ja * F.nx + ia], g10 = g[ja * F.nx + ib];
       const double g01 = g[jb * F.nx + ia], g11 = g[jb * F.nx + ib];
       v[c] = (1.0 - wx) * (1.0 - wy) * g00 + wx * (1.0 - wy) * g10 + (1.0 - wx) * wy * g01 + wx * wy * g11;
@@ -186,7 +337,11 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
 // h(eta) from an LDS copy; clamped outside [eta_min, eta_max], counting eta > eta_max.  The
 // rate only feeds the optical-depth decrement, so the device library's log serves.
 __device__ __forceinline__ double lookup_h(const double* sh, const Tabs& tb, double eta, unsigned& range) {
-  const double s = (log(eta) - tb.le0) / tb.dle;
+  if (eta == INFINITY) {
+    ++range;
+    return sh[tb.n_eta - 1];
+  }
+  const double s = (fast_log(eta) - tb.le0) / tb.dle;
   if (!(s > 0.0)) return sh[0];
   if (s >= tb.n_eta - 1) {
     ++range;
@@ -200,8 +355,12 @@ __device__ __forceinline__ double lookup_h(const double* sh, const Tabs& tb, dou
 // T(chi) from an LDS copy; zero below chi_pair_min (T < 1e-58 there); feeds only the
 // optical-depth decrement
 __device__ __forceinline__ double lookup_T(const double* sT, const Tabs& tb, double chi, unsigned& range) {
-  if (!(chi > 0.0)) return 0.0;
-  const double s = (log(chi) - tb.lc0) / tb.dlc;
+  if (!(chi >= tb.cp_min)) return 0.0;  // below the table (T ~ 0) or NaN
+  if (chi == INFINITY) {
+    ++range;
+    return sT[tb.n_cp - 1];
+  }
+  const double s = (fast_log(chi) - tb.lc0) / tb.dlc;
   if (s < 0.0) return 0.0;
   if (s >= tb.n_cp - 1) {
     ++range;
@@ -290,6 +449,25 @@ __device__ __forceinline__ long long wave_reserve(bool want, int64_t* counter) {
   return want ? base + prefix : -1;
 }
 
+// wave_reserve for lanes whose counters may differ: lanes are served one key (counter) at a time.
+// Every lane of the wave must call it.
+__device__ inline long long wave_reserve_grouped(bool want, int key, int64_t* counter) {
+  long long res = -1;
+  bool left = want;
+  unsigned long long mask;
+  while ((mask = __ballot(left)) != 0ull) {
+    const int leader = __ffsll((long long)mask) - 1;
+    const int lk = __shfl(key, leader);
+    const bool mine = left && key == lk;
+    const long long r = wave_reserve(mine, counter);
+    if (mine) {
+      res = r;
+      left = false;
+    }
+  }
+  return res;
+}
+
 // block-wide sums of a few accumulators; result valid in thread 0.  Every thread must call.
 template <int ND, int NU>
 __device__ inline void block_sum(double (&d)[ND], unsigned (&u)[NU], double* sd, unsigned* su) {
@@ -312,6 +490,29 @@ __device__ inline void block_sum(double (&d)[ND], unsigned (&u)[NU], double* sd,
     for (int w = 1; w < nw; ++w) {
 #pragma unroll
       for (int a = 0; a < ND; ++a) d[a] += sd[w * ND + a];
+#pragma unroll
+      for (int a = 0; a < NU; ++a) u[a] += su[w * NU + a];
+    }
+  }
+  __syncthreads();
+}
+
+// block-wide sums of unsigned accumulators; result valid in thread 0.  Every thread must call.
+template <int NU>
+__device__ inline void block_sum_u(unsigned (&u)[NU], unsigned* su) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int a = 0; a < NU; ++a) u[a] += __shfl_down(u[a], off);
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < NU; ++a) su[wave * NU + a] = u[a];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < nw; ++w) {
 #pragma unroll
       for (int a = 0; a < NU; ++a) u[a] += su[w * NU + a];
     }

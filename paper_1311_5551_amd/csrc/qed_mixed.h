@@ -47,14 +47,16 @@ __device__ __forceinline__ void field_at32(const qed_field& F, double x, double 
   } else if (FK == QED_FIELD_LP_PULSE) {
     const double psi = t - x - F.p[2];
     if (psi >= 0.0 && psi <= F.p[1]) {
-      const float s = sinf((float)(kPi * (psi / F.p[1])));
-      const float e = (float)F.p[0] * s * s * cosf(reduce_phase(psi + F.p[3]));
+      float s, c, d;
+      fast_sincosf((float)(kPi * (psi / F.p[1])), &s, &d);
+      fast_sincosf(reduce_phase(psi + F.p[3]), &d, &c);
+      const float e = (float)F.p[0] * s * s * c;
       E[1] = e;
       B[2] = e;
     }
   } else if (FK == QED_FIELD_CP_WAVE) {
     float sn, cs;
-    sincosf(reduce_phase(t - x + F.p[1]), &sn, &cs);
+    fast_sincosf(reduce_phase(t - x + F.p[1]), &sn, &cs);
     const float e0 = (float)F.p[0];
     E[1] = e0 * cs;
     E[2] = e0 * sn;
@@ -62,8 +64,8 @@ __device__ __forceinline__ void field_at32(const qed_field& F, double x, double 
     B[2] = e0 * cs;
   } else if (FK == QED_FIELD_CP_STANDING) {
     float st, ct, sx, cx;
-    sincosf(reduce_phase(t), &st, &ct);
-    sincosf(reduce_phase(x), &sx, &cx);
+    fast_sincosf(reduce_phase(t), &st, &ct);
+    fast_sincosf(reduce_phase(x), &sx, &cx);
     const float e2 = 2.0f * (float)F.p[0];
     E[1] = e2 * ct * cx;
     E[2] = e2 * st * cx;
@@ -84,7 +86,7 @@ __device__ __forceinline__ void field_at32(const qed_field& F, double x, double 
       const int64_t i0 = (int64_t)fx, j0 = (int64_t)fy;
       const int64_t ia = wrap_index(i0, F.nx), ib = wrap_index(i0 + 1, F.nx);
       const int64_t ja = wrap_index(j0, F.ny), jb = wrap_index(j0 + 1, F.ny);
-      const float* g = F.grid_dev + c * plane;
+      gptr<const float> g = as_global((const float*)F.grid_dev + c * plane);
       v[c] = (1.0f - wx) * (1.0f - wy) * g[ja * F.nx + ia] + wx * (1.0f - wy) * g[ja * F.nx + ib] +
              (1.0f - wx) * wy * g[jb * F.nx + ia] + wx * wy * g[jb * F.nx + ib];
     }

@@ -27,8 +27,8 @@ namespace qedk {
 // snapshot at the start of a step or pass
 // ---------------------------------------------------------------------------
 __global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
-                             Glob* __restrict__ glob, int64_t* __restrict__ base_lep, int64_t* __restrict__ base_ph,
-                             int chunk_lep, int chunk_ph, int advance_clock) {
+                             Glob* __restrict__ glob, EvCtl* __restrict__ evc, int64_t* __restrict__ base_lep,
+                             int64_t* __restrict__ base_ph, int chunk_lep, int chunk_ph, int advance_clock) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
     for (int s = 0; s < 3; ++s) {
       const qed_species& S = inst[i].s[s];
@@ -65,6 +65,8 @@ __global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, 
       glob->step_cur = glob->step_next;
       glob->step_next = glob->step_cur + 1;
     }
+    evc->count = 0;
+    evc->overflow = 0;
   }
 }
 
@@ -270,14 +272,219 @@ __global__ __launch_bounds__(256) void k_lepton_f64(StepArgs a) {
 // ---------------------------------------------------------------------------
 // photons, both precisions.  Position at the start of step n: x_b + (n - b) dt k/|k|.
 //
-// A thread first loads the birth positions, momenta and birth steps of all PPT particles it
-// owns in the chunk (independent loads in flight together), then works through them.  Most
-// photons sit where the field vanishes and need nothing more; the others decrement their pair
-// optical depth with a rate from the device library's trigonometry and log (the decrement only
-// decides the event step) and, at a pair event, recompute chi with correctly rounded functions
-// for the sampling that sets the pair momenta.  Event statistics stay in registers across the
-// block's chunks and are flushed when the instance changes.
+// The sweep (k_photon) is the bandwidth-bound part: every photon slot, every step.  A thread
+// first issues the loads of all PPT photons it owns in the chunk, then for each one evaluates
+// chi and T(chi) with the device library's trigonometry and log and, where T > 0, decrements
+// the optical depth (these values only decide the event step).  A photon whose depth reaches
+// zero is queued; the event pass (k_pair_events) recomputes chi from the stored photon with
+// correctly rounded functions, samples the energy split and appends the pair.  Keeping the rare
+// event work out of the sweep keeps the sweep's register footprint, and so its occupancy, at
+// what streaming the photon arrays needs.
 // ---------------------------------------------------------------------------
+template <int FK, int PPT, bool MIXED>
+__global__ __launch_bounds__(256) void k_photon(StepArgs a) {
+  using Real = typename std::conditional<MIXED, float, double>::type;
+  constexpr bool NEED_X = FK != QED_FIELD_UNIFORM;
+  constexpr bool NEED_Y = FK == QED_FIELD_GRID_CP_STANDING;
+  extern __shared__ double smem[];
+  __shared__ qed_field sF;  // field of the instance being processed
+  double* sT = smem;
+  float* sT32 = (float*)smem;
+  unsigned* sredu = (unsigned*)(smem + a.tb.n_cp);
+  for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) {
+    if (MIXED) sT32[i] = a.tb.T32[i];
+    else sT[i] = a.tb.T[i];
+  }
+
+  const int64_t step = uni64(a.glob->step_cur);
+  const double t = a.sc.t0 + (double)step * a.sc.dt;
+  const double dt = a.sc.dt;
+  const int64_t nch = uni64(a.glob->n_chunks[1]);
+  const int B = blockDim.x;
+  const int64_t CH = (int64_t)B * PPT;
+  const double rate = a.sc.a_pair * dt;
+
+  // context of the instance whose chunks the block is on (chunks [cb, ce) of the list)
+  int cur = -1;
+  int64_t cb = 0, ce = 0, n = 0;
+  gptr<const Real> KX = nullptr, KY = nullptr, KZ = nullptr, XB = nullptr, YB = nullptr;
+  gptr<const int32_t> BS = nullptr;
+  gptr<double> TAU = nullptr;
+  float tpf0 = 0.0f, psif_max = 0.0f;
+  unsigned uacc[3] = {0, 0, 0};  // in-field steps, chi above the table, non-finite tau
+  auto flush = [&](int ii) {
+    block_sum_u(uacc, sredu);
+    if (threadIdx.x == 0) {
+      InstAcc& A = a.acc[ii];
+      if (uacc[0]) atomicAdd(&A.n_field, (unsigned long long)uacc[0]);
+      if (uacc[1]) atomicAdd(&A.n_range, (unsigned long long)uacc[1]);
+      if (uacc[2]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[2]);
+    }
+    uacc[0] = uacc[1] = uacc[2] = 0;
+  };
+
+  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    if (c >= ce) {  // first chunk of another instance (c only grows)
+      if (cur >= 0) flush(cur);
+      const int ii = uni32(find_entry(a.base, a.n_base, c));
+      cur = ii;
+      cb = uni64(a.base[ii]);
+      ce = ii + 1 < a.n_base ? uni64(a.base[ii + 1]) : nch;
+      const qed_species& S = a.inst[ii].s[2];
+      KX = as_global((const Real*)uni_ptr(S.ux_dev));
+      KY = as_global((const Real*)uni_ptr(S.uy_dev));
+      KZ = as_global((const Real*)uni_ptr(S.uz_dev));
+      XB = as_global((const Real*)uni_ptr(S.x_dev));
+      YB = as_global((const Real*)uni_ptr(S.y_dev));
+      BS = as_global((const int32_t*)uni_ptr(S.birth_step_dev));
+      TAU = as_global(uni_ptr(S.tau_dev));
+      n = uni64(a.acc[ii].n_start[2]);
+      __syncthreads();  // the previous field copy is no longer read
+      const uint64_t* src = (const uint64_t*)&a.inst[ii].field;
+      for (int w = threadIdx.x; w < (int)(sizeof(qed_field) / 8); w += B) ((uint64_t*)&sF)[w] = src[w];
+      __syncthreads();
+      tpf0 = (float)sF.p[2];
+      psif_max = (float)sF.p[1];
+    }
+    const int64_t k0 = uni64((c - cb) * CH);  // first slot of the chunk
+    const int64_t rem = n - k0;        // slots of the chunk that exist: min(rem, CH)
+
+    // chunk-base pointers are uniform, lane offsets 32-bit
+    const gptr<const Real> kxc = KX + k0, kyc = KY + k0, kzc = KZ + k0, xbc = XB + k0, ybc = YB + k0;
+    const gptr<const int32_t> bsc = BS + k0;
+    const gptr<double> tauc = TAU + k0;
+    const double tt = t;
+    // in-field part for one photon; true when its optical depth reached zero
+    auto infield = [&](unsigned off, Real kx, Real ky, Real kz, Real xb, Real yb, int32_t bs) -> bool {
+      const Real eps = sqrt(kx * kx + ky * ky + kz * kz);
+      const Real inv = (Real)1 / eps;
+      const Real nx = kx * inv, ny = ky * inv, nz = kz * inv;
+      double x = 0.0, y = 0.0;
+      if (NEED_X) {
+        const double age = (double)(step - (int64_t)bs) * dt;
+        x = (double)xb + age * nx;
+        if (NEED_Y) y = (double)yb + age * ny;
+      }
+      double chi, T;
+      if (MIXED) {
+        float E[3], Bf[3];
+        field_at32<FK>(sF, x, y, tt, E, Bf);
+        const float ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
+        const float ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
+        const float az = E[2] + (nx * Bf[1] - ny * Bf[0]);
+        const float ne = nx * E[0] + ny * E[1] + nz * E[2];
+        const float r2 = (ax * ax + ay * ay + az * az) - ne * ne;
+        const float chif = 0.5f * (float)eps * sqrtf(r2 > 0.0f ? r2 : 0.0f);
+        chi = chif;
+        T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.dlc, chif, uacc[1], true);
+      } else {
+        double E[3], Bf[3];
+        field_at<FK, false>(sF, x, y, tt, E, Bf);
+        const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
+        const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
+        const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
+        const double ne = nx * E[0] + ny * E[1] + nz * E[2];
+        const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
+        chi = 0.5 * (double)eps * sqrt(r2 > 0.0 ? r2 : 0.0);
+        T = lookup_T(sT, a.tb, chi, uacc[1]);
+      }
+      bool pend = false;
+      if (T > 0.0) {
+        double tau = *at_off(tauc, off);
+        if (!(tau < 0.0)) {  // tau < 0: converted in an earlier step
+          ++uacc[0];
+          tau -= MIXED ? (double)((float)rate * (float)chi * (float)T * (float)inv) : rate * chi * T * (double)inv;
+          if (tau <= 0.0) {
+            pend = true;
+            tau = fmax(tau, kTauPendingMin);
+          }
+          if (!isfinite(tau)) ++uacc[2];
+          *at_off(tauc, off) = tau;
+        }
+      }
+      return pend;
+    };
+    auto enqueue = [&](unsigned off, bool pend) {
+      const long long slot = wave_reserve(pend, &a.q.ctl->count);
+      if (pend) {
+        if (slot < a.q.cap) a.q.ent[slot] = ((uint64_t)cur << kEvSlotBits) | (uint64_t)(k0 + off);
+        else a.q.ctl->overflow = 1;
+      }
+    };
+
+    if (FK == QED_FIELD_LP_PULSE) {
+      // phase 1: loads of all PPT photons, then the FP32 envelope test.  The pulse occupies
+      // psi = t - x - psi0 in [0, Psi]; the FP32 estimate of psi carries a margin far above its
+      // rounding error (a few FP32 ulps of |t| + |psi0| + |x_b| + age), so a photon it rejects
+      // is one the FP64 test would certainly find outside the pulse.
+      float kxf[PPT], kyf[PPT], kzf[PPT], xbf[PPT];
+      int32_t bs[PPT];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        if ((int64_t)off < rem) {
+          kxf[j] = (float)*at_off(kxc, off);
+          kyf[j] = (float)*at_off(kyc, off);
+          kzf[j] = (float)*at_off(kzc, off);
+          xbf[j] = (float)*at_off(xbc, off);
+          bs[j] = *at_off(bsc, off);
+        }
+      }
+      const float tpf = (float)t - tpf0;
+      const float mt = fabsf((float)t) + fabsf(tpf0);
+      unsigned gmask = 0;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        if ((int64_t)off < rem) {
+          const float nxf = kxf[j] * rsqrtf(kxf[j] * kxf[j] + kyf[j] * kyf[j] + kzf[j] * kzf[j]);
+          const float agef = (float)((double)(step - (int64_t)bs[j]) * dt);
+          const float psif = tpf - (xbf[j] + agef * nxf);
+          const float m = 1e-5f * (mt + fabsf(xbf[j]) + agef) + 1e-30f;
+          if (psif >= -m && psif <= psif_max + m) gmask |= 1u << j;
+        }
+      }
+      // phase 2: the photons inside the pulse, re-read (from cache) one at a time; not unrolled,
+      // so that one copy of the in-field code holds registers
+#pragma unroll 1
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        bool pend = false;
+        if (gmask & (1u << j))
+          pend = infield(off, *at_off(kxc, off), *at_off(kyc, off), *at_off(kzc, off), *at_off(xbc, off), Real(0),
+                         *at_off(bsc, off));
+        enqueue(off, pend);
+      }
+    } else {
+      Real kx[PPT], ky[PPT], kz[PPT], xb[PPT], yb[PPT];
+      int32_t bs[PPT];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        if ((int64_t)off < rem) {
+          kx[j] = *at_off(kxc, off);
+          ky[j] = *at_off(kyc, off);
+          kz[j] = *at_off(kzc, off);
+          if (NEED_X) {
+            xb[j] = *at_off(xbc, off);
+            bs[j] = *at_off(bsc, off);
+          }
+          if (NEED_Y) yb[j] = *at_off(ybc, off);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        bool pend = false;
+        if ((int64_t)off < rem) pend = infield(off, kx[j], ky[j], kz[j], NEED_X ? xb[j] : Real(0),
+                                               NEED_Y ? yb[j] : Real(0), NEED_X ? bs[j] : 0);
+        enqueue(off, pend);
+      }
+    }
+  }
+  if (cur >= 0) flush(cur);
+}
+
 template <bool MIXED>
 __device__ __forceinline__ void write_lepton(const qed_species& S, long long slot, double x, double y, double z,
                                              double ux, double uy, double uz, double tau, uint64_t uid, bool d3) {
@@ -301,193 +508,138 @@ __device__ __forceinline__ void write_lepton(const qed_species& S, long long slo
   S.uid_dev[slot] = uid;
 }
 
-template <int FK, int PPT, bool MIXED>
-__global__ __launch_bounds__(256) void k_photon(StepArgs a) {
+// Pair creation by photon k of instance ii (when `want`): chi at the photon's position (FP64
+// form: correctly rounded field), energy split f from the P_f table, electron with (1 - f) k
+// and positron with f k at the position after the step, fresh optical depths, photon removed.
+// Every lane of the wave calls this (the appends are wave-aggregated).
+template <int FK, bool MIXED>
+__device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k, bool want, int64_t step, double t) {
   using Real = typename std::conditional<MIXED, float, double>::type;
-  extern __shared__ double smem[];
-  double* sred = smem;
-  unsigned* sredu = (unsigned*)(sred + 16 * 3);
-  double* sT = (double*)(sredu + 16 * 5);
-  float* sT32 = (float*)sT;
-  for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) {
-    if (MIXED) sT32[i] = a.tb.T32[i];
-    else sT[i] = a.tb.T[i];
+  const double dt = a.sc.dt;
+  const qed_instance& I = a.inst[ii];
+  const qed_species& S = I.s[2];
+  const bool d3 = I.dims == 3;
+  double px = 0, py = 0, pz = 0, etau = 0, ptau = 0, ex = 0, ey = 0, ez = 0, pkx = 0, pky = 0, pkz = 0;
+  uint64_t euid = 0, puid = 0;
+  if (want) {
+    const Real kxr = ((const Real*)S.ux_dev)[k], kyr = ((const Real*)S.uy_dev)[k], kzr = ((const Real*)S.uz_dev)[k];
+    const Real xbr = ((const Real*)S.x_dev)[k], ybr = ((const Real*)S.y_dev)[k];
+    const int32_t bs = S.birth_step_dev[k];
+    const uint64_t uid = S.uid_dev[k];
+    const Real eps = sqrt(kxr * kxr + kyr * kyr + kzr * kzr);
+    const Real nx = kxr / eps, ny = kyr / eps, nz = kzr / eps;
+    const double age = (double)(step - (int64_t)bs) * dt;
+    const double x = (double)xbr + age * nx;
+    const double y = (double)ybr + age * ny;
+    double chi;
+    if (MIXED) {
+      float E[3], Bf[3];
+      field_at32<FK>(I.field, x, y, t, E, Bf);
+      const float ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
+      const float ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
+      const float az = E[2] + (nx * Bf[1] - ny * Bf[0]);
+      const float ne = nx * E[0] + ny * E[1] + nz * E[2];
+      const float r2 = (ax * ax + ay * ay + az * az) - ne * ne;
+      chi = 0.5f * (float)eps * sqrtf(r2 > 0.0f ? r2 : 0.0f);
+    } else {
+      double E[3], Bf[3];
+      field_at<FK, true>(I.field, x, y, t, E, Bf);
+      const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
+      const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
+      const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
+      const double ne = nx * E[0] + ny * E[1] + nz * E[2];
+      const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
+      chi = 0.5 * (double)eps * sqrt(r2 > 0.0 ? r2 : 0.0);
+    }
+    uint64_t r0[4], r1[4];
+    philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 0, I.seed, I.key_instance, r0);
+    philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 1, I.seed, I.key_instance, r1);
+    const double f = sample_f(a.tb, chi, unit_open(r0[0]));
+    const double kxd = kxr, kyd = kyr, kzd = kzr;
+    pkx = f * kxd;
+    pky = f * kyd;
+    pkz = f * kzd;
+    if (MIXED) {
+      ex = kxd - pkx;
+      ey = kyd - pky;
+      ez = kzd - pkz;
+    } else {
+      ex = (1.0 - f) * kxd;
+      ey = (1.0 - f) * kyd;
+      ez = (1.0 - f) * kzd;
+    }
+    const double gp = sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
+    const double ge = sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
+    const double epsd = MIXED ? sqrt(kxd * kxd + kyd * kyd + kzd * kzd) : (double)eps;
+    const double age1 = age + dt;
+    px = (double)xbr + age1 * nx;
+    py = (double)ybr + age1 * ny;
+    pz = d3 ? (double)((const Real*)S.z_dev)[k] + age1 * nz : 0.0;
+    euid = r0[1];
+    puid = r0[2];
+    etau = optical_depth(r0[3]);
+    ptau = optical_depth(r1[0]);
+    S.tau_dev[k] = kTauGone;
+    InstAcc& A = a.acc[ii];
+    atomicAdd(&A.defect_pair, gp + ge - epsd);
+    atomicAdd(&A.n_pair, 1ull);
   }
-  __syncthreads();
+  // append electron and positron, one atomic per wave and instance
+  const qed_species& Se = I.s[0];
+  const qed_species& Sp = I.s[1];
+  const long long se = wave_reserve_grouped(want, ii, Se.count_dev);
+  const long long spo = wave_reserve_grouped(want, ii, Sp.count_dev);
+  if (want) {
+    InstAcc& A = a.acc[ii];
+    if (se < Se.capacity) {
+      write_lepton<MIXED>(Se, se, px, py, pz, ex, ey, ez, etau, euid, d3);
+    } else {
+      atomicAdd(&A.n_dropped, 1ull);
+      atomicAdd(&A.dropped_energy, sqrt(1.0 + (ex * ex + ey * ey + ez * ez)));
+    }
+    if (spo < Sp.capacity) {
+      write_lepton<MIXED>(Sp, spo, px, py, pz, pkx, pky, pkz, ptau, puid, d3);
+    } else {
+      atomicAdd(&A.n_dropped, 1ull);
+      atomicAdd(&A.dropped_energy, sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz)));
+    }
+  }
+}
 
+// Event pass: the queued photons, or, when the queue overflowed, every photon whose optical
+// depth is in the converting state.  Both loops advance whole waves together, as the
+// wave-aggregated appends need.
+template <int FK, bool MIXED>
+__global__ __launch_bounds__(256) void k_pair_events(StepArgs a) {
   const int64_t step = a.glob->step_cur;
   const double t = a.sc.t0 + (double)step * a.sc.dt;
-  const double dt = a.sc.dt;
-  const int64_t nch = a.glob->n_chunks[1];
-  const int B = blockDim.x;
-  const int64_t CH = (int64_t)B * PPT;
-  const bool pairs = (a.sc.flags & QED_PAIRS) != 0;
-
-  int cur = -1;                        // instance the accumulators belong to
-  double dacc[3] = {0.0, 0.0, 0.0};    // defect, dropped energy, unused
-  unsigned uacc[5] = {0, 0, 0, 0, 0};  // pairs, in-field steps, range, nonfinite, dropped
-  auto flush = [&](int ii) {
-    block_sum(dacc, uacc, sred, sredu);
-    if (threadIdx.x == 0) {
-      InstAcc& A = a.acc[ii];
-      if (dacc[0] != 0.0) atomicAdd(&A.defect_pair, dacc[0]);
-      if (dacc[1] != 0.0) atomicAdd(&A.dropped_energy, dacc[1]);
-      if (uacc[0]) atomicAdd(&A.n_pair, (unsigned long long)uacc[0]);
-      if (uacc[1]) atomicAdd(&A.n_field, (unsigned long long)uacc[1]);
-      if (uacc[2]) atomicAdd(&A.n_range, (unsigned long long)uacc[2]);
-      if (uacc[3]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[3]);
-      if (uacc[4]) atomicAdd(&A.n_dropped, (unsigned long long)uacc[4]);
+  const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (!a.q.ctl->overflow) {
+    const int64_t cnt = a.q.ctl->count;
+    for (int64_t e0 = gtid - threadIdx.x % 64; e0 < cnt; e0 += stride) {
+      // whole waves iterate together; lanes past the end take no event
+      const int64_t e = e0 + threadIdx.x % 64;
+      const bool want = e < cnt;
+      const uint64_t ent = want ? a.q.ent[e] : 0;
+      pair_event<FK, MIXED>(a, (int)(ent >> kEvSlotBits), (int64_t)(ent & ((1ull << kEvSlotBits) - 1)), want, step,
+                            t);
     }
-    dacc[0] = dacc[1] = dacc[2] = 0.0;
-    uacc[0] = uacc[1] = uacc[2] = uacc[3] = uacc[4] = 0;
-  };
-
-  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-    const int ii = find_entry(a.base, a.n_base, c);
-    if (ii != cur) {
-      if (cur >= 0) flush(cur);
-      cur = ii;
-    }
-    const qed_instance& I = a.inst[ii];
-    const qed_species& S = I.s[2];
-    const int64_t n = a.acc[ii].n_start[2];
-    const int64_t k0 = (c - a.base[ii]) * CH + threadIdx.x;
-    const bool d3 = I.dims == 3;
-    const Real* KX = (const Real*)S.ux_dev;
-    const Real* KY = (const Real*)S.uy_dev;
-    const Real* KZ = (const Real*)S.uz_dev;
-    const Real* XB = (const Real*)S.x_dev;
-    const Real* YB = (const Real*)S.y_dev;
-    const Real* ZB = (const Real*)S.z_dev;
-
-    Real kx[PPT], ky[PPT], kz[PPT], xb[PPT], yb[PPT];
-    int32_t bs[PPT];
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      const int64_t k = k0 + (int64_t)j * B;
-      if (pairs && k < n) {
-        kx[j] = KX[k];
-        ky[j] = KY[k];
-        kz[j] = KZ[k];
-        xb[j] = XB[k];
-        yb[j] = YB[k];
-        bs[j] = S.birth_step_dev[k];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      const int64_t k = k0 + (int64_t)j * B;
-      bool born = false;
-      double px = 0, py = 0, pz = 0, etau = 0, ptau = 0, ex = 0, ey = 0, ez = 0, pkx = 0, pky = 0, pkz = 0;
-      uint64_t euid = 0, puid = 0;
-      if (pairs && k < n) {
-        const Real eps = sqrt(kx[j] * kx[j] + ky[j] * ky[j] + kz[j] * kz[j]);
-        const Real nx = kx[j] / eps, ny = ky[j] / eps, nz = kz[j] / eps;
-        const double age = (double)(step - (int64_t)bs[j]) * dt;
-        const double x = (double)xb[j] + age * nx;
-        const double y = (double)yb[j] + age * ny;
-        double chi, T;
-        if (MIXED) {
-          float E[3], Bf[3];
-          field_at32<FK>(I.field, x, y, t, E, Bf);
-          const float ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
-          const float ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
-          const float az = E[2] + (nx * Bf[1] - ny * Bf[0]);
-          const float ne = nx * E[0] + ny * E[1] + nz * E[2];
-          const float r2 = (ax * ax + ay * ay + az * az) - ne * ne;
-          const float chif = 0.5f * (float)eps * sqrtf(r2 > 0.0f ? r2 : 0.0f);
-          chi = chif;
-          T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.dlc, chif, uacc[2], true);
-        } else {
-          double E[3], Bf[3];
-          field_at<FK, false>(I.field, x, y, t, E, Bf);
-          const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
-          const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
-          const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
-          const double ne = nx * E[0] + ny * E[1] + nz * E[2];
-          const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
-          chi = 0.5 * (double)eps * sqrt(r2 > 0.0 ? r2 : 0.0);
-          T = lookup_T(sT, a.tb, chi, uacc[2]);
+  } else {
+    for (int ii = 0; ii < a.n_base; ++ii) {
+      const int64_t n = a.acc[ii].n_start[2];
+      const double* TAU = a.inst[ii].s[2].tau_dev;
+      for (int64_t k0 = gtid - threadIdx.x % 64; k0 < n; k0 += stride) {
+        const int64_t k = k0 + threadIdx.x % 64;
+        bool want = false;
+        if (k < n) {
+          const double tau = TAU[k];
+          want = tau <= 0.0 && tau >= kTauPendingMin;
         }
-        if (T > 0.0) {
-          double tau = S.tau_dev[k];
-          if (!(tau < 0.0)) {  // tau < 0: already converted
-            ++uacc[1];
-            tau -= MIXED ? (double)((float)(a.sc.a_pair * dt) * (float)chi * (float)T / (float)eps)
-                         : a.sc.a_pair * chi * T / (double)eps * dt;
-            if (tau <= 0.0) {
-              const uint64_t uid = S.uid_dev[k];
-              uint64_t r0[4], r1[4];
-              philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 0, I.seed, I.key_instance, r0);
-              philox4x64_10(uid, (uint64_t)step, KIND_PAIR, 1, I.seed, I.key_instance, r1);
-              if (!MIXED) {
-                // chi for the sampling with correctly rounded field values
-                double E[3], Bf[3];
-                field_at<FK, true>(I.field, x, y, t, E, Bf);
-                const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
-                const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
-                const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
-                const double ne = nx * E[0] + ny * E[1] + nz * E[2];
-                const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
-                chi = 0.5 * (double)eps * sqrt(r2 > 0.0 ? r2 : 0.0);
-              }
-              const double f = sample_f(a.tb, chi, unit_open(r0[0]));
-              const double kxd = kx[j], kyd = ky[j], kzd = kz[j];
-              pkx = f * kxd;
-              pky = f * kyd;
-              pkz = f * kzd;
-              if (MIXED) {
-                ex = kxd - pkx;
-                ey = kyd - pky;
-                ez = kzd - pkz;
-              } else {
-                ex = (1.0 - f) * kxd;
-                ey = (1.0 - f) * kyd;
-                ez = (1.0 - f) * kzd;
-              }
-              const double gp = sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
-              const double ge = sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
-              const double epsd = MIXED ? sqrt(kxd * kxd + kyd * kyd + kzd * kzd) : (double)eps;
-              dacc[0] += gp + ge - epsd;
-              const double age1 = age + dt;
-              px = (double)xb[j] + age1 * nx;
-              py = (double)yb[j] + age1 * ny;
-              pz = d3 ? (double)ZB[k] + age1 * nz : 0.0;
-              euid = r0[1];
-              puid = r0[2];
-              etau = optical_depth(r0[3]);
-              ptau = optical_depth(r1[0]);
-              born = true;
-              ++uacc[0];
-              tau = -1.0;  // annihilated
-            }
-            if (!isfinite(tau)) ++uacc[3];
-            S.tau_dev[k] = tau;
-          }
-        }
-      }
-      // append electron and positron, one atomic per wave each
-      const qed_species& Se = I.s[0];
-      const qed_species& Sp = I.s[1];
-      const long long se = wave_reserve(born, Se.count_dev);
-      const long long spo = wave_reserve(born, Sp.count_dev);
-      if (born) {
-        if (se < Se.capacity) {
-          write_lepton<MIXED>(Se, se, px, py, pz, ex, ey, ez, etau, euid, d3);
-        } else {
-          ++uacc[4];
-          dacc[1] += sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
-        }
-        if (spo < Sp.capacity) {
-          write_lepton<MIXED>(Sp, spo, px, py, pz, pkx, pky, pkz, ptau, puid, d3);
-        } else {
-          ++uacc[4];
-          dacc[1] += sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
-        }
+        pair_event<FK, MIXED>(a, ii, k, want, step, t);
       }
     }
   }
-  if (cur >= 0) flush(cur);
 }
 
 // ---------------------------------------------------------------------------
@@ -686,6 +838,11 @@ static void launch_lepton_fk(const StepArgs& a, dim3 grid, dim3 block, size_t sh
   if (mixed) hipLaunchKernelGGL(k_lepton_f32<FK>, grid, block, shm, s, a);
   else hipLaunchKernelGGL(k_lepton_f64<FK>, grid, block, shm, s, a);
 }
+template <int FK>
+static void launch_pair_events_fk(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s, bool mixed) {
+  if (mixed) hipLaunchKernelGGL((k_pair_events<FK, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_pair_events<FK, false>), grid, block, 0, s, a);
+}
 template <int FK, int PPT>
 static void launch_photon_ppt(const StepArgs& a, dim3 grid, dim3 block, size_t shm, hipStream_t s, bool mixed) {
   if (mixed) hipLaunchKernelGGL((k_photon<FK, PPT, true>), grid, block, shm, s, a);
@@ -701,10 +858,10 @@ static void launch_photon_fk(const StepArgs& a, dim3 grid, dim3 block, size_t sh
   }
 }
 
-void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, int64_t* base_lep,
+void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, int64_t* base_lep,
                        int64_t* base_ph, int chunk_lep, int chunk_ph, int advance, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, inst, n_inst, acc, glob, base_lep, base_ph, chunk_lep,
-                     chunk_ph, advance);
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, inst, n_inst, acc, glob, evc, base_lep, base_ph,
+                     chunk_lep, chunk_ph, advance);
 }
 
 void launch_set_step(Glob* glob, int64_t step, hipStream_t s) {
@@ -728,8 +885,19 @@ void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, h
   }
 }
 
+void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
+  const dim3 g(grid), b(block);
+  switch (fk) {
+    case QED_FIELD_UNIFORM: launch_pair_events_fk<QED_FIELD_UNIFORM>(a, g, b, s, mixed); break;
+    case QED_FIELD_LP_PULSE: launch_pair_events_fk<QED_FIELD_LP_PULSE>(a, g, b, s, mixed); break;
+    case QED_FIELD_CP_WAVE: launch_pair_events_fk<QED_FIELD_CP_WAVE>(a, g, b, s, mixed); break;
+    case QED_FIELD_CP_STANDING: launch_pair_events_fk<QED_FIELD_CP_STANDING>(a, g, b, s, mixed); break;
+    default: launch_pair_events_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, s, mixed); break;
+  }
+}
+
 void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
-  const size_t shm = (size_t)a.tb.n_cp * sizeof(double) + 16 * 3 * sizeof(double) + 16 * 5 * sizeof(unsigned) + 64;
+  const size_t shm = (size_t)a.tb.n_cp * sizeof(double) + 16 * 3 * sizeof(unsigned) + 64;
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_photon_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;

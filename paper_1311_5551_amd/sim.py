@@ -184,6 +184,9 @@ class Run:
     def set_launch(self, block, ppt):
         capi.qed_set_launch(self.ws, block, ppt)
 
+    def set_event_queue(self, capacity: int):
+        capi.qed_set_event_queue(self.ws, capacity)
+
     def step(self, n: int = 1):
         for _ in range(n):
             capi.qed_step(self.tables.handle, self.ws, self.params, self._s())
@@ -206,7 +209,7 @@ class Run:
         capi.qed_profile(self.ws, enable)
 
     def profile_read(self):
-        """(ms, launches) per kernel class: [set-up, lepton, photon]."""
+        """(ms, launches) per kernel class: [set-up, lepton, photon sweep, pair events]."""
         return capi.qed_profile_read(self.ws)
 
     def synchronize(self):

@@ -174,6 +174,21 @@ def test_batched_instances_equal_single_runs(shared_tables):
         assert lb["n_emit"] == ls["n_emit"] and lb["n_pair"] == ls["n_pair"]
 
 
+def test_event_queue_overflow_falls_back_to_sweep(shared_tables):
+    # a one-entry pair-event queue overflows on most steps with pairs; the sweep that then finds
+    # the converting photons gives the same particles as the queue
+    w, ra = _collision_run(shared_tables, n=2000)
+    _, rb = _collision_run(shared_tables, n=2000)
+    rb.set_event_queue(1)
+    ra.step(2600)
+    rb.step(2600)
+    la, lb = ra.ledger()[0], rb.ledger()[0]
+    assert la["n_pair"] == lb["n_pair"] > 5
+    _states_equal(ra, rb)
+    with pytest.raises(capi.QEDError):
+        rb.set_event_queue(0)
+
+
 def test_restart_from_saved_state_is_exact(shared_tables):
     w, ra = _collision_run(shared_tables, n=1500)
     ra.step(2600)
