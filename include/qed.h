@@ -207,6 +207,8 @@ typedef struct {
   int64_t n_emit, n_null, n_pair;  /* emissions, draws below the cut-off, pair creations */
   int64_t n_dropped, n_range, n_nonfinite;
   int64_t photon_steps_in_field;   /* photon steps that saw a non-zero pair rate */
+  int64_t lepton_steps_in_field;   /* lepton steps with the full push (all of them, except outside a
+                                      plane-wave pulse, where the push is the field-free drift) */
   int64_t particle_steps[3];       /* particles present at the start of each step, summed over the
                                       steps since qed_bind (photons: buffer slots, incl. dead ones
                                       not yet compacted) */
@@ -220,9 +222,10 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
 /* Kernel timing with HIP events recorded around each kernel of qed_step on its stream (not
  * available inside qed_run's graph replay).  qed_profile_read synchronises and writes, for the
  * QED_PROFILE_CLASSES kernel classes [0] step set-up (snapshot, grid refresh), [1] lepton
- * kernel, [2] photon sweep, [3] pair-creation pass, the summed durations in milliseconds and
- * the launch counts since qed_profile(ws, 1) or the previous read, and keeps timing. */
-#define QED_PROFILE_CLASSES 4
+ * sweep, [2] photon sweep, [3] pair-creation pass, [4] photon-emission pass, the summed
+ * durations in milliseconds and the launch counts since qed_profile(ws, 1) or the previous
+ * read, and keeps timing. */
+#define QED_PROFILE_CLASSES 5
 qed_status qed_profile(qed_workspace* ws, int32_t enable);
 qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches);
 

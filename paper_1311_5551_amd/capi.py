@@ -15,7 +15,7 @@ STATUS_NAMES = {0: "QED_OK", -1: "QED_ERR_ARG", -2: "QED_ERR_HIP", -3: "QED_ERR_
                 -4: "QED_ERR_NONFINITE", -5: "QED_ERR_STATE", -6: "QED_ERR_DEVICE"}
 QED_FP64, QED_FP32_MIXED = 0, 1
 QED_EMIT, QED_PAIRS, QED_PROPAGATE = 1, 2, 4
-QED_PROFILE_CLASSES = 4
+QED_PROFILE_CLASSES = 5
 QED_FIELD_UNIFORM, QED_FIELD_LP_PULSE, QED_FIELD_CP_WAVE, QED_FIELD_CP_STANDING, QED_FIELD_GRID_CP_STANDING = \
     0, 1, 2, 3, 4
 
@@ -63,7 +63,8 @@ class qed_ledger(C.Structure):
                 ("defect_emit", C.c_double), ("defect_pair", C.c_double), ("dropped_energy", C.c_double),
                 ("count", C.c_int64 * 3), ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
                 ("n_dropped", C.c_int64), ("n_range", C.c_int64), ("n_nonfinite", C.c_int64),
-                ("photon_steps_in_field", C.c_int64), ("particle_steps", C.c_int64 * 3), ("drift", C.c_double)]
+                ("photon_steps_in_field", C.c_int64), ("lepton_steps_in_field", C.c_int64),
+                ("particle_steps", C.c_int64 * 3), ("drift", C.c_double)]
 
     def as_dict(self) -> dict:
         d = {k: getattr(self, k) for k, _ in self._fields_}

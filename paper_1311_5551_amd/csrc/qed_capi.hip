@@ -101,9 +101,11 @@ struct qed_workspace {
   qed_instance* d_inst = nullptr;
   InstAcc* d_acc = nullptr;
   Glob* d_glob = nullptr;
-  EvCtl* d_evc = nullptr;
+  EvCtl* d_evc = nullptr;  // [0] pair-event queue, [1] emission queue
   uint64_t* d_evq = nullptr;
   int64_t evq_cap = 0;
+  EmitEv* d_emq = nullptr;
+  int64_t emq_cap = 0;
   int64_t* d_base = nullptr;  // 3 * max_inst: leptons (2 per instance) then photons
   int64_t* d_movers = nullptr;
   size_t movers_len = 0;
@@ -298,8 +300,8 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   const int chunk = B * ppt;
   const StepConst sc = step_const(p);
   int m = mark_begin(ws, 0, s);
-  launch_step_begin(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_evc, ws->d_base, ws->d_base + 2 * ws->max_inst,
-                    chunk,
+  launch_step_begin(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_evc, ws->d_evc + 1, ws->d_base,
+                    ws->d_base + 2 * ws->max_inst, chunk,
                     chunk, 1, s);
   if (ws->any_grid) launch_grid_refresh(ws->d_inst, ws->n_inst, ws->d_glob, sc, s);
   mark_end(ws, m, s);
@@ -313,6 +315,9 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.q.ctl = ws->d_evc;
   a.q.ent = ws->d_evq;
   a.q.cap = ws->evq_cap;
+  a.qe.ctl = ws->d_evc + 1;
+  a.qe.ent = ws->d_emq;
+  a.qe.cap = ws->emq_cap;
   const int grid = ws->cus * (2048 / B > 0 ? 2048 / B : 1);
   const bool mixed = ws->prec == QED_FP32_MIXED;
   a.base = ws->d_base;
@@ -320,6 +325,11 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   m = mark_begin(ws, 1, s);
   launch_lepton(ws->field_kind, a, grid, B, mixed, s);
   mark_end(ws, m, s);
+  if (p->flags & QED_EMIT) {
+    m = mark_begin(ws, 4, s);
+    launch_emit_events(ws->field_kind, a, ws->cus, 256, mixed, s);
+    mark_end(ws, m, s);
+  }
   if (p->flags & QED_PAIRS) {
     // photons only change state through the pair optical depth: without pair creation their
     // position is the closed form of their birth record and no pass runs
@@ -470,8 +480,8 @@ qed_status qed_workspace_create(int32_t max_inst, qed_workspace** out) {
   hipError_t e = hipMalloc((void**)&ws->d_inst, max_inst * sizeof(qed_instance));
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_acc, max_inst * sizeof(InstAcc));
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_glob, sizeof(Glob));
-  if (e == hipSuccess) e = hipMalloc((void**)&ws->d_evc, sizeof(EvCtl));
-  if (e == hipSuccess) e = hipMemset(ws->d_evc, 0, sizeof(EvCtl));
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->d_evc, 2 * sizeof(EvCtl));
+  if (e == hipSuccess) e = hipMemset(ws->d_evc, 0, 2 * sizeof(EvCtl));
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_evq, (size_t)kDefaultEventQueue * sizeof(uint64_t));
   if (e == hipSuccess) ws->evq_cap = kDefaultEventQueue;
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_base, 3 * (size_t)max_inst * sizeof(int64_t));
@@ -495,6 +505,7 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->d_glob);
   hipFree(ws->d_evc);
   hipFree(ws->d_evq);
+  hipFree(ws->d_emq);
   hipFree(ws->d_base);
   hipFree(ws->d_movers);
   delete ws;
@@ -588,6 +599,17 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
     ws->movers_len = 0;
     HIP_TRY(hipMalloc((void**)&ws->d_movers, (movers ? movers : 1) * sizeof(int64_t)));
     ws->movers_len = movers;
+  }
+  // emission queue: one entry per lepton slot (a lepton emits at most once per step)
+  int64_t leptons = 0;
+  for (int i = 0; i < n_inst; ++i) leptons += inst[i].s[0].capacity + inst[i].s[1].capacity;
+  if (leptons < 1) leptons = 1;
+  if (leptons > ws->emq_cap) {
+    hipFree(ws->d_emq);
+    ws->d_emq = nullptr;
+    ws->emq_cap = 0;
+    HIP_TRY(hipMalloc((void**)&ws->d_emq, (size_t)leptons * sizeof(EmitEv)));
+    ws->emq_cap = leptons;
   }
   HIP_TRY(hipMemcpy(ws->d_inst, inst, n_inst * sizeof(qed_instance), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ws->d_acc, acc0.data(), n_inst * sizeof(InstAcc), hipMemcpyHostToDevice));
@@ -744,6 +766,7 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
     L.n_range = (int64_t)A.n_range;
     L.n_nonfinite = (int64_t)A.n_nonfinite;
     L.photon_steps_in_field = (int64_t)A.n_field;
+    L.lepton_steps_in_field = (int64_t)A.n_field_lepton;
     for (int s = 0; s < 3; ++s) L.particle_steps[s] = (int64_t)A.particle_steps[s];
     const double resid = tot - L.energy0 - L.work - L.defect_emit - L.defect_pair + L.dropped_energy;
     L.drift = L.energy0 > 0.0 ? std::fabs(resid) / L.energy0 : std::fabs(resid);

@@ -91,7 +91,7 @@ struct InstAcc {
   double work, defect_emit, defect_pair, dropped_energy;
   double led_energy[3];
   unsigned long long led_count[3];
-  unsigned long long n_emit, n_null, n_pair, n_dropped, n_range, n_nonfinite, n_field;
+  unsigned long long n_emit, n_null, n_pair, n_dropped, n_range, n_nonfinite, n_field, n_field_lepton;
   unsigned long long particle_steps[3];  // particles (photon slots) present at the start of each step
 };
 
@@ -112,6 +112,17 @@ struct EvCtl {
 struct EvQueue {
   EvCtl* ctl;
   uint64_t* ent;
+  int64_t cap;
+};
+// Emission-event queue: (instance << 41 | species << 40 | slot) and the emitter's eta.  Sized to
+// the bound lepton capacity, so it cannot overflow (at most one event per lepton and step).
+struct EmitEv {
+  uint64_t key;
+  double eta;
+};
+struct EmitQueue {
+  EvCtl* ctl;
+  EmitEv* ent;
   int64_t cap;
 };
 constexpr int kEvSlotBits = 40;
@@ -466,6 +477,46 @@ __device__ inline long long wave_reserve_grouped(bool want, int key, int64_t* co
     }
   }
   return res;
+}
+
+// sums over the 64 lanes of a wave, every lane active; every lane gets the result
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ __forceinline__ unsigned wave_sum_u(unsigned v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+// Event statistics of the lanes of a wave added to the accumulators of each lane's instance:
+// one group of atomics per instance present in the wave.  kind 0: emission, 1: pair creation.
+// Every lane of the wave must call it, all lanes active.
+__device__ inline void add_event_stats(int kind, bool has, int ii, InstAcc* acc, double defect, double dropped_e,
+                                       unsigned n_ev, unsigned n_null, unsigned n_drop) {
+  bool left = has;
+  unsigned long long mask;
+  while ((mask = __ballot(left)) != 0ull) {
+    const int leader = __ffsll((long long)mask) - 1;
+    const int lk = __shfl(ii, leader);
+    const bool mine = left && ii == lk;
+    const double sd = wave_sum(mine ? defect : 0.0);
+    const double se = wave_sum(mine ? dropped_e : 0.0);
+    const unsigned sv = wave_sum_u(mine ? n_ev : 0u);
+    const unsigned sn = wave_sum_u(mine ? n_null : 0u);
+    const unsigned sp = wave_sum_u(mine ? n_drop : 0u);
+    if (__lane_id() == leader) {
+      InstAcc& A = acc[lk];
+      if (sd != 0.0) atomicAdd(kind == 0 ? &A.defect_emit : &A.defect_pair, sd);
+      if (se != 0.0) atomicAdd(&A.dropped_energy, se);
+      if (sv) atomicAdd(kind == 0 ? &A.n_emit : &A.n_pair, (unsigned long long)sv);
+      if (sn) atomicAdd(&A.n_null, (unsigned long long)sn);
+      if (sp) atomicAdd(&A.n_dropped, (unsigned long long)sp);
+    }
+    if (mine) left = false;
+  }
 }
 
 // block-wide sums of a few accumulators; result valid in thread 0.  Every thread must call.

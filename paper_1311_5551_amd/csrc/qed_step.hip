@@ -1,8 +1,10 @@
 // Per-step kernels of the QED Monte-Carlo step (Sec. 3 and 3.2 of the paper):
 //   k_step_begin   snapshot of the live counts, chunk lists, device clock
 //   k_grid_refresh analytic refresh of the 2-D Yee grid (grid field kind)
-//   k_lepton       push + eta + optical depth + photon emission (electrons and positrons)
-//   k_photon       ballistic photons + chi + pair optical depth + pair creation
+//   k_lepton       push + eta + emission optical depth (electrons and positrons)
+//   k_emit_events  photon emission by the leptons whose optical depth reached zero
+//   k_photon       ballistic photons + chi + pair optical depth
+//   k_pair_events  pair creation by the photons whose optical depth reached zero
 // and the auxiliary passes: optical-depth initialisation, compaction of dead photons and
 // the energy-ledger reduction.
 //
@@ -27,7 +29,8 @@ namespace qedk {
 // snapshot at the start of a step or pass
 // ---------------------------------------------------------------------------
 __global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
-                             Glob* __restrict__ glob, EvCtl* __restrict__ evc, int64_t* __restrict__ base_lep,
+                             Glob* __restrict__ glob, EvCtl* __restrict__ evc, EvCtl* __restrict__ emc,
+                             int64_t* __restrict__ base_lep,
                              int64_t* __restrict__ base_ph, int chunk_lep, int chunk_ph, int advance_clock) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
     for (int s = 0; s < 3; ++s) {
@@ -67,6 +70,8 @@ __global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, 
     }
     evc->count = 0;
     evc->overflow = 0;
+    emc->count = 0;
+    emc->overflow = 0;
   }
 }
 
@@ -115,58 +120,128 @@ __global__ void k_grid_refresh(const qed_instance* __restrict__ inst, int n_inst
 }
 
 // ---------------------------------------------------------------------------
-// leptons, FP64 form
+// leptons, both precisions.
+//
+// The sweep (k_lepton) pushes every electron and positron (Boris, field at the start-of-step
+// position), evaluates eta and decrements the emission optical depth; a lepton whose depth
+// reached zero is queued with its eta, and the emission pass (k_emit_events) samples chi,
+// applies the recoil, appends the photon and draws a new depth.  In the plane-wave pulse the
+// leptons outside the pulse see no field, where the Boris step reduces exactly to
+// x += dt u / gamma with u and tau unchanged: the sweep does only that for them (same values
+// as the full step, a third of its memory traffic).
+//
+// FP32-mixed form: the push, eta and h(eta) in FP32 on the high words; position and momentum
+// stored as (hi, lo) FP32 pairs updated by compensated addition; tau, chi sampling, recoil and
+// every ledger energy in FP64.
 // ---------------------------------------------------------------------------
-template <int FK>
-__global__ __launch_bounds__(256) void k_lepton_f64(StepArgs a) {
-  extern __shared__ double smem[];
-  double* sh = smem;
-  double* sred = smem + a.tb.n_eta;
-  unsigned* sredu = (unsigned*)(sred + 16 * 3);
-  for (int i = threadIdx.x; i < a.tb.n_eta; i += blockDim.x) sh[i] = a.tb.h[i];
-  __syncthreads();
+template <bool MIXED>
+struct LepPtr {
+  using Real = typename std::conditional<MIXED, float, double>::type;
+  gptr<Real> x, y, z, ux, uy, uz;
+  gptr<float> xl, yl, zl, uxl, uyl, uzl;
+  gptr<double> tau;
+};
 
-  const int64_t step = a.glob->step_cur;
+template <int FK, int PPT, bool MIXED>
+__global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
+  using Real = typename std::conditional<MIXED, float, double>::type;
+  extern __shared__ double smem[];
+  __shared__ qed_field sF;
+  double* sh = smem;
+  float* sh32 = (float*)smem;
+  double* sred = smem + a.tb.n_eta;
+  unsigned* sredu = (unsigned*)(sred + 16);
+  for (int i = threadIdx.x; i < a.tb.n_eta; i += blockDim.x) {
+    if (MIXED) sh32[i] = a.tb.h32[i];
+    else sh[i] = a.tb.h[i];
+  }
+
+  const int64_t step = uni64(a.glob->step_cur);
   const double t = a.sc.t0 + (double)step * a.sc.dt;
   const double dt = a.sc.dt;
-  const int64_t nch = a.glob->n_chunks[0];
+  const float dtf = (float)dt;
+  const int64_t nch = uni64(a.glob->n_chunks[0]);
   const int B = blockDim.x;
-  const int64_t CH = (int64_t)B * a.ppt;
+  const int64_t CH = (int64_t)B * PPT;
   const bool emit = (a.sc.flags & QED_EMIT) != 0;
+  const double agdt = a.sc.a_gamma * dt;
+
+  int cur = -1;  // chunk-list entry (2 instance + species) the context belongs to
+  int64_t cb = 0, ce = 0, n = 0;
+  LepPtr<MIXED> P{};
+  bool d3 = false;
+  double hq = 0.0;
+  float tpf0 = 0.0f, psif_max = 0.0f;
+  double dacc[1] = {0.0};              // field work
+  unsigned uacc[3] = {0, 0, 0};        // in-field steps, eta above the table, non-finite state
+  auto flush = [&](int entry) {
+    block_sum(dacc, uacc, sred, sredu);
+    if (threadIdx.x == 0) {
+      InstAcc& A = a.acc[entry >> 1];
+      if (dacc[0] != 0.0) atomicAdd(&A.work, dacc[0]);
+      if (uacc[0]) atomicAdd(&A.n_field_lepton, (unsigned long long)uacc[0]);
+      if (uacc[1]) atomicAdd(&A.n_range, (unsigned long long)uacc[1]);
+      if (uacc[2]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[2]);
+    }
+    dacc[0] = 0.0;
+    uacc[0] = uacc[1] = uacc[2] = 0;
+  };
 
   for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
-    const int idx = find_entry(a.base, a.n_base, c);
-    const int ii = idx >> 1, sp = idx & 1;
-    const qed_instance& I = a.inst[ii];
-    const qed_species& S = I.s[sp];
-    const qed_species& G = I.s[2];
-    const int64_t n = a.acc[ii].n_start[sp];
-    const int64_t k0 = (c - a.base[idx]) * CH;
-    const double q = sp == 0 ? -1.0 : 1.0;
-    const double hq = 0.5 * q * a.sc.kappa * dt;
-    const bool d3 = I.dims == 3;
-    double* X = (double*)S.x_dev;
-    double* Y = (double*)S.y_dev;
-    double* Z = (double*)S.z_dev;
-    double* UX = (double*)S.ux_dev;
-    double* UY = (double*)S.uy_dev;
-    double* UZ = (double*)S.uz_dev;
+    if (c >= ce) {
+      if (cur >= 0) flush(cur);
+      const int idx = uni32(find_entry(a.base, a.n_base, c));
+      cur = idx;
+      cb = uni64(a.base[idx]);
+      ce = idx + 1 < a.n_base ? uni64(a.base[idx + 1]) : nch;
+      const int ii = idx >> 1, sp = idx & 1;
+      const qed_instance& I = a.inst[ii];
+      const qed_species& S = I.s[sp];
+      P.x = as_global((Real*)uni_ptr(S.x_dev));
+      P.y = as_global((Real*)uni_ptr(S.y_dev));
+      P.z = as_global((Real*)uni_ptr(S.z_dev));
+      P.ux = as_global((Real*)uni_ptr(S.ux_dev));
+      P.uy = as_global((Real*)uni_ptr(S.uy_dev));
+      P.uz = as_global((Real*)uni_ptr(S.uz_dev));
+      if (MIXED) {
+        P.xl = as_global(uni_ptr(S.x_lo_dev));
+        P.yl = as_global(uni_ptr(S.y_lo_dev));
+        P.zl = as_global(uni_ptr(S.z_lo_dev));
+        P.uxl = as_global(uni_ptr(S.ux_lo_dev));
+        P.uyl = as_global(uni_ptr(S.uy_lo_dev));
+        P.uzl = as_global(uni_ptr(S.uz_lo_dev));
+      }
+      P.tau = as_global(uni_ptr(S.tau_dev));
+      n = uni64(a.acc[ii].n_start[sp]);
+      d3 = uni32(I.dims) == 3;
+      hq = 0.5 * (sp == 0 ? -1.0 : 1.0) * a.sc.kappa * dt;
+      __syncthreads();
+      const uint64_t* src = (const uint64_t*)&I.field;
+      for (int w = threadIdx.x; w < (int)(sizeof(qed_field) / 8); w += B) ((uint64_t*)&sF)[w] = src[w];
+      __syncthreads();
+      tpf0 = (float)sF.p[2];
+      psif_max = (float)sF.p[1];
+    }
+    const int64_t k0 = uni64((c - cb) * CH);
+    const int64_t rem = n - k0;
+    LepPtr<MIXED> C;  // chunk-base pointers
+    C.x = P.x + k0; C.y = P.y + k0; C.z = P.z + k0;
+    C.ux = P.ux + k0; C.uy = P.uy + k0; C.uz = P.uz + k0;
+    if (MIXED) {
+      C.xl = P.xl + k0; C.yl = P.yl + k0; C.zl = P.zl + k0;
+      C.uxl = P.uxl + k0; C.uyl = P.uyl + k0; C.uzl = P.uzl + k0;
+    }
+    C.tau = P.tau + k0;
 
-    double dacc[3] = {0.0, 0.0, 0.0};   // work, defect, dropped energy
-    unsigned uacc[5] = {0, 0, 0, 0, 0};  // emit, null, range, nonfinite, dropped
-
-    for (int j = 0; j < a.ppt; ++j) {
-      const int64_t k = k0 + (int64_t)j * B + threadIdx.x;
-      const bool active = k < n;
-      bool child = false;
-      double cx = 0, cy = 0, cz = 0, ckx = 0, cky = 0, ckz = 0, ctau = 0;
-      uint64_t cuid = 0;
-      if (active) {
-        double x = X[k], y = Y[k], z = d3 ? Z[k] : 0.0;
-        double ux = UX[k], uy = UY[k], uz = UZ[k], tau = S.tau_dev[k];
+    // full step of one lepton; returns true (and its eta) when its optical depth reached zero
+    auto full = [&](unsigned off, double* eta_out) -> bool {
+      bool pend = false;
+      if (!MIXED) {
+        double x = *at_off(C.x, off), y = *at_off(C.y, off), z = d3 ? *at_off(C.z, off) : 0.0;
+        const double ux = *at_off(C.ux, off), uy = *at_off(C.uy, off), uz = *at_off(C.uz, off);
+        double tau = *at_off(C.tau, off);
         double E[3], Bf[3];
-        field_at<FK>(I.field, x, y, t, E, Bf);
-        // Boris push
+        field_at<FK>(sF, x, y, t, E, Bf);
         const double g0 = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
         const double umx = ux + hq * E[0], umy = uy + hq * E[1], umz = uz + hq * E[2];
         const double gm = sqrt(1.0 + (umx * umx + umy * umy + umz * umz));
@@ -183,9 +258,6 @@ __global__ __launch_bounds__(256) void k_lepton_f64(StepArgs a) {
         x += dt * u1x / g1;
         y += dt * u1y / g1;
         if (d3) z += dt * u1z / g1;
-        ux = u1x;
-        uy = u1y;
-        uz = u1z;
         if (emit) {
           const double ax = g1 * E[0] + (u1y * Bf[2] - u1z * Bf[1]);
           const double ay = g1 * E[1] + (u1z * Bf[0] - u1x * Bf[2]);
@@ -194,78 +266,299 @@ __global__ __launch_bounds__(256) void k_lepton_f64(StepArgs a) {
           const double r2 = (ax * ax + ay * ay + az * az) - ue * ue;
           const double eta = sqrt(r2 > 0.0 ? r2 : 0.0);
           if (eta > 0.0) {
-            const double h = lookup_h(sh, a.tb, eta, uacc[2]);
+            const double h = lookup_h(sh, a.tb, eta, uacc[1]);
             tau -= a.sc.a_gamma * (eta / g1) * h * dt;
             if (tau <= 0.0) {
-              uint64_t r[4];
-              philox4x64_10(S.uid_dev[k], (uint64_t)step, KIND_EMIT, 0, I.seed, I.key_instance, r);
-              double chi;
-              if (sample_chi(a.tb, eta, unit_open(r[0]), &chi)) {
-                const double xi = 2.0 * chi / eta;
-                const double kx = xi * u1x, ky = xi * u1y, kz = xi * u1z;
-                ux = u1x - kx;
-                uy = u1y - ky;
-                uz = u1z - kz;
-                const double g2 = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
-                const double eps = sqrt(kx * kx + ky * ky + kz * kz);
-                dacc[1] += g2 + eps - g1;
-                child = true;
-                cx = x;
-                cy = y;
-                cz = z;
-                ckx = kx;
-                cky = ky;
-                ckz = kz;
-                ctau = optical_depth(r[3]);
-                cuid = r[2];
-                ++uacc[0];
-              } else {
-                ++uacc[1];
-              }
-              tau = optical_depth(r[1]);
+              pend = true;
+              *eta_out = eta;
             }
           }
         }
-        if (!isfinite(tau) || !isfinite(ux) || !isfinite(uy) || !isfinite(uz)) ++uacc[3];
-        X[k] = x;
-        Y[k] = y;
-        if (d3) Z[k] = z;
-        UX[k] = ux;
-        UY[k] = uy;
-        UZ[k] = uz;
-        S.tau_dev[k] = tau;
+        if (!isfinite(tau) || !isfinite(u1x) || !isfinite(u1y) || !isfinite(u1z)) ++uacc[2];
+        *at_off(C.x, off) = x;
+        *at_off(C.y, off) = y;
+        if (d3) *at_off(C.z, off) = z;
+        *at_off(C.ux, off) = u1x;
+        *at_off(C.uy, off) = u1y;
+        *at_off(C.uz, off) = u1z;
+        *at_off(C.tau, off) = tau;
+      } else {
+        float xh = *at_off(C.x, off), xl = *at_off(C.xl, off), yh = *at_off(C.y, off), yl = *at_off(C.yl, off);
+        float zh = d3 ? *at_off(C.z, off) : 0.0f, zl = d3 ? *at_off(C.zl, off) : 0.0f;
+        float uxh = *at_off(C.ux, off), uxl = *at_off(C.uxl, off), uyh = *at_off(C.uy, off),
+              uyl = *at_off(C.uyl, off), uzh = *at_off(C.uz, off), uzl = *at_off(C.uzl, off);
+        double tau = *at_off(C.tau, off);
+        const double ux0 = (double)uxh + uxl, uy0 = (double)uyh + uyl, uz0 = (double)uzh + uzl;
+        const double g0d = sqrt(1.0 + (ux0 * ux0 + uy0 * uy0 + uz0 * uz0));
+        float E[3], Bf[3];
+        field_at32<FK>(sF, (double)xh + xl, (double)yh + yl, t, E, Bf);
+        const float hqf = (float)hq;
+        const float umx = uxh + hqf * E[0], umy = uyh + hqf * E[1], umz = uzh + hqf * E[2];
+        const float gm = sqrtf(1.0f + (umx * umx + umy * umy + umz * umz));
+        const float tx = hqf / gm * Bf[0], ty = hqf / gm * Bf[1], tz = hqf / gm * Bf[2];
+        const float sf = 2.0f / (1.0f + (tx * tx + ty * ty + tz * tz));
+        const float sx = sf * tx, sy = sf * ty, sz = sf * tz;
+        const float upx = umx + (umy * tz - umz * ty), upy = umy + (umz * tx - umx * tz),
+                    upz = umz + (umx * ty - umy * tx);
+        // rotation increment (u+ - u-) formed directly, without cancellation
+        const float rx = upy * sz - upz * sy, ry = upz * sx - upx * sz, rz = upx * sy - upy * sx;
+        comp_add(uxh, uxl, 2.0f * hqf * E[0] + rx);
+        comp_add(uyh, uyl, 2.0f * hqf * E[1] + ry);
+        comp_add(uzh, uzl, 2.0f * hqf * E[2] + rz);
+        const float g1 = sqrtf(1.0f + (uxh * uxh + uyh * uyh + uzh * uzh));
+        comp_add(xh, xl, dtf * uxh / g1);
+        comp_add(yh, yl, dtf * uyh / g1);
+        if (d3) comp_add(zh, zl, dtf * uzh / g1);
+        // field work from the stored states (FP64), so the ledger closes on what is stored
+        const double ux1 = (double)uxh + uxl, uy1 = (double)uyh + uyl, uz1 = (double)uzh + uzl;
+        dacc[0] += sqrt(1.0 + (ux1 * ux1 + uy1 * uy1 + uz1 * uz1)) - g0d;
+        if (emit) {
+          const float ax = g1 * E[0] + (uyh * Bf[2] - uzh * Bf[1]);
+          const float ay = g1 * E[1] + (uzh * Bf[0] - uxh * Bf[2]);
+          const float az = g1 * E[2] + (uxh * Bf[1] - uyh * Bf[0]);
+          const float ue = uxh * E[0] + uyh * E[1] + uzh * E[2];
+          const float r2 = (ax * ax + ay * ay + az * az) - ue * ue;
+          const float eta = sqrtf(r2 > 0.0f ? r2 : 0.0f);
+          if (eta > 0.0f) {
+            const float h = lookup32(sh32, a.tb.n_eta, a.tb.le0, a.tb.dle, eta, uacc[1], false);
+            tau -= (double)((float)agdt * (eta / g1) * h);
+            if (tau <= 0.0) {
+              pend = true;
+              *eta_out = (double)eta;
+            }
+          }
+        }
+        if (!isfinite(tau) || !isfinite(uxh) || !isfinite(uyh) || !isfinite(uzh)) ++uacc[2];
+        *at_off(C.x, off) = xh;
+        *at_off(C.xl, off) = xl;
+        *at_off(C.y, off) = yh;
+        *at_off(C.yl, off) = yl;
+        if (d3) {
+          *at_off(C.z, off) = zh;
+          *at_off(C.zl, off) = zl;
+        }
+        *at_off(C.ux, off) = uxh;
+        *at_off(C.uxl, off) = uxl;
+        *at_off(C.uy, off) = uyh;
+        *at_off(C.uyl, off) = uyl;
+        *at_off(C.uz, off) = uzh;
+        *at_off(C.uzl, off) = uzl;
+        *at_off(C.tau, off) = tau;
       }
-      // append the photons of this pass, one atomic per wave
-      const long long slot = wave_reserve(child, G.count_dev);
-      if (child) {
-        if (slot < G.capacity) {
+      return pend;
+    };
+    auto enqueue = [&](unsigned off, bool pend, double eta) {
+      const long long slot = wave_reserve(pend, &a.qe.ctl->count);
+      if (pend) {
+        if (slot < a.qe.cap) {
+          a.qe.ent[slot].key = ((uint64_t)(cur >> 1) << 41) | ((uint64_t)(cur & 1) << 40) | (uint64_t)(k0 + off);
+          a.qe.ent[slot].eta = eta;
+        } else {
+          a.qe.ctl->overflow = 1;  // cannot happen: the queue holds one entry per lepton slot
+        }
+      }
+    };
+
+    if (FK == QED_FIELD_LP_PULSE) {
+      // phase 1: state of all PPT leptons; outside the pulse (FP32 phase test with a margin far
+      // above its rounding error) the drift, inside it a bit for phase 2
+      Real x[PPT], y[PPT], z[PPT], ux[PPT], uy[PPT], uz[PPT];
+      float xl[PPT], yl[PPT], zl[PPT];
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        if ((int64_t)off < rem) {
+          x[j] = *at_off(C.x, off);
+          y[j] = *at_off(C.y, off);
+          z[j] = d3 ? *at_off(C.z, off) : Real(0);
+          ux[j] = *at_off(C.ux, off);
+          uy[j] = *at_off(C.uy, off);
+          uz[j] = *at_off(C.uz, off);
+          if (MIXED) {
+            xl[j] = *at_off(C.xl, off);
+            yl[j] = *at_off(C.yl, off);
+            zl[j] = d3 ? *at_off(C.zl, off) : 0.0f;
+          }
+        }
+      }
+      const float tpf = (float)t - tpf0;
+      const float mt = fabsf((float)t) + fabsf(tpf0);
+      unsigned gmask = 0;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        if ((int64_t)off < rem) {
+          const float xf = (float)x[j];
+          const float psif = tpf - xf;
+          const float m = 1e-5f * (mt + fabsf(xf)) + 1e-30f;
+          if (psif >= -m && psif <= psif_max + m) {
+            gmask |= 1u << j;
+          } else if (!MIXED) {
+            const double g1 = sqrt(1.0 + (ux[j] * ux[j] + uy[j] * uy[j] + uz[j] * uz[j]));
+            *at_off(C.x, off) = x[j] + dt * ux[j] / g1;
+            *at_off(C.y, off) = y[j] + dt * uy[j] / g1;
+            if (d3) *at_off(C.z, off) = z[j] + dt * uz[j] / g1;
+            if (!isfinite(g1)) ++uacc[2];
+          } else {
+            const float g1 = sqrtf(1.0f + ((float)ux[j] * (float)ux[j] + (float)uy[j] * (float)uy[j] +
+                                           (float)uz[j] * (float)uz[j]));
+            float xh = (float)x[j], xlo = xl[j], yh = (float)y[j], ylo = yl[j];
+            comp_add(xh, xlo, dtf * (float)ux[j] / g1);
+            comp_add(yh, ylo, dtf * (float)uy[j] / g1);
+            *at_off(C.x, off) = (Real)xh;
+            *at_off(C.xl, off) = xlo;
+            *at_off(C.y, off) = (Real)yh;
+            *at_off(C.yl, off) = ylo;
+            if (d3) {
+              float zh = (float)z[j], zlo = zl[j];
+              comp_add(zh, zlo, dtf * (float)uz[j] / g1);
+              *at_off(C.z, off) = (Real)zh;
+              *at_off(C.zl, off) = zlo;
+            }
+            if (!isfinite(g1)) ++uacc[2];
+          }
+        }
+      }
+      // phase 2: the leptons inside the pulse, state re-read (from cache) one at a time
+#pragma unroll 1
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        bool pend = false;
+        double eta = 0.0;
+        if (gmask & (1u << j)) {
+          ++uacc[0];
+          pend = full(off, &eta);
+        }
+        enqueue(off, pend, eta);
+      }
+    } else {
+#pragma unroll 1
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        bool pend = false;
+        double eta = 0.0;
+        if ((int64_t)off < rem) {
+          ++uacc[0];
+          pend = full(off, &eta);
+        }
+        enqueue(off, pend, eta);
+      }
+    }
+  }
+  if (cur >= 0) flush(cur);
+}
+
+// Emission by the queued leptons: chi from the 2-D inverse CDF at the emitter's eta, photon
+// momentum (2 chi / eta) u along the emitter's momentum, recoil, photon appended at the
+// emitter's post-push position (born at the start of the next step), new optical depth.
+template <int FK, bool MIXED>
+__global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
+  using Real = typename std::conditional<MIXED, float, double>::type;
+  const int64_t step = a.glob->step_cur;
+  const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t cnt = min(a.qe.ctl->count, a.qe.cap);
+  const int lane = threadIdx.x % 64;
+  for (int64_t e0 = gtid - lane; e0 < cnt; e0 += stride) {  // whole waves iterate together
+    const int64_t e = e0 + lane;
+    const bool want = e < cnt;
+    EmitEv ev{0, 0.0};
+    if (want) ev = a.qe.ent[e];
+    const int ii = (int)(ev.key >> 41), sp = (int)((ev.key >> 40) & 1);
+    const int64_t k = (int64_t)(ev.key & ((1ull << 40) - 1));
+    const qed_instance& I = a.inst[ii];
+    const qed_species& S = I.s[sp];
+    const qed_species& G = I.s[2];
+    const bool d3 = I.dims == 3;
+    bool child = false;
+    double defect = 0.0, cx = 0, cy = 0, cz = 0, ckx = 0, cky = 0, ckz = 0, ctau = 0;
+    uint64_t cuid = 0;
+    unsigned n_null = 0;
+    if (want) {
+      uint64_t r[4];
+      philox4x64_10(S.uid_dev[k], (uint64_t)step, KIND_EMIT, 0, I.seed, I.key_instance, r);
+      gptr<Real> UX = as_global((Real*)S.ux_dev), UY = as_global((Real*)S.uy_dev), UZ = as_global((Real*)S.uz_dev);
+      double ux1, uy1, uz1;
+      if (MIXED) {
+        ux1 = (double)UX[k] + S.ux_lo_dev[k];
+        uy1 = (double)UY[k] + S.uy_lo_dev[k];
+        uz1 = (double)UZ[k] + S.uz_lo_dev[k];
+      } else {
+        ux1 = UX[k];
+        uy1 = UY[k];
+        uz1 = UZ[k];
+      }
+      const double g1 = sqrt(1.0 + (ux1 * ux1 + uy1 * uy1 + uz1 * uz1));
+      double chi;
+      if (sample_chi(a.tb, ev.eta, unit_open(r[0]), &chi)) {
+        const double xi = 2.0 * chi / ev.eta;
+        double ux, uy, uz;
+        if (MIXED) {
+          // the emitter loses exactly the stored (FP32) photon momentum
+          ckx = (float)(xi * ux1);
+          cky = (float)(xi * uy1);
+          ckz = (float)(xi * uz1);
+          float h, l;
+          split_double(ux1 - ckx, h, l); UX[k] = h; S.ux_lo_dev[k] = l; ux = (double)h + l;
+          split_double(uy1 - cky, h, l); UY[k] = h; S.uy_lo_dev[k] = l; uy = (double)h + l;
+          split_double(uz1 - ckz, h, l); UZ[k] = h; S.uz_lo_dev[k] = l; uz = (double)h + l;
+          cx = (double)((const float*)S.x_dev)[k] + S.x_lo_dev[k];
+          cy = (double)((const float*)S.y_dev)[k] + S.y_lo_dev[k];
+          cz = d3 ? (double)((const float*)S.z_dev)[k] + S.z_lo_dev[k] : 0.0;
+        } else {
+          ckx = xi * ux1;
+          cky = xi * uy1;
+          ckz = xi * uz1;
+          ux = ux1 - ckx;
+          uy = uy1 - cky;
+          uz = uz1 - ckz;
+          UX[k] = ux;
+          UY[k] = uy;
+          UZ[k] = uz;
+          cx = ((const double*)S.x_dev)[k];
+          cy = ((const double*)S.y_dev)[k];
+          cz = d3 ? ((const double*)S.z_dev)[k] : 0.0;
+        }
+        const double g2 = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
+        const double eps = sqrt(ckx * ckx + cky * cky + ckz * ckz);
+        defect = g2 + eps - g1;
+        child = true;
+        ctau = optical_depth(r[3]);
+        cuid = r[2];
+      } else {
+        n_null = 1;
+      }
+      S.tau_dev[k] = optical_depth(r[1]);
+    }
+    const long long slot = wave_reserve_grouped(child, ii, G.count_dev);
+    double dropped_e = 0.0;
+    unsigned n_drop = 0;
+    if (child) {
+      if (slot < G.capacity) {
+        if (MIXED) {
+          ((float*)G.x_dev)[slot] = (float)cx;
+          ((float*)G.y_dev)[slot] = (float)cy;
+          if (d3) ((float*)G.z_dev)[slot] = (float)cz;
+          ((float*)G.ux_dev)[slot] = (float)ckx;
+          ((float*)G.uy_dev)[slot] = (float)cky;
+          ((float*)G.uz_dev)[slot] = (float)ckz;
+        } else {
           ((double*)G.x_dev)[slot] = cx;
           ((double*)G.y_dev)[slot] = cy;
           if (d3) ((double*)G.z_dev)[slot] = cz;
           ((double*)G.ux_dev)[slot] = ckx;
           ((double*)G.uy_dev)[slot] = cky;
           ((double*)G.uz_dev)[slot] = ckz;
-          G.tau_dev[slot] = ctau;
-          G.uid_dev[slot] = cuid;
-          G.birth_step_dev[slot] = (int32_t)(step + 1);
-        } else {
-          ++uacc[4];
-          dacc[2] += sqrt(ckx * ckx + cky * cky + ckz * ckz);
         }
+        G.tau_dev[slot] = ctau;
+        G.uid_dev[slot] = cuid;
+        G.birth_step_dev[slot] = (int32_t)(step + 1);
+      } else {
+        n_drop = 1;
+        dropped_e = sqrt(ckx * ckx + cky * cky + ckz * ckz);
       }
     }
-    block_sum(dacc, uacc, sred, sredu);
-    if (threadIdx.x == 0) {
-      InstAcc& A = a.acc[ii];
-      if (dacc[0] != 0.0) atomicAdd(&A.work, dacc[0]);
-      if (dacc[1] != 0.0) atomicAdd(&A.defect_emit, dacc[1]);
-      if (dacc[2] != 0.0) atomicAdd(&A.dropped_energy, dacc[2]);
-      if (uacc[0]) atomicAdd(&A.n_emit, (unsigned long long)uacc[0]);
-      if (uacc[1]) atomicAdd(&A.n_null, (unsigned long long)uacc[1]);
-      if (uacc[2]) atomicAdd(&A.n_range, (unsigned long long)uacc[2]);
-      if (uacc[3]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[3]);
-      if (uacc[4]) atomicAdd(&A.n_dropped, (unsigned long long)uacc[4]);
-    }
+    add_event_stats(0, want, ii, a.acc, defect, dropped_e, child ? 1u : 0u, n_null, n_drop);
   }
 }
 
@@ -520,6 +813,8 @@ __device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k,
   const qed_species& S = I.s[2];
   const bool d3 = I.dims == 3;
   double px = 0, py = 0, pz = 0, etau = 0, ptau = 0, ex = 0, ey = 0, ez = 0, pkx = 0, pky = 0, pkz = 0;
+  double defect = 0.0, dropped_e = 0.0;
+  unsigned n_drop = 0;
   uint64_t euid = 0, puid = 0;
   if (want) {
     const Real kxr = ((const Real*)S.ux_dev)[k], kyr = ((const Real*)S.uy_dev)[k], kzr = ((const Real*)S.uz_dev)[k];
@@ -580,9 +875,7 @@ __device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k,
     etau = optical_depth(r0[3]);
     ptau = optical_depth(r1[0]);
     S.tau_dev[k] = kTauGone;
-    InstAcc& A = a.acc[ii];
-    atomicAdd(&A.defect_pair, gp + ge - epsd);
-    atomicAdd(&A.n_pair, 1ull);
+    defect = gp + ge - epsd;
   }
   // append electron and positron, one atomic per wave and instance
   const qed_species& Se = I.s[0];
@@ -590,20 +883,20 @@ __device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k,
   const long long se = wave_reserve_grouped(want, ii, Se.count_dev);
   const long long spo = wave_reserve_grouped(want, ii, Sp.count_dev);
   if (want) {
-    InstAcc& A = a.acc[ii];
     if (se < Se.capacity) {
       write_lepton<MIXED>(Se, se, px, py, pz, ex, ey, ez, etau, euid, d3);
     } else {
-      atomicAdd(&A.n_dropped, 1ull);
-      atomicAdd(&A.dropped_energy, sqrt(1.0 + (ex * ex + ey * ey + ez * ez)));
+      ++n_drop;
+      dropped_e += sqrt(1.0 + (ex * ex + ey * ey + ez * ez));
     }
     if (spo < Sp.capacity) {
       write_lepton<MIXED>(Sp, spo, px, py, pz, pkx, pky, pkz, ptau, puid, d3);
     } else {
-      atomicAdd(&A.n_dropped, 1ull);
-      atomicAdd(&A.dropped_energy, sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz)));
+      ++n_drop;
+      dropped_e += sqrt(1.0 + (pkx * pkx + pky * pky + pkz * pkz));
     }
   }
+  add_event_stats(1, want, ii, a.acc, defect, dropped_e, want ? 1u : 0u, 0u, n_drop);
 }
 
 // Event pass: the queued photons, or, when the queue overflowed, every photon whose optical
@@ -835,8 +1128,21 @@ hipError_t init_crmath() {
 }
 template <int FK>
 static void launch_lepton_fk(const StepArgs& a, dim3 grid, dim3 block, size_t shm, hipStream_t s, bool mixed) {
-  if (mixed) hipLaunchKernelGGL(k_lepton_f32<FK>, grid, block, shm, s, a);
-  else hipLaunchKernelGGL(k_lepton_f64<FK>, grid, block, shm, s, a);
+#define QED_LEP(P)                                                                   \
+  if (mixed) hipLaunchKernelGGL((k_lepton<FK, P, true>), grid, block, shm, s, a); \
+  else hipLaunchKernelGGL((k_lepton<FK, P, false>), grid, block, shm, s, a);
+  switch (a.ppt) {
+    case 1: QED_LEP(1) break;
+    case 2: QED_LEP(2) break;
+    case 8: QED_LEP(8) break;
+    default: QED_LEP(4) break;
+  }
+#undef QED_LEP
+}
+template <int FK>
+static void launch_emit_events_fk(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s, bool mixed) {
+  if (mixed) hipLaunchKernelGGL((k_emit_events<FK, true>), grid, block, 0, s, a);
+  else hipLaunchKernelGGL((k_emit_events<FK, false>), grid, block, 0, s, a);
 }
 template <int FK>
 static void launch_pair_events_fk(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s, bool mixed) {
@@ -858,9 +1164,9 @@ static void launch_photon_fk(const StepArgs& a, dim3 grid, dim3 block, size_t sh
   }
 }
 
-void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, int64_t* base_lep,
-                       int64_t* base_ph, int chunk_lep, int chunk_ph, int advance, hipStream_t s) {
-  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, inst, n_inst, acc, glob, evc, base_lep, base_ph,
+void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,
+                       int64_t* base_lep, int64_t* base_ph, int chunk_lep, int chunk_ph, int advance, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, inst, n_inst, acc, glob, evc, emc, base_lep, base_ph,
                      chunk_lep, chunk_ph, advance);
 }
 
@@ -872,9 +1178,19 @@ void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob,
   hipLaunchKernelGGL(k_grid_refresh, dim3(2048), dim3(256), 0, s, inst, n_inst, glob, sc);
 }
 
+void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
+  const dim3 g(grid), b(block);
+  switch (fk) {
+    case QED_FIELD_UNIFORM: launch_emit_events_fk<QED_FIELD_UNIFORM>(a, g, b, s, mixed); break;
+    case QED_FIELD_LP_PULSE: launch_emit_events_fk<QED_FIELD_LP_PULSE>(a, g, b, s, mixed); break;
+    case QED_FIELD_CP_WAVE: launch_emit_events_fk<QED_FIELD_CP_WAVE>(a, g, b, s, mixed); break;
+    case QED_FIELD_CP_STANDING: launch_emit_events_fk<QED_FIELD_CP_STANDING>(a, g, b, s, mixed); break;
+    default: launch_emit_events_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, s, mixed); break;
+  }
+}
+
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
-  const size_t shm = (size_t)a.tb.n_eta * (mixed ? sizeof(float) : sizeof(double)) + 16 * 3 * sizeof(double) +
-                     16 * 5 * sizeof(unsigned) + 64;
+  const size_t shm = (size_t)a.tb.n_eta * sizeof(double) + 16 * sizeof(double) + 16 * 3 * sizeof(unsigned) + 64;
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_lepton_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;

@@ -209,7 +209,7 @@ class Run:
         capi.qed_profile(self.ws, enable)
 
     def profile_read(self):
-        """(ms, launches) per kernel class: [set-up, lepton, photon sweep, pair events]."""
+        """(ms, launches) per kernel class: [set-up, lepton sweep, photon sweep, pair events, emission events]."""
         return capi.qed_profile_read(self.ws)
 
     def synchronize(self):
