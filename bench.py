@@ -34,9 +34,12 @@ def log(msg):
 def kernel_bytes(form, kind, led0, led1):
     """Algorithmic HBM bytes of one kernel class over the timed region.
 
-    Leptons, per particle-step: 56 B read (x, u, tau) + 56 B written in FP64 (FP32-mixed: the
-    same 112 B as hi/lo words of position and momentum plus the FP64 tau); per event the
-    emitter's uid (8 B) and the photon record written (FP64 68 B, FP32-mixed 44 B).
+    Lepton sweep, per particle-step in 3-D: with the full push 56 B read (x, u, tau) + 56 B
+    written in FP64 (FP32-mixed: the same 112 B as hi/lo words of position and momentum plus
+    the FP64 tau); outside the plane-wave pulse (field-free drift) x and u read, x written:
+    72 B in FP64, 60 B in FP32-mixed (hi/lo position, high words of u); + 16 B per queued
+    emission event.  The emission pass (separate class) reads the event's lepton and writes the
+    photon.
     Photon sweep, per photon slot-step, with a field that depends on x only (the plane-wave
     pulse): k (3 words), x at birth (1 word) and the birth step (4 B): 36 B in FP64, 20 B in
     FP32-mixed; + 16 B (tau read and written) for the photons that see a non-zero pair rate;
@@ -45,8 +48,9 @@ def kernel_bytes(form, kind, led0, led1):
     d = lambda k, i=None: (led1[k][i] - led0[k][i]) if i is not None else (led1[k] - led0[k])
     if kind == "lepton":
         steps = d("particle_steps", 0) + d("particle_steps", 1)
-        per, child = (112, 68) if form == "fp64" else (112, 44)
-        return steps * per + (d("n_emit") + d("n_null")) * 8 + d("n_emit") * child
+        full = d("lepton_steps_in_field")
+        drift = 72 if form == "fp64" else 60
+        return full * 112 + (steps - full) * drift + (d("n_emit") + d("n_null")) * 16
     steps = d("particle_steps", 2)
     base = 36 if form == "fp64" else 20
     return steps * base + d("photon_steps_in_field") * 16 + d("n_pair") * 8
@@ -127,11 +131,13 @@ def run_form(form, args, tables):
     status = sorted(set(l["status"] for l in led1))
     res = dict(form=form, workload=workload, n_inst=n_inst, seconds=t1 - t0, particle_steps=int(psteps),
                value=psteps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / args.steps,
-               kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2], pair_events=ms[3]),
-               launches=dict(setup=launches[0], lepton=launches[1], photon=launches[2], pair_events=launches[3]),
+               kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2], pair_events=ms[3], emit_events=ms[4]),
+               launches=dict(setup=launches[0], lepton=launches[1], photon=launches[2], pair_events=launches[3],
+                             emit_events=launches[4]),
                photons_end=int(agg1["count"][2]), pairs=int(agg1["n_pair"] - agg0["n_pair"]),
                emissions=int(agg1["n_emit"] - agg0["n_emit"]), drift_max=max(l["drift"] for l in led1),
                photon_steps_in_field=int(agg1["photon_steps_in_field"] - agg0["photon_steps_in_field"]),
+               lepton_steps_in_field=int(agg1["lepton_steps_in_field"] - agg0["lepton_steps_in_field"]),
                status=status)
     kind = "photon" if ms[2] >= ms[1] else "lepton"
     byts = kernel_bytes(form, kind, agg0, agg1)
@@ -139,7 +145,7 @@ def run_form(form, args, tables):
     avg_s = (ms[2] if kind == "photon" else ms[1]) / max(n_l, 1) * 1e-3
     achieved = byts / max(n_l, 1) / avg_s / 1e9
     traffic = measured_traffic(kind, form)
-    res["roofline"] = {"kernel": "k_%s<%s>" % (kind, form), "bound": "hbm",
+    res["roofline"] = {"kernel": "k_%s (%s)" % (kind, form), "bound": "hbm",
                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                        "traffic": traffic, "algorithmic_bytes_per_launch": byts / max(n_l, 1),
                        "mean_launch_us": avg_s * 1e6}
@@ -151,7 +157,7 @@ def run_form(form, args, tables):
 
 def _aggregate(leds):
     out = {"particle_steps": [0, 0, 0], "count": [0, 0, 0]}
-    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field"):
+    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field", "lepton_steps_in_field"):
         out[k] = sum(l[k] for l in leds)
     for i in range(3):
         out["particle_steps"][i] = sum(l["particle_steps"][i] for l in leds)
@@ -191,6 +197,8 @@ def main():
     ap.add_argument("--forms", default="fp64", help="comma list of fp64, fp32, batched; the first is `value`")
     ap.add_argument("--cpu-families", type=int, default=1500)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain device copy of 1 GiB, 20 times (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the QED step shards by particle family with no per-step "
@@ -199,6 +207,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        n = 1 << 27
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(20):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 20}))
+        return
     from paper_1311_5551_amd.sim import Tables
     torch.cuda.set_device(0)
     log("building tables on the GPU")

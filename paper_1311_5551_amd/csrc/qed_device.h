@@ -53,6 +53,40 @@ __device__ __forceinline__ T* uni_ptr(T* p) {
 }
 __device__ __forceinline__ double uni_f64(double v) { return __longlong_as_double(uni64(__double_as_longlong(v))); }
 
+// Raw buffer access: a scalar resource (base, size in bytes) plus a 32-bit lane byte offset.
+// Loads at or past the size return zero and stores there are dropped, in hardware.  Word 3 of
+// the resource is the gfx9-family value for untyped (raw) access.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef __amdgpu_buffer_rsrc_t bufres;
+constexpr int kBufWord3 = 0x00020000;
+// (base and size are made explicitly uniform: a resource must live in scalar registers)
+template <class P>
+__device__ __forceinline__ bufres make_buf(P base, uint32_t bytes) {
+  const uint64_t b = (uint64_t)uni64((int64_t)(uintptr_t)base);
+  return __builtin_amdgcn_make_buffer_rsrc((void*)(uintptr_t)b, (short)0, uni32((int)bytes), kBufWord3);
+}
+template <class T>
+__device__ __forceinline__ T buf_ld(bufres r, uint32_t byte_off);
+template <>
+__device__ __forceinline__ double buf_ld<double>(bufres r, uint32_t o) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0));
+}
+template <>
+__device__ __forceinline__ float buf_ld<float>(bufres r, uint32_t o) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0));
+}
+template <>
+__device__ __forceinline__ int32_t buf_ld<int32_t>(bufres r, uint32_t o) {
+  return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
+}
+__device__ __forceinline__ void buf_st(bufres r, uint32_t o, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, o, 0, 0);
+}
+__device__ __forceinline__ void buf_st(bufres r, uint32_t o, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, o, 0, 0);
+}
+
+
 // Device copy of the tables plus their grid constants.
 struct Tabs {
   int n_eta;

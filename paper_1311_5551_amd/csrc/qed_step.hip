@@ -224,22 +224,36 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
     }
     const int64_t k0 = uni64((c - cb) * CH);
     const int64_t rem = n - k0;
-    LepPtr<MIXED> C;  // chunk-base pointers
-    C.x = P.x + k0; C.y = P.y + k0; C.z = P.z + k0;
-    C.ux = P.ux + k0; C.uy = P.uy + k0; C.uz = P.uz + k0;
+    // buffer resources over the chunk's live slots (uniform); lane offsets in bytes
+    const uint32_t nlive = (uint32_t)(rem < CH ? rem : CH);
+    const uint32_t rb = nlive * (uint32_t)sizeof(Real);
+    struct {
+      bufres x, y, z, ux, uy, uz, xl, yl, zl, uxl, uyl, uzl, tau;
+    } C;
+    C.x = make_buf(P.x + k0, rb);
+    C.y = make_buf(P.y + k0, rb);
+    C.z = make_buf(P.z + k0, d3 ? rb : 0u);
+    C.ux = make_buf(P.ux + k0, rb);
+    C.uy = make_buf(P.uy + k0, rb);
+    C.uz = make_buf(P.uz + k0, rb);
     if (MIXED) {
-      C.xl = P.xl + k0; C.yl = P.yl + k0; C.zl = P.zl + k0;
-      C.uxl = P.uxl + k0; C.uyl = P.uyl + k0; C.uzl = P.uzl + k0;
+      C.xl = make_buf(P.xl + k0, nlive * 4u);
+      C.yl = make_buf(P.yl + k0, nlive * 4u);
+      C.zl = make_buf(P.zl + k0, d3 ? nlive * 4u : 0u);
+      C.uxl = make_buf(P.uxl + k0, nlive * 4u);
+      C.uyl = make_buf(P.uyl + k0, nlive * 4u);
+      C.uzl = make_buf(P.uzl + k0, nlive * 4u);
     }
-    C.tau = P.tau + k0;
+    C.tau = make_buf(P.tau + k0, nlive * 8u);
+    constexpr uint32_t SR = sizeof(Real);
 
     // full step of one lepton; returns true (and its eta) when its optical depth reached zero
     auto full = [&](unsigned off, double* eta_out) -> bool {
       bool pend = false;
       if (!MIXED) {
-        double x = *at_off(C.x, off), y = *at_off(C.y, off), z = d3 ? *at_off(C.z, off) : 0.0;
-        const double ux = *at_off(C.ux, off), uy = *at_off(C.uy, off), uz = *at_off(C.uz, off);
-        double tau = *at_off(C.tau, off);
+        double x = buf_ld<Real>(C.x, off * SR), y = buf_ld<Real>(C.y, off * SR), z = d3 ? buf_ld<Real>(C.z, off * SR) : 0.0;
+        const double ux = buf_ld<Real>(C.ux, off * SR), uy = buf_ld<Real>(C.uy, off * SR), uz = buf_ld<Real>(C.uz, off * SR);
+        double tau = buf_ld<double>(C.tau, off * 8u);
         double E[3], Bf[3];
         field_at<FK>(sF, x, y, t, E, Bf);
         const double g0 = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
@@ -275,19 +289,19 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
           }
         }
         if (!isfinite(tau) || !isfinite(u1x) || !isfinite(u1y) || !isfinite(u1z)) ++uacc[2];
-        *at_off(C.x, off) = x;
-        *at_off(C.y, off) = y;
-        if (d3) *at_off(C.z, off) = z;
-        *at_off(C.ux, off) = u1x;
-        *at_off(C.uy, off) = u1y;
-        *at_off(C.uz, off) = u1z;
-        *at_off(C.tau, off) = tau;
+        buf_st(C.x, off * SR, (Real)(x));
+        buf_st(C.y, off * SR, (Real)(y));
+        if (d3) buf_st(C.z, off * SR, (Real)(z));
+        buf_st(C.ux, off * SR, (Real)(u1x));
+        buf_st(C.uy, off * SR, (Real)(u1y));
+        buf_st(C.uz, off * SR, (Real)(u1z));
+        buf_st(C.tau, off * 8u, (double)(tau));
       } else {
-        float xh = *at_off(C.x, off), xl = *at_off(C.xl, off), yh = *at_off(C.y, off), yl = *at_off(C.yl, off);
-        float zh = d3 ? *at_off(C.z, off) : 0.0f, zl = d3 ? *at_off(C.zl, off) : 0.0f;
-        float uxh = *at_off(C.ux, off), uxl = *at_off(C.uxl, off), uyh = *at_off(C.uy, off),
-              uyl = *at_off(C.uyl, off), uzh = *at_off(C.uz, off), uzl = *at_off(C.uzl, off);
-        double tau = *at_off(C.tau, off);
+        float xh = buf_ld<Real>(C.x, off * SR), xl = buf_ld<float>(C.xl, off * 4u), yh = buf_ld<Real>(C.y, off * SR), yl = buf_ld<float>(C.yl, off * 4u);
+        float zh = d3 ? buf_ld<Real>(C.z, off * SR) : 0.0f, zl = d3 ? buf_ld<float>(C.zl, off * 4u) : 0.0f;
+        float uxh = buf_ld<Real>(C.ux, off * SR), uxl = buf_ld<float>(C.uxl, off * 4u), uyh = buf_ld<Real>(C.uy, off * SR),
+              uyl = buf_ld<float>(C.uyl, off * 4u), uzh = buf_ld<Real>(C.uz, off * SR), uzl = buf_ld<float>(C.uzl, off * 4u);
+        double tau = buf_ld<double>(C.tau, off * 8u);
         const double ux0 = (double)uxh + uxl, uy0 = (double)uyh + uyl, uz0 = (double)uzh + uzl;
         const double g0d = sqrt(1.0 + (ux0 * ux0 + uy0 * uy0 + uz0 * uz0));
         float E[3], Bf[3];
@@ -329,21 +343,21 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
           }
         }
         if (!isfinite(tau) || !isfinite(uxh) || !isfinite(uyh) || !isfinite(uzh)) ++uacc[2];
-        *at_off(C.x, off) = xh;
-        *at_off(C.xl, off) = xl;
-        *at_off(C.y, off) = yh;
-        *at_off(C.yl, off) = yl;
+        buf_st(C.x, off * SR, (Real)(xh));
+        buf_st(C.xl, off * 4u, (float)(xl));
+        buf_st(C.y, off * SR, (Real)(yh));
+        buf_st(C.yl, off * 4u, (float)(yl));
         if (d3) {
-          *at_off(C.z, off) = zh;
-          *at_off(C.zl, off) = zl;
+          buf_st(C.z, off * SR, (Real)(zh));
+          buf_st(C.zl, off * 4u, (float)(zl));
         }
-        *at_off(C.ux, off) = uxh;
-        *at_off(C.uxl, off) = uxl;
-        *at_off(C.uy, off) = uyh;
-        *at_off(C.uyl, off) = uyl;
-        *at_off(C.uz, off) = uzh;
-        *at_off(C.uzl, off) = uzl;
-        *at_off(C.tau, off) = tau;
+        buf_st(C.ux, off * SR, (Real)(uxh));
+        buf_st(C.uxl, off * 4u, (float)(uxl));
+        buf_st(C.uy, off * SR, (Real)(uyh));
+        buf_st(C.uyl, off * 4u, (float)(uyl));
+        buf_st(C.uz, off * SR, (Real)(uzh));
+        buf_st(C.uzl, off * 4u, (float)(uzl));
+        buf_st(C.tau, off * 8u, (double)(tau));
       }
       return pend;
     };
@@ -365,20 +379,18 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
       Real x[PPT], y[PPT], z[PPT], ux[PPT], uy[PPT], uz[PPT];
       float xl[PPT], yl[PPT], zl[PPT];
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
+      for (int j = 0; j < PPT; ++j) {  // slots past the chunk's live ones read as zero
         const unsigned off = threadIdx.x + j * B;
-        if ((int64_t)off < rem) {
-          x[j] = *at_off(C.x, off);
-          y[j] = *at_off(C.y, off);
-          z[j] = d3 ? *at_off(C.z, off) : Real(0);
-          ux[j] = *at_off(C.ux, off);
-          uy[j] = *at_off(C.uy, off);
-          uz[j] = *at_off(C.uz, off);
-          if (MIXED) {
-            xl[j] = *at_off(C.xl, off);
-            yl[j] = *at_off(C.yl, off);
-            zl[j] = d3 ? *at_off(C.zl, off) : 0.0f;
-          }
+        x[j] = buf_ld<Real>(C.x, off * SR);
+        y[j] = buf_ld<Real>(C.y, off * SR);
+        z[j] = buf_ld<Real>(C.z, off * SR);
+        ux[j] = buf_ld<Real>(C.ux, off * SR);
+        uy[j] = buf_ld<Real>(C.uy, off * SR);
+        uz[j] = buf_ld<Real>(C.uz, off * SR);
+        if (MIXED) {
+          xl[j] = buf_ld<float>(C.xl, off * 4u);
+          yl[j] = buf_ld<float>(C.yl, off * 4u);
+          zl[j] = buf_ld<float>(C.zl, off * 4u);
         }
       }
       const float tpf = (float)t - tpf0;
@@ -395,9 +407,9 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
             gmask |= 1u << j;
           } else if (!MIXED) {
             const double g1 = sqrt(1.0 + (ux[j] * ux[j] + uy[j] * uy[j] + uz[j] * uz[j]));
-            *at_off(C.x, off) = x[j] + dt * ux[j] / g1;
-            *at_off(C.y, off) = y[j] + dt * uy[j] / g1;
-            if (d3) *at_off(C.z, off) = z[j] + dt * uz[j] / g1;
+            buf_st(C.x, off * SR, (Real)(x[j] + dt * ux[j] / g1));
+            buf_st(C.y, off * SR, (Real)(y[j] + dt * uy[j] / g1));
+            if (d3) buf_st(C.z, off * SR, (Real)(z[j] + dt * uz[j] / g1));
             if (!isfinite(g1)) ++uacc[2];
           } else {
             const float g1 = sqrtf(1.0f + ((float)ux[j] * (float)ux[j] + (float)uy[j] * (float)uy[j] +
@@ -405,15 +417,15 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
             float xh = (float)x[j], xlo = xl[j], yh = (float)y[j], ylo = yl[j];
             comp_add(xh, xlo, dtf * (float)ux[j] / g1);
             comp_add(yh, ylo, dtf * (float)uy[j] / g1);
-            *at_off(C.x, off) = (Real)xh;
-            *at_off(C.xl, off) = xlo;
-            *at_off(C.y, off) = (Real)yh;
-            *at_off(C.yl, off) = ylo;
+            buf_st(C.x, off * SR, (Real)((Real)xh));
+            buf_st(C.xl, off * 4u, (float)(xlo));
+            buf_st(C.y, off * SR, (Real)((Real)yh));
+            buf_st(C.yl, off * 4u, (float)(ylo));
             if (d3) {
               float zh = (float)z[j], zlo = zl[j];
               comp_add(zh, zlo, dtf * (float)uz[j] / g1);
-              *at_off(C.z, off) = (Real)zh;
-              *at_off(C.zl, off) = zlo;
+              buf_st(C.z, off * SR, (Real)((Real)zh));
+              buf_st(C.zl, off * 4u, (float)(zlo));
             }
             if (!isfinite(g1)) ++uacc[2];
           }
@@ -642,10 +654,12 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     const int64_t k0 = uni64((c - cb) * CH);  // first slot of the chunk
     const int64_t rem = n - k0;        // slots of the chunk that exist: min(rem, CH)
 
-    // chunk-base pointers are uniform, lane offsets 32-bit
-    const gptr<const Real> kxc = KX + k0, kyc = KY + k0, kzc = KZ + k0, xbc = XB + k0, ybc = YB + k0;
-    const gptr<const int32_t> bsc = BS + k0;
-    const gptr<double> tauc = TAU + k0;
+    // buffer resources over the chunk's live slots (uniform); lane offsets in bytes
+    const uint32_t nlive = (uint32_t)(rem < CH ? rem : CH);
+    const bufres rkx = make_buf(KX + k0, nlive * sizeof(Real)), rky = make_buf(KY + k0, nlive * sizeof(Real)),
+                 rkz = make_buf(KZ + k0, nlive * sizeof(Real)), rxb = make_buf(XB + k0, nlive * sizeof(Real)),
+                 ryb = make_buf(YB + k0, nlive * sizeof(Real)), rbs = make_buf(BS + k0, nlive * 4u),
+                 rtau = make_buf(TAU + k0, nlive * 8u);
     const double tt = t;
     // in-field part for one photon; true when its optical depth reached zero
     auto infield = [&](unsigned off, Real kx, Real ky, Real kz, Real xb, Real yb, int32_t bs) -> bool {
@@ -683,7 +697,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       }
       bool pend = false;
       if (T > 0.0) {
-        double tau = *at_off(tauc, off);
+        double tau = buf_ld<double>(rtau, off * 8u);
         if (!(tau < 0.0)) {  // tau < 0: converted in an earlier step
           ++uacc[0];
           tau -= MIXED ? (double)((float)rate * (float)chi * (float)T * (float)inv) : rate * chi * T * (double)inv;
@@ -692,7 +706,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
             tau = fmax(tau, kTauPendingMin);
           }
           if (!isfinite(tau)) ++uacc[2];
-          *at_off(tauc, off) = tau;
+          buf_st(rtau, off * 8u, tau);
         }
       }
       return pend;
@@ -715,13 +729,12 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         const unsigned off = threadIdx.x + j * B;
-        if ((int64_t)off < rem) {
-          kxf[j] = (float)*at_off(kxc, off);
-          kyf[j] = (float)*at_off(kyc, off);
-          kzf[j] = (float)*at_off(kzc, off);
-          xbf[j] = (float)*at_off(xbc, off);
-          bs[j] = *at_off(bsc, off);
-        }
+        const uint32_t o = off * (uint32_t)sizeof(Real);
+        kxf[j] = (float)buf_ld<Real>(rkx, o);
+        kyf[j] = (float)buf_ld<Real>(rky, o);
+        kzf[j] = (float)buf_ld<Real>(rkz, o);
+        xbf[j] = (float)buf_ld<Real>(rxb, o);
+        bs[j] = buf_ld<int32_t>(rbs, off * 4u);
       }
       const float tpf = (float)t - tpf0;
       const float mt = fabsf((float)t) + fabsf(tpf0);
@@ -743,9 +756,11 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       for (int j = 0; j < PPT; ++j) {
         const unsigned off = threadIdx.x + j * B;
         bool pend = false;
-        if (gmask & (1u << j))
-          pend = infield(off, *at_off(kxc, off), *at_off(kyc, off), *at_off(kzc, off), *at_off(xbc, off), Real(0),
-                         *at_off(bsc, off));
+        if (gmask & (1u << j)) {
+          const uint32_t o = off * (uint32_t)sizeof(Real);
+          pend = infield(off, buf_ld<Real>(rkx, o), buf_ld<Real>(rky, o), buf_ld<Real>(rkz, o), buf_ld<Real>(rxb, o),
+                         Real(0), buf_ld<int32_t>(rbs, off * 4u));
+        }
         enqueue(off, pend);
       }
     } else {
@@ -754,16 +769,15 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         const unsigned off = threadIdx.x + j * B;
-        if ((int64_t)off < rem) {
-          kx[j] = *at_off(kxc, off);
-          ky[j] = *at_off(kyc, off);
-          kz[j] = *at_off(kzc, off);
-          if (NEED_X) {
-            xb[j] = *at_off(xbc, off);
-            bs[j] = *at_off(bsc, off);
-          }
-          if (NEED_Y) yb[j] = *at_off(ybc, off);
+        const uint32_t o = off * (uint32_t)sizeof(Real);
+        kx[j] = buf_ld<Real>(rkx, o);
+        ky[j] = buf_ld<Real>(rky, o);
+        kz[j] = buf_ld<Real>(rkz, o);
+        if (NEED_X) {
+          xb[j] = buf_ld<Real>(rxb, o);
+          bs[j] = buf_ld<int32_t>(rbs, off * 4u);
         }
+        if (NEED_Y) yb[j] = buf_ld<Real>(ryb, o);
       }
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
