@@ -77,60 +77,148 @@ def measured_traffic(kernel, form):
     return d.get("bytes_per_launch")
 
 
-def run_form(form, args, tables):
-    import torch
+def tune_launch(form, args, tables):
+    """Autotuned sweep launch shapes for a form: the tuner runs on a separate run of the same
+    collision (tune_scale times the electrons; the best shape depends on the population size, so
+    full size by default), at points spread over the run (before, during and after the
+    collision), and each kernel gets the shape with the smallest population-weighted sum of its
+    per-particle times over the points, an estimate of its total time in the run."""
+    from paper_1311_5551_amd import autotune, capi, workloads as W
+    from paper_1311_5551_amd.sim import Run
+    prec = capi.QED_FP64 if form == "fp64" else capi.QED_FP32_MIXED
+    w = W.collision_config2(n=max(int(args.electrons * args.tune_scale), 1000), n_steps=20000)
+    run = Run(w, tables, precision=prec)
+    points = [int(x) for x in args.tune_at.split(",")]
+    log("%s: autotuning launch shapes on a %d-electron replica at steps %s" % (form, w.n, points))
+    results = []
+    for p in points:
+        while run.step_index < p:
+            run.step(1)
+            if run.step_index % args.compact_every == 0:
+                run.compact()
+        results.append(autotune.tune(run, steps_per_trial=6, rounds=2, min_particles=1000))
+    res = autotune.combine(results)
+    autotune.apply(run, res)
+    run.close()
+    log("%s: tuned lepton %s photon %s" % (form, res["lepton"], res["photon"]))
+    return res
+
+
+def size_batched(ws, tables, args, probe_n=64):
+    """Buffer capacities of the batched instances from a probe run: the first `probe_n`
+    electrons of every instance (the same families as in the full run) through the whole
+    window; each species gets 1.3x its probe yield per initial electron plus a margin."""
     from paper_1311_5551_amd import capi, workloads as W
     from paper_1311_5551_amd.sim import Run
+    probe = []
+    for w in ws:
+        p = W.subset(w, range(min(w.n, probe_n)))
+        p.capacity = dict(electron=2000 * p.n + 4096, positron=2000 * p.n + 4096, photon=4000 * p.n + 8192)
+        probe.append(p)
+    run = Run(probe, tables, precision=capi.QED_FP32_MIXED)
+    log("batched: sizing buffers from a %d-electron probe run" % sum(p.n for p in probe))
+    for i in range(4000):
+        run.step(1)
+        if (i + 1) % args.compact_every == 0:
+            run.compact()
+    led = run.ledger()
+    run.close()
+    if any(l["status"] != "QED_OK" for l in led):
+        raise RuntimeError("batched probe run: %s" % sorted(set(l["status"] for l in led)))
+    for w, p, l in zip(ws, probe, led):
+        y_e = l["count"][0] / p.n
+        y_p = l["count"][1] / p.n
+        y_g = (l["n_emit"] + l["n_pair"]) / p.n  # photons emitted (an upper bound of the live ones)
+        w.capacity = dict(electron=int(1.3 * y_e * w.n) + 4096, positron=int(1.3 * y_p * w.n) + 4096,
+                          photon=int(1.3 * y_g * w.n) + 16384)
 
-    total = args.warmup + args.steps
-    if form in ("fp64", "fp32"):
+
+def run_form(form, args, tables, tuned):
+    import torch
+    from paper_1311_5551_amd import autotune, capi, workloads as W
+    from paper_1311_5551_amd.sim import Run
+
+    batched = form == "batched"
+    if not batched:
+        total = args.warmup + args.steps
         w = W.collision_config2(n=args.electrons, n_steps=max(total, 20000))
         ws = [w]
         workload = ("collision_lp_a200: %d electrons gamma~N(2000,10%%) sigma 2um vs LP a0=200 lambda 1um "
                     "30fs sin^2, dt=lambda/200c, steps %d..%d of 20000, emission+pairs, compaction every %d"
                     % (w.n, args.warmup, total, args.compact_every))
+        warmup, steps = args.warmup, args.steps
     else:
-        ws = W.batched_config5(n_steps=4000)
-        for w in ws:
-            w.capacity = dict(electron=3 * w.n + 4096, positron=2 * w.n + 4096,
-                              photon=int(w.n * (40 + 0.5 * float(w.notes.split()[0].split("=")[1]))) + 8192)
-        workload = ("batched_collisions: 256 instances, N_i=10^U(3,6) (total %d electrons), a0~U(50,500), "
-                    "gamma0 log-U[500,5000], steps %d..%d of a 4000-step window centred on the collisions"
-                    % (sum(w.n for w in ws), args.warmup, total))
+        # the C5 instance mix with every N_i scaled by batched_scale (see DESIGN.md: at full size the
+        # 4000-step window emits ~4.5e9 photons, ~200 GB)
+        ws = W.batched_config5(n_steps=4000, n_scale=args.batched_scale)
+        size_batched(ws, tables, args)
+        warmup, steps = args.batched_warmup, 4000 - args.batched_warmup
+        workload = ("batched_collisions: 256 instances, N_i=floor(%g*10^U(3,6)) (total %d electrons), a0~U(50,500), "
+                    "gamma0 log-U[500,5000], FP32-mixed, steps %d..4000 of a 4000-step window centred on the "
+                    "collisions, hipGraph replay of %d-step graphs, compaction every %d"
+                    % (args.batched_scale, sum(w.n for w in ws), warmup, args.compact_every, args.compact_every))
     prec = capi.QED_FP64 if form == "fp64" else capi.QED_FP32_MIXED
     log("%s: allocating and binding (%s)" % (form, workload[:60]))
     run = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
+    if tuned is not None:
+        autotune.apply(run, tuned)
     step = 0
-    log("%s: %d warmup steps" % (form, args.warmup))
-    for _ in range(args.warmup):
+    log("%s: %d warmup steps" % (form, warmup))
+    for _ in range(warmup):
         run.step(1)
         step += 1
         if step % args.compact_every == 0:
             run.compact()
     led0 = run.ledger()
-    run.profile(True)
+    if not batched:
+        run.profile(True)
     run.synchronize()
-    log("%s: timing %d steps" % (form, args.steps))
+    log("%s: timing %d steps" % (form, steps))
     t0 = time.perf_counter()
-    for i in range(args.steps):
-        run.step(1)
-        step += 1
-        if step % args.compact_every == 0:
-            run.compact()
-        if i and i % 2000 == 0:
-            log("%s: step %d" % (form, step))
+    if batched:
+        # graph replay: whole compaction periods as captured graphs, compaction between them
+        done = 0
+        while done < steps:
+            k = min(args.compact_every - step % args.compact_every, steps - done)
+            run.run(k, graph_steps=k if k == args.compact_every else 0)
+            step += k
+            done += k
+            if step % args.compact_every == 0:
+                run.compact()
+            if done % 1000 == 0:
+                log("%s: step %d" % (form, step))
+    else:
+        for i in range(steps):
+            run.step(1)
+            step += 1
+            if step % args.compact_every == 0:
+                run.compact()
+            if i and i % 2000 == 0:
+                log("%s: step %d" % (form, step))
     run.synchronize()
     t1 = time.perf_counter()
-    ms, launches = run.profile_read()
-    run.profile(False)
     led1 = run.ledger()
+    if batched:
+        # kernel times from eager, profiled steps after the timed window (graph replay records none)
+        l0p = led1
+        run.profile(True)
+        for _ in range(args.batched_profile_steps):
+            run.step(1)
+        ms, launches = run.profile_read()
+        run.profile(False)
+        lk0, lk1 = _aggregate(l0p), _aggregate(run.ledger())
+    else:
+        ms, launches = run.profile_read()
+        run.profile(False)
     n_inst = len(ws)
     agg0 = _aggregate(led0)
     agg1 = _aggregate(led1)
+    if not batched:
+        lk0, lk1 = agg0, agg1
     psteps = sum(agg1["particle_steps"]) - sum(agg0["particle_steps"])
     status = sorted(set(l["status"] for l in led1))
     res = dict(form=form, workload=workload, n_inst=n_inst, seconds=t1 - t0, particle_steps=int(psteps),
-               value=psteps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / args.steps,
+               value=psteps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / steps,
                kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2], pair_events=ms[3], emit_events=ms[4]),
                launches=dict(setup=launches[0], lepton=launches[1], photon=launches[2], pair_events=launches[3],
                              emit_events=launches[4]),
@@ -138,9 +226,12 @@ def run_form(form, args, tables):
                emissions=int(agg1["n_emit"] - agg0["n_emit"]), drift_max=max(l["drift"] for l in led1),
                photon_steps_in_field=int(agg1["photon_steps_in_field"] - agg0["photon_steps_in_field"]),
                lepton_steps_in_field=int(agg1["lepton_steps_in_field"] - agg0["lepton_steps_in_field"]),
-               status=status)
+               dropped=int(sum(l["n_dropped"] for l in led1)), status=status,
+               launch={k: (tuned.get(k) if tuned else None) for k in ("lepton", "photon")})
+    if batched:
+        res["kernel_timing_window"] = "%d eager steps after the timed window" % args.batched_profile_steps
     kind = "photon" if ms[2] >= ms[1] else "lepton"
-    byts = kernel_bytes(form, kind, agg0, agg1)
+    byts = kernel_bytes("fp64" if form == "fp64" else "fp32", kind, lk0, lk1)
     n_l = launches[2] if kind == "photon" else launches[1]
     avg_s = (ms[2] if kind == "photon" else ms[1]) / max(n_l, 1) * 1e-3
     achieved = byts / max(n_l, 1) / avg_s / 1e9
@@ -196,6 +287,14 @@ def main():
     ap.add_argument("--ppt", type=int, default=4)
     ap.add_argument("--forms", default="fp64", help="comma list of fp64, fp32, batched; the first is `value`")
     ap.add_argument("--cpu-families", type=int, default=1500)
+    ap.add_argument("--tune", choices=("replica", "none"), default="replica",
+                    help="autotune the sweep launch shapes per form on a replica run (default) or use --block/--ppt")
+    ap.add_argument("--tune-scale", type=float, default=1.0, help="electrons of the tuning run / --electrons")
+    ap.add_argument("--tune-at", default="5000,10000,11500,13000,14500,16000,17500,19000",
+                    help="steps of the tuning run at which trials run (population-weighted sum)")
+    ap.add_argument("--batched-scale", type=float, default=0.1)
+    ap.add_argument("--batched-warmup", type=int, default=200)
+    ap.add_argument("--batched-profile-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB, 20 times (reference for HBM byte counters)")
@@ -221,7 +320,13 @@ def main():
     log("building tables on the GPU")
     tables = Tables.build()
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    results = [run_form(f, args, tables) for f in forms]
+    tuned = {}
+    results = []
+    for f in forms:
+        key = "fp64" if f == "fp64" else "fp32"
+        if args.tune == "replica" and key not in tuned:
+            tuned[key] = tune_launch(key, args, tables)
+        results.append(run_form(f, args, tables, tuned.get(key)))
     main_r = results[0]
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     out = {
@@ -238,7 +343,8 @@ def main():
         "dtype": "f64" if main_r["form"] == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": main_r["workload"], "form": main_r["form"], "instances": main_r["n_inst"],
-                   "launch": {"block": args.block, "particles_per_thread": args.ppt}},
+                   "launch": main_r["launch"] if args.tune == "replica" else
+                   {"block": args.block, "particles_per_thread": args.ppt}},
         "roofline": main_r["roofline"],
         "cpu_baseline": cpu,
         "detail": {r["form"]: {k: v for k, v in r.items() if k not in ("workload",)} for r in results},

@@ -159,9 +159,15 @@ void qed_workspace_destroy(qed_workspace* ws);
 qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
                     const qed_step_params* params);
 
-/* Launch shape of the step kernels: threads per block (64..256, multiple of 64) and particles
- * per thread (1, 2, 4 or 8).  Takes effect from the next step. */
+/* Launch shape of the sweep kernels: threads per block (64..256, multiple of 64) and particles
+ * per thread (1, 2, 4 or 8); qed_set_launch sets both sweeps, qed_set_kernel_launch one of
+ * them (kernel = QED_KERNEL_LEPTON or QED_KERNEL_PHOTON, the profile-class indices).  Takes
+ * effect from the next step; drops a captured graph.  Results do not depend on the shape
+ * (per-uid random streams); only the order of floating-point sums in the ledger does. */
+#define QED_KERNEL_LEPTON 1
+#define QED_KERNEL_PHOTON 2
 qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt);
+qed_status qed_set_kernel_launch(qed_workspace* ws, int32_t kernel, int32_t block, int32_t ppt);
 
 /* Capacity (entries of 8 bytes, 1..2^32; default 2^20) of the per-step queue through which the
  * photon pass hands photons whose optical depth reached zero to the pair-creation pass.  A step

@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "QED_OK", -1: "QED_ERR_ARG", -2: "QED_ERR_HIP", -3: "QED_ERR_
 QED_FP64, QED_FP32_MIXED = 0, 1
 QED_EMIT, QED_PAIRS, QED_PROPAGATE = 1, 2, 4
 QED_PROFILE_CLASSES = 5
+QED_KERNEL_LEPTON, QED_KERNEL_PHOTON = 1, 2
 QED_FIELD_UNIFORM, QED_FIELD_LP_PULSE, QED_FIELD_CP_WAVE, QED_FIELD_CP_STANDING, QED_FIELD_GRID_CP_STANDING = \
     0, 1, 2, 3, 4
 
@@ -85,6 +86,7 @@ _SIGNATURES = {
     "qed_bind": (C.c_int, [_vp, C.POINTER(qed_instance), C.c_int32, C.POINTER(qed_step_params)]),
     "qed_set_launch": (C.c_int, [_vp, C.c_int32, C.c_int32]),
     "qed_set_event_queue": (C.c_int, [_vp, C.c_int64]),
+    "qed_set_kernel_launch": (C.c_int, [_vp, C.c_int32, C.c_int32, C.c_int32]),
     "qed_init_optical_depth": (C.c_int, [_vp, _vp]),
     "qed_set_step": (C.c_int, [_vp, C.c_int64, _vp]),
     "qed_step": (C.c_int, [_vp, _vp, C.POINTER(qed_step_params), _vp]),
@@ -171,6 +173,10 @@ def qed_bind(ws, insts, params: qed_step_params):
 
 def qed_set_launch(ws, block: int, ppt: int):
     return check(lib().qed_set_launch(ws, block, ppt))
+
+
+def qed_set_kernel_launch(ws, kernel: int, block: int, ppt: int):
+    return check(lib().qed_set_kernel_launch(ws, kernel, block, ppt))
 
 
 def qed_set_event_queue(ws, capacity: int):

@@ -109,7 +109,7 @@ struct qed_workspace {
   int64_t* d_base = nullptr;  // 3 * max_inst: leptons (2 per instance) then photons
   int64_t* d_movers = nullptr;
   size_t movers_len = 0;
-  int block = 256, ppt = 4;
+  int block[2] = {256, 256}, ppt[2] = {4, 4};  // launch shapes: [0] lepton sweep, [1] photon sweep
   // kernel timing: event pairs per kernel class, reused across reads
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -296,20 +296,17 @@ void mark_end(qed_workspace* ws, int slot, hipStream_t s) {
 }
 
 qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
-  const int B = ws->block, ppt = ws->ppt;
-  const int chunk = B * ppt;
+  const int BL = ws->block[0], BP = ws->block[1];
   const StepConst sc = step_const(p);
   int m = mark_begin(ws, 0, s);
   launch_step_begin(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_evc, ws->d_evc + 1, ws->d_base,
-                    ws->d_base + 2 * ws->max_inst, chunk,
-                    chunk, 1, s);
+                    ws->d_base + 2 * ws->max_inst, BL * ws->ppt[0], BP * ws->ppt[1], 1, s);
   if (ws->any_grid) launch_grid_refresh(ws->d_inst, ws->n_inst, ws->d_glob, sc, s);
   mark_end(ws, m, s);
   StepArgs a;
   a.inst = ws->d_inst;
   a.acc = ws->d_acc;
   a.glob = ws->d_glob;
-  a.ppt = ppt;
   a.tb = device_tabs(tb);
   a.sc = sc;
   a.q.ctl = ws->d_evc;
@@ -318,12 +315,13 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.qe.ctl = ws->d_evc + 1;
   a.qe.ent = ws->d_emq;
   a.qe.cap = ws->emq_cap;
-  const int grid = ws->cus * (2048 / B > 0 ? 2048 / B : 1);
+  // persistent grids: 2048 threads per CU, blocks striding over the chunk list
   const bool mixed = ws->prec == QED_FP32_MIXED;
   a.base = ws->d_base;
   a.n_base = 2 * ws->n_inst;
+  a.ppt = ws->ppt[0];
   m = mark_begin(ws, 1, s);
-  launch_lepton(ws->field_kind, a, grid, B, mixed, s);
+  launch_lepton(ws->field_kind, a, ws->cus * (2048 / BL), BL, mixed, s);
   mark_end(ws, m, s);
   if (p->flags & QED_EMIT) {
     m = mark_begin(ws, 4, s);
@@ -335,8 +333,9 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
     // position is the closed form of their birth record and no pass runs
     a.base = ws->d_base + 2 * ws->max_inst;
     a.n_base = ws->n_inst;
+    a.ppt = ws->ppt[1];
     m = mark_begin(ws, 2, s);
-    launch_photon(ws->field_kind, a, grid, B, mixed, s);
+    launch_photon(ws->field_kind, a, ws->cus * (2048 / BP), BP, mixed, s);
     mark_end(ws, m, s);
     m = mark_begin(ws, 3, s);
     launch_pair_events(ws->field_kind, a, ws->cus, 256, mixed, s);
@@ -511,14 +510,22 @@ void qed_workspace_destroy(qed_workspace* ws) {
   delete ws;
 }
 
-qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt) {
+qed_status qed_set_kernel_launch(qed_workspace* ws, int32_t kernel, int32_t block, int32_t ppt) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
+  if (kernel != QED_KERNEL_LEPTON && kernel != QED_KERNEL_PHOTON)
+    return fail(QED_ERR_ARG, "kernel = %d: need QED_KERNEL_LEPTON or QED_KERNEL_PHOTON", kernel);
   if (block < 64 || block > 256 || block % 64) return fail(QED_ERR_ARG, "block = %d: need 64..256, multiple of 64", block);
   if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) return fail(QED_ERR_ARG, "ppt = %d: need 1, 2, 4 or 8", ppt);
-  if (ws->block != block || ws->ppt != ppt) drop_graph(ws);
-  ws->block = block;
-  ws->ppt = ppt;
+  const int k = kernel == QED_KERNEL_LEPTON ? 0 : 1;
+  if (ws->block[k] != block || ws->ppt[k] != ppt) drop_graph(ws);
+  ws->block[k] = block;
+  ws->ppt[k] = ppt;
   return QED_OK;
+}
+
+qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt) {
+  qed_status st = qed_set_kernel_launch(ws, QED_KERNEL_LEPTON, block, ppt);
+  return st ? st : qed_set_kernel_launch(ws, QED_KERNEL_PHOTON, block, ppt);
 }
 
 qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst, const qed_step_params* params) {
@@ -663,7 +670,8 @@ qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_p
   if (graph_steps > 0 && n_steps >= graph_steps) {
     char key[256];
     snprintf(key, sizeof(key), "%p|%a|%a|%a|%u|%d|%d|%d|%d", (const void*)tables, params->t0, params->dt,
-             params->lambda_L, params->flags, (int)params->precision, ws->block, ws->ppt, graph_steps);
+             params->lambda_L, params->flags, (int)params->precision, ws->block[0] * 16 + ws->ppt[0],
+             ws->block[1] * 16 + ws->ppt[1], graph_steps);
     if (ws->graph_key != key) {
       drop_graph(ws);
       HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));

@@ -252,6 +252,41 @@ __device__ __forceinline__ void fast_sincos(double x, double* sn, double* cs) {
   *cs = q == 0 ? cv : q == 1 ? -sv : q == 2 ? -cv : sv;
 }
 
+// sin(x + qs pi/2) alone (same reduction and polynomials as fast_sincos, one of the two
+// evaluated): qs = 0 sin, qs = 1 cos
+__device__ __forceinline__ double fast_sinq(double x, int qs) {
+  using namespace fastm;
+  const double k = rint(x * kTwoOverPi);
+  const double r = ((x - k * kPio2A) - k * kPio2B) - k * kPio2C;
+  const double r2 = r * r;
+  const int q = ((int)(int64_t)k + qs) & 3;
+  double v;
+  if (q & 1) {  // +-cos r
+    double pc = f18;
+    pc = pc * r2 - f16;
+    pc = pc * r2 + f14;
+    pc = pc * r2 - f12;
+    pc = pc * r2 + f10;
+    pc = pc * r2 - f8;
+    pc = pc * r2 + f6;
+    pc = pc * r2 - f4;
+    v = (1.0 - f2 * r2) - r2 * (r2 * pc);
+  } else {  // +-sin r
+    double ps = f17;
+    ps = ps * r2 - f15;
+    ps = ps * r2 + f13;
+    ps = ps * r2 - f11;
+    ps = ps * r2 + f9;
+    ps = ps * r2 - f7;
+    ps = ps * r2 + f5;
+    ps = ps * r2 - f3;
+    v = r + r * (r2 * ps);
+  }
+  return (q & 2) ? -v : v;
+}
+__device__ __forceinline__ double fast_sin(double x) { return fast_sinq(x, 0); }
+__device__ __forceinline__ double fast_cos(double x) { return fast_sinq(x, 1); }
+
 // natural log of a finite x > 0: x = m 2^e with m in [1/sqrt2, sqrt2), log m = 2 atanh(s),
 // s = (m - 1)/(m + 1), |s| <= 0.172, by its odd series to s^25 (truncation below 1e-19).
 __device__ __forceinline__ double fast_log(double x) {
@@ -297,9 +332,20 @@ __device__ __forceinline__ void fast_sincosf(float x, float* sn, float* cs) {
   *cs = q == 0 ? cv : q == 1 ? -sv : q == 2 ? -cv : sv;
 }
 
+// Per-instance constants of a field derived once per kernel and instance (fast paths only).
+struct FieldK {
+  double pi_over_len;  // plane-wave pulse: pi / Psi
+};
+__device__ __forceinline__ FieldK field_k(const qed_field& F) {
+  FieldK k;
+  k.pi_over_len = F.kind == QED_FIELD_LP_PULSE ? kPi / F.p[1] : 0.0;
+  return k;
+}
+constexpr double kInvTwoPi = 0.15915494309189533577;
+
 template <int FK, bool EXACT = true>
 __device__ __forceinline__ void field_at(const qed_field& F, double x, double y, double t, double E[3],
-                                         double B[3]) {
+                                         double B[3], const FieldK* K = nullptr) {
   E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = 0.0;
   if (FK == QED_FIELD_UNIFORM) {
     E[0] = F.p[0];
@@ -315,9 +361,10 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
       if (EXACT) {
         s = cr_sin(kPi * psi / F.p[1]);
         c = cr_cos(psi + F.p[3]);
-      } else {
-        fast_sincos(kPi * psi / F.p[1], &s, &d);
-        fast_sincos(psi + F.p[3], &d, &c);
+      } else {  // K: pi / Psi precomputed
+        s = fast_sin(psi * K->pi_over_len);
+        c = fast_cos(psi + F.p[3]);
+        (void)d;
       }
       const double e = F.p[0] * s * s * c;
       E[1] = e;

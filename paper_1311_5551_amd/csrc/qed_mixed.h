@@ -31,11 +31,12 @@ __device__ __forceinline__ void split_double(double v, float& hi, float& lo) {
 // phase psi reduced to [-pi, pi] in FP64, returned as float
 __device__ __forceinline__ float reduce_phase(double psi) {
   const double two_pi = 2.0 * kPi;
-  return (float)(psi - two_pi * rint(psi / two_pi));
+  return (float)(psi - two_pi * rint(psi * kInvTwoPi));
 }
 
 template <int FK>
-__device__ __forceinline__ void field_at32(const qed_field& F, double x, double y, double t, float E[3], float B[3]) {
+__device__ __forceinline__ void field_at32(const qed_field& F, const FieldK& K, double x, double y, double t, float E[3],
+                                           float B[3]) {
   E[0] = E[1] = E[2] = B[0] = B[1] = B[2] = 0.0f;
   if (FK == QED_FIELD_UNIFORM) {
     E[0] = (float)F.p[0];
@@ -48,7 +49,7 @@ __device__ __forceinline__ void field_at32(const qed_field& F, double x, double 
     const double psi = t - x - F.p[2];
     if (psi >= 0.0 && psi <= F.p[1]) {
       float s, c, d;
-      fast_sincosf((float)(kPi * (psi / F.p[1])), &s, &d);
+      fast_sincosf((float)(psi * K.pi_over_len), &s, &d);
       fast_sincosf(reduce_phase(psi + F.p[3]), &d, &c);
       const float e = (float)F.p[0] * s * s * c;
       E[1] = e;

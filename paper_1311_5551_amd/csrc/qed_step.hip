@@ -10,9 +10,10 @@
 //
 // Work decomposition: every species of every bound instance is cut into chunks of
 // blockDim * ppt consecutive particles; a prefix array over (instance, species) maps a
-// global chunk index to its particles.  Blocks stride over the chunk list, so one launch
-// serves one instance or hundreds of instances of very different sizes, and the counts
-// never leave the device (the step sequence can be captured in a HIP graph).
+// global chunk index to its particles.  Each block of a persistent grid takes a contiguous run
+// of that list, so one launch serves one instance or hundreds of instances of very different
+// sizes, and the counts never leave the device (the step sequence can be captured in a HIP
+// graph).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -172,6 +173,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   bool d3 = false;
   double hq = 0.0;
   float tpf0 = 0.0f, psif_max = 0.0f;
+  FieldK fK{0.0};
   double dacc[1] = {0.0};              // field work
   unsigned uacc[3] = {0, 0, 0};        // in-field steps, eta above the table, non-finite state
   auto flush = [&](int entry) {
@@ -187,7 +189,11 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
     uacc[0] = uacc[1] = uacc[2] = 0;
   };
 
-  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+  // each block takes a contiguous run of chunks, so it changes instance at most once per
+  // instance boundary inside its run
+  const int64_t per_block = (nch + gridDim.x - 1) / gridDim.x;
+  const int64_t c_end = min(nch, (int64_t)blockIdx.x * per_block + per_block);
+  for (int64_t c = (int64_t)blockIdx.x * per_block; c < c_end; ++c) {
     if (c >= ce) {
       if (cur >= 0) flush(cur);
       const int idx = uni32(find_entry(a.base, a.n_base, c));
@@ -221,6 +227,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
       __syncthreads();
       tpf0 = (float)sF.p[2];
       psif_max = (float)sF.p[1];
+      fK.pi_over_len = uni_f64(field_k(sF).pi_over_len);
     }
     const int64_t k0 = uni64((c - cb) * CH);
     const int64_t rem = n - k0;
@@ -305,7 +312,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
         const double ux0 = (double)uxh + uxl, uy0 = (double)uyh + uyl, uz0 = (double)uzh + uzl;
         const double g0d = sqrt(1.0 + (ux0 * ux0 + uy0 * uy0 + uz0 * uz0));
         float E[3], Bf[3];
-        field_at32<FK>(sF, (double)xh + xl, (double)yh + yl, t, E, Bf);
+        field_at32<FK>(sF, fK, (double)xh + xl, (double)yh + yl, t, E, Bf);
         const float hqf = (float)hq;
         const float umx = uxh + hqf * E[0], umy = uyh + hqf * E[1], umz = uzh + hqf * E[2];
         const float gm = sqrtf(1.0f + (umx * umx + umy * umy + umz * umz));
@@ -596,6 +603,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   double* sT = smem;
   float* sT32 = (float*)smem;
   unsigned* sredu = (unsigned*)(smem + a.tb.n_cp);
+  unsigned* slist = sredu + 16 * 3;  // per wave: 64 * PPT slot offsets (pulse field only)
   for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) {
     if (MIXED) sT32[i] = a.tb.T32[i];
     else sT[i] = a.tb.T[i];
@@ -616,6 +624,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   gptr<const int32_t> BS = nullptr;
   gptr<double> TAU = nullptr;
   float tpf0 = 0.0f, psif_max = 0.0f;
+  FieldK fK{0.0};
   unsigned uacc[3] = {0, 0, 0};  // in-field steps, chi above the table, non-finite tau
   auto flush = [&](int ii) {
     block_sum_u(uacc, sredu);
@@ -628,7 +637,11 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     uacc[0] = uacc[1] = uacc[2] = 0;
   };
 
-  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+  // each block takes a contiguous run of chunks, so it changes instance at most once per
+  // instance boundary inside its run
+  const int64_t per_block = (nch + gridDim.x - 1) / gridDim.x;
+  const int64_t c_end = min(nch, (int64_t)blockIdx.x * per_block + per_block);
+  for (int64_t c = (int64_t)blockIdx.x * per_block; c < c_end; ++c) {
     if (c >= ce) {  // first chunk of another instance (c only grows)
       if (cur >= 0) flush(cur);
       const int ii = uni32(find_entry(a.base, a.n_base, c));
@@ -650,6 +663,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       __syncthreads();
       tpf0 = (float)sF.p[2];
       psif_max = (float)sF.p[1];
+      fK.pi_over_len = uni_f64(field_k(sF).pi_over_len);
     }
     const int64_t k0 = uni64((c - cb) * CH);  // first slot of the chunk
     const int64_t rem = n - k0;        // slots of the chunk that exist: min(rem, CH)
@@ -675,7 +689,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       double chi, T;
       if (MIXED) {
         float E[3], Bf[3];
-        field_at32<FK>(sF, x, y, tt, E, Bf);
+        field_at32<FK>(sF, fK, x, y, tt, E, Bf);
         const float ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
         const float ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
         const float az = E[2] + (nx * Bf[1] - ny * Bf[0]);
@@ -686,7 +700,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
         T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.dlc, chif, uacc[1], true);
       } else {
         double E[3], Bf[3];
-        field_at<FK, false>(sF, x, y, tt, E, Bf);
+        field_at<FK, false>(sF, x, y, tt, E, Bf, &fK);
         const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
         const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
         const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
@@ -750,19 +764,42 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
           if (psif >= -m && psif <= psif_max + m) gmask |= 1u << j;
         }
       }
-      // phase 2: the photons inside the pulse, re-read (from cache) one at a time; not unrolled,
-      // so that one copy of the in-field code holds registers
-#pragma unroll 1
-      for (int j = 0; j < PPT; ++j) {
-        const unsigned off = threadIdx.x + j * B;
+      // phase 2: the photons inside the pulse, packed densely across the wave through a per-wave
+      // LDS list (so the in-field code runs on full waves however the photons are spread), state
+      // re-read from cache; one copy of the in-field code holds registers
+      const int lane = threadIdx.x & 63;
+      unsigned* list = slist + (threadIdx.x >> 6) * (64 * PPT);
+      const int cnt = __popc(gmask);
+      int incl = cnt;
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o);
+        if (lane >= o) incl += v;
+      }
+      const int total = __shfl(incl, 63);
+      int w = incl - cnt;
+#pragma unroll
+      for (int j = 0; j < PPT; ++j)
+        if (gmask & (1u << j)) list[w++] = threadIdx.x + j * B;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      for (int e0 = 0; e0 < total; e0 += 64) {  // wave-uniform trip count
+        const int e = e0 + lane;
         bool pend = false;
-        if (gmask & (1u << j)) {
+        unsigned off = 0;
+        if (e < total) {
+          off = list[e];
           const uint32_t o = off * (uint32_t)sizeof(Real);
           pend = infield(off, buf_ld<Real>(rkx, o), buf_ld<Real>(rky, o), buf_ld<Real>(rkz, o), buf_ld<Real>(rxb, o),
                          Real(0), buf_ld<int32_t>(rbs, off * 4u));
         }
         enqueue(off, pend);
       }
+      // the list is rewritten for the next chunk only after every lane has read it
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else {
       Real kx[PPT], ky[PPT], kz[PPT], xb[PPT], yb[PPT];
       int32_t bs[PPT];
@@ -843,7 +880,7 @@ __device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k,
     double chi;
     if (MIXED) {
       float E[3], Bf[3];
-      field_at32<FK>(I.field, x, y, t, E, Bf);
+      field_at32<FK>(I.field, field_k(I.field), x, y, t, E, Bf);
       const float ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
       const float ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
       const float az = E[2] + (nx * Bf[1] - ny * Bf[0]);
@@ -1227,7 +1264,8 @@ void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mix
 }
 
 void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
-  const size_t shm = (size_t)a.tb.n_cp * sizeof(double) + 16 * 3 * sizeof(unsigned) + 64;
+  const size_t shm = (size_t)a.tb.n_cp * sizeof(double) + 16 * 3 * sizeof(unsigned) +
+                     (fk == QED_FIELD_LP_PULSE ? (size_t)block * a.ppt * sizeof(unsigned) : 0) + 64;
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_photon_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;

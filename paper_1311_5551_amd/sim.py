@@ -184,6 +184,9 @@ class Run:
     def set_launch(self, block, ppt):
         capi.qed_set_launch(self.ws, block, ppt)
 
+    def set_kernel_launch(self, kernel: int, block: int, ppt: int):
+        capi.qed_set_kernel_launch(self.ws, kernel, block, ppt)
+
     def set_event_queue(self, capacity: int):
         capi.qed_set_event_queue(self.ws, capacity)
 

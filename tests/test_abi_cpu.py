@@ -47,6 +47,7 @@ def test_arguments_rejected_before_any_device_work(lib):
     assert lib.qed_workspace_create(0, C.byref(out)) == capi.QED_ERR_ARG
     assert lib.qed_set_launch(None, 256, 4) == capi.QED_ERR_ARG
     assert lib.qed_set_event_queue(None, 1024) == capi.QED_ERR_ARG
+    assert lib.qed_set_kernel_launch(None, capi.QED_KERNEL_PHOTON, 256, 4) == capi.QED_ERR_ARG
     assert lib.qed_step(None, None, None, None) == capi.QED_ERR_ARG
     assert lib.qed_compact(None, None) == capi.QED_ERR_ARG
     assert lib.qed_energy_ledger(None, None, None) == capi.QED_ERR_ARG

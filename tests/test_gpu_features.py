@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_1311_5551_amd import capi, workloads as W
+from paper_1311_5551_amd import autotune, capi, workloads as W
 from paper_1311_5551_amd.sim import Run, Tables
 
 from parity import compare_species, oracle_run, record
@@ -187,6 +187,22 @@ def test_event_queue_overflow_falls_back_to_sweep(shared_tables):
     _states_equal(ra, rb)
     with pytest.raises(capi.QEDError):
         rb.set_event_queue(0)
+
+
+def test_autotuned_shapes_leave_particles_unchanged(shared_tables):
+    # the tuner's trial steps run with every candidate shape; per-uid results equal a run with the
+    # default shape, and each sweep gets a shape
+    w, ra = _collision_run(shared_tables, n=2000)
+    _, rb = _collision_run(shared_tables, n=2000)
+    ra.step(1500)
+    rb.step(1500)
+    res = autotune.tune(rb, steps_per_trial=3, rounds=1, min_particles=10)
+    assert res["lepton"] is not None and res["photon"] is not None
+    assert len(res["trials"]) == len(autotune.CANDIDATES)
+    ra.step(rb.step_index - ra.step_index)
+    rb.step(300)
+    ra.step(300)
+    _states_equal(ra, rb)
 
 
 def test_restart_from_saved_state_is_exact(shared_tables):
