@@ -104,6 +104,30 @@ def tune_launch(form, args, tables):
     return res
 
 
+TUNED_CACHE = os.path.join(ROOT, "paper_1311_5551_amd", "tuned_launch.json")
+
+
+def tuned_launch(form, args, tables):
+    """Cached tuned shapes for (device, form, collision workload size, kernel sources), else a
+    fresh tuning whose result is written to gpurun_out/tuned_launch.json (entries of that file
+    are what the package's cache holds)."""
+    import torch
+    from paper_1311_5551_amd import autotune, capi
+    prec = capi.QED_FP64 if form == "fp64" else capi.QED_FP32_MIXED
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    key = autotune.cache_key(arch, prec, 1, 1, args.electrons) + "|src" + source_hash()
+    if args.tune == "auto":
+        hit = autotune.cache_load(TUNED_CACHE, key)
+        if hit:
+            log("%s: cached launch shapes %s" % (form, {k: hit[k] for k in ("lepton", "photon")}))
+            return hit
+    res = tune_launch(form, args, tables)
+    out = os.path.join(ROOT, "gpurun_out", "tuned_launch.json")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    autotune.cache_store(out, key, res)
+    return res
+
+
 def size_batched(ws, tables, args, probe_n=64):
     """Buffer capacities of the batched instances from a probe run: the first `probe_n`
     electrons of every instance (the same families as in the full run) through the whole
@@ -287,8 +311,10 @@ def main():
     ap.add_argument("--ppt", type=int, default=4)
     ap.add_argument("--forms", default="fp64", help="comma list of fp64, fp32, batched; the first is `value`")
     ap.add_argument("--cpu-families", type=int, default=1500)
-    ap.add_argument("--tune", choices=("replica", "none"), default="replica",
-                    help="autotune the sweep launch shapes per form on a replica run (default) or use --block/--ppt")
+    ap.add_argument("--tune", choices=("auto", "replica", "none"), default="auto",
+                    help="sweep launch shapes per form: auto = the tuned shapes cached in "
+                         "paper_1311_5551_amd/tuned_launch.json for this device, form, workload and kernel sources, "
+                         "else tune; replica = tune now; none = --block/--ppt")
     ap.add_argument("--tune-scale", type=float, default=1.0, help="electrons of the tuning run / --electrons")
     ap.add_argument("--tune-at", default="5000,10000,11500,13000,14500,16000,17500,19000",
                     help="steps of the tuning run at which trials run (population-weighted sum)")
@@ -324,8 +350,8 @@ def main():
     results = []
     for f in forms:
         key = "fp64" if f == "fp64" else "fp32"
-        if args.tune == "replica" and key not in tuned:
-            tuned[key] = tune_launch(key, args, tables)
+        if args.tune != "none" and key not in tuned:
+            tuned[key] = tuned_launch(key, args, tables)
         results.append(run_form(f, args, tables, tuned.get(key)))
     main_r = results[0]
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
