@@ -217,7 +217,8 @@ typedef struct {
                                       plane-wave pulse, where the push is the field-free drift) */
   int64_t particle_steps[3];       /* particles present at the start of each step, summed over the
                                       steps since qed_bind (photons: buffer slots, incl. dead ones
-                                      not yet compacted) */
+                                      not yet compacted, counted in steps with QED_PAIRS, the steps
+                                      in which photons are advanced) */
   double drift;           /* |sum energy - energy0 - work - defects + dropped| / energy0 */
 } qed_ledger;
 

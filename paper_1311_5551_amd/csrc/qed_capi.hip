@@ -300,7 +300,8 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   const StepConst sc = step_const(p);
   int m = mark_begin(ws, 0, s);
   launch_step_begin(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_evc, ws->d_evc + 1, ws->d_base,
-                    ws->d_base + 2 * ws->max_inst, BL * ws->ppt[0], BP * ws->ppt[1], 1, s);
+                    ws->d_base + 2 * ws->max_inst, BL * ws->ppt[0], BP * ws->ppt[1], 1,
+                    (p->flags & QED_PAIRS) ? 1 : 0, s);
   if (ws->any_grid) launch_grid_refresh(ws->d_inst, ws->n_inst, ws->d_glob, sc, s);
   mark_end(ws, m, s);
   StepArgs a;

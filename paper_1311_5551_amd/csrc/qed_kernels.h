@@ -25,8 +25,8 @@ hipError_t init_crmath();
 hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnchi_min, double* dlnchi, double* P,
                                double* T, double* fgrid, double* Pf, double* knorm, hipStream_t s);
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,
-                       int64_t* base_lep,
-                       int64_t* base_ph, int chunk_lep, int chunk_ph, int advance, hipStream_t s);
+                       int64_t* base_lep, int64_t* base_ph, int chunk_lep, int chunk_ph, int advance,
+                       int count_photons, hipStream_t s);
 void launch_set_step(Glob* glob, int64_t step, hipStream_t s);
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s);
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);

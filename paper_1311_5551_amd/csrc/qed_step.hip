@@ -32,7 +32,8 @@ namespace qedk {
 __global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
                              Glob* __restrict__ glob, EvCtl* __restrict__ evc, EvCtl* __restrict__ emc,
                              int64_t* __restrict__ base_lep,
-                             int64_t* __restrict__ base_ph, int chunk_lep, int chunk_ph, int advance_clock) {
+                             int64_t* __restrict__ base_ph, int chunk_lep, int chunk_ph, int advance_clock,
+                             int count_photons) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
     for (int s = 0; s < 3; ++s) {
       const qed_species& S = inst[i].s[s];
@@ -47,7 +48,8 @@ __global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, 
         if (c < 0) c = 0;
       }
       acc[i].n_start[s] = c;
-      if (advance_clock) acc[i].particle_steps[s] += (unsigned long long)c;
+      // particle-steps: leptons every step; photon slots in steps that run the photon pass
+      if (advance_clock && (s < 2 || count_photons)) acc[i].particle_steps[s] += (unsigned long long)c;
     }
   }
   __syncthreads();
@@ -1216,9 +1218,10 @@ static void launch_photon_fk(const StepArgs& a, dim3 grid, dim3 block, size_t sh
 }
 
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,
-                       int64_t* base_lep, int64_t* base_ph, int chunk_lep, int chunk_ph, int advance, hipStream_t s) {
+                       int64_t* base_lep, int64_t* base_ph, int chunk_lep, int chunk_ph, int advance,
+                       int count_photons, hipStream_t s) {
   hipLaunchKernelGGL(k_step_begin, dim3(1), dim3(256), 0, s, inst, n_inst, acc, glob, evc, emc, base_lep, base_ph,
-                     chunk_lep, chunk_ph, advance);
+                     chunk_lep, chunk_ph, advance, count_photons);
 }
 
 void launch_set_step(Glob* glob, int64_t step, hipStream_t s) {
