@@ -185,7 +185,7 @@ qed_status qed_set_step(qed_workspace* ws, int64_t step, qed_stream stream);
 /* One Monte-Carlo step (Sec. 3; in the PIC coupling of Sec. 3.2 it follows the particle push):
  * for every lepton present at the start of the step: fields at (x^n, t^n), Boris push, eta,
  * tau -= lambda_gamma(eta) dt; on tau <= 0 sample chi from P_chi, recoil, append the photon and
- * redraw tau.  For every photon (QED_PROPAGATE): move at c, chi, tau -= lambda_pm(chi) dt; on
+ * redraw tau.  For every photon (QED_PAIRS): move at c, chi, tau -= lambda_pm(chi) dt; on
  * tau <= 0 sample f from P_f, append the pair, mark the photon dead.  Children are first stepped
  * in the next step.  Never allocates; async on `stream`; device-side conditions (full buffers,
  * non-finite state) are reported by the next qed_energy_ledger. */

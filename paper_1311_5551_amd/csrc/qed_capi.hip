@@ -316,18 +316,22 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.qe.ctl = ws->d_evc + 1;
   a.qe.ent = ws->d_emq;
   a.qe.cap = ws->emq_cap;
-  // persistent grids: 2048 threads per CU, blocks striding over the chunk list
+  // persistent grids: 2048 threads per CU, blocks taking contiguous runs of the chunk list.
+  // The passes run in order on `stream`: the photon sweep alone saturates HBM, so running the
+  // lepton passes beside it on a second stream (their data are disjoint) shares bandwidth
+  // rather than adding any.
   const bool mixed = ws->prec == QED_FP32_MIXED;
+  hipStream_t sl = s;
   a.base = ws->d_base;
   a.n_base = 2 * ws->n_inst;
   a.ppt = ws->ppt[0];
-  m = mark_begin(ws, 1, s);
-  launch_lepton(ws->field_kind, a, ws->cus * (2048 / BL), BL, mixed, s);
-  mark_end(ws, m, s);
+  m = mark_begin(ws, 1, sl);
+  launch_lepton(ws->field_kind, a, ws->cus * (2048 / BL), BL, mixed, sl);
+  mark_end(ws, m, sl);
   if (p->flags & QED_EMIT) {
-    m = mark_begin(ws, 4, s);
-    launch_emit_events(ws->field_kind, a, ws->cus, 256, mixed, s);
-    mark_end(ws, m, s);
+    m = mark_begin(ws, 4, sl);
+    launch_emit_events(ws->field_kind, a, ws->cus, 256, mixed, sl);
+    mark_end(ws, m, sl);
   }
   if (p->flags & QED_PAIRS) {
     // photons only change state through the pair optical depth: without pair creation their
@@ -598,6 +602,7 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
   std::memset(acc0.data(), 0, n_inst * sizeof(InstAcc));
   size_t off = 0;
   for (int i = 0; i < n_inst; ++i) {
+    acc0[i].n_pair_compacted = ~0ull;  // the first compaction after a bind always runs
     acc0[i].mover_off = (int64_t)off;
     off += (size_t)inst[i].s[2].capacity;
   }

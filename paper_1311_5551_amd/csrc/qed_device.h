@@ -127,6 +127,9 @@ struct InstAcc {
   unsigned long long led_count[3];
   unsigned long long n_emit, n_null, n_pair, n_dropped, n_range, n_nonfinite, n_field, n_field_lepton;
   unsigned long long particle_steps[3];  // particles (photon slots) present at the start of each step
+  unsigned long long n_pair_compacted;   // n_pair at the last compaction (~0: unknown, e.g. after bind)
+  int32_t compact_skip;                  // this compaction has nothing to remove
+  int32_t pad_;
 };
 
 // Workspace-global device state.

@@ -752,18 +752,24 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
         xbf[j] = (float)buf_ld<Real>(rxb, o);
         bs[j] = buf_ld<int32_t>(rbs, off * 4u);
       }
+      // A second exact cull: in the pulse |E| = |B| <= a (the amplitude) and chi = (eps/2)|e||1 - n_x|
+      // <= eps a, while T(chi) = 0 below the table's chi_min; a photon with eps a below chi_min
+      // (with the same relative margin) has no pair rate anywhere in the pulse.
       const float tpf = (float)t - tpf0;
       const float mt = fabsf((float)t) + fabsf(tpf0);
+      const float eps_min = (float)(a.tb.cp_min / fabs(sF.p[0])) * (1.0f - 1e-5f);
       unsigned gmask = 0;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
         const unsigned off = threadIdx.x + j * B;
         if ((int64_t)off < rem) {
-          const float nxf = kxf[j] * rsqrtf(kxf[j] * kxf[j] + kyf[j] * kyf[j] + kzf[j] * kzf[j]);
+          const float k2 = kxf[j] * kxf[j] + kyf[j] * kyf[j] + kzf[j] * kzf[j];
+          const float rk = rsqrtf(k2);
+          const float nxf = kxf[j] * rk;
           const float agef = (float)((double)(step - (int64_t)bs[j]) * dt);
           const float psif = tpf - (xbf[j] + agef * nxf);
           const float m = 1e-5f * (mt + fabsf(xbf[j]) + agef) + 1e-30f;
-          if (psif >= -m && psif <= psif_max + m) gmask |= 1u << j;
+          if (psif >= -m && psif <= psif_max + m && k2 * rk >= eps_min) gmask |= 1u << j;
         }
       }
       // phase 2: the photons inside the pulse, packed densely across the wave through a per-wave
@@ -1072,9 +1078,14 @@ __global__ void k_compact_prep(const qed_instance* __restrict__ inst, int n_inst
     if (n < 0) n = 0;
     if (S.count_dev) *S.count_dev = n;
     acc[i].n_start[2] = n;
-    acc[i].n_live = 0;
     acc[i].hole_ctr = 0;
     acc[i].mover_ctr = 0;
+    // photons are removed only by pair creation: with no pair event since the last compaction
+    // there is nothing to remove (the first compaction after a bind always runs)
+    const bool skip = acc[i].n_pair_compacted == acc[i].n_pair;
+    acc[i].compact_skip = skip ? 1 : 0;
+    acc[i].n_live = skip ? n : 0;
+    acc[i].n_pair_compacted = acc[i].n_pair;
   }
 }
 
@@ -1082,6 +1093,7 @@ __global__ __launch_bounds__(256) void k_compact_count(const qed_instance* __res
   __shared__ double sred[16];
   __shared__ unsigned sredu[16];
   const int ii = blockIdx.y;
+  if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
   const int64_t n = acc[ii].n_start[2];
   double d[1] = {0.0};
@@ -1095,6 +1107,7 @@ __global__ __launch_bounds__(256) void k_compact_count(const qed_instance* __res
 __global__ __launch_bounds__(256) void k_compact_movers(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
                                                         int64_t* __restrict__ movers) {
   const int ii = blockIdx.y;
+  if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
   const int64_t n = acc[ii].n_start[2], L = acc[ii].n_live;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1111,6 +1124,7 @@ template <bool MIXED>
 __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
                                                       const int64_t* __restrict__ movers) {
   const int ii = blockIdx.y;
+  if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
   const int64_t L = acc[ii].n_live, n = acc[ii].n_start[2];
   const long long n_movers = (long long)acc[ii].mover_ctr;
@@ -1291,10 +1305,13 @@ void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixe
 
 void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, bool mixed, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
-  hipLaunchKernelGGL(k_compact_count, dim3(128, n_inst), dim3(256), 0, s, inst, acc);
-  hipLaunchKernelGGL(k_compact_movers, dim3(128, n_inst), dim3(256), 0, s, inst, acc, movers);
-  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, dim3(128, n_inst), dim3(256), 0, s, inst, acc, movers);
-  else hipLaunchKernelGGL(k_compact_fill<false>, dim3(128, n_inst), dim3(256), 0, s, inst, acc, movers);
+  // blocks per instance: enough to stream one large instance at full bandwidth; blocks past an
+  // instance's photons (or of an instance with nothing to remove) return at once
+  const dim3 g(n_inst == 1 ? 2048 : 256, n_inst);
+  hipLaunchKernelGGL(k_compact_count, g, dim3(256), 0, s, inst, acc);
+  hipLaunchKernelGGL(k_compact_movers, g, dim3(256), 0, s, inst, acc, movers);
+  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers);
+  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers);
   hipLaunchKernelGGL(k_compact_finish, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
 }
 
