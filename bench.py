@@ -31,8 +31,12 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(form, kind, led0, led1):
+def kernel_bytes(form, kind, led0, led1, grid=False):
     """Algorithmic HBM bytes of one kernel class over the timed region.
+
+    grid=True (the 2-D grid workload, FP64): lepton full step 48 B read (x, y, u, tau) + 48 B
+    written; photon slot 44 B (k, x and y at birth, birth step), the gather of the FP32 grid not
+    counted (the 201 MB grid is read from the cache hierarchy, its refresh is the set-up class).
 
     Lepton sweep, per particle-step in 3-D: with the full push 56 B read (x, u, tau) + 56 B
     written in FP64 (FP32-mixed: the same 112 B as hi/lo words of position and momentum plus
@@ -46,6 +50,10 @@ def kernel_bytes(form, kind, led0, led1):
     + 8 B per queued pair event.  The pair pass (separate class) reads the event's photon and
     writes the two leptons."""
     d = lambda k, i=None: (led1[k][i] - led0[k][i]) if i is not None else (led1[k] - led0[k])
+    if grid:
+        if kind == "lepton":
+            return (d("particle_steps", 0) + d("particle_steps", 1)) * 96 + (d("n_emit") + d("n_null")) * 16
+        return d("particle_steps", 2) * 44 + d("photon_steps_in_field") * 16 + d("n_pair") * 8
     if kind == "lepton":
         steps = d("particle_steps", 0) + d("particle_steps", 1)
         full = d("lepton_steps_in_field")
@@ -128,6 +136,33 @@ def tuned_launch(form, args, tables):
     return res
 
 
+def size_grid(w, tables, args, probe_n=100_000):
+    """Steps until the grid workload's population reaches 4x the initial electrons, and buffer
+    capacities, from a probe run of the first `probe_n` electrons (uniformly spread over the
+    grid, so their yields per electron are those of the full run)."""
+    from paper_1311_5551_amd import capi, workloads as W
+    from paper_1311_5551_amd.sim import Run
+    p = W.subset(w, range(min(w.n, probe_n)))
+    p.capacity = dict(electron=20 * p.n + 4096, positron=20 * p.n + 4096, photon=40 * p.n + 4096)
+    run = Run(p, tables, precision=capi.QED_FP64)
+    log("grid: probe run of %d electrons to find the 4x step" % p.n)
+    k = 0
+    while k < 2000:
+        run.step(1)
+        k += 1
+        led = run.ledger()[0]
+        if led["status"] != "QED_OK":
+            raise RuntimeError("grid probe run: %s" % led["status"])
+        if sum(led["count"]) >= 4 * p.n:
+            break
+    run.close()
+    y = [c / p.n for c in led["count"]]
+    w.capacity = dict(electron=int(1.3 * y[0] * w.n) + 4096, positron=int(1.3 * y[1] * w.n) + 4096,
+                      photon=int(1.3 * y[2] * w.n) + 4096)
+    log("grid: %d steps, yields per electron %s" % (k, [round(v, 3) for v in y]))
+    return k
+
+
 def size_batched(ws, tables, args, probe_n=64):
     """Buffer capacities of the batched instances from a probe run: the first `probe_n`
     electrons of every instance (the same families as in the full run) through the whole
@@ -163,7 +198,15 @@ def run_form(form, args, tables, tuned):
     from paper_1311_5551_amd.sim import Run
 
     batched = form == "batched"
-    if not batched:
+    if form == "grid":
+        w = W.grid_config3(n=args.grid_electrons)
+        steps = size_grid(w, tables, args)
+        ws, warmup = [w], 0
+        workload = ("grid_cp_standing_a500: %d electrons at rest, uniform over a periodic 4096x2048 FP32 Yee grid "
+                    "(dx = lambda/128), standing wave of two CP lasers a0=500 refreshed analytically each step, "
+                    "first-order gather, 2D3V, FP64 particles, dt=lambda/400c, steps 0..%d (until the population "
+                    "reaches 4x)" % (w.n, steps))
+    elif not batched:
         total = args.warmup + args.steps
         w = W.collision_config2(n=args.electrons, n_steps=max(total, 20000))
         ws = [w]
@@ -181,7 +224,7 @@ def run_form(form, args, tables, tuned):
                     "gamma0 log-U[500,5000], FP32-mixed, steps %d..4000 of a 4000-step window centred on the "
                     "collisions, hipGraph replay of %d-step graphs, compaction every %d"
                     % (args.batched_scale, sum(w.n for w in ws), warmup, args.compact_every, args.compact_every))
-    prec = capi.QED_FP64 if form == "fp64" else capi.QED_FP32_MIXED
+    prec = capi.QED_FP64 if form in ("fp64", "grid") else capi.QED_FP32_MIXED
     log("%s: allocating and binding (%s)" % (form, workload[:60]))
     run = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
     if tuned is not None:
@@ -255,7 +298,7 @@ def run_form(form, args, tables, tuned):
     if batched:
         res["kernel_timing_window"] = "%d eager steps after the timed window" % args.batched_profile_steps
     kind = "photon" if ms[2] >= ms[1] else "lepton"
-    byts = kernel_bytes("fp64" if form == "fp64" else "fp32", kind, lk0, lk1)
+    byts = kernel_bytes("fp64" if form in ("fp64", "grid") else "fp32", kind, lk0, lk1, grid=form == "grid")
     n_l = launches[2] if kind == "photon" else launches[1]
     avg_s = (ms[2] if kind == "photon" else ms[1]) / max(n_l, 1) * 1e-3
     achieved = byts / max(n_l, 1) / avg_s / 1e9
@@ -309,7 +352,8 @@ def main():
     ap.add_argument("--compact-every", type=int, default=100)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--ppt", type=int, default=4)
-    ap.add_argument("--forms", default="fp64", help="comma list of fp64, fp32, batched; the first is `value`")
+    ap.add_argument("--forms", default="fp64,fp32,batched,grid",
+                    help="comma list of fp64, fp32, batched, grid; the first gives `value` and `roofline`")
     ap.add_argument("--cpu-families", type=int, default=1500)
     ap.add_argument("--tune", choices=("auto", "replica", "none"), default="auto",
                     help="sweep launch shapes per form: auto = the tuned shapes cached in "
@@ -319,6 +363,7 @@ def main():
     ap.add_argument("--tune-at", default="5000,10000,11500,13000,14500,16000,17500,19000",
                     help="steps of the tuning run at which trials run (population-weighted sum)")
     ap.add_argument("--batched-scale", type=float, default=0.1)
+    ap.add_argument("--grid-electrons", type=int, default=16_000_000)
     ap.add_argument("--batched-warmup", type=int, default=200)
     ap.add_argument("--batched-profile-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -349,7 +394,7 @@ def main():
     tuned = {}
     results = []
     for f in forms:
-        key = "fp64" if f == "fp64" else "fp32"
+        key = "fp64" if f in ("fp64", "grid") else "fp32"
         if args.tune != "none" and key not in tuned:
             tuned[key] = tuned_launch(key, args, tables)
         results.append(run_form(f, args, tables, tuned.get(key)))

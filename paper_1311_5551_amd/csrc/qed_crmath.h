@@ -140,16 +140,27 @@ __device__ __noinline__ void cr_sincos(double x, double* sn, double* cs) {
   *cs = q == 0 ? cv : q == 1 ? -sv : q == 2 ? -cv : sv;
 }
 
-__device__ inline double cr_sin(double x) {
-  double s, c;
-  cr_sincos(x, &s, &c);
-  return s;
+// sin(x + qs pi/2) alone: the same reduction and the same double-double polynomial as the
+// matching output of cr_sincos (so the same bits), with only the polynomial the quadrant needs
+// evaluated.  qs = 0: sin, qs = 1: cos.
+__device__ __noinline__ double cr_sinq(double x, int qs) {
+  if (!(fabs(x) < 1048576.0)) return qs ? cos(x) : sin(x);
+  const double k = rint(x * kTwoOverPi);
+  dd r = dd_add(dd{x - k * kPio2A, 0.0}, dd_two_prod(-k, kPio2B));
+  r = dd_fast_two_sum(r.hi, r.lo - k * kPio2C);
+  const dd r2 = dd_mul(r, r);
+  const dd mr2 = {-r2.hi, -r2.lo};
+  const int q = (((int)fmod(k, 4.0) + 4) + qs) & 3;
+  const bool odd = (q & 1) == 0;  // true: sin r series (odd factorials), false: cos r series
+  dd p = odd ? c_inv_fact[29] : c_inv_fact[28];
+#pragma unroll
+  for (int n = 13; n >= 0; --n) p = dd_add(dd_mul(p, mr2), odd ? c_inv_fact[2 * n + 1] : c_inv_fact[2 * n]);
+  if (odd) p = dd_mul(p, r);
+  const double v = p.hi + p.lo;
+  return (q & 2) ? -v : v;
 }
 
-__device__ inline double cr_cos(double x) {
-  double s, c;
-  cr_sincos(x, &s, &c);
-  return c;
-}
+__device__ inline double cr_sin(double x) { return cr_sinq(x, 0); }
+__device__ inline double cr_cos(double x) { return cr_sinq(x, 1); }
 
 }  // namespace qedk
