@@ -205,7 +205,8 @@ def run_form(form, args, tables, tuned):
         workload = ("grid_cp_standing_a500: %d electrons at rest, uniform over a periodic 4096x2048 FP32 Yee grid "
                     "(dx = lambda/128), standing wave of two CP lasers a0=500 refreshed analytically each step, "
                     "first-order gather, 2D3V, FP64 particles, dt=lambda/400c, steps 0..%d (until the population "
-                    "reaches 4x)" % (w.n, steps))
+                    "reaches 4x), particles sorted by 8x8-cell tile every %d steps"
+                    % (w.n, steps, args.grid_sort_every))
     elif not batched:
         total = args.warmup + args.steps
         w = W.collision_config2(n=args.electrons, n_steps=max(total, 20000))
@@ -256,6 +257,8 @@ def run_form(form, args, tables, tuned):
                 log("%s: step %d" % (form, step))
     else:
         for i in range(steps):
+            if form == "grid" and i % args.grid_sort_every == 0:
+                run.sort()  # tile order for the grid gathers, inside the timed region
             run.step(1)
             step += 1
             if step % args.compact_every == 0:
@@ -364,6 +367,7 @@ def main():
                     help="steps of the tuning run at which trials run (population-weighted sum)")
     ap.add_argument("--batched-scale", type=float, default=0.1)
     ap.add_argument("--grid-electrons", type=int, default=16_000_000)
+    ap.add_argument("--grid-sort-every", type=int, default=10, help="grid form: steps between spatial sorts")
     ap.add_argument("--batched-warmup", type=int, default=200)
     ap.add_argument("--batched-profile-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")

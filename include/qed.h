@@ -197,6 +197,15 @@ qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_
 qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params,
                    int64_t n_steps, int32_t graph_steps, qed_stream stream);
 
+/* Reorders the particles of every bound instance with a grid field (QED_FIELD_GRID_CP_STANDING)
+ * by 8 x 8-cell tile of their position (photons: position at the start of the next step, using
+ * params->dt), so that neighbouring particles gather from the same grid cache lines.  A counting
+ * sort and a permutation of every array of each species; the order within a tile is not
+ * specified, per-uid results of later steps are unchanged.  Allocates its scratch on the first
+ * call that needs it (synchronising `stream`), then is async; up to 2^32 - 1 slots per species
+ * (QED_ERR_ARG beyond).  Instances with analytic fields are left as they are. */
+qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream stream);
+
 /* Removes dead photons (tau < 0) from every bound photon species by moving live photons from
  * the tail into the holes (order is not preserved).  Async. */
 qed_status qed_compact(qed_workspace* ws, qed_stream stream);

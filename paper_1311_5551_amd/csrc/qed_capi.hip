@@ -4,6 +4,7 @@
 // runs in the kernels of qed_tables.hip, qed_step.hip and qed_mixed.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -106,6 +107,8 @@ struct qed_workspace {
   int64_t evq_cap = 0;
   EmitEv* d_emq = nullptr;
   int64_t emq_cap = 0;
+  SortScratch sort;  // allocated by the first qed_sort that needs it
+  int64_t sort_cap = 0;
   int64_t* d_base = nullptr;  // 3 * max_inst: leptons (2 per instance) then photons
   int64_t* d_movers = nullptr;
   size_t movers_len = 0;
@@ -510,6 +513,10 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->d_evc);
   hipFree(ws->d_evq);
   hipFree(ws->d_emq);
+  hipFree(ws->sort.key);
+  hipFree(ws->sort.dst);
+  hipFree(ws->sort.hist);
+  hipFree(ws->sort.stage);
   hipFree(ws->d_base);
   hipFree(ws->d_movers);
   delete ws;
@@ -619,6 +626,10 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
   if (leptons < 1) leptons = 1;
   if (leptons > ws->emq_cap) {
     hipFree(ws->d_emq);
+  hipFree(ws->sort.key);
+  hipFree(ws->sort.dst);
+  hipFree(ws->sort.hist);
+  hipFree(ws->sort.stage);
     ws->d_emq = nullptr;
     ws->emq_cap = 0;
     HIP_TRY(hipMalloc((void**)&ws->d_emq, (size_t)leptons * sizeof(EmitEv)));
@@ -706,6 +717,48 @@ qed_status qed_profile(qed_workspace* ws, int32_t enable) {
   ws->profiling = enable != 0;
   ws->ev_marks.clear();
   ws->ev_used = 0;
+  return QED_OK;
+}
+
+qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream stream) {
+  if (!ws || !params) return fail(QED_ERR_ARG, "NULL argument");
+  if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
+  if (!(params->dt > 0.0) || !std::isfinite(params->dt)) return fail(QED_ERR_ARG, "dt must be positive");
+  int64_t cap = 0;
+  int tiles = 0;
+  for (const qed_instance& I : ws->inst) {
+    if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    for (int s = 0; s < 3; ++s) cap = std::max<int64_t>(cap, I.s[s].capacity);
+    tiles = std::max(tiles, ((I.field.nx + 7) / 8) * ((I.field.ny + 7) / 8));
+  }
+  if (cap == 0) return QED_OK;  // no grid instance: nothing to reorder
+  if (cap >= (int64_t(1) << 32)) return fail(QED_ERR_ARG, "qed_sort handles up to 2^32 - 1 slots per species");
+  HIP_TRY(hipSetDevice(ws->device));
+  if (cap > ws->sort_cap || tiles > ws->sort.hist_len) {
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    hipFree(ws->sort.key);
+    hipFree(ws->sort.dst);
+    hipFree(ws->sort.hist);
+    hipFree(ws->sort.stage);
+    ws->sort = SortScratch();
+    ws->sort_cap = 0;
+    HIP_TRY(hipMalloc((void**)&ws->sort.key, (size_t)cap * sizeof(int32_t)));
+    HIP_TRY(hipMalloc((void**)&ws->sort.dst, (size_t)cap * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc((void**)&ws->sort.hist, (size_t)tiles * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc(&ws->sort.stage, (size_t)cap * 8));
+    ws->sort.hist_len = tiles;
+    ws->sort_cap = cap;
+  }
+  const bool mixed = ws->prec == QED_FP32_MIXED;
+  for (int ii = 0; ii < ws->n_inst; ++ii) {
+    const qed_instance& I = ws->inst[ii];
+    if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    for (int s = 0; s < 3; ++s) {
+      if (I.s[s].capacity == 0) continue;
+      HIP_TRY(launch_sort_species(ws->d_inst, I, ii, s, ws->d_glob, params->dt, mixed, ws->sort, ws->cus * 8,
+                                  (hipStream_t)stream));
+    }
+  }
   return QED_OK;
 }
 

@@ -204,7 +204,12 @@ __device__ __forceinline__ double optical_depth(uint64_t r) { return -cr_log(uni
 // fields at a point (FP64); the grid kind gathers FP32 node values with CIC weights
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t wrap_index(int64_t i, int n) {
-  int64_t r = i % n;
+  // periodic index in [0, n): the in-range and one-off cases (almost every particle) without the
+  // 64-bit remainder, which the GPU evaluates in software
+  if (i >= 0 && i < n) return i;
+  if (i == -1) return n - 1;
+  if (i == n) return 0;
+  const int64_t r = i % n;
   return r < 0 ? r + n : r;
 }
 
@@ -345,6 +350,23 @@ __device__ __forceinline__ FieldK field_k(const qed_field& F) {
   return k;
 }
 constexpr double kInvTwoPi = 0.15915494309189533577;
+
+// An upper bound of |E| + |B| anywhere in a field (grid kind: the standing wave its refresh
+// writes; bilinear weights keep interpolated values within the node values).  Since
+// chi = (eps/2)(|E + n x B|^2 - (n.E)^2)^(1/2) <= (eps/2)(|E| + |B|), photons with
+// eps < 2 chi_min / bound see no pair rate (T = 0 below the table).
+__device__ __forceinline__ double field_bound(const qed_field& F) {
+  switch (F.kind) {
+    case QED_FIELD_UNIFORM:
+      return sqrt(F.p[0] * F.p[0] + F.p[1] * F.p[1] + F.p[2] * F.p[2]) +
+             sqrt(F.p[3] * F.p[3] + F.p[4] * F.p[4] + F.p[5] * F.p[5]);
+    case QED_FIELD_LP_PULSE:
+    case QED_FIELD_CP_WAVE:
+      return 2.0 * fabs(F.p[0]);
+    default:  // standing waves: |E|, |B| <= 2 a each
+      return 4.0 * fabs(F.p[0]);
+  }
+}
 
 template <int FK, bool EXACT = true>
 __device__ __forceinline__ void field_at(const qed_field& F, double x, double y, double t, double E[3],
@@ -542,6 +564,29 @@ __device__ __forceinline__ long long wave_reserve(bool want, int64_t* counter) {
   if (lane == leader) base = (long long)atomicAdd((unsigned long long*)counter, (unsigned long long)total);
   base = __shfl(base, leader);
   return want ? base + prefix : -1;
+}
+
+// Slots for the block's `want` lanes from one counter with one atomic per block: wave counts by
+// ballot, their prefix in LDS, one atomicAdd by thread 0.  Every thread of the block must call it
+// the same number of times (it synchronises); s_wave holds >= 16 entries.
+__device__ inline long long block_reserve(bool want, int64_t* counter, unsigned* s_wave, long long* s_base) {
+  const unsigned long long m = __ballot(want);
+  const int lane = __lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) s_wave[wv] = (unsigned)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned tot = 0;
+    for (int w = 0; w < nw; ++w) {
+      const unsigned c = s_wave[w];
+      s_wave[w] = tot;
+      tot += c;
+    }
+    *s_base = tot ? (long long)atomicAdd((unsigned long long*)counter, (unsigned long long)tot) : 0;
+  }
+  __syncthreads();
+  const long long r = want ? *s_base + s_wave[wv] + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+  __syncthreads();  // s_wave and s_base are reused by the next call
+  return r;
 }
 
 // wave_reserve for lanes whose counters may differ: lanes are served one key (counter) at a time.

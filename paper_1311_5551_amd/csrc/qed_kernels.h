@@ -21,7 +21,18 @@ struct StepArgs {
   EmitQueue qe;               // emission events of the step (lepton passes)
 };
 
+// scratch of the spatial sort (sized by the caller for the largest species and tile count)
+struct SortScratch {
+  int32_t* key = nullptr;
+  uint32_t* dst = nullptr;
+  uint32_t* hist = nullptr;
+  int hist_len = 0;
+  void* stage = nullptr;  // 8 bytes per slot
+};
+
 hipError_t init_crmath();
+hipError_t launch_sort_species(const qed_instance* inst_dev, const qed_instance& inst_host, int ii, int s,
+                               const Glob* glob, double dt, bool mixed, const SortScratch& w, int grid, hipStream_t st);
 hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnchi_min, double* dlnchi, double* P,
                                double* T, double* fgrid, double* Pf, double* knorm, hipStream_t s);
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,

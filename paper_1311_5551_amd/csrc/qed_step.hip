@@ -97,27 +97,38 @@ __device__ __forceinline__ int find_entry(const int64_t* __restrict__ base, int 
 // ---------------------------------------------------------------------------
 __global__ void k_grid_refresh(const qed_instance* __restrict__ inst, int n_inst, const Glob* __restrict__ glob,
                                StepConst sc) {
+  // the wave is uniform in y: one thread per column and strip of kRows rows evaluates the two
+  // column factors once and writes the strip (consecutive threads: consecutive columns)
+  constexpr int kRows = 16;
   const double t = sc.t0 + (double)glob->step_cur * sc.dt;
+  double st, ct;
+  cr_sincos(t, &st, &ct);
   for (int ii = 0; ii < n_inst; ++ii) {
     const qed_field& F = inst[ii].field;
     if (F.kind != QED_FIELD_GRID_CP_STANDING) continue;
     const int64_t plane = (int64_t)F.nx * F.ny;
-    double st, ct;
-    cr_sincos(t, &st, &ct);
+    const int64_t strips = (F.ny + kRows - 1) / kRows;
     const double e2 = 2.0 * F.p[0];
-    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < plane; q += (int64_t)gridDim.x * blockDim.x) {
-      const int64_t i = q % F.nx;
-      // components at x offsets 0 (Ey, Ez, Bx) and 1/2 (Ex, By, Bz); the wave is uniform in y
+    gptr<float> g = as_global(F.grid_dev);
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < F.nx * strips;
+         q += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t i = q % F.nx, j0 = (q / F.nx) * kRows;
+      // components at x offsets 0 (Ey, Ez, Bx) and 1/2 (Ex, By, Bz)
       const double xa = F.x0 + (double)i * F.dx;
       const double xb = F.x0 + ((double)i + 0.5) * F.dx;
       const double ca = cr_cos(xa), cb = cr_sin(xb);
-      float* g = F.grid_dev;
-      g[q] = 0.0f;                                          // Ex
-      g[plane + q] = (float)(e2 * ct * ca);                 // Ey(i, j+1/2)
-      g[2 * plane + q] = (float)(e2 * st * ca);             // Ez(i, j)
-      g[3 * plane + q] = 0.0f;                              // Bx
-      g[4 * plane + q] = (float)(e2 * ct * cb);             // By(i+1/2, j)
-      g[5 * plane + q] = (float)(e2 * st * cb);             // Bz(i+1/2, j+1/2)
+      const float ey = (float)(e2 * ct * ca), ez = (float)(e2 * st * ca);
+      const float by = (float)(e2 * ct * cb), bz = (float)(e2 * st * cb);
+      const int64_t j1 = min((int64_t)F.ny, j0 + kRows);
+      for (int64_t j = j0; j < j1; ++j) {
+        const int64_t c = j * F.nx + i;
+        g[c] = 0.0f;              // Ex
+        g[plane + c] = ey;        // Ey(i, j+1/2)
+        g[2 * plane + c] = ez;    // Ez(i, j)
+        g[3 * plane + c] = 0.0f;  // Bx
+        g[4 * plane + c] = by;    // By(i+1/2, j)
+        g[5 * plane + c] = bz;    // Bz(i+1/2, j+1/2)
+      }
     }
   }
 }
@@ -150,6 +161,8 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double smem[];
   __shared__ qed_field sF;
+  __shared__ unsigned s_wave[16];  // queue reservation: wave offsets, block base
+  __shared__ long long s_base;
   double* sh = smem;
   float* sh32 = (float*)smem;
   double* sred = smem + a.tb.n_eta;
@@ -371,7 +384,9 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
       return pend;
     };
     auto enqueue = [&](unsigned off, bool pend, double eta) {
-      const long long slot = wave_reserve(pend, &a.qe.ctl->count);
+      // one atomic per block: with a few percent of leptons emitting per step nearly every wave
+      // has an event, and per-wave atomics on the one queue counter would serialise
+      const long long slot = block_reserve(pend, &a.qe.ctl->count, s_wave, &s_base);
       if (pend) {
         if (slot < a.qe.cap) {
           a.qe.ent[slot].key = ((uint64_t)(cur >> 1) << 41) | ((uint64_t)(cur & 1) << 40) | (uint64_t)(k0 + off);
@@ -627,6 +642,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   gptr<double> TAU = nullptr;
   float tpf0 = 0.0f, psif_max = 0.0f;
   FieldK fK{0.0};
+  double eps_min = 0.0;          // photons below this energy have no pair rate in this field
   unsigned uacc[3] = {0, 0, 0};  // in-field steps, chi above the table, non-finite tau
   auto flush = [&](int ii) {
     block_sum_u(uacc, sredu);
@@ -666,6 +682,8 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       tpf0 = (float)sF.p[2];
       psif_max = (float)sF.p[1];
       fK.pi_over_len = uni_f64(field_k(sF).pi_over_len);
+      // margin: FP32 rounding of the energy test (~1e-7) and of chi (~1e-15)
+      eps_min = uni_f64(2.0 * a.tb.cp_min / field_bound(sF) * (1.0 - 1e-5));
     }
     const int64_t k0 = uni64((c - cb) * CH);  // first slot of the chunk
     const int64_t rem = n - k0;        // slots of the chunk that exist: min(rem, CH)
@@ -752,12 +770,10 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
         xbf[j] = (float)buf_ld<Real>(rxb, o);
         bs[j] = buf_ld<int32_t>(rbs, off * 4u);
       }
-      // A second exact cull: in the pulse |E| = |B| <= a (the amplitude) and chi = (eps/2)|e||1 - n_x|
-      // <= eps a, while T(chi) = 0 below the table's chi_min; a photon with eps a below chi_min
-      // (with the same relative margin) has no pair rate anywhere in the pulse.
+      // A second exact cull: a photon below eps_min (field_bound) has no pair rate anywhere.
       const float tpf = (float)t - tpf0;
       const float mt = fabsf((float)t) + fabsf(tpf0);
-      const float eps_min = (float)(a.tb.cp_min / fabs(sF.p[0])) * (1.0f - 1e-5f);
+      const float eps_minf = (float)eps_min;
       unsigned gmask = 0;
 #pragma unroll
       for (int j = 0; j < PPT; ++j) {
@@ -769,7 +785,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
           const float agef = (float)((double)(step - (int64_t)bs[j]) * dt);
           const float psif = tpf - (xbf[j] + agef * nxf);
           const float m = 1e-5f * (mt + fabsf(xbf[j]) + agef) + 1e-30f;
-          if (psif >= -m && psif <= psif_max + m && k2 * rk >= eps_min) gmask |= 1u << j;
+          if (psif >= -m && psif <= psif_max + m && k2 * rk >= eps_minf) gmask |= 1u << j;
         }
       }
       // phase 2: the photons inside the pulse, packed densely across the wave through a per-wave
@@ -828,8 +844,10 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       for (int j = 0; j < PPT; ++j) {
         const unsigned off = threadIdx.x + j * B;
         bool pend = false;
-        if ((int64_t)off < rem) pend = infield(off, kx[j], ky[j], kz[j], NEED_X ? xb[j] : Real(0),
-                                               NEED_Y ? yb[j] : Real(0), NEED_X ? bs[j] : 0);
+        const double k2 = (double)kx[j] * kx[j] + (double)ky[j] * ky[j] + (double)kz[j] * kz[j];
+        if ((int64_t)off < rem && k2 >= eps_min * eps_min)  // no pair rate below eps_min
+          pend = infield(off, kx[j], ky[j], kz[j], NEED_X ? xb[j] : Real(0), NEED_Y ? yb[j] : Real(0),
+                         NEED_X ? bs[j] : 0);
         enqueue(off, pend);
       }
     }

@@ -202,6 +202,9 @@ class Run:
     def compact(self):
         capi.qed_compact(self.ws, self._s())
 
+    def sort(self):
+        capi.qed_sort(self.ws, self.params, self._s())
+
     def ledger(self):
         st, led = capi.qed_energy_ledger(self.ws, len(self.insts), self._s())
         for d in led:

@@ -205,6 +205,38 @@ def test_autotuned_shapes_leave_particles_unchanged(shared_tables):
     _states_equal(ra, rb)
 
 
+def test_spatial_sort_reorders_without_changing_particles(shared_tables):
+    # grid workload: sorting by tile keeps every particle (per uid, bit for bit) and the steps
+    # after it give the same particles as steps without sorting
+    def make():
+        w = W.grid_config3(n=3000, nx=256, ny=64, n_steps=200, seed=2)
+        w.capacity = dict(electron=20 * w.n, positron=20 * w.n, photon=100 * w.n)
+        return w, Run(w, shared_tables)
+    _, ra = make()
+    _, rb = make()
+    ra.step(100)
+    rb.step(100)
+    before = {name: rb.species(0, name) for name in ("electron", "positron", "photon")}
+    rb.sort()
+    for name, b in before.items():
+        a = rb.species(0, name)
+        assert len(a["uid"]) == len(b["uid"])
+        oa, ob = np.argsort(a["uid"]), np.argsort(b["uid"])
+        for k in b:
+            np.testing.assert_array_equal(a[k][oa], b[k][ob], err_msg="%s.%s" % (name, k))
+    # the sort moved electrons into tile order: cell-row keys are non-decreasing in slot order
+    e = rb.species(0, "electron")
+    tile = (np.floor(e["y"] / (2 * np.pi / 128)).astype(np.int64) % 64 // 8) * 32 + \
+        (np.floor(e["x"] / (2 * np.pi / 128)).astype(np.int64) % 256 // 8)
+    assert np.all(np.diff(tile) >= 0)
+    for _ in range(10):
+        ra.step(10)
+        rb.step(10)
+        rb.sort()
+    _states_equal(ra, rb)
+    assert ra.ledger()[0]["status"] == rb.ledger()[0]["status"] == "QED_OK"
+
+
 def test_restart_from_saved_state_is_exact(shared_tables):
     w, ra = _collision_run(shared_tables, n=1500)
     ra.step(2600)
