@@ -22,6 +22,8 @@ _LIB = None
 FLAG_EMIT = 1
 FLAG_PAIRS = 2
 FLAG_PROPAGATE = 4
+FLAG_RR_QUANTUM = 8      # continuous radiation reaction, power P_c g(eta) (eqs. 8, 9, Appendix A)
+FLAG_RR_CLASSICAL = 16   # continuous radiation reaction, classical power (g = 1)
 
 FIELD_UNIFORM = 0
 FIELD_LP_PULSE = 1
@@ -57,7 +59,8 @@ class _Tables(C.Structure):
                 ("dlnchi", C.POINTER(C.c_double)), ("P_chi", C.POINTER(C.c_double)),
                 ("n_chi_pair", C.c_int32), ("chi_pair_min", C.c_double), ("chi_pair_max", C.c_double),
                 ("T", C.POINTER(C.c_double)), ("n_f", C.c_int32),
-                ("f_grid", C.POINTER(C.c_double)), ("P_f", C.POINTER(C.c_double))]
+                ("f_grid", C.POINTER(C.c_double)), ("P_f", C.POINTER(C.c_double)),
+                ("g", C.POINTER(C.c_double))]
 
 
 _DP = C.POINTER(C.c_double)
@@ -74,7 +77,8 @@ class _Ledger(C.Structure):
     _fields_ = [("energy0", C.c_double * 3), ("energy", C.c_double * 3), ("count", C.c_int64 * 3),
                 ("work", C.c_double), ("defect_emit", C.c_double), ("defect_pair", C.c_double),
                 ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
-                ("n_range", C.c_int64), ("n_nonfinite", C.c_int64), ("particle_steps", C.c_int64)]
+                ("n_range", C.c_int64), ("n_nonfinite", C.c_int64), ("particle_steps", C.c_int64),
+                ("radiated", C.c_double)]
 
 
 def lib():
@@ -98,7 +102,7 @@ def lib():
         L.oracle_philox.argtypes = [C.POINTER(C.c_uint64)] * 3
         L.oracle_philox.restype = None
         L.oracle_gauss_legendre.argtypes = [C.c_int, _DP, _DP]
-        L.oracle_build_tables.argtypes = [C.POINTER(_TableParams)] + [_DP] * 8
+        L.oracle_build_tables.argtypes = [C.POINTER(_TableParams)] + [_DP] * 9
         L.oracle_build_tables.restype = C.c_int
         L.oracle_run.argtypes = [C.POINTER(_Config), C.POINTER(_Tables), C.POINTER(_Species),
                                  C.POINTER(_Species), C.POINTER(_Ledger)]
@@ -185,17 +189,18 @@ DEFAULT_TABLE_PARAMS = dict(n_eta=256, eta_min=1e-4, eta_max=1e2, n_chi=256, cut
 
 
 def build_tables(**overrides) -> dict:
-    """The look-up tables of Sec. 3 (h, T_pm, P_chi, P_f) as numpy arrays."""
+    """The look-up tables of Sec. 3 (h, T_pm, P_chi, P_f) and g(eta) of Appendix A as numpy arrays."""
     p = dict(DEFAULT_TABLE_PARAMS)
     p.update(overrides)
     tp = _TableParams(**p)
     ne, nc, npair, nf = p["n_eta"], p["n_chi"], p["n_chi_pair"], p["n_f"]
     t = dict(params=p,
              h=np.empty(ne), lnchi_min=np.empty(ne), dlnchi=np.empty(ne), P_chi=np.empty((ne, nc)),
-             T=np.empty(npair), f_grid=np.empty(nf), P_f=np.empty((npair, nf)), k_norm=np.empty(npair))
+             T=np.empty(npair), f_grid=np.empty(nf), P_f=np.empty((npair, nf)), k_norm=np.empty(npair),
+             g=np.empty(ne))
     rc = lib().oracle_build_tables(C.byref(tp), *[t[k].ctypes.data_as(_DP) for k in
                                                   ("h", "lnchi_min", "dlnchi", "P_chi", "T", "f_grid",
-                                                   "P_f", "k_norm")])
+                                                   "P_f", "k_norm", "g")])
     if rc != 0:
         raise ValueError("oracle_build_tables rejected its parameters")
     return t
@@ -268,6 +273,10 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
                   chi_pair_min=p["chi_pair_min"], chi_pair_max=p["chi_pair_max"],
                   T=tables["T"].ctypes.data_as(_DP), n_f=p["n_f"],
                   f_grid=tables["f_grid"].ctypes.data_as(_DP), P_f=tables["P_f"].ctypes.data_as(_DP))
+    g_arr = None
+    if tables.get("g") is not None:
+        g_arr = np.ascontiguousarray(tables["g"], dtype=np.float64)  # held for the call
+        tab.g = g_arr.ctypes.data_as(_DP)
     conf = _Config()
     conf.field_kind = cfg.field_kind
     fp = list(cfg.field) + [0.0] * (16 - len(cfg.field))
@@ -313,6 +322,8 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
         rc = L.oracle_run(C.byref(conf), C.byref(tab), ins, outs, C.byref(led))
         if rc == 0:
             break
+        if rc == -2:
+            raise ValueError("oracle_run: inconsistent radiation-reaction flags (or no g table)")
         # outputs did not fit: retry with the sizes the oracle reported (same result, deterministic)
         cap = [int(outs[i].count) + 1 for i in range(3)]
     else:
@@ -326,6 +337,7 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
             res[name].pop("z")
     ledger = dict(energy0=list(led.energy0), energy=list(led.energy), count=list(led.count),
                   work=led.work, defect_emit=led.defect_emit, defect_pair=led.defect_pair,
+                  radiated=led.radiated,
                   n_emit=led.n_emit, n_null=led.n_null, n_pair=led.n_pair, n_range=led.n_range,
                   n_nonfinite=led.n_nonfinite, particle_steps=led.particle_steps)
     return res, ledger

@@ -510,12 +510,13 @@ typedef struct {
 
 // Caller-allocated outputs:
 //   h[n_eta], lnchi_min[n_eta], dlnchi[n_eta], P_chi[n_eta*n_chi],
-//   T[n_chi_pair], f_grid[n_f], P_f[n_chi_pair*n_f], k_norm[n_chi_pair].
+//   T[n_chi_pair], f_grid[n_f], P_f[n_chi_pair*n_f], k_norm[n_chi_pair], and g[n_eta]
+//   (may be NULL): the quantum reduction g(eta_i) of the radiated power (Appendix A).
 // Row i of P_chi holds P(eta_i, chi_ij) on ln chi_ij = lnchi_min[i] + j dlnchi[i],
 // from chi_min (the 1e-9 energy cut) to eta_i/2; P(eta_i, chi_min) is the share of
 // emissions below the cut and the last column is exactly 1.
 int oracle_build_tables(const oracle_table_params* p, double* h, double* lnchi_min, double* dlnchi,
-                        double* P_chi, double* T, double* f_grid, double* P_f, double* k_norm) {
+                        double* P_chi, double* T, double* f_grid, double* P_f, double* k_norm, double* g) {
   const int ne = p->n_eta, nc = p->n_chi, np = p->n_chi_pair, nf = p->n_f;
   if (ne < 2 || nc < 2 || np < 2 || nf < 3) return -1;
   const double le0 = std::log(p->eta_min), le1 = std::log(p->eta_max);
@@ -541,6 +542,7 @@ int oracle_build_tables(const oracle_table_params* p, double* h, double* lnchi_m
     }
     const double hval = cum[nc - 1];
     h[i] = hval;
+    if (g) g[i] = synch_g(eta);
     lnchi_min[i] = smin;
     dlnchi[i] = ds;
     for (int j = 0; j < nc - 1; ++j) P_chi[(size_t)i * nc + j] = cum[j] / hval;
@@ -581,7 +583,13 @@ int oracle_build_tables(const oracle_table_params* p, double* h, double* lnchi_m
 // ============================================================================
 namespace {
 
-enum : uint32_t { FLAG_EMIT = 1u, FLAG_PAIRS = 2u, FLAG_PROPAGATE = 4u };
+enum : uint32_t {
+  FLAG_EMIT = 1u,
+  FLAG_PAIRS = 2u,
+  FLAG_PROPAGATE = 4u,
+  FLAG_RR_QUANTUM = 8u,    // continuous radiation reaction with the quantum reduction g(eta)
+  FLAG_RR_CLASSICAL = 16u  // continuous radiation reaction with the classical power (g = 1)
+};
 enum : uint64_t { KIND_INIT = 0, KIND_EMIT = 1, KIND_PAIR = 2 };
 enum : int32_t {
   FIELD_UNIFORM = 0,      // p[0..2] = E, p[3..5] = B
@@ -595,6 +603,7 @@ struct Tables {
   int n_eta;
   double le0, dle;
   const double* h;
+  const double* g;  // may be null when no step uses FLAG_RR_QUANTUM
   int n_chi;
   const double* lnchi_min;
   const double* dlnchi;
@@ -621,7 +630,7 @@ struct Config {
   int64_t step0, n_steps;
   uint64_t seed, instance;
   uint32_t flags;
-  double kappa, a_gamma, a_pair;
+  double kappa, a_gamma, a_pair, a_rr;
 };
 
 struct Vec3 {
@@ -732,6 +741,19 @@ double lookup_h(const Tables& tb, double eta, int64_t* range_hi) {
   return (1.0 - w) * tb.h[i] + w * tb.h[i + 1];
 }
 
+// g(eta): on the grid of h, interpolated and clamped the same way.
+double lookup_g(const Tables& tb, double eta, int64_t* range_hi) {
+  const double s = (cr_log(eta) - tb.le0) / tb.dle;
+  if (!(s > 0.0)) return tb.g[0];
+  if (s >= tb.n_eta - 1) {
+    ++*range_hi;
+    return tb.g[tb.n_eta - 1];
+  }
+  const int i = (int)std::floor(s);
+  const double w = s - i;
+  return (1.0 - w) * tb.g[i] + w * tb.g[i + 1];
+}
+
 // T(chi): as h, but zero below chi_pair_min where T < 1e-58.
 double lookup_T(const Tables& tb, double chi, int64_t* range_hi) {
   if (!(chi > 0.0)) return 0.0;
@@ -828,6 +850,7 @@ struct Tally {
   double work = 0.0;       // sum of field work on leptons (Boris identity)
   double defect_emit = 0.0;
   double defect_pair = 0.0;
+  double radiated = 0.0;   // energy removed by continuous radiation reaction
   int64_t n_emit = 0, n_null = 0, n_pair = 0, n_range = 0, n_nonfinite = 0;
 };
 
@@ -867,6 +890,25 @@ void step_lepton(Particle& p, const Config& c, const Tables& tb, int64_t n, std:
   p.ux = u1.x;
   p.uy = u1.y;
   p.uz = u1.z;
+
+  if (c.flags & (FLAG_RR_QUANTUM | FLAG_RR_CLASSICAL)) {
+    // continuous radiation reaction: the lepton loses the radiated power P_c g(eta)
+    // (eqs. 8 and 9 with Appendix A's g; g = 1 for the classical power) over dt,
+    // dgamma = -(2/3) alpha kappa eta^2 g dt, along its momentum and never below rest
+    const Vec3 a = g1 * E + cross(u1, B);
+    const double ue = dot(u1, E);
+    const double eta = std::sqrt(std::max(0.0, dot(a, a) - ue * ue));
+    if (eta > 0.0) {
+      const double gfac = (c.flags & FLAG_RR_QUANTUM) ? lookup_g(tb, eta, &tl.n_range) : 1.0;
+      const double g2 = std::max(g1 - c.a_rr * eta * eta * gfac * c.dt, 1.0);
+      const double umag = std::sqrt(dot(u1, u1));
+      const double scale = umag > 0.0 ? std::sqrt((g2 - 1.0) * (g2 + 1.0)) / umag : 0.0;
+      p.ux = scale * u1.x;
+      p.uy = scale * u1.y;
+      p.uz = scale * u1.z;
+      tl.radiated += g1 - gamma_of(p.ux, p.uy, p.uz);
+    }
+  }
 
   if (c.flags & FLAG_EMIT) {
     // eta = |F_{mu nu} p^nu| / (m c E_s) = sqrt(|gamma E + u x B|^2 - (u.E)^2)
@@ -1010,6 +1052,7 @@ typedef struct {
   int32_t n_f;
   const double* f_grid;
   const double* P_f;
+  const double* g;  // g(eta) on the h grid; needed only with the quantum reaction flag
 } oracle_tables;
 
 typedef struct {
@@ -1028,6 +1071,7 @@ typedef struct {
   double work, defect_emit, defect_pair;
   int64_t n_emit, n_null, n_pair, n_range, n_nonfinite;
   int64_t particle_steps;  // live particles advanced, summed over steps
+  double radiated;         // energy removed by continuous radiation reaction
 } oracle_ledger;
 
 // Runs n_steps steps starting at step0 for every family rooted at an input particle.
@@ -1054,12 +1098,17 @@ int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_
   c.kappa = cfg->lambda_L / kLambdaCompton;
   c.a_gamma = std::sqrt(3.0) * kAlpha * c.kappa / (2.0 * kPi);
   c.a_pair = kAlpha * c.kappa;
+  c.a_rr = 2.0 / 3.0 * kAlpha * c.kappa;
+  if ((c.flags & FLAG_RR_QUANTUM) && (c.flags & FLAG_RR_CLASSICAL)) return -2;
+  if ((c.flags & (FLAG_RR_QUANTUM | FLAG_RR_CLASSICAL)) && (c.flags & FLAG_EMIT)) return -2;
+  if ((c.flags & FLAG_RR_QUANTUM) && !tab->g) return -2;
 
   Tables tb;
   tb.n_eta = tab->n_eta;
   tb.le0 = std::log(tab->eta_min);
   tb.dle = (std::log(tab->eta_max) - tb.le0) / (tab->n_eta - 1);
   tb.h = tab->h;
+  tb.g = tab->g;
   tb.n_chi = tab->n_chi;
   tb.lnchi_min = tab->lnchi_min;
   tb.dlnchi = tab->dlnchi;
@@ -1147,6 +1196,7 @@ int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_
     led->work += tl.work;
     led->defect_emit += tl.defect_emit;
     led->defect_pair += tl.defect_pair;
+    led->radiated += tl.radiated;
     led->n_emit += tl.n_emit;
     led->n_null += tl.n_null;
     led->n_pair += tl.n_pair;
