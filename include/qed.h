@@ -41,7 +41,14 @@ typedef enum { QED_FP64 = 0, QED_FP32_MIXED = 1 } qed_precision;
 enum {
   QED_EMIT = 1u,      /* leptons emit photons (Sec. 3: optical depth, P_chi sampling, recoil) */
   QED_PAIRS = 2u,     /* photons create pairs (Sec. 3: optical depth with T_pm, P_f sampling) */
-  QED_PROPAGATE = 4u  /* photons are stepped; without it emitted photons are only recorded (Sec. 3.1) */
+  QED_PROPAGATE = 4u, /* photons are stepped; without it emitted photons are only recorded (Sec. 3.1) */
+  /* Deterministic radiation reaction instead of emission (Sec. 2.4, eqs. 8 and 9): after the push
+   * each lepton loses the energy radiated in the step, dgamma/dt = -(2/3) alpha kappa eta^2 g(eta)
+   * in code time, along its momentum; no photons are made, the energy goes to the ledger's
+   * `radiated`.  QED_RR_QUANTUM uses the quantum reduction g(eta) from the tables, QED_RR_CLASSICAL
+   * g = 1 (the Landau-Lifshitz leading term).  Each excludes QED_EMIT and the other. */
+  QED_RR_QUANTUM = 8u,
+  QED_RR_CLASSICAL = 16u
 };
 
 /* field kinds; p[] parameters in code units */
@@ -80,10 +87,13 @@ typedef struct qed_tables qed_tables; /* opaque, immutable after creation, share
  *   lnchi_min[n_eta], dlnchi[n_eta]  row grids: ln chi_ij = lnchi_min[i] + j dlnchi[i]
  *   P_chi[n_eta][n_chi]           P(eta_i, chi_ij); column 0 is the share below the cut, last is 1
  *   T[n_chi_pair]                 T_pm(chi_k) = 0.16 K_{1/3}^2(2/(3 chi_k)) / chi_k  (Appendix B)
- *   f_grid[n_f], P_f[n_chi_pair][n_f], k_norm[n_chi_pair]   cumulative p_f and its normaliser */
+ *   f_grid[n_f], P_f[n_chi_pair][n_f], k_norm[n_chi_pair]   cumulative p_f and its normaliser
+ *   g[n_eta]                      g(eta_i) = 3 sqrt3 / (2 pi eta_i^2) int_0^{eta_i/2} F dchi, the
+ *                                 quantum reduction of the radiated power (Appendix A, eq. 8) */
 typedef struct {
   qed_table_params params;
   const double *h, *lnchi_min, *dlnchi, *P_chi, *T, *f_grid, *P_f, *k_norm;
+  const double* g;            /* NULL for tables supplied without g */
 } qed_table_view;
 
 /* Builds all tables on the current device (FP64 quadrature of the Appendix A/B integrals) and
@@ -91,11 +101,12 @@ typedef struct {
 qed_status qed_build_tables(const qed_table_params* params, qed_tables** out);
 
 /* Wraps tables supplied as host arrays (e.g. published tables), laid out as in qed_table_view;
- * k_norm may be NULL.  Copies them; the caller keeps its arrays. */
+ * k_norm and g may be NULL (without g, steps with QED_RR_QUANTUM return QED_ERR_STATE).  Copies
+ * them; the caller keeps its arrays. */
 qed_status qed_tables_from_host(const qed_table_params* params, const double* h, const double* lnchi_min,
                                 const double* dlnchi, const double* P_chi, const double* T,
                                 const double* f_grid, const double* P_f, const double* k_norm,
-                                qed_tables** out);
+                                const double* g, qed_tables** out);
 
 qed_status qed_tables_view(const qed_tables* tables, qed_table_view* out);
 void qed_tables_destroy(qed_tables* tables);
@@ -143,7 +154,7 @@ typedef struct {
   double t0;          /* code time of step 0: step n runs from t0 + n dt to t0 + (n+1) dt */
   double dt;
   double lambda_L;    /* laser wavelength (m) that defines the code units */
-  uint32_t flags;     /* QED_EMIT | QED_PAIRS | QED_PROPAGATE */
+  uint32_t flags;     /* QED_EMIT | QED_PAIRS | QED_PROPAGATE | QED_RR_QUANTUM | QED_RR_CLASSICAL */
   qed_precision precision;
 } qed_step_params;
 
@@ -218,6 +229,7 @@ typedef struct {
   double defect_emit;     /* sum over emissions of gamma_after + |k| - gamma_before */
   double defect_pair;     /* sum over pair creations of gamma_- + gamma_+ - |k| */
   double dropped_energy;  /* energy of children that did not fit their buffer */
+  double radiated;        /* energy removed by deterministic radiation reaction (QED_RR_*) */
   int64_t count[3];
   int64_t n_emit, n_null, n_pair;  /* emissions, draws below the cut-off, pair creations */
   int64_t n_dropped, n_range, n_nonfinite;
@@ -228,7 +240,7 @@ typedef struct {
                                       steps since qed_bind (photons: buffer slots, incl. dead ones
                                       not yet compacted, counted in steps with QED_PAIRS, the steps
                                       in which photons are advanced) */
-  double drift;           /* |sum energy - energy0 - work - defects + dropped| / energy0 */
+  double drift;           /* |sum energy - energy0 - work - defects + dropped + radiated| / energy0 */
 } qed_ledger;
 
 /* Fills out[0..n_inst-1] for the bound instances.  Synchronises `stream`.  Returns

@@ -15,6 +15,7 @@ STATUS_NAMES = {0: "QED_OK", -1: "QED_ERR_ARG", -2: "QED_ERR_HIP", -3: "QED_ERR_
                 -4: "QED_ERR_NONFINITE", -5: "QED_ERR_STATE", -6: "QED_ERR_DEVICE"}
 QED_FP64, QED_FP32_MIXED = 0, 1
 QED_EMIT, QED_PAIRS, QED_PROPAGATE = 1, 2, 4
+QED_RR_QUANTUM, QED_RR_CLASSICAL = 8, 16
 QED_PROFILE_CLASSES = 5
 QED_KERNEL_LEPTON, QED_KERNEL_PHOTON = 1, 2
 QED_FIELD_UNIFORM, QED_FIELD_LP_PULSE, QED_FIELD_CP_WAVE, QED_FIELD_CP_STANDING, QED_FIELD_GRID_CP_STANDING = \
@@ -33,7 +34,7 @@ class qed_table_params(C.Structure):
 
 class qed_table_view(C.Structure):
     _fields_ = [("params", qed_table_params), ("h", _DP), ("lnchi_min", _DP), ("dlnchi", _DP), ("P_chi", _DP),
-                ("T", _DP), ("f_grid", _DP), ("P_f", _DP), ("k_norm", _DP)]
+                ("T", _DP), ("f_grid", _DP), ("P_f", _DP), ("k_norm", _DP), ("g", _DP)]
 
 
 class qed_species(C.Structure):
@@ -62,7 +63,7 @@ class qed_step_params(C.Structure):
 class qed_ledger(C.Structure):
     _fields_ = [("energy", C.c_double * 3), ("energy0", C.c_double), ("work", C.c_double),
                 ("defect_emit", C.c_double), ("defect_pair", C.c_double), ("dropped_energy", C.c_double),
-                ("count", C.c_int64 * 3), ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
+                ("radiated", C.c_double), ("count", C.c_int64 * 3), ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
                 ("n_dropped", C.c_int64), ("n_range", C.c_int64), ("n_nonfinite", C.c_int64),
                 ("photon_steps_in_field", C.c_int64), ("lepton_steps_in_field", C.c_int64),
                 ("particle_steps", C.c_int64 * 3), ("drift", C.c_double)]
@@ -78,7 +79,7 @@ class qed_ledger(C.Structure):
 # name -> (restype, argtypes)
 _SIGNATURES = {
     "qed_build_tables": (C.c_int, [C.POINTER(qed_table_params), C.POINTER(_vp)]),
-    "qed_tables_from_host": (C.c_int, [C.POINTER(qed_table_params)] + [_DP] * 8 + [C.POINTER(_vp)]),
+    "qed_tables_from_host": (C.c_int, [C.POINTER(qed_table_params)] + [_DP] * 9 + [C.POINTER(_vp)]),
     "qed_tables_view": (C.c_int, [_vp, C.POINTER(qed_table_view)]),
     "qed_tables_destroy": (None, [_vp]),
     "qed_workspace_create": (C.c_int, [C.c_int32, C.POINTER(_vp)]),
@@ -139,10 +140,11 @@ def qed_build_tables(params: qed_table_params):
     return h
 
 
-def qed_tables_from_host(params, h, lnchi_min, dlnchi, P_chi, T, f_grid, P_f, k_norm=None):
+def qed_tables_from_host(params, h, lnchi_min, dlnchi, P_chi, T, f_grid, P_f, k_norm=None, g=None):
     out = _vp()
     arrs = [h, lnchi_min, dlnchi, P_chi, T, f_grid, P_f]
-    ptrs = [a.ctypes.data_as(_DP) for a in arrs] + [k_norm.ctypes.data_as(_DP) if k_norm is not None else None]
+    ptrs = [a.ctypes.data_as(_DP) for a in arrs] + [a.ctypes.data_as(_DP) if a is not None else None
+                                                    for a in (k_norm, g)]
     check(lib().qed_tables_from_host(C.byref(params), *ptrs, C.byref(out)))
     return out
 

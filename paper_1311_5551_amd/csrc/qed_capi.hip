@@ -81,9 +81,10 @@ struct qed_tables {
   qed_table_params p{};
   int device = 0;
   double *h = nullptr, *lnchi_min = nullptr, *dlnchi = nullptr, *P = nullptr, *T = nullptr, *fgrid = nullptr,
-         *Pf = nullptr, *knorm = nullptr;
+         *Pf = nullptr, *knorm = nullptr, *g = nullptr;
   float *h32 = nullptr, *T32 = nullptr;
-  std::vector<double> hh, hlnchi, hdlnchi, hP, hT, hf, hPf, hk;
+  std::vector<double> hh, hlnchi, hdlnchi, hP, hT, hf, hPf, hk, hg;
+  bool has_g = false;
 };
 
 constexpr int64_t kDefaultEventQueue = int64_t(1) << 20;
@@ -136,6 +137,7 @@ void free_tables(qed_tables* t) {
   hipFree(t->fgrid);
   hipFree(t->Pf);
   hipFree(t->knorm);
+  hipFree(t->g);
   hipFree(t->h32);
   hipFree(t->T32);
   delete t;
@@ -173,7 +175,8 @@ qed_status alloc_tables(qed_tables* t) {
   if ((st = dalloc(&t->h, p.n_eta)) || (st = dalloc(&t->lnchi_min, p.n_eta)) || (st = dalloc(&t->dlnchi, p.n_eta)) ||
       (st = dalloc(&t->P, (size_t)p.n_eta * p.n_chi)) || (st = dalloc(&t->T, p.n_chi_pair)) ||
       (st = dalloc(&t->fgrid, p.n_f)) || (st = dalloc(&t->Pf, (size_t)p.n_chi_pair * p.n_f)) ||
-      (st = dalloc(&t->knorm, p.n_chi_pair)) || (st = dalloc(&t->h32, p.n_eta)) || (st = dalloc(&t->T32, p.n_chi_pair)))
+      (st = dalloc(&t->knorm, p.n_chi_pair)) || (st = dalloc(&t->g, p.n_eta)) || (st = dalloc(&t->h32, p.n_eta)) ||
+      (st = dalloc(&t->T32, p.n_chi_pair)))
     return st;
   return QED_OK;
 }
@@ -190,7 +193,9 @@ qed_status finish_tables(qed_tables* t, bool from_device) {
     t->hf.resize(p.n_f);
     t->hPf.resize((size_t)p.n_chi_pair * p.n_f);
     t->hk.resize(p.n_chi_pair);
+    t->hg.resize(p.n_eta);
     HIP_TRY(hipMemcpy(t->hh.data(), t->h, p.n_eta * 8, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(t->hg.data(), t->g, p.n_eta * 8, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(t->hlnchi.data(), t->lnchi_min, p.n_eta * 8, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(t->hdlnchi.data(), t->dlnchi, p.n_eta * 8, hipMemcpyDeviceToHost));
     HIP_TRY(hipMemcpy(t->hP.data(), t->P, t->hP.size() * 8, hipMemcpyDeviceToHost));
@@ -208,6 +213,8 @@ qed_status finish_tables(qed_tables* t, bool from_device) {
       if (!(P[j] >= 0.0 && P[j] <= 1.0) || (j && P[j] < P[j - 1]))
         return fail(QED_ERR_STATE, "P_chi row %d is not a cumulative distribution at column %d", i, j);
     if (P[p.n_chi - 1] != 1.0) return fail(QED_ERR_STATE, "P_chi row %d does not end at 1", i);
+    if (t->has_g && !(t->hg[i] > 0.0 && t->hg[i] <= 1.0 + 1e-12))
+      return fail(QED_ERR_STATE, "g row %d = %g outside (0, 1]", i, t->hg[i]);
   }
   for (int k = 0; k < p.n_chi_pair; ++k) {
     if (!(t->hT[k] >= 0.0) || !std::isfinite(t->hT[k])) return fail(QED_ERR_STATE, "T row %d not finite", k);
@@ -233,6 +240,7 @@ Tabs device_tabs(const qed_tables* t) {
   tb.dle = (std::log(p.eta_max) - tb.le0) / (p.n_eta - 1);
   tb.h = t->h;
   tb.h32 = t->h32;
+  tb.g = t->has_g ? t->g : nullptr;
   tb.n_chi = p.n_chi;
   tb.lnchi_min = t->lnchi_min;
   tb.dlnchi = t->dlnchi;
@@ -254,7 +262,11 @@ qed_status check_params(const qed_workspace* ws, const qed_step_params* p) {
   if (!finite_pos(p->dt)) return fail(QED_ERR_ARG, "dt = %g must be finite and positive", p->dt);
   if (!std::isfinite(p->t0)) return fail(QED_ERR_ARG, "t0 = %g must be finite", p->t0);
   if (!finite_pos(p->lambda_L)) return fail(QED_ERR_ARG, "lambda_L = %g must be finite and positive", p->lambda_L);
-  if (p->flags & ~7u) return fail(QED_ERR_ARG, "unknown flag bits 0x%x", p->flags);
+  if (p->flags & ~31u) return fail(QED_ERR_ARG, "unknown flag bits 0x%x", p->flags);
+  if ((p->flags & (QED_RR_QUANTUM | QED_RR_CLASSICAL)) == (QED_RR_QUANTUM | QED_RR_CLASSICAL))
+    return fail(QED_ERR_ARG, "QED_RR_QUANTUM and QED_RR_CLASSICAL exclude each other");
+  if ((p->flags & (QED_RR_QUANTUM | QED_RR_CLASSICAL)) && (p->flags & QED_EMIT))
+    return fail(QED_ERR_ARG, "deterministic radiation reaction replaces emission: drop QED_EMIT");
   if ((p->flags & QED_PAIRS) && !(p->flags & QED_PROPAGATE))
     return fail(QED_ERR_ARG, "QED_PAIRS needs QED_PROPAGATE (pairs come from stepped photons)");
   if (p->precision != QED_FP64 && p->precision != QED_FP32_MIXED)
@@ -271,6 +283,7 @@ StepConst step_const(const qed_step_params* p) {
   sc.kappa = p->lambda_L / kLambdaCompton;
   sc.a_gamma = std::sqrt(3.0) * kAlpha * sc.kappa / (2.0 * kPi);
   sc.a_pair = kAlpha * sc.kappa;
+  sc.a_rr = 2.0 / 3.0 * kAlpha * sc.kappa;
   sc.flags = p->flags;
   return sc;
 }
@@ -392,7 +405,9 @@ qed_status qed_build_tables(const qed_table_params* params, qed_tables** out) {
     free_tables(t);
     return st;
   }
-  hipError_t e = launch_build_tables(t->p, t->h, t->lnchi_min, t->dlnchi, t->P, t->T, t->fgrid, t->Pf, t->knorm, nullptr);
+  t->has_g = true;
+  hipError_t e = launch_build_tables(t->p, t->h, t->lnchi_min, t->dlnchi, t->P, t->T, t->fgrid, t->Pf, t->knorm,
+                                     t->g, nullptr);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_tables(t);
@@ -408,7 +423,7 @@ qed_status qed_build_tables(const qed_table_params* params, qed_tables** out) {
 
 qed_status qed_tables_from_host(const qed_table_params* params, const double* h, const double* lnchi_min,
                                 const double* dlnchi, const double* P_chi, const double* T, const double* f_grid,
-                                const double* P_f, const double* k_norm, qed_tables** out) {
+                                const double* P_f, const double* k_norm, const double* g, qed_tables** out) {
   if (!out) return fail(QED_ERR_ARG, "out is NULL");
   *out = nullptr;
   qed_status st = check_table_params(params);
@@ -429,6 +444,9 @@ qed_status qed_tables_from_host(const qed_table_params* params, const double* h,
   t->hPf.assign(P_f, P_f + (size_t)p.n_chi_pair * p.n_f);
   if (k_norm) t->hk.assign(k_norm, k_norm + p.n_chi_pair);
   else t->hk.assign(p.n_chi_pair, 0.0);
+  t->has_g = g != nullptr;
+  if (g) t->hg.assign(g, g + p.n_eta);
+  else t->hg.assign(p.n_eta, 0.0);
   auto up = [&](double* d, const std::vector<double>& v) {
     return hipMemcpy(d, v.data(), v.size() * 8, hipMemcpyHostToDevice);
   };
@@ -445,6 +463,7 @@ qed_status qed_tables_from_host(const qed_table_params* params, const double* h,
   if (e == hipSuccess) e = up(t->fgrid, t->hf);
   if (e == hipSuccess) e = up(t->Pf, t->hPf);
   if (e == hipSuccess) e = up(t->knorm, t->hk);
+  if (e == hipSuccess) e = up(t->g, t->hg);
   if (e != hipSuccess) {
     free_tables(t);
     return fail(QED_ERR_HIP, "table upload: %s", hipGetErrorString(e));
@@ -468,6 +487,7 @@ qed_status qed_tables_view(const qed_tables* t, qed_table_view* out) {
   out->f_grid = t->hf.data();
   out->P_f = t->hPf.data();
   out->k_norm = t->hk.data();
+  out->g = t->has_g ? t->hg.data() : nullptr;
   return QED_OK;
 }
 
@@ -668,6 +688,8 @@ qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_
   if (tables->device != ws->device) return fail(QED_ERR_STATE, "tables and workspace are on different devices");
   qed_status st = check_params(ws, params);
   if (st) return st;
+  if ((params->flags & QED_RR_QUANTUM) && !tables->has_g)
+    return fail(QED_ERR_STATE, "QED_RR_QUANTUM needs tables with g (built, or supplied with g)");
   return enqueue_step(tables, ws, params, (hipStream_t)stream);
 }
 
@@ -678,6 +700,8 @@ qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_p
   if (tables->device != ws->device) return fail(QED_ERR_STATE, "tables and workspace are on different devices");
   qed_status st = check_params(ws, params);
   if (st) return st;
+  if ((params->flags & QED_RR_QUANTUM) && !tables->has_g)
+    return fail(QED_ERR_STATE, "QED_RR_QUANTUM needs tables with g (built, or supplied with g)");
   if (n_steps < 0) return fail(QED_ERR_ARG, "n_steps < 0");
   if (graph_steps < 0 || graph_steps > 100000) return fail(QED_ERR_ARG, "graph_steps = %d outside [0, 1e5]", graph_steps);
   hipStream_t s = (hipStream_t)stream;
@@ -826,6 +850,7 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
     L.defect_emit = A.defect_emit * w;
     L.defect_pair = A.defect_pair * w;
     L.dropped_energy = A.dropped_energy * w;
+    L.radiated = A.radiated * w;
     L.n_emit = (int64_t)A.n_emit;
     L.n_null = (int64_t)A.n_null;
     L.n_pair = (int64_t)A.n_pair;
@@ -835,7 +860,7 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
     L.photon_steps_in_field = (int64_t)A.n_field;
     L.lepton_steps_in_field = (int64_t)A.n_field_lepton;
     for (int s = 0; s < 3; ++s) L.particle_steps[s] = (int64_t)A.particle_steps[s];
-    const double resid = tot - L.energy0 - L.work - L.defect_emit - L.defect_pair + L.dropped_energy;
+    const double resid = tot - L.energy0 - L.work - L.defect_emit - L.defect_pair + L.dropped_energy + L.radiated;
     L.drift = L.energy0 > 0.0 ? std::fabs(resid) / L.energy0 : std::fabs(resid);
     dropped |= A.n_dropped > 0;
     nonfinite |= A.n_nonfinite > 0;

@@ -93,6 +93,7 @@ struct Tabs {
   double le0, dle;             // ln eta_min, ln-spacing of the eta rows
   const double* h;
   const float* h32;
+  const double* g;             // quantum reduction of the radiated power, per eta row (or NULL)
   int n_chi;
   const double* lnchi_min;     // per row: ln chi_0 and ln-spacing of the columns
   const double* dlnchi;
@@ -113,6 +114,7 @@ struct StepConst {
   double kappa;     // lambda_L / lambda_c = m c^2 / (hbar w)
   double a_gamma;   // sqrt(3) alpha kappa / (2 pi): eq. 2 in code time
   double a_pair;    // alpha kappa: eq. 3 in code time
+  double a_rr;      // (2/3) alpha kappa: classical radiated power per eta^2 in code time (eq. 9)
   uint32_t flags;
 };
 
@@ -122,7 +124,7 @@ struct InstAcc {
   int64_t n_live;              // compaction: live photons
   int64_t mover_off;           // compaction: offset of this instance's mover list
   unsigned long long hole_ctr, mover_ctr;
-  double work, defect_emit, defect_pair, dropped_energy;
+  double work, defect_emit, defect_pair, dropped_energy, radiated;
   double led_energy[3];
   unsigned long long led_count[3];
   unsigned long long n_emit, n_null, n_pair, n_dropped, n_range, n_nonfinite, n_field, n_field_lepton;
@@ -471,6 +473,20 @@ __device__ __forceinline__ double lookup_h(const double* sh, const Tabs& tb, dou
 
 // T(chi) from an LDS copy; zero below chi_pair_min (T < 1e-58 there); feeds only the
 // optical-depth decrement
+// g(eta) for the deterministic radiation reaction: it changes momenta, so the index uses the
+// correctly rounded log (both sides of the parity contract); clamped at the table ends.
+__device__ __forceinline__ double lookup_g(const double* sg, const Tabs& tb, double eta, unsigned& range) {
+  const double s = (cr_log(eta) - tb.le0) / tb.dle;
+  if (!(s > 0.0)) return sg[0];
+  if (s >= tb.n_eta - 1) {
+    ++range;
+    return sg[tb.n_eta - 1];
+  }
+  const int i = (int)floor(s);
+  const double w = s - i;
+  return (1.0 - w) * sg[i] + w * sg[i + 1];
+}
+
 __device__ __forceinline__ double lookup_T(const double* sT, const Tabs& tb, double chi, unsigned& range) {
   if (!(chi >= tb.cp_min)) return 0.0;  // below the table (T ~ 0) or NaN
   if (chi == INFINITY) {

@@ -34,7 +34,7 @@ hipError_t init_crmath();
 hipError_t launch_sort_species(const qed_instance* inst_dev, const qed_instance& inst_host, int ii, int s,
                                const Glob* glob, double dt, bool mixed, const SortScratch& w, int grid, hipStream_t st);
 hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnchi_min, double* dlnchi, double* P,
-                               double* T, double* fgrid, double* Pf, double* knorm, hipStream_t s);
+                               double* T, double* fgrid, double* Pf, double* knorm, double* g, hipStream_t s);
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,
                        int64_t* base_lep, int64_t* base_ph, int chunk_lep, int chunk_ph, int advance,
                        int count_photons, hipStream_t s);

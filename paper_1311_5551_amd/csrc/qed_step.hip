@@ -167,8 +167,12 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   float* sh32 = (float*)smem;
   double* sred = smem + a.tb.n_eta;
   unsigned* sredu = (unsigned*)(sred + 16);
+  // deterministic radiation reaction (QED_RR_*) replaces emission; its g table takes h's place
+  const bool rr = (a.sc.flags & (QED_RR_QUANTUM | QED_RR_CLASSICAL)) != 0;
+  const bool rr_q = (a.sc.flags & QED_RR_QUANTUM) != 0;
   for (int i = threadIdx.x; i < a.tb.n_eta; i += blockDim.x) {
-    if (MIXED) sh32[i] = a.tb.h32[i];
+    if (rr_q) sh[i] = a.tb.g[i];
+    else if (MIXED) sh32[i] = a.tb.h32[i];
     else sh[i] = a.tb.h[i];
   }
 
@@ -189,13 +193,14 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   double hq = 0.0;
   float tpf0 = 0.0f, psif_max = 0.0f;
   FieldK fK{0.0};
-  double dacc[1] = {0.0};              // field work
+  double dacc[2] = {0.0, 0.0};         // field work, energy radiated (deterministic reaction)
   unsigned uacc[3] = {0, 0, 0};        // in-field steps, eta above the table, non-finite state
   auto flush = [&](int entry) {
     block_sum(dacc, uacc, sred, sredu);
     if (threadIdx.x == 0) {
       InstAcc& A = a.acc[entry >> 1];
       if (dacc[0] != 0.0) atomicAdd(&A.work, dacc[0]);
+      if (dacc[1] != 0.0) atomicAdd(&A.radiated, dacc[1]);
       if (uacc[0]) atomicAdd(&A.n_field_lepton, (unsigned long long)uacc[0]);
       if (uacc[1]) atomicAdd(&A.n_range, (unsigned long long)uacc[1]);
       if (uacc[2]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[2]);
@@ -294,6 +299,27 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
         x += dt * u1x / g1;
         y += dt * u1y / g1;
         if (d3) z += dt * u1z / g1;
+        double wx = u1x, wy = u1y, wz = u1z;  // stored momentum
+        if (rr) {
+          // continuous reaction (eqs. 8, 9): gamma -> max(gamma - (2/3) alpha kappa eta^2 g dt, 1)
+          // along u; the energy removed is what the stored momentum lost
+          const double ax = g1 * E[0] + (u1y * Bf[2] - u1z * Bf[1]);
+          const double ay = g1 * E[1] + (u1z * Bf[0] - u1x * Bf[2]);
+          const double az = g1 * E[2] + (u1x * Bf[1] - u1y * Bf[0]);
+          const double ue = u1x * E[0] + u1y * E[1] + u1z * E[2];
+          const double r2 = (ax * ax + ay * ay + az * az) - ue * ue;
+          const double eta = sqrt(r2 > 0.0 ? r2 : 0.0);
+          if (eta > 0.0) {
+            const double gq = rr_q ? lookup_g(sh, a.tb, eta, uacc[1]) : 1.0;
+            const double gn = fmax(g1 - a.sc.a_rr * eta * eta * gq * dt, 1.0);
+            const double um = sqrt(u1x * u1x + u1y * u1y + u1z * u1z);
+            const double sc = um > 0.0 ? sqrt((gn - 1.0) * (gn + 1.0)) / um : 0.0;
+            wx = sc * u1x;
+            wy = sc * u1y;
+            wz = sc * u1z;
+            dacc[1] += g1 - sqrt(1.0 + (wx * wx + wy * wy + wz * wz));
+          }
+        }
         if (emit) {
           const double ax = g1 * E[0] + (u1y * Bf[2] - u1z * Bf[1]);
           const double ay = g1 * E[1] + (u1z * Bf[0] - u1x * Bf[2]);
@@ -310,13 +336,13 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
             }
           }
         }
-        if (!isfinite(tau) || !isfinite(u1x) || !isfinite(u1y) || !isfinite(u1z)) ++uacc[2];
+        if (!isfinite(tau) || !isfinite(wx) || !isfinite(wy) || !isfinite(wz)) ++uacc[2];
         buf_st(C.x, off * SR, (Real)(x));
         buf_st(C.y, off * SR, (Real)(y));
         if (d3) buf_st(C.z, off * SR, (Real)(z));
-        buf_st(C.ux, off * SR, (Real)(u1x));
-        buf_st(C.uy, off * SR, (Real)(u1y));
-        buf_st(C.uz, off * SR, (Real)(u1z));
+        buf_st(C.ux, off * SR, (Real)(wx));
+        buf_st(C.uy, off * SR, (Real)(wy));
+        buf_st(C.uz, off * SR, (Real)(wz));
         buf_st(C.tau, off * 8u, (double)(tau));
       } else {
         float xh = buf_ld<Real>(C.x, off * SR), xl = buf_ld<float>(C.xl, off * 4u), yh = buf_ld<Real>(C.y, off * SR), yl = buf_ld<float>(C.yl, off * 4u);
@@ -347,7 +373,29 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
         if (d3) comp_add(zh, zl, dtf * uzh / g1);
         // field work from the stored states (FP64), so the ledger closes on what is stored
         const double ux1 = (double)uxh + uxl, uy1 = (double)uyh + uyl, uz1 = (double)uzh + uzl;
-        dacc[0] += sqrt(1.0 + (ux1 * ux1 + uy1 * uy1 + uz1 * uz1)) - g0d;
+        const double g1d = sqrt(1.0 + (ux1 * ux1 + uy1 * uy1 + uz1 * uz1));
+        dacc[0] += g1d - g0d;
+        if (rr) {
+          // continuous reaction with eta in FP32 (as for emission) and the energy update in
+          // FP64 on the stored momentum; the energy removed is what the stored pairs lost
+          const float ax = g1 * E[0] + (uyh * Bf[2] - uzh * Bf[1]);
+          const float ay = g1 * E[1] + (uzh * Bf[0] - uxh * Bf[2]);
+          const float az = g1 * E[2] + (uxh * Bf[1] - uyh * Bf[0]);
+          const float ue = uxh * E[0] + uyh * E[1] + uzh * E[2];
+          const float r2 = (ax * ax + ay * ay + az * az) - ue * ue;
+          const double eta = (double)sqrtf(r2 > 0.0f ? r2 : 0.0f);
+          if (eta > 0.0) {
+            const double gq = rr_q ? lookup_g(sh, a.tb, eta, uacc[1]) : 1.0;
+            const double gn = fmax(g1d - a.sc.a_rr * eta * eta * gq * dt, 1.0);
+            const double um = sqrt(ux1 * ux1 + uy1 * uy1 + uz1 * uz1);
+            const double sc = um > 0.0 ? sqrt((gn - 1.0) * (gn + 1.0)) / um : 0.0;
+            split_double(sc * ux1, uxh, uxl);
+            split_double(sc * uy1, uyh, uyl);
+            split_double(sc * uz1, uzh, uzl);
+            const double vx = (double)uxh + uxl, vy = (double)uyh + uyl, vz = (double)uzh + uzl;
+            dacc[1] += g1d - sqrt(1.0 + (vx * vx + vy * vy + vz * vz));
+          }
+        }
         if (emit) {
           const float ax = g1 * E[0] + (uyh * Bf[2] - uzh * Bf[1]);
           const float ay = g1 * E[1] + (uzh * Bf[0] - uxh * Bf[2]);
@@ -465,7 +513,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
           ++uacc[0];
           pend = full(off, &eta);
         }
-        enqueue(off, pend, eta);
+        if (emit) enqueue(off, pend, eta);  // emit is uniform over the block
       }
     } else {
 #pragma unroll 1
@@ -477,7 +525,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
           ++uacc[0];
           pend = full(off, &eta);
         }
-        enqueue(off, pend, eta);
+        if (emit) enqueue(off, pend, eta);  // emit is uniform over the block
       }
     }
   }

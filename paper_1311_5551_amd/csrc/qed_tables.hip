@@ -124,11 +124,12 @@ __device__ double integrate_block(const GL16& gl, double a, double va, double vb
   return block_reduce(s, red);
 }
 
-// Row i of h and P_chi.  Steps: total energy of the spectrum; v_c of the 1e-9 energy cut
+// Row i of h, g and P_chi.  Steps: total energy of the spectrum (and g from it); v_c of the 1e-9 energy cut
 // (Newton on the cumulative energy); log-spaced chi grid from chi_min to eta/2; number
 // integral of each segment; prefix sums normalised by h = the total number integral.
 __global__ __launch_bounds__(kRowThreads) void k_build_eta_rows(qed_table_params p, GL16 gl, double* h,
-                                                                  double* lnchi_min, double* dlnchi, double* P) {
+                                                                  double* lnchi_min, double* dlnchi, double* P,
+                                                                  double* g) {
   __shared__ double red[kRowThreads];
   __shared__ double seg[1024];
   __shared__ double sh_vc;
@@ -143,6 +144,8 @@ __global__ __launch_bounds__(kRowThreads) void k_build_eta_rows(qed_table_params
   const double e_tail = 0.75 * dens_energy(a, kV0);
   const double e_tot = e_tail + integrate_block(gl, a, kV0, vmax, 1, red);
   const double target = p.cutoff_energy_frac * e_tot;
+  // g = 3 sqrt3 / (2 pi eta^2) int_0^{eta/2} F dchi, and the energy density is in units of eta/2
+  if (threadIdx.x == 0) g[i] = 3.0 * sqrt(3.0) / (4.0 * kPi * eta) * e_tot;
 
   // starting point: at small y the cumulative energy is (3/4) of the density (power law)
   if (threadIdx.x == 0) {
@@ -298,9 +301,9 @@ static GL16 gauss_legendre16() {
 }
 
 hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnchi_min, double* dlnchi, double* P,
-                               double* T, double* fgrid, double* Pf, double* knorm, hipStream_t s) {
+                               double* T, double* fgrid, double* Pf, double* knorm, double* g, hipStream_t s) {
   const GL16 gl = gauss_legendre16();
-  hipLaunchKernelGGL(k_build_eta_rows, dim3(p.n_eta), dim3(kRowThreads), 0, s, p, gl, h, lnchi_min, dlnchi, P);
+  hipLaunchKernelGGL(k_build_eta_rows, dim3(p.n_eta), dim3(kRowThreads), 0, s, p, gl, h, lnchi_min, dlnchi, P, g);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_build_pair_rows, dim3(p.n_chi_pair), dim3(kRowThreads), 0, s, p, gl, T, fgrid, Pf, knorm);

@@ -36,7 +36,8 @@ class Tables:
         arrs = [np.ascontiguousarray(t[k], dtype=np.float64) for k in
                 ("h", "lnchi_min", "dlnchi", "P_chi", "T", "f_grid", "P_f")]
         kn = np.ascontiguousarray(t["k_norm"], dtype=np.float64) if "k_norm" in t else None
-        return cls(capi.qed_tables_from_host(capi.qed_table_params(**p), *arrs, kn), p)
+        g = np.ascontiguousarray(t["g"], dtype=np.float64) if t.get("g") is not None else None
+        return cls(capi.qed_tables_from_host(capi.qed_table_params(**p), *arrs, kn, g), p)
 
     def view(self) -> dict:
         v = capi.qed_tables_view(self.handle)
@@ -45,7 +46,8 @@ class Tables:
         get = lambda ptr, n: np.ctypeslib.as_array(ptr, shape=(n,)).copy()
         return dict(params=dict(p), h=get(v.h, ne), lnchi_min=get(v.lnchi_min, ne), dlnchi=get(v.dlnchi, ne),
                     P_chi=get(v.P_chi, ne * nc).reshape(ne, nc), T=get(v.T, npair), f_grid=get(v.f_grid, nf),
-                    P_f=get(v.P_f, npair * nf).reshape(npair, nf), k_norm=get(v.k_norm, npair))
+                    P_f=get(v.P_f, npair * nf).reshape(npair, nf), k_norm=get(v.k_norm, npair),
+                    g=get(v.g, ne) if v.g else None)
 
     def __del__(self):
         try:

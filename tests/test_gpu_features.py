@@ -286,3 +286,48 @@ def test_fp32_mixed_against_fp64(gpu_tables_default):
 @pytest.fixture(scope="module")
 def gpu_tables_default():
     return Tables.build()
+
+
+def test_radiation_reaction_flags(oracle_tables):
+    # the quantum drag needs g; the classical one does not; either excludes stochastic emission
+    t_nog = Tables.from_arrays({k: v for k, v in oracle_tables.items() if k != "g"})
+    assert t_nog.view()["g"] is None
+    r = Run(W.uniform_b(16, 100.0, 1e-3, 0.01, 2, capi.QED_RR_QUANTUM), t_nog)
+    with pytest.raises(capi.QEDError) as e:
+        r.step(1)
+    assert e.value.status == capi.QED_ERR_STATE
+    r.close()
+    r = Run(W.uniform_b(16, 100.0, 1e-3, 0.01, 2, capi.QED_RR_CLASSICAL), t_nog)
+    r.step(2)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK" and led["radiated"] > 0
+    r.close()
+    for flags in (capi.QED_EMIT | capi.QED_RR_QUANTUM, capi.QED_RR_QUANTUM | capi.QED_RR_CLASSICAL):
+        with pytest.raises(capi.QEDError) as e:
+            Run(W.uniform_b(16, 100.0, 1e-3, 0.01, 2, flags), t_nog)
+        assert e.value.status == capi.QED_ERR_ARG
+
+
+def test_radiation_reaction_fp32_mixed(shared_tables):
+    # FP32-mixed drag against the FP64 one (same tables): per-lepton gamma and the mean loss
+    w = W.collision(20000, a0=200.0, n_steps=2600, meet_step=1300, seed=5, flags=capi.QED_RR_QUANTUM)
+    w.capacity = dict(electron=w.n + 1024, positron=1024, photon=1024)
+    r64 = Run(w, shared_tables)
+    r32 = Run(w, shared_tables, precision=capi.QED_FP32_MIXED)
+    r64.step(w.n_steps)
+    r32.step(w.n_steps)
+    l64, l32 = r64.ledger()[0], r32.ledger()[0]
+    a, b = r64.species(0, "electron"), r32.species(0, "electron")
+    oa, ob = np.argsort(a["uid"]), np.argsort(b["uid"])
+    ga = np.sqrt(1 + a["ux"][oa] ** 2 + a["uy"][oa] ** 2 + a["uz"][oa] ** 2)
+    gb = np.sqrt(1 + b["ux"][ob] ** 2 + b["uy"][ob] ** 2 + b["uz"][ob] ** 2)
+    rel = np.abs(gb - ga) / ga
+    rec = dict(gamma_rel_p50=float(np.median(rel)), gamma_rel_max=float(rel.max()),
+               radiated_rel=abs(l32["radiated"] - l64["radiated"]) / l64["radiated"], drift_32=l32["drift"])
+    record("rr_fp32_mixed_vs_fp64", rec)
+    assert l32["status"] == "QED_OK"
+    assert l64["radiated"] > 0.05 * l64["energy0"]
+    # FP32 push increments round at ~6e-8 each; over 1300 in-pulse steps the walk stays ~1e-6
+    assert rec["gamma_rel_max"] < 4e-5
+    assert rec["radiated_rel"] < 1e-7
+    assert l32["drift"] < 1e-9

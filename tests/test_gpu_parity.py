@@ -32,9 +32,10 @@ def gpu_tables_small():
 def _compare_tables(tg, to, tol, label=None):
     assert tg["params"] == to["params"]
     if label:
-        _record("tables_" + label, {k: float(np.max(np.abs(tg[k] - to[k]) / (np.abs(to[k]) if k in ("h", "T", "k_norm")
+        _record("tables_" + label, {k: float(np.max(np.abs(tg[k] - to[k]) / (np.abs(to[k]) if k in ("h", "T", "k_norm", "g")
                                                                                   else 1.0)))
-                                    for k in ("h", "lnchi_min", "dlnchi", "P_chi", "T", "f_grid", "P_f", "k_norm")})
+                                    for k in ("h", "lnchi_min", "dlnchi", "P_chi", "T", "f_grid", "P_f", "k_norm",
+                                              "g")})
     np.testing.assert_allclose(tg["h"], to["h"], rtol=tol["h"], atol=0)
     np.testing.assert_allclose(tg["lnchi_min"], to["lnchi_min"], rtol=0, atol=tol["lnchi"])
     np.testing.assert_allclose(tg["dlnchi"], to["dlnchi"], rtol=tol["lnchi"], atol=0)
@@ -43,6 +44,7 @@ def _compare_tables(tg, to, tol, label=None):
     np.testing.assert_allclose(tg["f_grid"], to["f_grid"], rtol=0, atol=4e-16)
     np.testing.assert_allclose(tg["P_f"], to["P_f"], rtol=0, atol=tol["P"])
     np.testing.assert_allclose(tg["k_norm"], to["k_norm"], rtol=tol["h"], atol=0)
+    np.testing.assert_allclose(tg["g"], to["g"], rtol=tol["h"], atol=0)
 
 
 # table tolerances: both sides integrate to ~1e-14 relative; the chi_min root and the
@@ -207,3 +209,49 @@ def test_grid_gather_parity(shared_tables, oracle_tables):
     r = _gpu_run(w, shared_tables)
     assert r.ledger()[0]["status"] == "QED_OK"
     _check_parity(r, w, o_res, o_led, label="grid")
+
+
+# Deterministic radiation reaction (eq. 9): the continuous drag replaces the emission step.  No
+# random draws and no thresholds, so with the oracle's tables every momentum meets the strict
+# bars; the radiated energy agrees to summation order.
+RR_MODES = {"quantum": capi.QED_RR_QUANTUM, "classical": capi.QED_RR_CLASSICAL}
+
+
+def _rr_workload(geometry, flags):
+    if geometry == "uniform_b":      # eta0 = 1, gamma 1000 -> ~510 (quantum) over 1000 steps
+        w = W.uniform_b(2000, 1000.0, 1e-3, 0.002, 1000, flags)
+    elif geometry == "cp_wave":      # paper test 2 geometry, field work and drag together
+        w = W.cp_wave_test2(400, dt_over_qed=0.3, seed=4, pairs=False)
+        w.flags = flags
+    else:                            # LP collision: drift outside the pulse, drag inside
+        w = W.collision(1500, a0=200.0, n_steps=2600, meet_step=1300, seed=11, flags=flags)
+    w.capacity = dict(electron=w.n + 1024, positron=1024, photon=1024)
+    return w
+
+
+@pytest.mark.parametrize("geometry", ["uniform_b", "cp_wave", "collision"])
+@pytest.mark.parametrize("mode", ["quantum", "classical"])
+def test_radiation_reaction_parity(mode, geometry, shared_tables, oracle_tables):
+    w = _rr_workload(geometry, RR_MODES[mode])
+    o_res, o_led = oracle_run(w, oracle_tables)
+    r = _gpu_run(w, shared_tables)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK"
+    _check_parity(r, w, o_res, o_led, label="rr_%s_%s" % (mode, geometry))
+    assert len(r.species(0, "electron")["uid"]) == w.n
+    assert led["count"][2] == 0 and led["n_emit"] == 0 and led["count"][1] == 0
+    assert o_led["radiated"] > 0.01 * o_led["energy0"][0]
+    assert led["radiated"] == pytest.approx(o_led["radiated"], rel=1e-10)
+    assert led["work"] == pytest.approx(o_led["work"], rel=1e-9, abs=1e-12 * o_led["energy0"][0])
+    assert led["n_range"] == o_led["n_range"]
+    assert led["drift"] < 1e-12
+
+
+@pytest.mark.parametrize("mode", ["quantum", "classical"])
+def test_radiation_reaction_gpu_tables(mode, gpu_tables, oracle_tables):
+    # GPU-built g against the oracle's: the drag differs by the tables' ~1e-13, far inside E2E bars
+    w = _rr_workload("collision", RR_MODES[mode])
+    o_res, o_led = oracle_run(w, oracle_tables)
+    r = _gpu_run(w, gpu_tables)
+    _check_parity(r, w, o_res, o_led, label="rr_%s_gpu_tables" % mode, **_bars("gpu_built"))
+    assert r.ledger()[0]["radiated"] == pytest.approx(o_led["radiated"], rel=1e-9)
