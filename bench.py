@@ -35,8 +35,9 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     """Algorithmic HBM bytes of one kernel class over the timed region.
 
     grid=True (the 2-D grid workload, FP64): lepton full step 48 B read (x, y, u, tau) + 48 B
-    written; photon slot 44 B (k, x and y at birth, birth step), the gather of the FP32 grid not
-    counted (the 201 MB grid is read from the cache hierarchy, its refresh is the set-up class).
+    written; photon slot 8 B (pair window) + 44 B per photon inside its window (k, x and y at
+    birth, birth step), the gather of the FP32 grid not counted (the 201 MB grid is read from
+    the cache hierarchy, its refresh is the set-up class).
 
     Lepton sweep, per particle-step in 3-D: with the full push 56 B read (x, u, tau) + 56 B
     written in FP64 (FP32-mixed: the same 112 B as hi/lo words of position and momentum plus
@@ -44,24 +45,25 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     72 B in FP64, 60 B in FP32-mixed (hi/lo position, high words of u); + 16 B per queued
     emission event.  The emission pass (separate class) reads the event's lepton and writes the
     photon.
-    Photon sweep, per photon slot-step, with a field that depends on x only (the plane-wave
-    pulse): k (3 words), x at birth (1 word) and the birth step (4 B): 36 B in FP64, 20 B in
-    FP32-mixed; + 16 B (tau read and written) for the photons that see a non-zero pair rate;
-    + 8 B per queued pair event.  The pair pass (separate class) reads the event's photon and
-    writes the two leptons."""
+    Photon sweep, per photon slot-step: its pair window (8 B); per photon inside its window, with
+    a field that depends on x only (the plane-wave pulse), k (3 words), x at birth (1 word) and
+    the birth step (4 B): 36 B in FP64, 20 B in FP32-mixed; + 16 B (tau read and written) for
+    the photons that see a non-zero pair rate; + 8 B per queued pair event.  The pair pass
+    (separate class) reads the event's photon and writes the two leptons."""
     d = lambda k, i=None: (led1[k][i] - led0[k][i]) if i is not None else (led1[k] - led0[k])
     if grid:
         if kind == "lepton":
             return (d("particle_steps", 0) + d("particle_steps", 1)) * 96 + (d("n_emit") + d("n_null")) * 16
-        return d("particle_steps", 2) * 44 + d("photon_steps_in_field") * 16 + d("n_pair") * 8
+        return (d("particle_steps", 2) * 8 + d("photon_steps_active") * 44 + d("photon_steps_in_field") * 16
+                + d("n_pair") * 8)
     if kind == "lepton":
         steps = d("particle_steps", 0) + d("particle_steps", 1)
         full = d("lepton_steps_in_field")
         drift = 72 if form == "fp64" else 60
         return full * 112 + (steps - full) * drift + (d("n_emit") + d("n_null")) * 16
-    steps = d("particle_steps", 2)
-    base = 36 if form == "fp64" else 20
-    return steps * base + d("photon_steps_in_field") * 16 + d("n_pair") * 8
+    full = 36 if form == "fp64" else 20
+    return (d("particle_steps", 2) * 8 + d("photon_steps_active") * full + d("photon_steps_in_field") * 16
+            + d("n_pair") * 8)
 
 
 def source_hash():
@@ -166,7 +168,7 @@ def size_grid(w, tables, args, probe_n=100_000):
 def size_batched(ws, tables, args, probe_n=64):
     """Buffer capacities of the batched instances from a probe run: the first `probe_n`
     electrons of every instance (the same families as in the full run) through the whole
-    window; each species gets 1.3x its probe yield per initial electron plus a margin."""
+    schedule; each species gets 1.3x its probe yield per initial electron plus a margin."""
     from paper_1311_5551_amd import capi, workloads as W
     from paper_1311_5551_amd.sim import Run
     probe = []
@@ -176,7 +178,7 @@ def size_batched(ws, tables, args, probe_n=64):
         probe.append(p)
     run = Run(probe, tables, precision=capi.QED_FP32_MIXED)
     log("batched: sizing buffers from a %d-electron probe run" % sum(p.n for p in probe))
-    for i in range(4000):
+    for i in range(ws[0].n_steps):
         run.step(1)
         if (i + 1) % args.compact_every == 0:
             run.compact()
@@ -216,15 +218,18 @@ def run_form(form, args, tables, tuned):
                     % (w.n, args.warmup, total, args.compact_every))
         warmup, steps = args.warmup, args.steps
     else:
-        # the C5 instance mix with every N_i scaled by batched_scale (at full size the
-        # 4000-step window emits ~4.5e9 photons, ~200 GB)
-        ws = W.batched_config5(n_steps=4000, n_scale=args.batched_scale)
+        # the C5 instance mix with every N_i scaled by batched_scale, on the collision schedule of
+        # the FP64 line (dt = lambda/200c, the pulse meets each beam at the middle step); at full
+        # size the collisions emit ~4.5e9 photons (~200 GB) and the run would take minutes
+        total = args.batched_steps
+        ws = W.batched_config5(n_steps=total, n_scale=args.batched_scale)
         size_batched(ws, tables, args)
-        warmup, steps = args.batched_warmup, 4000 - args.batched_warmup
+        warmup, steps = args.batched_warmup, total - args.batched_warmup
         workload = ("batched_collisions: 256 instances, N_i=floor(%g*10^U(3,6)) (total %d electrons), a0~U(50,500), "
-                    "gamma0 log-U[500,5000], FP32-mixed, steps %d..4000 of a 4000-step window centred on the "
-                    "collisions, hipGraph replay of %d-step graphs, compaction every %d"
-                    % (args.batched_scale, sum(w.n for w in ws), warmup, args.compact_every, args.compact_every))
+                    "gamma0 log-U[500,5000], FP32-mixed, dt=lambda/200c, steps %d..%d of %d (collisions at step "
+                    "%d), hipGraph replay of %d-step graphs, compaction every %d"
+                    % (args.batched_scale, sum(w.n for w in ws), warmup, total, total, total // 2,
+                       args.compact_every, args.compact_every))
     prec = capi.QED_FP64 if form in ("fp64", "grid") else capi.QED_FP32_MIXED
     log("%s: allocating and binding (%s)" % (form, workload[:60]))
     run = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
@@ -295,6 +300,7 @@ def run_form(form, args, tables, tuned):
                photons_end=int(agg1["count"][2]), pairs=int(agg1["n_pair"] - agg0["n_pair"]),
                emissions=int(agg1["n_emit"] - agg0["n_emit"]), drift_max=max(l["drift"] for l in led1),
                photon_steps_in_field=int(agg1["photon_steps_in_field"] - agg0["photon_steps_in_field"]),
+               photon_steps_active=int(agg1["photon_steps_active"] - agg0["photon_steps_active"]),
                lepton_steps_in_field=int(agg1["lepton_steps_in_field"] - agg0["lepton_steps_in_field"]),
                dropped=int(sum(l["n_dropped"] for l in led1)), status=status,
                launch={k: (tuned.get(k) if tuned else None) for k in ("lepton", "photon")})
@@ -318,7 +324,7 @@ def run_form(form, args, tables, tuned):
 
 def _aggregate(leds):
     out = {"particle_steps": [0, 0, 0], "count": [0, 0, 0]}
-    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field", "lepton_steps_in_field"):
+    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field", "photon_steps_active", "lepton_steps_in_field"):
         out[k] = sum(l[k] for l in leds)
     for i in range(3):
         out["particle_steps"][i] = sum(l["particle_steps"][i] for l in leds)
@@ -369,6 +375,7 @@ def main():
     ap.add_argument("--grid-electrons", type=int, default=16_000_000)
     ap.add_argument("--grid-sort-every", type=int, default=10, help="grid form: steps between spatial sorts")
     ap.add_argument("--batched-warmup", type=int, default=200)
+    ap.add_argument("--batched-steps", type=int, default=20000)
     ap.add_argument("--batched-profile-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",

@@ -199,7 +199,10 @@ qed_status qed_set_step(qed_workspace* ws, int64_t step, qed_stream stream);
  * redraw tau.  For every photon (QED_PAIRS): move at c, chi, tau -= lambda_pm(chi) dt; on
  * tau <= 0 sample f from P_f, append the pair, mark the photon dead.  Children are first stepped
  * in the next step.  Never allocates; async on `stream`; device-side conditions (full buffers,
- * non-finite state) are reported by the next qed_energy_ledger. */
+ * non-finite state) are reported by the next qed_energy_ledger.  The first step after qed_bind,
+ * and any step whose t0, dt or tables differ from the previous one's, also enqueues a pass that
+ * sets every photon's pair window (the steps in which its pair rate can be non-zero); a caller
+ * capturing qed_step into its own graph should run one step before capturing. */
 qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params,
                     qed_stream stream);
 
@@ -234,6 +237,8 @@ typedef struct {
   int64_t n_emit, n_null, n_pair;  /* emissions, draws below the cut-off, pair creations */
   int64_t n_dropped, n_range, n_nonfinite;
   int64_t photon_steps_in_field;   /* photon steps that saw a non-zero pair rate */
+  int64_t photon_steps_active;     /* photon steps evaluated in full: those inside the photon's pair
+                                      window (the steps in which its pair rate can be non-zero) */
   int64_t lepton_steps_in_field;   /* lepton steps with the full push (all of them, except outside a
                                       plane-wave pulse, where the push is the field-free drift) */
   int64_t particle_steps[3];       /* particles present at the start of each step, summed over the

@@ -113,6 +113,13 @@ struct qed_workspace {
   int64_t* d_base = nullptr;  // 3 * max_inst: leptons (2 per instance) then photons
   int64_t* d_movers = nullptr;
   size_t movers_len = 0;
+  // pair windows of the photons (one int2 per photon slot, instances at acc.mover_off), valid
+  // for the step constants and table they were computed with
+  int2* d_win = nullptr;
+  size_t win_len = 0;
+  bool win_valid = false;
+  double win_t0 = 0.0, win_dt = 0.0, win_cp_min = 0.0;
+  std::vector<int64_t> win_off;
   int block[2] = {256, 256}, ppt[2] = {4, 4};  // launch shapes: [0] lepton sweep, [1] photon sweep
   // kernel timing: event pairs per kernel class, reused across reads
   bool profiling = false;
@@ -332,6 +339,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.qe.ctl = ws->d_evc + 1;
   a.qe.ent = ws->d_emq;
   a.qe.cap = ws->emq_cap;
+  a.win = ws->d_win;
   // persistent grids: 2048 threads per CU, blocks taking contiguous runs of the chunk list.
   // The passes run in order on `stream`: the photon sweep alone saturates HBM, so running the
   // lepton passes beside it on a second stream (their data are disjoint) shares bandwidth
@@ -363,6 +371,21 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
     mark_end(ws, m, s);
   }
   HIP_TRY(hipGetLastError());
+  return QED_OK;
+}
+
+// (Re)computes the photons' pair windows when the step constants or tables differ from those
+// they were made with.  Enqueued on `s` outside any graph capture.
+qed_status ensure_windows(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
+  const double cp_min = device_tabs(tb).cp_min;
+  if (ws->win_valid && ws->win_t0 == p->t0 && ws->win_dt == p->dt && ws->win_cp_min == cp_min) return QED_OK;
+  launch_photon_windows(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_win, p->t0, p->dt, cp_min,
+                        ws->prec == QED_FP32_MIXED, s);
+  HIP_TRY(hipGetLastError());
+  ws->win_valid = true;
+  ws->win_t0 = p->t0;
+  ws->win_dt = p->dt;
+  ws->win_cp_min = cp_min;
   return QED_OK;
 }
 
@@ -539,6 +562,7 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->sort.stage);
   hipFree(ws->d_base);
   hipFree(ws->d_movers);
+  hipFree(ws->d_win);
   delete ws;
 }
 
@@ -640,16 +664,22 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
     HIP_TRY(hipMalloc((void**)&ws->d_movers, (movers ? movers : 1) * sizeof(int64_t)));
     ws->movers_len = movers;
   }
+  if (movers > ws->win_len || !ws->d_win) {
+    hipFree(ws->d_win);
+    ws->d_win = nullptr;
+    ws->win_len = 0;
+    HIP_TRY(hipMalloc((void**)&ws->d_win, (movers ? movers : 1) * sizeof(int2)));
+    ws->win_len = movers ? movers : 1;
+  }
+  ws->win_valid = false;  // computed by the first step, which knows t0, dt and the tables
+  ws->win_off.resize(n_inst);
+  for (int i = 0; i < n_inst; ++i) ws->win_off[i] = acc0[i].mover_off;
   // emission queue: one entry per lepton slot (a lepton emits at most once per step)
   int64_t leptons = 0;
   for (int i = 0; i < n_inst; ++i) leptons += inst[i].s[0].capacity + inst[i].s[1].capacity;
   if (leptons < 1) leptons = 1;
   if (leptons > ws->emq_cap) {
     hipFree(ws->d_emq);
-  hipFree(ws->sort.key);
-  hipFree(ws->sort.dst);
-  hipFree(ws->sort.hist);
-  hipFree(ws->sort.stage);
     ws->d_emq = nullptr;
     ws->emq_cap = 0;
     HIP_TRY(hipMalloc((void**)&ws->d_emq, (size_t)leptons * sizeof(EmitEv)));
@@ -690,6 +720,7 @@ qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_
   if (st) return st;
   if ((params->flags & QED_RR_QUANTUM) && !tables->has_g)
     return fail(QED_ERR_STATE, "QED_RR_QUANTUM needs tables with g (built, or supplied with g)");
+  if ((st = ensure_windows(tables, ws, params, (hipStream_t)stream))) return st;
   return enqueue_step(tables, ws, params, (hipStream_t)stream);
 }
 
@@ -707,6 +738,7 @@ qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_p
   hipStream_t s = (hipStream_t)stream;
   if (graph_steps > 0 && s == nullptr) return fail(QED_ERR_ARG, "graph replay needs a non-null stream");
   if (graph_steps > 0 && ws->profiling) return fail(QED_ERR_STATE, "kernel timing is on; graph replay cannot record it");
+  if ((st = ensure_windows(tables, ws, params, s))) return st;
   int64_t done = 0;
   if (graph_steps > 0 && n_steps >= graph_steps) {
     char key[256];
@@ -779,7 +811,8 @@ qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream
     if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
     for (int s = 0; s < 3; ++s) {
       if (I.s[s].capacity == 0) continue;
-      HIP_TRY(launch_sort_species(ws->d_inst, I, ii, s, ws->d_glob, params->dt, mixed, ws->sort, ws->cus * 8,
+      HIP_TRY(launch_sort_species(ws->d_inst, I, ii, s, ws->d_glob, params->dt, mixed, ws->sort,
+                                  ws->d_win + ws->win_off[ii], ws->cus * 8,
                                   (hipStream_t)stream));
     }
   }
@@ -822,7 +855,8 @@ qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches) {
 qed_status qed_compact(qed_workspace* ws, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
-  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_movers, ws->prec == QED_FP32_MIXED, (hipStream_t)stream);
+  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_movers, ws->d_win, ws->prec == QED_FP32_MIXED,
+                 (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return QED_OK;
 }
@@ -858,6 +892,7 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
     L.n_range = (int64_t)A.n_range;
     L.n_nonfinite = (int64_t)A.n_nonfinite;
     L.photon_steps_in_field = (int64_t)A.n_field;
+    L.photon_steps_active = (int64_t)A.n_active;
     L.lepton_steps_in_field = (int64_t)A.n_field_lepton;
     for (int s = 0; s < 3; ++s) L.particle_steps[s] = (int64_t)A.particle_steps[s];
     const double resid = tot - L.energy0 - L.work - L.defect_emit - L.defect_pair + L.dropped_energy + L.radiated;

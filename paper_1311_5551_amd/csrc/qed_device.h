@@ -4,6 +4,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <limits.h>
 #include <stdint.h>
 
 #include "../../include/qed.h"
@@ -79,6 +80,10 @@ template <>
 __device__ __forceinline__ int32_t buf_ld<int32_t>(bufres r, uint32_t o) {
   return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
 }
+__device__ __forceinline__ int2 buf_ld_int2(bufres r, uint32_t o) {
+  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0);
+  return make_int2((int)v[0], (int)v[1]);
+}
 __device__ __forceinline__ void buf_st(bufres r, uint32_t o, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, o, 0, 0);
 }
@@ -122,12 +127,14 @@ struct StepConst {
 struct InstAcc {
   int64_t n_start[3];          // particles present at the start of the step (or pass)
   int64_t n_live;              // compaction: live photons
-  int64_t mover_off;           // compaction: offset of this instance's mover list
+  int64_t mover_off;           // offset of this instance's photon slots in the workspace's per-photon
+                               // arrays (compaction movers, photon windows)
   unsigned long long hole_ctr, mover_ctr;
   double work, defect_emit, defect_pair, dropped_energy, radiated;
   double led_energy[3];
   unsigned long long led_count[3];
   unsigned long long n_emit, n_null, n_pair, n_dropped, n_range, n_nonfinite, n_field, n_field_lepton;
+  unsigned long long n_active;           // photon steps inside the photon's window (evaluated in full)
   unsigned long long particle_steps[3];  // particles (photon slots) present at the start of each step
   unsigned long long n_pair_compacted;   // n_pair at the last compaction (~0: unknown, e.g. after bind)
   int32_t compact_skip;                  // this compaction has nothing to remove
@@ -368,6 +375,57 @@ __device__ __forceinline__ double field_bound(const qed_field& F) {
     default:  // standing waves: |E|, |B| <= 2 a each
       return 4.0 * fabs(F.p[0]);
   }
+}
+
+// Photons below this energy have no pair rate in the field: chi <= (eps / 2) field_bound, and T
+// is zero below the table's chi_min (margin for the FP32 rounding of eps and chi).
+__device__ __forceinline__ double pair_eps_min(const qed_field& F, double cp_min) {
+  return 2.0 * cp_min / field_bound(F) * (1.0 - 1e-5);
+}
+
+// A step n is inside a window w when w.x <= n <= w.y; INT_MIN and INT_MAX stand for no bound.
+__device__ __forceinline__ bool in_window(int2 w, int64_t n) {
+  return w.x <= w.y && (w.x == INT_MIN || n >= (int64_t)w.x) && (w.y == INT_MAX || n <= (int64_t)w.y);
+}
+
+// The steps [lo, hi] in which a photon can have a pair rate (eq. 3 needs chi >= chi_min); in
+// every other step its QED step is a no-op.  Empty (lo > hi) below pair_eps_min.  In a plane
+// wave along x (E_y = B_z = e for the pulse; |E| = |B| = E0 for the CP wave) a photon with
+// direction n sees |E + n x B|^2 - (n.E)^2 = (1 - n_x)^2 e^2, so chi = (eps/2)(1 - n_x)|e|:
+// the CP wave gives a constant chi, and in the pulse chi <= (eps/2)(1 - n_x) E0 sin^2(pi psi/Psi),
+// which reaches chi_min only for psi in [psi_a, Psi - psi_a].  psi = t - x - psi0 at the photon
+// grows linearly in the step index n (by dt (1 - n_x) >= 0 per step, x = x_b + (n - b) dt n_x),
+// so those steps form one interval.  Allowances: (1 - n_x) e and chi as the FP32 sweep evaluates
+// them (cancellation of e - n_x e, rounding of eps, E0 and the FP32 sine), and psi as either
+// sweep forms it (FP64 sums; the FP32 direction n_x, ~5e-7 relative, times the photon's age).
+// Other fields get no finite support.
+__device__ inline int2 photon_window(const qed_field& F, double eps_min, double cp_min, double t0, double dt,
+                                     double kx, double ky, double kz, double xb, int32_t bs) {
+  const int2 none = make_int2(INT_MAX, INT_MIN), all = make_int2(INT_MIN, INT_MAX);
+  const double eps = sqrt(kx * kx + ky * ky + kz * kz);
+  if (!(eps >= eps_min)) return none;
+  if (F.kind != QED_FIELD_LP_PULSE && F.kind != QED_FIELD_CP_WAVE) return all;
+  // 1 - n_x without cancellation for photons moving along +x
+  const double omn = kx > 0.0 ? (ky * ky + kz * kz) / (eps * (eps + kx)) : 1.0 - kx / eps;
+  // FP32: e - n_x e and the rounding of |a|^2 - (n.e)^2 (whose parts are up to 2 (1 - n_x) e^2)
+  // add at most ~1e-7 + sqrt(1.2e-7 (1 - n_x)) to (1 - n_x); eps, E0 and sin^2 ~1e-6 relative
+  const double cmax = 0.5 * eps * (omn + 1e-6 + sqrt(1e-6 * omn)) * fabs(F.p[0]) * (1.0 + 1e-5);
+  if (!(cmax >= cp_min)) return none;
+  if (F.kind == QED_FIELD_CP_WAVE) return all;
+  const double nx = kx / eps, len = F.p[1], psi0 = F.p[2];
+  const double psa = len / kPi * asin(sqrt(cp_min / cmax)) * (1.0 - 1e-9);  // sin^2 >= cp_min / cmax
+  const double S = dt * (1.0 - nx);                                         // psi(n) = A + S n
+  const double A = (t0 - xb - psi0) + (double)bs * dt * nx;
+  const double r = 1e-6 * dt;                                               // per step of age
+  const double m = 1e-9 * (fabs(t0) + fabs(xb) + fabs(psi0) + len + fabs((double)bs * dt)) + 1e-9;
+  // A + S n >= psa - m - r (n - b)   and   A + S n <= len - psa + m + r (n - b)
+  const double lo = (psa - m - A + r * bs) / (S + r);
+  const double hi = S - r > 0.0 ? (len - psa + m - A - r * bs) / (S - r) : INFINITY;
+  const double lim = 2.0e9;
+  const int ilo = lo < -lim ? INT_MIN : lo > lim ? INT_MAX : (int)floor(lo) - 2;
+  const int ihi = hi > lim ? INT_MAX : hi < -lim ? INT_MIN : (int)ceil(hi) + 2;
+  if (!(lo <= hi + 4.0)) return none;  // also NaN
+  return make_int2(ilo, ihi);
 }
 
 template <int FK, bool EXACT = true>

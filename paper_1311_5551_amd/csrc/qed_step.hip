@@ -637,6 +637,12 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
         G.tau_dev[slot] = ctau;
         G.uid_dev[slot] = cuid;
         G.birth_step_dev[slot] = (int32_t)(step + 1);
+        // the steps in which the new photon can create a pair, from its stored state
+        const double sx = MIXED ? (double)(float)cx : cx;
+        const double skx = MIXED ? (double)(float)ckx : ckx, sky = MIXED ? (double)(float)cky : cky,
+                     skz = MIXED ? (double)(float)ckz : ckz;
+        a.win[a.acc[ii].mover_off + slot] = photon_window(I.field, pair_eps_min(I.field, a.tb.cp_min), a.tb.cp_min,
+                                                          a.sc.t0, a.sc.dt, skx, sky, skz, sx, (int32_t)(step + 1));
       } else {
         n_drop = 1;
         dropped_e = sqrt(ckx * ckx + cky * cky + ckz * ckz);
@@ -649,14 +655,16 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
 // ---------------------------------------------------------------------------
 // photons, both precisions.  Position at the start of step n: x_b + (n - b) dt k/|k|.
 //
-// The sweep (k_photon) is the bandwidth-bound part: every photon slot, every step.  A thread
-// first issues the loads of all PPT photons it owns in the chunk, then for each one evaluates
-// chi and T(chi) with the device library's trigonometry and log and, where T > 0, decrements
-// the optical depth (these values only decide the event step).  A photon whose depth reaches
-// zero is queued; the event pass (k_pair_events) recomputes chi from the stored photon with
-// correctly rounded functions, samples the energy split and appends the pair.  Keeping the rare
-// event work out of the sweep keeps the sweep's register footprint, and so its occupancy, at
-// what streaming the photon arrays needs.
+// The sweep (k_photon) is the bandwidth-bound part: every photon slot, every step.  Each photon
+// carries a window of steps outside which it has no pair rate (photon_window: below the energy
+// that can reach chi_min in the field, or outside a pulse's support); it is set when the photon
+// is appended and moves with it.  A thread reads the windows of the PPT photons it owns in the
+// chunk; only the photons inside their window are read in full and evaluate chi and T(chi), with
+// the device library's trigonometry and log, and, where T > 0, decrement the optical depth (these
+// values only decide the event step).  A photon whose depth reaches zero is queued; the event
+// pass (k_pair_events) recomputes chi from the stored photon with correctly rounded functions,
+// samples the energy split and appends the pair.  Keeping the rare event work out of the sweep
+// keeps the sweep's register footprint, and so its occupancy, at what streaming needs.
 // ---------------------------------------------------------------------------
 template <int FK, int PPT, bool MIXED>
 __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
@@ -668,7 +676,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   double* sT = smem;
   float* sT32 = (float*)smem;
   unsigned* sredu = (unsigned*)(smem + a.tb.n_cp);
-  unsigned* slist = sredu + 16 * 3;  // per wave: 64 * PPT slot offsets (pulse field only)
+  unsigned* slist = sredu + 16 * 3;  // per wave: 64 * PPT slot offsets
   for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) {
     if (MIXED) sT32[i] = a.tb.T32[i];
     else sT[i] = a.tb.T[i];
@@ -688,10 +696,9 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   gptr<const Real> KX = nullptr, KY = nullptr, KZ = nullptr, XB = nullptr, YB = nullptr;
   gptr<const int32_t> BS = nullptr;
   gptr<double> TAU = nullptr;
-  float tpf0 = 0.0f, psif_max = 0.0f;
+  gptr<int2> WIN = nullptr;
   FieldK fK{0.0};
-  double eps_min = 0.0;          // photons below this energy have no pair rate in this field
-  unsigned uacc[3] = {0, 0, 0};  // in-field steps, chi above the table, non-finite tau
+  unsigned uacc[4] = {0, 0, 0, 0};  // in-field steps, chi above the table, non-finite tau, in-window steps
   auto flush = [&](int ii) {
     block_sum_u(uacc, sredu);
     if (threadIdx.x == 0) {
@@ -699,8 +706,9 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       if (uacc[0]) atomicAdd(&A.n_field, (unsigned long long)uacc[0]);
       if (uacc[1]) atomicAdd(&A.n_range, (unsigned long long)uacc[1]);
       if (uacc[2]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[2]);
+      if (uacc[3]) atomicAdd(&A.n_active, (unsigned long long)uacc[3]);
     }
-    uacc[0] = uacc[1] = uacc[2] = 0;
+    uacc[0] = uacc[1] = uacc[2] = uacc[3] = 0;
   };
 
   // each block takes a contiguous run of chunks, so it changes instance at most once per
@@ -722,27 +730,23 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       YB = as_global((const Real*)uni_ptr(S.y_dev));
       BS = as_global((const int32_t*)uni_ptr(S.birth_step_dev));
       TAU = as_global(uni_ptr(S.tau_dev));
+      WIN = as_global(uni_ptr(a.win)) + uni64(a.acc[ii].mover_off);
       n = uni64(a.acc[ii].n_start[2]);
       __syncthreads();  // the previous field copy is no longer read
       const uint64_t* src = (const uint64_t*)&a.inst[ii].field;
       for (int w = threadIdx.x; w < (int)(sizeof(qed_field) / 8); w += B) ((uint64_t*)&sF)[w] = src[w];
       __syncthreads();
-      tpf0 = (float)sF.p[2];
-      psif_max = (float)sF.p[1];
       fK.pi_over_len = uni_f64(field_k(sF).pi_over_len);
-      // margin: FP32 rounding of the energy test (~1e-7) and of chi (~1e-15)
-      eps_min = uni_f64(2.0 * a.tb.cp_min / field_bound(sF) * (1.0 - 1e-5));
     }
     const int64_t k0 = uni64((c - cb) * CH);  // first slot of the chunk
-    const int64_t rem = n - k0;        // slots of the chunk that exist: min(rem, CH)
+    const int64_t rem = n - k0;               // slots of the chunk that exist: min(rem, CH)
 
     // buffer resources over the chunk's live slots (uniform); lane offsets in bytes
     const uint32_t nlive = (uint32_t)(rem < CH ? rem : CH);
     const bufres rkx = make_buf(KX + k0, nlive * sizeof(Real)), rky = make_buf(KY + k0, nlive * sizeof(Real)),
                  rkz = make_buf(KZ + k0, nlive * sizeof(Real)), rxb = make_buf(XB + k0, nlive * sizeof(Real)),
                  ryb = make_buf(YB + k0, nlive * sizeof(Real)), rbs = make_buf(BS + k0, nlive * 4u),
-                 rtau = make_buf(TAU + k0, nlive * 8u);
-    const double tt = t;
+                 rtau = make_buf(TAU + k0, nlive * 8u), rwin = make_buf(WIN + k0, nlive * 8u);
     // in-field part for one photon; true when its optical depth reached zero
     auto infield = [&](unsigned off, Real kx, Real ky, Real kz, Real xb, Real yb, int32_t bs) -> bool {
       const Real eps = sqrt(kx * kx + ky * ky + kz * kz);
@@ -757,7 +761,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       double chi, T;
       if (MIXED) {
         float E[3], Bf[3];
-        field_at32<FK>(sF, fK, x, y, tt, E, Bf);
+        field_at32<FK>(sF, fK, x, y, t, E, Bf);
         const float ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
         const float ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
         const float az = E[2] + (nx * Bf[1] - ny * Bf[0]);
@@ -768,7 +772,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
         T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.dlc, chif, uacc[1], true);
       } else {
         double E[3], Bf[3];
-        field_at<FK, false>(sF, x, y, tt, E, Bf, &fK);
+        field_at<FK, false>(sF, x, y, t, E, Bf, &fK);
         const double ax = E[0] + (ny * Bf[2] - nz * Bf[1]);
         const double ay = E[1] + (nz * Bf[0] - nx * Bf[2]);
         const double az = E[2] + (nx * Bf[1] - ny * Bf[0]);
@@ -801,104 +805,54 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       }
     };
 
-    if (FK == QED_FIELD_LP_PULSE) {
-      // phase 1: loads of all PPT photons, then the FP32 envelope test.  The pulse occupies
-      // psi = t - x - psi0 in [0, Psi]; the FP32 estimate of psi carries a margin far above its
-      // rounding error (a few FP32 ulps of |t| + |psi0| + |x_b| + age), so a photon it rejects
-      // is one the FP64 test would certainly find outside the pulse.
-      float kxf[PPT], kyf[PPT], kzf[PPT], xbf[PPT];
-      int32_t bs[PPT];
+    // phase 1: the window of every slot (8 B); a photon outside its window has no pair rate in
+    // this step (photon_window), so nothing else of it is read
+    int2 wv[PPT];
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const unsigned off = threadIdx.x + j * B;
-        const uint32_t o = off * (uint32_t)sizeof(Real);
-        kxf[j] = (float)buf_ld<Real>(rkx, o);
-        kyf[j] = (float)buf_ld<Real>(rky, o);
-        kzf[j] = (float)buf_ld<Real>(rkz, o);
-        xbf[j] = (float)buf_ld<Real>(rxb, o);
-        bs[j] = buf_ld<int32_t>(rbs, off * 4u);
-      }
-      // A second exact cull: a photon below eps_min (field_bound) has no pair rate anywhere.
-      const float tpf = (float)t - tpf0;
-      const float mt = fabsf((float)t) + fabsf(tpf0);
-      const float eps_minf = (float)eps_min;
-      unsigned gmask = 0;
+    for (int j = 0; j < PPT; ++j) wv[j] = buf_ld_int2(rwin, (threadIdx.x + j * B) * 8u);
+    unsigned gmask = 0;
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const unsigned off = threadIdx.x + j * B;
-        if ((int64_t)off < rem) {
-          const float k2 = kxf[j] * kxf[j] + kyf[j] * kyf[j] + kzf[j] * kzf[j];
-          const float rk = rsqrtf(k2);
-          const float nxf = kxf[j] * rk;
-          const float agef = (float)((double)(step - (int64_t)bs[j]) * dt);
-          const float psif = tpf - (xbf[j] + agef * nxf);
-          const float m = 1e-5f * (mt + fabsf(xbf[j]) + agef) + 1e-30f;
-          if (psif >= -m && psif <= psif_max + m && k2 * rk >= eps_minf) gmask |= 1u << j;
-        }
-      }
-      // phase 2: the photons inside the pulse, packed densely across the wave through a per-wave
-      // LDS list (so the in-field code runs on full waves however the photons are spread), state
-      // re-read from cache; one copy of the in-field code holds registers
-      const int lane = threadIdx.x & 63;
-      unsigned* list = slist + (threadIdx.x >> 6) * (64 * PPT);
-      const int cnt = __popc(gmask);
-      int incl = cnt;
+    for (int j = 0; j < PPT; ++j)
+      if ((int64_t)(threadIdx.x + j * B) < rem && in_window(wv[j], step)) gmask |= 1u << j;
+    // phase 2: the photons inside their windows, packed densely across the wave through a
+    // per-wave LDS list (so the in-field code runs on full waves however the photons are
+    // spread); one copy of the in-field code holds registers.  Most waves have none.
+    if (__ballot(gmask != 0) == 0) continue;
+    const int lane = threadIdx.x & 63;
+    unsigned* list = slist + (threadIdx.x >> 6) * (64 * PPT);
+    const int cnt = __popc(gmask);
+    uacc[3] += cnt;
+    int incl = cnt;
 #pragma unroll
-      for (int o = 1; o < 64; o <<= 1) {
-        const int v = __shfl_up(incl, o);
-        if (lane >= o) incl += v;
-      }
-      const int total = __shfl(incl, 63);
-      int w = incl - cnt;
-#pragma unroll
-      for (int j = 0; j < PPT; ++j)
-        if (gmask & (1u << j)) list[w++] = threadIdx.x + j * B;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      for (int e0 = 0; e0 < total; e0 += 64) {  // wave-uniform trip count
-        const int e = e0 + lane;
-        bool pend = false;
-        unsigned off = 0;
-        if (e < total) {
-          off = list[e];
-          const uint32_t o = off * (uint32_t)sizeof(Real);
-          pend = infield(off, buf_ld<Real>(rkx, o), buf_ld<Real>(rky, o), buf_ld<Real>(rkz, o), buf_ld<Real>(rxb, o),
-                         Real(0), buf_ld<int32_t>(rbs, off * 4u));
-        }
-        enqueue(off, pend);
-      }
-      // the list is rewritten for the next chunk only after every lane has read it
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-      Real kx[PPT], ky[PPT], kz[PPT], xb[PPT], yb[PPT];
-      int32_t bs[PPT];
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const unsigned off = threadIdx.x + j * B;
-        const uint32_t o = off * (uint32_t)sizeof(Real);
-        kx[j] = buf_ld<Real>(rkx, o);
-        ky[j] = buf_ld<Real>(rky, o);
-        kz[j] = buf_ld<Real>(rkz, o);
-        if (NEED_X) {
-          xb[j] = buf_ld<Real>(rxb, o);
-          bs[j] = buf_ld<int32_t>(rbs, off * 4u);
-        }
-        if (NEED_Y) yb[j] = buf_ld<Real>(ryb, o);
-      }
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const unsigned off = threadIdx.x + j * B;
-        bool pend = false;
-        const double k2 = (double)kx[j] * kx[j] + (double)ky[j] * ky[j] + (double)kz[j] * kz[j];
-        if ((int64_t)off < rem && k2 >= eps_min * eps_min)  // no pair rate below eps_min
-          pend = infield(off, kx[j], ky[j], kz[j], NEED_X ? xb[j] : Real(0), NEED_Y ? yb[j] : Real(0),
-                         NEED_X ? bs[j] : 0);
-        enqueue(off, pend);
-      }
+    for (int o = 1; o < 64; o <<= 1) {
+      const int v = __shfl_up(incl, o);
+      if (lane >= o) incl += v;
     }
+    const int total = __shfl(incl, 63);
+    int w = incl - cnt;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j)
+      if (gmask & (1u << j)) list[w++] = threadIdx.x + j * B;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int e0 = 0; e0 < total; e0 += 64) {  // wave-uniform trip count
+      const int e = e0 + lane;
+      bool pend = false;
+      unsigned off = 0;
+      if (e < total) {
+        off = list[e];
+        const uint32_t o = off * (uint32_t)sizeof(Real);
+        pend = infield(off, buf_ld<Real>(rkx, o), buf_ld<Real>(rky, o), buf_ld<Real>(rkz, o),
+                       NEED_X ? buf_ld<Real>(rxb, o) : Real(0), NEED_Y ? buf_ld<Real>(ryb, o) : Real(0),
+                       NEED_X ? buf_ld<int32_t>(rbs, off * 4u) : 0);
+      }
+      enqueue(off, pend);
+    }
+    // the list is rewritten for the next chunk only after every lane has read it
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (cur >= 0) flush(cur);
 }
@@ -1000,6 +954,7 @@ __device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k,
     etau = optical_depth(r0[3]);
     ptau = optical_depth(r1[0]);
     S.tau_dev[k] = kTauGone;
+    a.win[a.acc[ii].mover_off + k] = make_int2(INT_MAX, INT_MIN);
     defect = gp + ge - epsd;
   }
   // append electron and positron, one atomic per wave and instance
@@ -1188,7 +1143,7 @@ __global__ __launch_bounds__(256) void k_compact_movers(const qed_instance* __re
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
-                                                      const int64_t* __restrict__ movers) {
+                                                      const int64_t* __restrict__ movers, int2* __restrict__ win) {
   const int ii = blockIdx.y;
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
@@ -1222,6 +1177,7 @@ __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __rest
       S.tau_dev[k] = S.tau_dev[src];
       S.uid_dev[k] = S.uid_dev[src];
       S.birth_step_dev[k] = S.birth_step_dev[src];
+      win[acc[ii].mover_off + k] = win[acc[ii].mover_off + src];
     }
   }
 }
@@ -1230,6 +1186,30 @@ __global__ void k_compact_finish(const qed_instance* __restrict__ inst, int n_in
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
     const qed_species& S = inst[i].s[2];
     if (S.count_dev) *S.count_dev = acc[i].n_live;
+  }
+}
+
+// Pair windows of every photon present (after a bind, or when the step's t0, dt or tables
+// change); grid: x strides photons, y = instance.
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_photon_windows(const qed_instance* __restrict__ inst,
+                                                        const InstAcc* __restrict__ acc, int2* __restrict__ win,
+                                                        double t0, double dt, double cp_min) {
+  using Real = typename std::conditional<MIXED, float, double>::type;
+  const int ii = blockIdx.y;
+  const qed_species& S = inst[ii].s[2];
+  if (S.capacity == 0 || !S.count_dev) return;
+  const int64_t n = min(*S.count_dev, S.capacity);
+  const double eps_min = pair_eps_min(inst[ii].field, cp_min);
+  int2* W = win + acc[ii].mover_off;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
+    if (S.tau_dev[k] < kTauPendingMin) {  // converted, waiting for compaction
+      W[k] = make_int2(INT_MAX, INT_MIN);
+      continue;
+    }
+    W[k] = photon_window(inst[ii].field, eps_min, cp_min, t0, dt, ((const Real*)S.ux_dev)[k], ((const Real*)S.uy_dev)[k],
+                         ((const Real*)S.uz_dev)[k], ((const Real*)S.x_dev)[k], S.birth_step_dev[k]);
   }
 }
 
@@ -1347,8 +1327,9 @@ void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mix
 }
 
 void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
+  // T table, block reduction, and the per-wave lists of in-window photon slots (64 * ppt each)
   const size_t shm = (size_t)a.tb.n_cp * sizeof(double) + 16 * 3 * sizeof(unsigned) +
-                     (fk == QED_FIELD_LP_PULSE ? (size_t)block * a.ppt * sizeof(unsigned) : 0) + 64;
+                     (size_t)block * a.ppt * sizeof(unsigned) + 64;
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_photon_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;
@@ -1369,15 +1350,23 @@ void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixe
   else hipLaunchKernelGGL(k_ledger<false>, dim3(128, 3 * n_inst), dim3(256), 0, s, inst, acc);
 }
 
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, bool mixed, hipStream_t s) {
+void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, int2* win, double t0, double dt,
+                           double cp_min, bool mixed, hipStream_t s) {
+  const dim3 g(n_inst == 1 ? 2048 : 64, n_inst);
+  if (mixed) hipLaunchKernelGGL(k_photon_windows<true>, g, dim3(256), 0, s, inst, acc, win, t0, dt, cp_min);
+  else hipLaunchKernelGGL(k_photon_windows<false>, g, dim3(256), 0, s, inst, acc, win, t0, dt, cp_min);
+}
+
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, int2* win, bool mixed,
+                    hipStream_t s) {
   hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   // blocks per instance: enough to stream one large instance at full bandwidth; blocks past an
   // instance's photons (or of an instance with nothing to remove) return at once
   const dim3 g(n_inst == 1 ? 2048 : 256, n_inst);
   hipLaunchKernelGGL(k_compact_count, g, dim3(256), 0, s, inst, acc);
   hipLaunchKernelGGL(k_compact_movers, g, dim3(256), 0, s, inst, acc, movers);
-  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers);
-  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers);
+  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers, win);
+  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers, win);
   hipLaunchKernelGGL(k_compact_finish, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
 }
 

@@ -189,6 +189,37 @@ def collision(n: int, a0: float = 200.0, gamma_mean: float = 2000.0, gamma_rel_s
     return w
 
 
+def photon_population(n: int, eps_min: float = 10.0, eps_max: float = 1e5, sigma_um: float = 2.0,
+                      comoving_x: tuple | None = None, seed: int = 1, uid0: int = 1 << 40) -> dict:
+    """Photons (birth step 0) around the origin for the collision geometry: energies
+    log-uniform in [eps_min, eps_max]; directions 60% along -x, 20% isotropic, 10% at a small
+    angle to +x (1 - n_x log-uniform in [1e-12, 1e-4]) and 10% exactly along +x (moving with
+    the pulse); Gaussian positions with sigma = sigma_um, except that the photons moving along
+    +x are spread uniformly in x over `comoving_x` when it is given."""
+    rng = np.random.Generator(np.random.Philox(key=np.array([seed, 0xF0700], dtype=np.uint64)))
+    eps = 10.0 ** rng.uniform(math.log10(eps_min), math.log10(eps_max), n)
+    kind = rng.uniform(0.0, 1.0, n)
+    d = np.zeros((n, 3))
+    d[:, 0] = -1.0
+    iso = (kind >= 0.6) & (kind < 0.8)
+    c = rng.uniform(-1.0, 1.0, n)
+    phi = rng.uniform(0.0, 2.0 * math.pi, n)
+    s_ = np.sqrt(1.0 - c * c)
+    d[iso] = np.stack([c, s_ * np.cos(phi), s_ * np.sin(phi)], axis=1)[iso]
+    near = (kind >= 0.8) & (kind < 0.9)
+    om = 10.0 ** rng.uniform(-12.0, -4.0, n)         # 1 - cos(theta)
+    sn = np.sqrt(om * (2.0 - om))
+    d[near] = np.stack([1.0 - om, sn * np.cos(phi), sn * np.sin(phi)], axis=1)[near]
+    d[kind >= 0.9] = (1.0, 0.0, 0.0)
+    sig = um_to_code(sigma_um)
+    x = rng.normal(0.0, sig, n)
+    if comoving_x is not None:
+        x = np.where(kind >= 0.8, rng.uniform(comoving_x[0], comoving_x[1], n), x)
+    return {"x": x, "y": rng.normal(0.0, sig, n), "z": rng.normal(0.0, sig, n),
+            "ux": eps * d[:, 0], "uy": eps * d[:, 1], "uz": eps * d[:, 2],
+            "uid": np.arange(uid0, uid0 + n, dtype=np.uint64), "birth_step": np.zeros(n, dtype=np.int64)}
+
+
 def collision_config2(n: int = 1_000_000, n_steps: int = 20_000) -> Workload:
     """1e6 electrons, gamma ~ N(2000, 10%), sigma = 2 um, LP a0 = 200, lambda = 1 um,
     30 fs (intensity FWHM) sin^2 envelope, dt = lambda/(200 c), 20000 steps, pairs on."""

@@ -255,3 +255,57 @@ def test_radiation_reaction_gpu_tables(mode, gpu_tables, oracle_tables):
     r = _gpu_run(w, gpu_tables)
     _check_parity(r, w, o_res, o_led, label="rr_%s_gpu_tables" % mode, **_bars("gpu_built"))
     assert r.ledger()[0]["radiated"] == pytest.approx(o_led["radiated"], rel=1e-9)
+
+
+# Pair windows: every photon carries the steps in which its pair rate can be non-zero (the pulse's
+# support along its path, and the energy that can reach chi_min); only those steps are evaluated.
+# Photons given at bind (windows from the first step's pass), ahead of, inside and behind the
+# pulse, head-on, isotropic, nearly and exactly co-moving with it: per-uid parity with the
+# oracle, which evaluates every photon in every step.
+def _photon_window_workload(n=20000, seed=7):
+    w = W.collision(1, a0=200.0, n_steps=2600, meet_step=1300, seed=seed, flags=W.FLAG_PAIRS | W.FLAG_PROPAGATE)
+    w.electrons = {k: v[:0] for k, v in w.electrons.items()}
+    w.capacity = dict(electron=2 * n + 1024, positron=2 * n + 1024, photon=n + 1024)
+    # co-moving photons from behind the pulse, through it, to ahead of it (psi = t - x - psi0)
+    psi_len, psi0 = w.field[1], w.field[2]
+    return w, W.photon_population(n, comoving_x=(-psi0 - psi_len - 20.0, -psi0 + 20.0), seed=seed)
+
+
+def test_photon_windows_parity(shared_tables, oracle_tables):
+    w, ph = _photon_window_workload()
+    o_res, o_led = oracle_run(w, oracle_tables, photons=ph)
+    r = Run(w, shared_tables, photons=ph)
+    r.step(w.n_steps)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK"
+    _check_parity(r, w, o_res, o_led, label="photon_windows")
+    assert o_led["n_pair"] > 100
+    assert led["n_pair"] == o_led["n_pair"]
+    slots = led["particle_steps"][2]
+    _record("photon_windows_counts", {"slot_steps": slots, "active": led["photon_steps_active"],
+                                      "in_field": led["photon_steps_in_field"], "pairs": led["n_pair"]})
+    # the windows hold every step with a pair rate and leave out the photons below the energy cut
+    # (~8% of this population) and the co-moving ones outside the pulse (~15%)
+    assert led["photon_steps_in_field"] <= led["photon_steps_active"] < 0.8 * slots
+
+
+def test_photon_windows_fp32_mixed(shared_tables):
+    # the FP32-mixed sweep evaluates the same photon steps as the FP64 one (its windows are
+    # widened for the FP32 direction; they differ only where a stored FP32 momentum moves a
+    # window edge by a step) and converts the same photons.  It sees fewer steps with T > 0:
+    # T(chi) underflows FP32 below chi ~ 0.02 (T < 1e-38 there, no pair rate to speak of).
+    w, ph = _photon_window_workload(n=50000, seed=8)
+    r64 = Run(w, shared_tables, photons=ph)
+    r32 = Run(w, shared_tables, photons=ph, precision=capi.QED_FP32_MIXED)
+    r64.step(w.n_steps)
+    r32.step(w.n_steps)
+    l64, l32 = r64.ledger()[0], r32.ledger()[0]
+    rec = dict(in_field_64=l64["photon_steps_in_field"], in_field_32=l32["photon_steps_in_field"],
+               active_64=l64["photon_steps_active"], active_32=l32["photon_steps_active"],
+               pairs_64=l64["n_pair"], pairs_32=l32["n_pair"])
+    _record("photon_windows_fp32", rec)
+    assert l32["status"] == "QED_OK"
+    assert abs(rec["active_32"] - rec["active_64"]) <= 1e-6 * rec["active_64"] + 10
+    assert rec["in_field_32"] <= rec["in_field_64"] <= rec["active_64"]
+    assert abs(rec["pairs_32"] - rec["pairs_64"]) <= 0.02 * rec["pairs_64"] + 5
+    assert l32["drift"] < 1e-9
