@@ -231,64 +231,72 @@ def run_form(form, args, tables, tuned):
                     % (args.batched_scale, sum(w.n for w in ws), warmup, total, total, total // 2,
                        args.compact_every, args.compact_every))
     prec = capi.QED_FP64 if form in ("fp64", "grid") else capi.QED_FP32_MIXED
+    graphs = form != "grid"  # the grid form reorders its particles between steps (qed_sort)
+
+    def make_run():
+        r = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
+        if tuned is not None:
+            autotune.apply(r, tuned)
+        return r
+
+    def advance(run, step, k, graph):
+        """k steps from `step`: graph replay of whole compaction periods, compaction between them."""
+        done = 0
+        while done < k:
+            n = min(args.compact_every - step % args.compact_every, k - done)
+            if graph:
+                run.run(n, graph_steps=n if n == args.compact_every else 0)
+            else:
+                for i in range(n):
+                    if form == "grid" and (done + i) % args.grid_sort_every == 0:
+                        run.sort()  # tile order for the grid gathers, inside the timed region
+                    run.step(1)
+            step += n
+            done += n
+            if step % args.compact_every == 0:
+                run.compact()
+            if done % 2000 < n and done < k:
+                log("%s: step %d" % (form, step))
+        return step
+
     log("%s: allocating and binding (%s)" % (form, workload[:60]))
-    run = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
-    if tuned is not None:
-        autotune.apply(run, tuned)
-    step = 0
+    run = make_run()
     log("%s: %d warmup steps" % (form, warmup))
-    for _ in range(warmup):
-        run.step(1)
-        step += 1
-        if step % args.compact_every == 0:
-            run.compact()
+    step = advance(run, 0, warmup, graphs)
     led0 = run.ledger()
-    if not batched:
+    if not graphs:
         run.profile(True)
     run.synchronize()
     log("%s: timing %d steps" % (form, steps))
     t0 = time.perf_counter()
-    if batched:
-        # graph replay: whole compaction periods as captured graphs, compaction between them
-        done = 0
-        while done < steps:
-            k = min(args.compact_every - step % args.compact_every, steps - done)
-            run.run(k, graph_steps=k if k == args.compact_every else 0)
-            step += k
-            done += k
-            if step % args.compact_every == 0:
-                run.compact()
-            if done % 1000 == 0:
-                log("%s: step %d" % (form, step))
-    else:
-        for i in range(steps):
-            if form == "grid" and i % args.grid_sort_every == 0:
-                run.sort()  # tile order for the grid gathers, inside the timed region
-            run.step(1)
-            step += 1
-            if step % args.compact_every == 0:
-                run.compact()
-            if i and i % 2000 == 0:
-                log("%s: step %d" % (form, step))
+    step = advance(run, step, steps, graphs)
     run.synchronize()
     t1 = time.perf_counter()
     led1 = run.ledger()
-    if batched:
-        # kernel times from eager, profiled steps after the timed window (graph replay records none)
-        l0p = led1
+    # kernel times: HIP events around every kernel class on the run's stream, over the same
+    # steps replayed eagerly from the same initial state (graph replay records no per-kernel
+    # events, and the events would add launch gaps to the timed run)
+    if graphs:
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+        log("%s: kernel timing pass (eager, %d + %d steps)" % (form, warmup, steps))
+        run = make_run()
+        step = advance(run, 0, warmup, True)
+        lk0 = run.ledger()
         run.profile(True)
-        for _ in range(args.batched_profile_steps):
-            run.step(1)
+        step = advance(run, step, steps, False)
         ms, launches = run.profile_read()
         run.profile(False)
-        lk0, lk1 = _aggregate(l0p), _aggregate(run.ledger())
+        lk1 = run.ledger()
+        lk0, lk1 = _aggregate(lk0), _aggregate(lk1)
     else:
         ms, launches = run.profile_read()
         run.profile(False)
     n_inst = len(ws)
     agg0 = _aggregate(led0)
     agg1 = _aggregate(led1)
-    if not batched:
+    if not graphs:
         lk0, lk1 = agg0, agg1
     psteps = sum(agg1["particle_steps"]) - sum(agg0["particle_steps"])
     status = sorted(set(l["status"] for l in led1))
@@ -304,8 +312,9 @@ def run_form(form, args, tables, tuned):
                lepton_steps_in_field=int(agg1["lepton_steps_in_field"] - agg0["lepton_steps_in_field"]),
                dropped=int(sum(l["n_dropped"] for l in led1)), status=status,
                launch={k: (tuned.get(k) if tuned else None) for k in ("lepton", "photon")})
-    if batched:
-        res["kernel_timing_window"] = "%d eager steps after the timed window" % args.batched_profile_steps
+    if graphs:
+        res["kernel_timing"] = ("HIP events per kernel class over the same steps replayed eagerly from the same "
+                                "initial state (the timed run replays captured HIP graphs)")
     kind = "photon" if ms[2] >= ms[1] else "lepton"
     byts = kernel_bytes("fp64" if form in ("fp64", "grid") else "fp32", kind, lk0, lk1, grid=form == "grid")
     n_l = launches[2] if kind == "photon" else launches[1]
@@ -376,7 +385,6 @@ def main():
     ap.add_argument("--grid-sort-every", type=int, default=10, help="grid form: steps between spatial sorts")
     ap.add_argument("--batched-warmup", type=int, default=200)
     ap.add_argument("--batched-steps", type=int, default=20000)
-    ap.add_argument("--batched-profile-steps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain device copy of 1 GiB, 20 times (reference for HBM byte counters)")

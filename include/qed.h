@@ -171,7 +171,7 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
                     const qed_step_params* params);
 
 /* Launch shape of the sweep kernels: threads per block (64..256, multiple of 64) and particles
- * per thread (1, 2, 4 or 8); qed_set_launch sets both sweeps, qed_set_kernel_launch one of
+ * per thread (1, 2, 4 or 8; the photon sweep also 16); qed_set_launch sets both sweeps, qed_set_kernel_launch one of
  * them (kernel = QED_KERNEL_LEPTON or QED_KERNEL_PHOTON, the profile-class indices).  Takes
  * effect from the next step; drops a captured graph.  Results do not depend on the shape
  * (per-uid random streams); only the order of floating-point sums in the ledger does. */

@@ -20,8 +20,9 @@ import os
 from . import capi
 
 BLOCKS = (64, 128, 256)
-PPTS = (1, 2, 4, 8)
+PPTS = (1, 2, 4, 8, 16)  # 16 for the photon sweep only (the lepton sweep then runs 8)
 CANDIDATES = tuple((b, p) for b in BLOCKS for p in PPTS)
+LEPTON_MAX_PPT = 8
 KERNELS = {"lepton": capi.QED_KERNEL_LEPTON, "photon": capi.QED_KERNEL_PHOTON}
 
 
@@ -42,7 +43,8 @@ def tune(run, steps_per_trial: int = 10, rounds: int = 2, candidates=CANDIDATES,
     for r in range(rounds):
         order = list(candidates) if r % 2 == 0 else list(reversed(candidates))
         for (b, p) in order:
-            run.set_launch(b, p)
+            run.set_kernel_launch(capi.QED_KERNEL_LEPTON, b, min(p, LEPTON_MAX_PPT))
+            run.set_kernel_launch(capi.QED_KERNEL_PHOTON, b, p)
             run.step(1)
             l0 = _slots(run.ledger())
             run.profile(True)
@@ -54,7 +56,7 @@ def tune(run, steps_per_trial: int = 10, rounds: int = 2, candidates=CANDIDATES,
             rec = {"block": b, "ppt": p, "round": r, "lepton_ms": ms[1], "photon_ms": ms[2],
                    "lepton_particles": d_lep, "photon_particles": d_ph}
             trials.append(rec)
-            if d_lep >= min_particles * steps_per_trial:
+            if d_lep >= min_particles * steps_per_trial and p <= LEPTON_MAX_PPT:
                 per[(b, p)]["lepton"].append(ms[1] * 1e6 / d_lep * 1e6)
             if d_ph >= min_particles * steps_per_trial:
                 per[(b, p)]["photon"].append(ms[2] * 1e6 / d_ph * 1e6)

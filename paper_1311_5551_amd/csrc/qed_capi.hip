@@ -116,10 +116,10 @@ struct qed_workspace {
   // pair windows of the photons (one int2 per photon slot, instances at acc.mover_off), valid
   // for the step constants and table they were computed with
   int2* d_win = nullptr;
+  PhotonRec* d_rec = nullptr;
   size_t win_len = 0;
   bool win_valid = false;
   double win_t0 = 0.0, win_dt = 0.0, win_cp_min = 0.0;
-  std::vector<int64_t> win_off;
   int block[2] = {256, 256}, ppt[2] = {4, 4};  // launch shapes: [0] lepton sweep, [1] photon sweep
   // kernel timing: event pairs per kernel class, reused across reads
   bool profiling = false;
@@ -340,6 +340,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.qe.ent = ws->d_emq;
   a.qe.cap = ws->emq_cap;
   a.win = ws->d_win;
+  a.rec = ws->d_rec;
   // persistent grids: 2048 threads per CU, blocks taking contiguous runs of the chunk list.
   // The passes run in order on `stream`: the photon sweep alone saturates HBM, so running the
   // lepton passes beside it on a second stream (their data are disjoint) shares bandwidth
@@ -379,7 +380,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
 qed_status ensure_windows(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
   const double cp_min = device_tabs(tb).cp_min;
   if (ws->win_valid && ws->win_t0 == p->t0 && ws->win_dt == p->dt && ws->win_cp_min == cp_min) return QED_OK;
-  launch_photon_windows(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_win, p->t0, p->dt, cp_min,
+  launch_photon_windows(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_win, ws->d_rec, p->t0, p->dt, cp_min,
                         ws->prec == QED_FP32_MIXED, s);
   HIP_TRY(hipGetLastError());
   ws->win_valid = true;
@@ -563,6 +564,7 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->d_base);
   hipFree(ws->d_movers);
   hipFree(ws->d_win);
+  hipFree(ws->d_rec);
   delete ws;
 }
 
@@ -571,7 +573,8 @@ qed_status qed_set_kernel_launch(qed_workspace* ws, int32_t kernel, int32_t bloc
   if (kernel != QED_KERNEL_LEPTON && kernel != QED_KERNEL_PHOTON)
     return fail(QED_ERR_ARG, "kernel = %d: need QED_KERNEL_LEPTON or QED_KERNEL_PHOTON", kernel);
   if (block < 64 || block > 256 || block % 64) return fail(QED_ERR_ARG, "block = %d: need 64..256, multiple of 64", block);
-  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8) return fail(QED_ERR_ARG, "ppt = %d: need 1, 2, 4 or 8", ppt);
+  if (ppt != 1 && ppt != 2 && ppt != 4 && ppt != 8 && !(ppt == 16 && kernel == QED_KERNEL_PHOTON))
+    return fail(QED_ERR_ARG, "ppt = %d: need 1, 2, 4 or 8 (or 16 for the photon sweep)", ppt);
   const int k = kernel == QED_KERNEL_LEPTON ? 0 : 1;
   if (ws->block[k] != block || ws->ppt[k] != ppt) drop_graph(ws);
   ws->block[k] = block;
@@ -666,14 +669,15 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
   }
   if (movers > ws->win_len || !ws->d_win) {
     hipFree(ws->d_win);
+    hipFree(ws->d_rec);
     ws->d_win = nullptr;
+    ws->d_rec = nullptr;
     ws->win_len = 0;
     HIP_TRY(hipMalloc((void**)&ws->d_win, (movers ? movers : 1) * sizeof(int2)));
+    HIP_TRY(hipMalloc((void**)&ws->d_rec, (movers ? movers : 1) * sizeof(PhotonRec)));
     ws->win_len = movers ? movers : 1;
   }
   ws->win_valid = false;  // computed by the first step, which knows t0, dt and the tables
-  ws->win_off.resize(n_inst);
-  for (int i = 0; i < n_inst; ++i) ws->win_off[i] = acc0[i].mover_off;
   // emission queue: one entry per lepton slot (a lepton emits at most once per step)
   int64_t leptons = 0;
   for (int i = 0; i < n_inst; ++i) leptons += inst[i].s[0].capacity + inst[i].s[1].capacity;
@@ -811,11 +815,11 @@ qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream
     if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
     for (int s = 0; s < 3; ++s) {
       if (I.s[s].capacity == 0) continue;
-      HIP_TRY(launch_sort_species(ws->d_inst, I, ii, s, ws->d_glob, params->dt, mixed, ws->sort,
-                                  ws->d_win + ws->win_off[ii], ws->cus * 8,
+      HIP_TRY(launch_sort_species(ws->d_inst, I, ii, s, ws->d_glob, params->dt, mixed, ws->sort, ws->cus * 8,
                                   (hipStream_t)stream));
     }
   }
+  ws->win_valid = false;  // the photons moved: their windows and records are set again by the next step
   return QED_OK;
 }
 
@@ -855,7 +859,7 @@ qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches) {
 qed_status qed_compact(qed_workspace* ws, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
-  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_movers, ws->d_win, ws->prec == QED_FP32_MIXED,
+  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_movers, ws->d_win, ws->d_rec, ws->prec == QED_FP32_MIXED,
                  (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return QED_OK;

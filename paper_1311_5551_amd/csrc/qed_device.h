@@ -383,6 +383,16 @@ __device__ __forceinline__ double pair_eps_min(const qed_field& F, double cp_min
   return 2.0 * cp_min / field_bound(F) * (1.0 - 1e-5);
 }
 
+// What the photon sweep reads of a photon inside its window, in one 64-byte line (a copy of its
+// stored direction-and-birth state in FP64; exact for both precisions): the SoA arrays of a
+// sparse set of photons would cost a line per array.
+struct __attribute__((aligned(64))) PhotonRec {
+  double kx, ky, kz, xb, yb;
+  int32_t bs;
+  int32_t pad0;
+  double pad1[2];
+};
+
 // A step n is inside a window w when w.x <= n <= w.y; INT_MIN and INT_MAX stand for no bound.
 __device__ __forceinline__ bool in_window(int2 w, int64_t n) {
   return w.x <= w.y && (w.x == INT_MIN || n >= (int64_t)w.x) && (w.y == INT_MAX || n <= (int64_t)w.y);

@@ -20,6 +20,7 @@ struct StepArgs {
   EvQueue q;                  // pair events of the step (photon passes)
   EmitQueue qe;               // emission events of the step (lepton passes)
   int2* win;                  // per-photon pair windows; instance i's slots from acc[i].mover_off
+  PhotonRec* rec;             // per-photon records for the in-window evaluation (same indexing)
 };
 
 // scratch of the spatial sort (sized by the caller for the largest species and tile count)
@@ -33,8 +34,7 @@ struct SortScratch {
 
 hipError_t init_crmath();
 hipError_t launch_sort_species(const qed_instance* inst_dev, const qed_instance& inst_host, int ii, int s,
-                               const Glob* glob, double dt, bool mixed, const SortScratch& w, int2* win, int grid,
-                               hipStream_t st);
+                               const Glob* glob, double dt, bool mixed, const SortScratch& w, int grid, hipStream_t st);
 hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnchi_min, double* dlnchi, double* P,
                                double* T, double* fgrid, double* Pf, double* knorm, double* g, hipStream_t s);
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,
@@ -48,9 +48,9 @@ void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mix
 void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s);
 void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s);
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, int2* win, bool mixed,
-                    hipStream_t s);
-void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, int2* win, double t0, double dt,
-                           double cp_min, bool mixed, hipStream_t s);
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, int2* win, PhotonRec* rec,
+                    bool mixed, hipStream_t s);
+void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, int2* win, PhotonRec* rec,
+                           double t0, double dt, double cp_min, bool mixed, hipStream_t s);
 
 }  // namespace qedk

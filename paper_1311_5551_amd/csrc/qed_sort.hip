@@ -114,8 +114,7 @@ static void permute(const qed_species* sp_dev, void* a, void* stage, const uint3
 }
 
 hipError_t launch_sort_species(const qed_instance* inst_dev, const qed_instance& inst_host, int ii, int s,
-                               const Glob* glob, double dt, bool mixed, const SortScratch& w, int2* win, int grid,
-                               hipStream_t st) {
+                               const Glob* glob, double dt, bool mixed, const SortScratch& w, int grid, hipStream_t st) {
   const qed_field& F = inst_host.field;
   const int tiles_x = (F.nx + kTile - 1) / kTile, tiles_y = (F.ny + kTile - 1) / kTile;
   const int n_tiles = tiles_x * tiles_y;
@@ -157,10 +156,7 @@ hipError_t launch_sort_species(const qed_instance* inst_dev, const qed_instance&
   }
   permute<double>(sp_dev, S.tau_dev, w.stage, w.dst, grid, st);
   permute<uint64_t>(sp_dev, S.uid_dev, w.stage, w.dst, grid, st);
-  if (s == 2) {
-    permute<int32_t>(sp_dev, S.birth_step_dev, w.stage, w.dst, grid, st);
-    permute<uint64_t>(sp_dev, win, w.stage, w.dst, grid, st);  // the photons' pair windows
-  }
+  if (s == 2) permute<int32_t>(sp_dev, S.birth_step_dev, w.stage, w.dst, grid, st);
   return hipGetLastError();
 }
 

@@ -29,12 +29,18 @@ namespace qedk {
 // ---------------------------------------------------------------------------
 // snapshot at the start of a step or pass
 // ---------------------------------------------------------------------------
-__global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
-                             Glob* __restrict__ glob, EvCtl* __restrict__ evc, EvCtl* __restrict__ emc,
-                             int64_t* __restrict__ base_lep,
-                             int64_t* __restrict__ base_ph, int chunk_lep, int chunk_ph, int advance_clock,
-                             int count_photons) {
-  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+__global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restrict__ inst, int n_inst,
+                                                    InstAcc* __restrict__ acc, Glob* __restrict__ glob,
+                                                    EvCtl* __restrict__ evc, EvCtl* __restrict__ emc,
+                                                    int64_t* __restrict__ base_lep, int64_t* __restrict__ base_ph,
+                                                    int chunk_lep, int chunk_ph, int advance_clock, int count_photons) {
+  // each thread takes a contiguous range of instances: counts, then a block scan of the chunk
+  // totals, then the chunk-list prefix of its range
+  __shared__ int64_t s_lep[256], s_ph[256];
+  const int per = (n_inst + blockDim.x - 1) / blockDim.x;
+  const int b = min(n_inst, (int)threadIdx.x * per), e = min(n_inst, b + per);
+  int64_t sl = 0, sp = 0;
+  for (int i = b; i < e; ++i) {
     for (int s = 0; s < 3; ++s) {
       const qed_species& S = inst[i].s[s];
       int64_t c = 0;
@@ -50,23 +56,33 @@ __global__ void k_step_begin(const qed_instance* __restrict__ inst, int n_inst, 
       acc[i].n_start[s] = c;
       // particle-steps: leptons every step; photon slots in steps that run the photon pass
       if (advance_clock && (s < 2 || count_photons)) acc[i].particle_steps[s] += (unsigned long long)c;
+      if (s < 2) sl += (c + chunk_lep - 1) / chunk_lep;
+      else sp += (c + chunk_ph - 1) / chunk_ph;
     }
   }
+  s_lep[threadIdx.x] = sl;
+  s_ph[threadIdx.x] = sp;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t b = 0;
-    for (int i = 0; i < n_inst; ++i)
-      for (int s = 0; s < 2; ++s) {
-        base_lep[2 * i + s] = b;
-        b += (acc[i].n_start[s] + chunk_lep - 1) / chunk_lep;
-      }
-    glob->n_chunks[0] = b;
-    b = 0;
-    for (int i = 0; i < n_inst; ++i) {
-      base_ph[i] = b;
-      b += (acc[i].n_start[2] + chunk_ph - 1) / chunk_ph;
+  for (int o = 1; o < (int)blockDim.x; o <<= 1) {  // inclusive scans of the per-thread totals
+    const int64_t vl = threadIdx.x >= o ? s_lep[threadIdx.x - o] : 0;
+    const int64_t vp = threadIdx.x >= o ? s_ph[threadIdx.x - o] : 0;
+    __syncthreads();
+    s_lep[threadIdx.x] += vl;
+    s_ph[threadIdx.x] += vp;
+    __syncthreads();
+  }
+  int64_t rl = s_lep[threadIdx.x] - sl, rp = s_ph[threadIdx.x] - sp;
+  for (int i = b; i < e; ++i) {
+    for (int s = 0; s < 2; ++s) {
+      base_lep[2 * i + s] = rl;
+      rl += (acc[i].n_start[s] + chunk_lep - 1) / chunk_lep;
     }
-    glob->n_chunks[1] = b;
+    base_ph[i] = rp;
+    rp += (acc[i].n_start[2] + chunk_ph - 1) / chunk_ph;
+  }
+  if (threadIdx.x == blockDim.x - 1) {
+    glob->n_chunks[0] = s_lep[threadIdx.x];
+    glob->n_chunks[1] = s_ph[threadIdx.x];
     if (advance_clock) {
       glob->step_cur = glob->step_next;
       glob->step_next = glob->step_cur + 1;
@@ -641,8 +657,17 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
         const double sx = MIXED ? (double)(float)cx : cx;
         const double skx = MIXED ? (double)(float)ckx : ckx, sky = MIXED ? (double)(float)cky : cky,
                      skz = MIXED ? (double)(float)ckz : ckz;
-        a.win[a.acc[ii].mover_off + slot] = photon_window(I.field, pair_eps_min(I.field, a.tb.cp_min), a.tb.cp_min,
-                                                          a.sc.t0, a.sc.dt, skx, sky, skz, sx, (int32_t)(step + 1));
+        const double sy = MIXED ? (double)(float)cy : cy;
+        const int64_t pk = a.acc[ii].mover_off + slot;
+        a.win[pk] = photon_window(I.field, pair_eps_min(I.field, a.tb.cp_min), a.tb.cp_min, a.sc.t0, a.sc.dt, skx, sky,
+                                  skz, sx, (int32_t)(step + 1));
+        PhotonRec& R = a.rec[pk];
+        R.kx = skx;
+        R.ky = sky;
+        R.kz = skz;
+        R.xb = sx;
+        R.yb = sy;
+        R.bs = (int32_t)(step + 1);
       } else {
         n_drop = 1;
         dropped_e = sqrt(ckx * ckx + cky * cky + ckz * ckz);
@@ -693,10 +718,9 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   // context of the instance whose chunks the block is on (chunks [cb, ce) of the list)
   int cur = -1;
   int64_t cb = 0, ce = 0, n = 0;
-  gptr<const Real> KX = nullptr, KY = nullptr, KZ = nullptr, XB = nullptr, YB = nullptr;
-  gptr<const int32_t> BS = nullptr;
   gptr<double> TAU = nullptr;
   gptr<int2> WIN = nullptr;
+  gptr<const PhotonRec> REC = nullptr;
   FieldK fK{0.0};
   unsigned uacc[4] = {0, 0, 0, 0};  // in-field steps, chi above the table, non-finite tau, in-window steps
   auto flush = [&](int ii) {
@@ -723,14 +747,9 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       cb = uni64(a.base[ii]);
       ce = ii + 1 < a.n_base ? uni64(a.base[ii + 1]) : nch;
       const qed_species& S = a.inst[ii].s[2];
-      KX = as_global((const Real*)uni_ptr(S.ux_dev));
-      KY = as_global((const Real*)uni_ptr(S.uy_dev));
-      KZ = as_global((const Real*)uni_ptr(S.uz_dev));
-      XB = as_global((const Real*)uni_ptr(S.x_dev));
-      YB = as_global((const Real*)uni_ptr(S.y_dev));
-      BS = as_global((const int32_t*)uni_ptr(S.birth_step_dev));
       TAU = as_global(uni_ptr(S.tau_dev));
       WIN = as_global(uni_ptr(a.win)) + uni64(a.acc[ii].mover_off);
+      REC = as_global((const PhotonRec*)uni_ptr(a.rec)) + uni64(a.acc[ii].mover_off);
       n = uni64(a.acc[ii].n_start[2]);
       __syncthreads();  // the previous field copy is no longer read
       const uint64_t* src = (const uint64_t*)&a.inst[ii].field;
@@ -743,12 +762,10 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
 
     // buffer resources over the chunk's live slots (uniform); lane offsets in bytes
     const uint32_t nlive = (uint32_t)(rem < CH ? rem : CH);
-    const bufres rkx = make_buf(KX + k0, nlive * sizeof(Real)), rky = make_buf(KY + k0, nlive * sizeof(Real)),
-                 rkz = make_buf(KZ + k0, nlive * sizeof(Real)), rxb = make_buf(XB + k0, nlive * sizeof(Real)),
-                 ryb = make_buf(YB + k0, nlive * sizeof(Real)), rbs = make_buf(BS + k0, nlive * 4u),
-                 rtau = make_buf(TAU + k0, nlive * 8u), rwin = make_buf(WIN + k0, nlive * 8u);
+    const bufres rtau = make_buf(TAU + k0, nlive * 8u), rwin = make_buf(WIN + k0, nlive * 8u);
+    const gptr<const PhotonRec> rrec = REC + k0;
     // in-field part for one photon; true when its optical depth reached zero
-    auto infield = [&](unsigned off, Real kx, Real ky, Real kz, Real xb, Real yb, int32_t bs) -> bool {
+    auto infield = [&](unsigned off, Real kx, Real ky, Real kz, Real xb, Real yb, int32_t bs, double tau) -> bool {
       const Real eps = sqrt(kx * kx + ky * ky + kz * kz);
       const Real inv = (Real)1 / eps;
       const Real nx = kx * inv, ny = ky * inv, nz = kz * inv;
@@ -783,7 +800,6 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       }
       bool pend = false;
       if (T > 0.0) {
-        double tau = buf_ld<double>(rtau, off * 8u);
         if (!(tau < 0.0)) {  // tau < 0: converted in an earlier step
           ++uacc[0];
           tau -= MIXED ? (double)((float)rate * (float)chi * (float)T * (float)inv) : rate * chi * T * (double)inv;
@@ -836,16 +852,19 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
     for (int e0 = 0; e0 < total; e0 += 64) {  // wave-uniform trip count
       const int e = e0 + lane;
       bool pend = false;
       unsigned off = 0;
       if (e < total) {
         off = list[e];
-        const uint32_t o = off * (uint32_t)sizeof(Real);
-        pend = infield(off, buf_ld<Real>(rkx, o), buf_ld<Real>(rky, o), buf_ld<Real>(rkz, o),
-                       NEED_X ? buf_ld<Real>(rxb, o) : Real(0), NEED_Y ? buf_ld<Real>(ryb, o) : Real(0),
-                       NEED_X ? buf_ld<int32_t>(rbs, off * 4u) : 0);
+        // one line per photon: the record holds the stored values exactly
+        const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
+        const dbl2 q0 = q[0], q1 = q[1], q2 = q[2];
+        const double tau = buf_ld<double>(rtau, off * 8u);
+        pend = infield(off, (Real)q0.x, (Real)q0.y, (Real)q1.x, NEED_X ? (Real)q1.y : Real(0),
+                       NEED_Y ? (Real)q2.x : Real(0), NEED_X ? (int32_t)(uint32_t)__double_as_longlong(q2.y) : 0, tau);
       }
       enqueue(off, pend);
     }
@@ -1143,7 +1162,8 @@ __global__ __launch_bounds__(256) void k_compact_movers(const qed_instance* __re
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
-                                                      const int64_t* __restrict__ movers, int2* __restrict__ win) {
+                                                      const int64_t* __restrict__ movers, int2* __restrict__ win,
+                                                      PhotonRec* __restrict__ rec) {
   const int ii = blockIdx.y;
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
@@ -1178,6 +1198,7 @@ __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __rest
       S.uid_dev[k] = S.uid_dev[src];
       S.birth_step_dev[k] = S.birth_step_dev[src];
       win[acc[ii].mover_off + k] = win[acc[ii].mover_off + src];
+      rec[acc[ii].mover_off + k] = rec[acc[ii].mover_off + src];
     }
   }
 }
@@ -1194,7 +1215,8 @@ __global__ void k_compact_finish(const qed_instance* __restrict__ inst, int n_in
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_photon_windows(const qed_instance* __restrict__ inst,
                                                         const InstAcc* __restrict__ acc, int2* __restrict__ win,
-                                                        double t0, double dt, double cp_min) {
+                                                        PhotonRec* __restrict__ rec, double t0, double dt,
+                                                        double cp_min) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   const int ii = blockIdx.y;
   const qed_species& S = inst[ii].s[2];
@@ -1202,14 +1224,23 @@ __global__ __launch_bounds__(256) void k_photon_windows(const qed_instance* __re
   const int64_t n = min(*S.count_dev, S.capacity);
   const double eps_min = pair_eps_min(inst[ii].field, cp_min);
   int2* W = win + acc[ii].mover_off;
+  PhotonRec* R = rec + acc[ii].mover_off;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
-    if (S.tau_dev[k] < kTauPendingMin) {  // converted, waiting for compaction
-      W[k] = make_int2(INT_MAX, INT_MIN);
-      continue;
-    }
-    W[k] = photon_window(inst[ii].field, eps_min, cp_min, t0, dt, ((const Real*)S.ux_dev)[k], ((const Real*)S.uy_dev)[k],
-                         ((const Real*)S.uz_dev)[k], ((const Real*)S.x_dev)[k], S.birth_step_dev[k]);
+    PhotonRec r;
+    r.kx = ((const Real*)S.ux_dev)[k];
+    r.ky = ((const Real*)S.uy_dev)[k];
+    r.kz = ((const Real*)S.uz_dev)[k];
+    r.xb = ((const Real*)S.x_dev)[k];
+    r.yb = ((const Real*)S.y_dev)[k];
+    r.bs = S.birth_step_dev[k];
+    r.pad0 = 0;
+    r.pad1[0] = r.pad1[1] = 0.0;
+    R[k] = r;
+    // converted photons (waiting for compaction) have no window
+    W[k] = S.tau_dev[k] < kTauPendingMin
+               ? make_int2(INT_MAX, INT_MIN)
+               : photon_window(inst[ii].field, eps_min, cp_min, t0, dt, r.kx, r.ky, r.kz, r.xb, r.bs);
   }
 }
 
@@ -1273,6 +1304,7 @@ static void launch_photon_fk(const StepArgs& a, dim3 grid, dim3 block, size_t sh
     case 1: launch_photon_ppt<FK, 1>(a, grid, block, shm, s, mixed); break;
     case 2: launch_photon_ppt<FK, 2>(a, grid, block, shm, s, mixed); break;
     case 8: launch_photon_ppt<FK, 8>(a, grid, block, shm, s, mixed); break;
+    case 16: launch_photon_ppt<FK, 16>(a, grid, block, shm, s, mixed); break;
     default: launch_photon_ppt<FK, 4>(a, grid, block, shm, s, mixed); break;
   }
 }
@@ -1350,23 +1382,23 @@ void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixe
   else hipLaunchKernelGGL(k_ledger<false>, dim3(128, 3 * n_inst), dim3(256), 0, s, inst, acc);
 }
 
-void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, int2* win, double t0, double dt,
-                           double cp_min, bool mixed, hipStream_t s) {
+void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, int2* win, PhotonRec* rec,
+                           double t0, double dt, double cp_min, bool mixed, hipStream_t s) {
   const dim3 g(n_inst == 1 ? 2048 : 64, n_inst);
-  if (mixed) hipLaunchKernelGGL(k_photon_windows<true>, g, dim3(256), 0, s, inst, acc, win, t0, dt, cp_min);
-  else hipLaunchKernelGGL(k_photon_windows<false>, g, dim3(256), 0, s, inst, acc, win, t0, dt, cp_min);
+  if (mixed) hipLaunchKernelGGL(k_photon_windows<true>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
+  else hipLaunchKernelGGL(k_photon_windows<false>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
 }
 
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, int2* win, bool mixed,
-                    hipStream_t s) {
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, int2* win, PhotonRec* rec,
+                    bool mixed, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   // blocks per instance: enough to stream one large instance at full bandwidth; blocks past an
   // instance's photons (or of an instance with nothing to remove) return at once
   const dim3 g(n_inst == 1 ? 2048 : 256, n_inst);
   hipLaunchKernelGGL(k_compact_count, g, dim3(256), 0, s, inst, acc);
   hipLaunchKernelGGL(k_compact_movers, g, dim3(256), 0, s, inst, acc, movers);
-  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers, win);
-  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers, win);
+  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers, win, rec);
+  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers, win, rec);
   hipLaunchKernelGGL(k_compact_finish, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
 }
 

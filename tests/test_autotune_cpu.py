@@ -5,7 +5,7 @@ from paper_1311_5551_amd import autotune
 
 
 def test_candidates_are_the_supported_shapes():
-    assert set(autotune.CANDIDATES) == {(b, p) for b in (64, 128, 256) for p in (1, 2, 4, 8)}
+    assert set(autotune.CANDIDATES) == {(b, p) for b in (64, 128, 256) for p in (1, 2, 4, 8, 16)}
 
 
 def test_cache_round_trip(tmp_path):
