@@ -691,6 +691,8 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
 // samples the energy split and appends the pair.  Keeping the rare event work out of the sweep
 // keeps the sweep's register footprint, and so its occupancy, at what streaming needs.
 // ---------------------------------------------------------------------------
+constexpr int kPhotonRun = 4;  // chunks per run of the photon sweep's round-robin deal
+
 template <int FK, int PPT, bool MIXED>
 __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   using Real = typename std::conditional<MIXED, float, double>::type;
@@ -735,11 +737,12 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     uacc[0] = uacc[1] = uacc[2] = uacc[3] = 0;
   };
 
-  // each block takes a contiguous run of chunks, so it changes instance at most once per
-  // instance boundary inside its run
-  const int64_t per_block = (nch + gridDim.x - 1) / gridDim.x;
-  const int64_t c_end = min(nch, (int64_t)blockIdx.x * per_block + per_block);
-  for (int64_t c = (int64_t)blockIdx.x * per_block; c < c_end; ++c) {
+  // the chunk list is dealt to the blocks in runs of kPhotonRun chunks, round robin: the photons
+  // that need the in-field evaluation (the newest, at the end of the arrays) spread over all
+  // blocks.  A block's chunks still only grow, so it changes instance at most once per instance
+  // boundary it crosses.
+  const int64_t stride = (int64_t)gridDim.x * kPhotonRun;
+  for (int64_t c = (int64_t)blockIdx.x * kPhotonRun; c < nch; c += ((c + 1) % kPhotonRun) ? 1 : stride - kPhotonRun + 1) {
     if (c >= ce) {  // first chunk of another instance (c only grows)
       if (cur >= 0) flush(cur);
       const int ii = uni32(find_entry(a.base, a.n_base, c));
