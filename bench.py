@@ -231,7 +231,9 @@ def run_form(form, args, tables, tuned):
                     % (args.batched_scale, sum(w.n for w in ws), warmup, total, total, total // 2,
                        args.compact_every, args.compact_every))
     prec = capi.QED_FP64 if form in ("fp64", "grid") else capi.QED_FP32_MIXED
-    graphs = form != "grid"  # the grid form reorders its particles between steps (qed_sort)
+    # the grid form reorders its particles between steps (qed_sort); --no-graphs runs every step
+    # eagerly with the kernel timers on (for profilers that cannot follow graph replay)
+    graphs = form != "grid" and not args.no_graphs
 
     def make_run():
         r = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
@@ -384,6 +386,8 @@ def main():
     ap.add_argument("--grid-electrons", type=int, default=16_000_000)
     ap.add_argument("--grid-sort-every", type=int, default=10, help="grid form: steps between spatial sorts")
     ap.add_argument("--batched-warmup", type=int, default=200)
+    ap.add_argument("--no-graphs", action="store_true",
+                    help="time eager launches with per-kernel HIP events instead of graph replay")
     ap.add_argument("--batched-steps", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
