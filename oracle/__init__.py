@@ -99,6 +99,9 @@ def lib():
                      "oracle_cr_sin", "oracle_cr_cos"):
             getattr(L, name).argtypes = [C.c_double]
             getattr(L, name).restype = C.c_double
+        for name in ("oracle_number_cumulative", "oracle_pf_cumulative"):
+            getattr(L, name).argtypes = [C.c_double, _DP, C.c_int, _DP]
+            getattr(L, name).restype = None
         L.oracle_philox.argtypes = [C.POINTER(C.c_uint64)] * 3
         L.oracle_philox.restype = None
         L.oracle_gauss_legendre.argtypes = [C.c_int, _DP, _DP]
@@ -181,6 +184,22 @@ def philox(counter, key):
     P = C.POINTER(C.c_uint64)
     lib().oracle_philox(c.ctypes.data_as(P), k.ctypes.data_as(P), o.ctypes.data_as(P))
     return o
+
+
+def number_cumulative(eta, chi):
+    """int_0^chi F(eta, chi')/chi' dchi' at ascending chi (Appendix A)."""
+    c = np.ascontiguousarray(chi, dtype=np.float64)
+    out = np.empty_like(c)
+    lib().oracle_number_cumulative(float(eta), c.ctypes.data_as(_DP), len(c), out.ctypes.data_as(_DP))
+    return out
+
+
+def pf_cumulative(chi, f):
+    """int_0^f p_f(f', chi) df' at ascending f in [0, 1] (Appendix B, normalised)."""
+    a = np.ascontiguousarray(f, dtype=np.float64)
+    out = np.empty_like(a)
+    lib().oracle_pf_cumulative(float(chi), a.ctypes.data_as(_DP), len(a), out.ctypes.data_as(_DP))
+    return out
 
 
 # ---- tables ------------------------------------------------------------------

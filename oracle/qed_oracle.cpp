@@ -484,6 +484,52 @@ double oracle_cutoff_chi(double eta, double frac) { return cutoff_chi(eta, frac)
 double oracle_T(double chi) { return pair_T(chi); }
 double oracle_pair_k(double chi) { return pair_k(chi); }
 double oracle_pf(double f, double chi) { return pair_split_unnorm(f, chi) / pair_k(chi); }
+// Cumulative emission number int_0^{chi_i} F/chi' dchi' (Appendix A) at n ascending chi_i,
+// integrated piece by piece between them (chi above eta/2 gives h(eta)).
+void oracle_number_cumulative(double eta, const double* chi, int n, double* out) {
+  const double stop = std::log(0.5 * eta), s0 = stop - kTailSpan;
+  double acc = 0.0, s_prev = s0;
+  bool started = false;
+  for (int i = 0; i < n; ++i) {
+    const double s = chi[i] > 0.0 ? std::min(std::log(chi[i]), stop) : -INFINITY;
+    if (s <= s0) {  // below the quadrature span: the small-chi power law, int_0^chi F/chi = 3 F(chi)
+      out[i] = s == -INFINITY ? 0.0 : 3.0 * synch_F_s(eta, s, stop);
+      continue;
+    }
+    if (!started) {
+      acc = 3.0 * synch_F_s(eta, s0, stop);
+      s_prev = s0;
+      started = true;
+    }
+    // pieces are resolved to 1e-16 of h (a piece in the exponential tail has no relative scale)
+    if (s > s_prev) acc += number_integral(eta, s_prev, s, 1e-16 * synch_h(eta));
+    s_prev = std::max(s_prev, s);
+    out[i] = acc;
+  }
+}
+// Cumulative normalised energy split int_0^{f_i} p_f(f', chi) df' (Appendix B) at n ascending
+// f_i in [0, 1].
+void oracle_pf_cumulative(double chi, const double* f, int n, double* out) {
+  const double k = pair_k(chi);
+  if (!(k > 0.0)) {  // chi so small that p_f underflows everywhere (no pairs are made there)
+    for (int i = 0; i < n; ++i) out[i] = 0.0;
+    return;
+  }
+  double acc = 0.0, prev = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double fi = std::min(std::max(f[i], 0.0), 1.0);
+    if (fi > prev) {
+      // the integrand has one-sided features at both ends: split at 1/2
+      const double tol = 1e-16 * k;  // pieces where p_f is exponentially small have no relative scale
+      if (prev < 0.5 && fi > 0.5)
+        acc += pair_split_integral(chi, prev, 0.5, tol) + pair_split_integral(chi, 0.5, fi, tol);
+      else
+        acc += pair_split_integral(chi, prev, fi, tol);
+      prev = fi;
+    }
+    out[i] = acc / k;
+  }
+}
 void oracle_philox(const uint64_t* ctr, const uint64_t* key, uint64_t* out) { philox4x64_10(ctr, key, out); }
 double oracle_cr_exp(double x) { return cr_exp(x); }
 double oracle_cr_log(double x) { return cr_log(x); }
