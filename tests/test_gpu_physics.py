@@ -1,13 +1,18 @@
 """The HIP path against the paper's own ensemble results (Sec. 4, Table 2): the uniform-B test
 problems 1 and 3 run through the C ABI with GPU-built tables, at the paper's electron count
 for test 3 and a tenth of it for test 1; energy per initial electron in electrons, photons
-and positrons against Table 2, and the ledger closing on the per-event defects."""
+and positrons against Table 2, and the ledger closing on the per-event defects.  Then the
+electron and photon spectra of test 1 against the direct solution of the kinetic equations
+(eqs. 6-7), as the paper checks its own Monte-Carlo (Figs. 2-4)."""
 import os
 
+import numpy as np
 import pytest
 
 from paper_1311_5551_amd import workloads as W
 from paper_1311_5551_amd.sim import Run, Tables
+
+from parity import record
 
 pytestmark = pytest.mark.gpu
 
@@ -50,3 +55,48 @@ def test_table2_energy_partition_on_gpu(test, n, tol, gpu_tables):
     # no field work in a static B: the books close on the defects alone
     assert led["drift"] < 1e-12
     assert abs(led["work"]) < 1e-9 * led["energy0"]
+
+
+def _coarse_bins(edges, lo, per_bin=6):
+    """Coarse bins made of whole solver cells: every per_bin-th cell edge from the first at or above lo."""
+    first = int(np.searchsorted(edges, lo))
+    b = edges[first::per_bin]
+    return b if b[-1] == edges[-1] else np.append(b, edges[-1])
+
+
+def _coarse(edges, fine, bins):
+    """The solver's cell contents summed over the coarse bins (bins are cell edges)."""
+    i = np.searchsorted(edges, bins)
+    return np.array([fine[i[k]:i[k + 1]].sum() for k in range(len(bins) - 1)])
+
+
+def test_spectra_match_master_equation_on_gpu(gpu_tables):
+    # paper test 1 with pairs at dt = 0.05 Delta t_QED, 1e6 electrons through the C ABI: the
+    # electron and photon spectra at 1 fs against the direct solution of eqs. 6-7 (Fig. 2a, 2c)
+    from oracle import master as M
+    n = 1_000_000
+    w = W.paper_test(1, n, 0.05)
+    w.capacity = dict(electron=n + 200_000, positron=200_000, photon=16 * n)
+    r = Run(w, gpu_tables)
+    r.step(w.n_steps)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK"
+    s = M.solve(1e-3, 1000.0, W.fs_to_code(1.0), cells_per_e=20, pairs=True)
+    e = r.species(0, "electron")
+    ph = r.species(0, "photon")
+    ge = np.sqrt(1.0 + e["ux"] ** 2 + e["uy"] ** 2 + e["uz"] ** 2)
+    eps = np.sqrt(ph["ux"] ** 2 + ph["uy"] ** 2 + ph["uz"] ** 2)
+    rec = {}
+    for name, vals, fine, lo in (("electron", ge, s.electron, 30.0), ("photon", eps, s.photon, 3.0)):
+        bins = _coarse_bins(s.edges, lo)
+        mc = np.histogram(vals, bins=bins)[0] / n
+        me = _coarse(s.edges, fine, bins)
+        sig = np.sqrt(np.maximum(me, 1e-12) / n)
+        # bins holding >= 1e-4 of the particles (the far tail is the scheme's numerical diffusion)
+        dev = np.where(me >= 1e-4, np.abs(mc - me) / (4.0 * sig + 0.05 * me), 0.0)
+        rec[name] = {"mc": mc.tolist(), "master": me.tolist(), "worst": float(dev.max())}
+        assert dev.max() < 1.0, (name, mc, me)
+    record("spectra_vs_master_test1", rec)
+    # and the energies: the direct solution is the dt -> 0 limit, the run has dt = 0.05 Delta t_QED
+    assert led["energy"][0] / n == pytest.approx(s.energy("electron"), rel=0.015)
+    assert led["energy"][2] / n == pytest.approx(s.energy("photon"), rel=0.015)
