@@ -437,8 +437,11 @@ def main():
         "dtype": "f64" if main_r["form"] == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": main_r["workload"], "form": main_r["form"], "instances": main_r["n_inst"],
-                   "launch": main_r["launch"] if args.tune == "replica" else
-                   {"block": args.block, "particles_per_thread": args.ppt}},
+                   # the shapes the run used: tuned (cache or replica) per sweep, else the command line
+                   "launch": ({k: {"block": v["block"], "particles_per_thread": v["ppt"]}
+                               for k, v in main_r["launch"].items() if v}
+                              if any(main_r["launch"].values()) else
+                              {"block": args.block, "particles_per_thread": args.ppt})},
         "roofline": main_r["roofline"],
         "cpu_baseline": cpu,
         "detail": {r["form"]: {k: v for k, v in r.items() if k not in ("workload",)} for r in results},
