@@ -70,24 +70,30 @@ def _coarse(edges, fine, bins):
     return np.array([fine[i[k]:i[k + 1]].sum() for k in range(len(bins) - 1)])
 
 
-def test_spectra_match_master_equation_on_gpu(gpu_tables):
-    # paper test 1 with pairs at dt = 0.05 Delta t_QED, 1e6 electrons through the C ABI: the
-    # electron and photon spectra at 1 fs against the direct solution of eqs. 6-7 (Fig. 2a, 2c)
+@pytest.mark.parametrize("test,b,t_fs", [(1, 1e-3, 1.0), (3, 9e-3, 0.1)])
+def test_spectra_match_master_equation_on_gpu(test, b, t_fs, gpu_tables):
+    # paper tests 1 and 3 with pairs at dt = 0.05 Delta t_QED, 1e6 electrons through the C ABI:
+    # the electron, photon (and for test 3 positron) spectra at t0 against the direct solution of
+    # eqs. 6-7 (Figs. 2 and 4)
     from oracle import master as M
     n = 1_000_000
-    w = W.paper_test(1, n, 0.05)
-    w.capacity = dict(electron=n + 200_000, positron=200_000, photon=16 * n)
+    w = W.paper_test(test, n, 0.05)
+    w.capacity = dict(electron=n + 400_000, positron=400_000, photon=16 * n)
     r = Run(w, gpu_tables)
     r.step(w.n_steps)
     led = r.ledger()[0]
     assert led["status"] == "QED_OK"
-    s = M.solve(1e-3, 1000.0, W.fs_to_code(1.0), cells_per_e=20, pairs=True)
+    s = M.solve(b, 1000.0, W.fs_to_code(t_fs), cells_per_e=20, pairs=True)
     e = r.species(0, "electron")
+    pos = r.species(0, "positron")
     ph = r.species(0, "photon")
-    ge = np.sqrt(1.0 + e["ux"] ** 2 + e["uy"] ** 2 + e["uz"] ** 2)
+    energy = lambda d: np.sqrt(1.0 + d["ux"] ** 2 + d["uy"] ** 2 + d["uz"] ** 2)
     eps = np.sqrt(ph["ux"] ** 2 + ph["uy"] ** 2 + ph["uz"] ** 2)
+    cases = [("electron", energy(e), s.electron, 30.0), ("photon", eps, s.photon, 3.0)]
+    if test == 3:
+        cases.append(("positron", energy(pos), s.positron, 3.0))
     rec = {}
-    for name, vals, fine, lo in (("electron", ge, s.electron, 30.0), ("photon", eps, s.photon, 3.0)):
+    for name, vals, fine, lo in cases:
         bins = _coarse_bins(s.edges, lo)
         mc = np.histogram(vals, bins=bins)[0] / n
         me = _coarse(s.edges, fine, bins)
@@ -96,7 +102,9 @@ def test_spectra_match_master_equation_on_gpu(gpu_tables):
         dev = np.where(me >= 1e-4, np.abs(mc - me) / (4.0 * sig + 0.05 * me), 0.0)
         rec[name] = {"mc": mc.tolist(), "master": me.tolist(), "worst": float(dev.max())}
         assert dev.max() < 1.0, (name, mc, me)
-    record("spectra_vs_master_test1", rec)
+    record("spectra_vs_master_test%d" % test, rec)
     # and the energies: the direct solution is the dt -> 0 limit, the run has dt = 0.05 Delta t_QED
     assert led["energy"][0] / n == pytest.approx(s.energy("electron"), rel=0.015)
     assert led["energy"][2] / n == pytest.approx(s.energy("photon"), rel=0.015)
+    if test == 3:
+        assert led["energy"][1] / n == pytest.approx(s.energy("positron"), rel=0.03)
