@@ -35,7 +35,7 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     """Algorithmic HBM bytes of one kernel class over the timed region.
 
     grid=True (the 2-D grid workload, FP64): lepton full step 48 B read (x, y, u, tau) + 48 B
-    written; photon slot 8 B (pair window) + 44 B per photon inside its window (k, x and y at
+    written; photon slot 4 B (pair window) + 44 B per photon inside its window (k, x and y at
     birth, birth step), the gather of the FP32 grid not counted (the 201 MB grid is read from
     the cache hierarchy, its refresh is the set-up class).
 
@@ -45,7 +45,7 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     72 B in FP64, 60 B in FP32-mixed (hi/lo position, high words of u); + 16 B per queued
     emission event.  The emission pass (separate class) reads the event's lepton and writes the
     photon.
-    Photon sweep, per photon slot-step: its pair window (8 B); per photon inside its window, with
+    Photon sweep, per photon slot-step: its pair window (4 B); per photon inside its window, with
     a field that depends on x only (the plane-wave pulse), k (3 words), x at birth (1 word) and
     the birth step (4 B): 36 B in FP64, 20 B in FP32-mixed; + 16 B (tau read and written) for
     the photons that see a non-zero pair rate; + 8 B per queued pair event.  The pair pass
@@ -54,7 +54,7 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     if grid:
         if kind == "lepton":
             return (d("particle_steps", 0) + d("particle_steps", 1)) * 96 + (d("n_emit") + d("n_null")) * 16
-        return (d("particle_steps", 2) * 8 + d("photon_steps_active") * 44 + d("photon_steps_in_field") * 16
+        return (d("particle_steps", 2) * 4 + d("photon_steps_active") * 44 + d("photon_steps_in_field") * 16
                 + d("n_pair") * 8)
     if kind == "lepton":
         steps = d("particle_steps", 0) + d("particle_steps", 1)
@@ -62,7 +62,7 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
         drift = 72 if form == "fp64" else 60
         return full * 112 + (steps - full) * drift + (d("n_emit") + d("n_null")) * 16
     full = 36 if form == "fp64" else 20
-    return (d("particle_steps", 2) * 8 + d("photon_steps_active") * full + d("photon_steps_in_field") * 16
+    return (d("particle_steps", 2) * 4 + d("photon_steps_active") * full + d("photon_steps_in_field") * 16
             + d("n_pair") * 8)
 
 

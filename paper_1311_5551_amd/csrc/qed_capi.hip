@@ -115,8 +115,8 @@ struct qed_workspace {
   size_t movers_len = 0;
   // pair windows of the photons (one int2 per photon slot, instances at acc.mover_off), valid
   // for the step constants and table they were computed with
-  int2* d_win = nullptr;
-  PhotonRec* d_rec = nullptr;
+  uint32_t* d_win = nullptr;
+  void* d_rec = nullptr;     // PhotonRec (FP64) or PhotonRec32 (FP32-mixed) per photon slot
   size_t win_len = 0;
   bool win_valid = false;
   double win_t0 = 0.0, win_dt = 0.0, win_cp_min = 0.0;
@@ -673,8 +673,8 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
     ws->d_win = nullptr;
     ws->d_rec = nullptr;
     ws->win_len = 0;
-    HIP_TRY(hipMalloc((void**)&ws->d_win, (movers ? movers : 1) * sizeof(int2)));
-    HIP_TRY(hipMalloc((void**)&ws->d_rec, (movers ? movers : 1) * sizeof(PhotonRec)));
+    HIP_TRY(hipMalloc((void**)&ws->d_win, (movers ? movers : 1) * sizeof(uint32_t)));
+    HIP_TRY(hipMalloc((void**)&ws->d_rec, (movers ? movers : 1) * sizeof(PhotonRec)));  // either record kind
     ws->win_len = movers ? movers : 1;
   }
   ws->win_valid = false;  // computed by the first step, which knows t0, dt and the tables

@@ -7,6 +7,8 @@
 #include <limits.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "../../include/qed.h"
 #include "qed_crmath.h"
 
@@ -79,10 +81,6 @@ __device__ __forceinline__ float buf_ld<float>(bufres r, uint32_t o) {
 template <>
 __device__ __forceinline__ int32_t buf_ld<int32_t>(bufres r, uint32_t o) {
   return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
-}
-__device__ __forceinline__ int2 buf_ld_int2(bufres r, uint32_t o) {
-  const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, o, 0, 0);
-  return make_int2((int)v[0], (int)v[1]);
 }
 __device__ __forceinline__ void buf_st(bufres r, uint32_t o, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, o, 0, 0);
@@ -383,19 +381,37 @@ __device__ __forceinline__ double pair_eps_min(const qed_field& F, double cp_min
   return 2.0 * cp_min / field_bound(F) * (1.0 - 1e-5);
 }
 
-// What the photon sweep reads of a photon inside its window, in one 64-byte line (a copy of its
-// stored direction-and-birth state in FP64; exact for both precisions): the SoA arrays of a
-// sparse set of photons would cost a line per array.
+// What the photon sweep reads of a photon inside its window, in one line: a copy of its stored
+// direction-and-birth state (64 bytes in FP64; 32 bytes, the stored FP32 values, in the FP32-mixed
+// form).  The SoA arrays of a sparse set of photons would cost a line per array.
 struct __attribute__((aligned(64))) PhotonRec {
   double kx, ky, kz, xb, yb;
   int32_t bs;
   int32_t pad0;
   double pad1[2];
 };
+struct __attribute__((aligned(32))) PhotonRec32 {
+  float kx, ky, kz, xb, yb;
+  int32_t bs;
+  int32_t pad[2];
+};
+template <bool MIXED>
+using PhotonRecT = typename std::conditional<MIXED, PhotonRec32, PhotonRec>::type;
 
-// A step n is inside a window w when w.x <= n <= w.y; INT_MIN and INT_MAX stand for no bound.
-__device__ __forceinline__ bool in_window(int2 w, int64_t n) {
-  return w.x <= w.y && (w.x == INT_MIN || n >= (int64_t)w.x) && (w.y == INT_MAX || n <= (int64_t)w.y);
+// A window is stored in 32 bits: first and last step as 16-bit fields (lo | hi << 16), saturated
+// so that the stored window always holds the exact one: lo at 65535 stands for "from 65535 or
+// later", hi at 65535 for "no last step".  An empty window is lo = 65535, hi = 0.  Past step
+// 65535 only the windows without a last step stay open: that culls less, never wrongly.
+constexpr uint32_t kWinEmpty = 0x0000FFFFu;
+__device__ __forceinline__ uint32_t pack_window(int2 w) {
+  if (w.x > w.y || w.y < 0) return kWinEmpty;  // empty, or over before step 0
+  const uint32_t lo = (uint32_t)min(max(w.x, 0), 65535);
+  const uint32_t hi = w.y >= 65535 ? 65535u : (uint32_t)w.y;
+  return lo | (hi << 16);
+}
+__device__ __forceinline__ bool in_window(uint32_t w, int64_t n) {
+  const int64_t lo = w & 0xFFFFu, hi = w >> 16;
+  return lo <= hi && lo <= (n < 65535 ? n : 65535) && (hi == 65535 || n <= hi);
 }
 
 // The steps [lo, hi] in which a photon can have a pair rate (eq. 3 needs chi >= chi_min); in

@@ -19,8 +19,8 @@ struct StepArgs {
   StepConst sc;
   EvQueue q;                  // pair events of the step (photon passes)
   EmitQueue qe;               // emission events of the step (lepton passes)
-  int2* win;                  // per-photon pair windows; instance i's slots from acc[i].mover_off
-  PhotonRec* rec;             // per-photon records for the in-window evaluation (same indexing)
+  uint32_t* win;              // per-photon pair windows (pack_window); instance i's slots from acc[i].mover_off
+  void* rec;                  // per-photon records (PhotonRecT<MIXED>) for the in-window evaluation
 };
 
 // scratch of the spatial sort (sized by the caller for the largest species and tile count)
@@ -48,9 +48,9 @@ void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mix
 void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s);
 void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s);
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, int2* win, PhotonRec* rec,
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, uint32_t* win, void* rec,
                     bool mixed, hipStream_t s);
-void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, int2* win, PhotonRec* rec,
+void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, uint32_t* win, void* rec,
                            double t0, double dt, double cp_min, bool mixed, hipStream_t s);
 
 }  // namespace qedk

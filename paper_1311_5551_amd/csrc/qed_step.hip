@@ -659,9 +659,9 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
                      skz = MIXED ? (double)(float)ckz : ckz;
         const double sy = MIXED ? (double)(float)cy : cy;
         const int64_t pk = a.acc[ii].mover_off + slot;
-        a.win[pk] = photon_window(I.field, pair_eps_min(I.field, a.tb.cp_min), a.tb.cp_min, a.sc.t0, a.sc.dt, skx, sky,
-                                  skz, sx, (int32_t)(step + 1));
-        PhotonRec& R = a.rec[pk];
+        a.win[pk] = pack_window(photon_window(I.field, pair_eps_min(I.field, a.tb.cp_min), a.tb.cp_min, a.sc.t0,
+                                              a.sc.dt, skx, sky, skz, sx, (int32_t)(step + 1)));
+        PhotonRecT<MIXED>& R = ((PhotonRecT<MIXED>*)a.rec)[pk];
         R.kx = skx;
         R.ky = sky;
         R.kz = skz;
@@ -721,8 +721,8 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   int cur = -1;
   int64_t cb = 0, ce = 0, n = 0;
   gptr<double> TAU = nullptr;
-  gptr<int2> WIN = nullptr;
-  gptr<const PhotonRec> REC = nullptr;
+  gptr<uint32_t> WIN = nullptr;
+  gptr<const PhotonRecT<MIXED>> REC = nullptr;
   FieldK fK{0.0};
   unsigned uacc[4] = {0, 0, 0, 0};  // in-field steps, chi above the table, non-finite tau, in-window steps
   auto flush = [&](int ii) {
@@ -752,7 +752,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       const qed_species& S = a.inst[ii].s[2];
       TAU = as_global(uni_ptr(S.tau_dev));
       WIN = as_global(uni_ptr(a.win)) + uni64(a.acc[ii].mover_off);
-      REC = as_global((const PhotonRec*)uni_ptr(a.rec)) + uni64(a.acc[ii].mover_off);
+      REC = as_global((const PhotonRecT<MIXED>*)uni_ptr(a.rec)) + uni64(a.acc[ii].mover_off);
       n = uni64(a.acc[ii].n_start[2]);
       __syncthreads();  // the previous field copy is no longer read
       const uint64_t* src = (const uint64_t*)&a.inst[ii].field;
@@ -765,8 +765,8 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
 
     // buffer resources over the chunk's live slots (uniform); lane offsets in bytes
     const uint32_t nlive = (uint32_t)(rem < CH ? rem : CH);
-    const bufres rtau = make_buf(TAU + k0, nlive * 8u), rwin = make_buf(WIN + k0, nlive * 8u);
-    const gptr<const PhotonRec> rrec = REC + k0;
+    const bufres rtau = make_buf(TAU + k0, nlive * 8u), rwin = make_buf(WIN + k0, nlive * 4u);
+    const gptr<const PhotonRecT<MIXED>> rrec = REC + k0;
     // in-field part for one photon; true when its optical depth reached zero
     auto infield = [&](unsigned off, Real kx, Real ky, Real kz, Real xb, Real yb, int32_t bs, double tau) -> bool {
       const Real eps = sqrt(kx * kx + ky * ky + kz * kz);
@@ -824,11 +824,11 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       }
     };
 
-    // phase 1: the window of every slot (8 B); a photon outside its window has no pair rate in
+    // phase 1: the window of every slot (4 B); a photon outside its window has no pair rate in
     // this step (photon_window), so nothing else of it is read
-    int2 wv[PPT];
+    uint32_t wv[PPT];
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) wv[j] = buf_ld_int2(rwin, (threadIdx.x + j * B) * 8u);
+    for (int j = 0; j < PPT; ++j) wv[j] = (uint32_t)buf_ld<int32_t>(rwin, (threadIdx.x + j * B) * 4u);
     unsigned gmask = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
@@ -863,11 +863,20 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       if (e < total) {
         off = list[e];
         // one line per photon: the record holds the stored values exactly
-        const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
-        const dbl2 q0 = q[0], q1 = q[1], q2 = q[2];
         const double tau = buf_ld<double>(rtau, off * 8u);
-        pend = infield(off, (Real)q0.x, (Real)q0.y, (Real)q1.x, NEED_X ? (Real)q1.y : Real(0),
-                       NEED_Y ? (Real)q2.x : Real(0), NEED_X ? (int32_t)(uint32_t)__double_as_longlong(q2.y) : 0, tau);
+        if (MIXED) {
+          typedef float flt4 __attribute__((ext_vector_type(4)));
+          const gptr<const flt4> q = (gptr<const flt4>)(rrec + off);
+          const flt4 q0 = q[0], q1 = q[1];
+          pend = infield(off, (Real)q0.x, (Real)q0.y, (Real)q0.z, NEED_X ? (Real)q0.w : Real(0),
+                         NEED_Y ? (Real)q1.x : Real(0), NEED_X ? (int32_t)__float_as_uint(q1.y) : 0, tau);
+        } else {
+          const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
+          const dbl2 q0 = q[0], q1 = q[1], q2 = q[2];
+          pend = infield(off, (Real)q0.x, (Real)q0.y, (Real)q1.x, NEED_X ? (Real)q1.y : Real(0),
+                         NEED_Y ? (Real)q2.x : Real(0), NEED_X ? (int32_t)(uint32_t)__double_as_longlong(q2.y) : 0,
+                         tau);
+        }
       }
       enqueue(off, pend);
     }
@@ -976,7 +985,7 @@ __device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k,
     etau = optical_depth(r0[3]);
     ptau = optical_depth(r1[0]);
     S.tau_dev[k] = kTauGone;
-    a.win[a.acc[ii].mover_off + k] = make_int2(INT_MAX, INT_MIN);
+    a.win[a.acc[ii].mover_off + k] = kWinEmpty;
     defect = gp + ge - epsd;
   }
   // append electron and positron, one atomic per wave and instance
@@ -1165,8 +1174,9 @@ __global__ __launch_bounds__(256) void k_compact_movers(const qed_instance* __re
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
-                                                      const int64_t* __restrict__ movers, int2* __restrict__ win,
-                                                      PhotonRec* __restrict__ rec) {
+                                                      const int64_t* __restrict__ movers, uint32_t* __restrict__ win,
+                                                      void* __restrict__ rec_v) {
+  PhotonRecT<MIXED>* rec = (PhotonRecT<MIXED>*)rec_v;
   const int ii = blockIdx.y;
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
@@ -1217,8 +1227,8 @@ __global__ void k_compact_finish(const qed_instance* __restrict__ inst, int n_in
 // change); grid: x strides photons, y = instance.
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_photon_windows(const qed_instance* __restrict__ inst,
-                                                        const InstAcc* __restrict__ acc, int2* __restrict__ win,
-                                                        PhotonRec* __restrict__ rec, double t0, double dt,
+                                                        const InstAcc* __restrict__ acc, uint32_t* __restrict__ win,
+                                                        void* __restrict__ rec_v, double t0, double dt,
                                                         double cp_min) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   const int ii = blockIdx.y;
@@ -1226,24 +1236,22 @@ __global__ __launch_bounds__(256) void k_photon_windows(const qed_instance* __re
   if (S.capacity == 0 || !S.count_dev) return;
   const int64_t n = min(*S.count_dev, S.capacity);
   const double eps_min = pair_eps_min(inst[ii].field, cp_min);
-  int2* W = win + acc[ii].mover_off;
-  PhotonRec* R = rec + acc[ii].mover_off;
+  uint32_t* W = win + acc[ii].mover_off;
+  PhotonRecT<MIXED>* R = (PhotonRecT<MIXED>*)rec_v + acc[ii].mover_off;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
-    PhotonRec r;
+    PhotonRecT<MIXED> r{};
     r.kx = ((const Real*)S.ux_dev)[k];
     r.ky = ((const Real*)S.uy_dev)[k];
     r.kz = ((const Real*)S.uz_dev)[k];
     r.xb = ((const Real*)S.x_dev)[k];
     r.yb = ((const Real*)S.y_dev)[k];
     r.bs = S.birth_step_dev[k];
-    r.pad0 = 0;
-    r.pad1[0] = r.pad1[1] = 0.0;
     R[k] = r;
     // converted photons (waiting for compaction) have no window
     W[k] = S.tau_dev[k] < kTauPendingMin
-               ? make_int2(INT_MAX, INT_MIN)
-               : photon_window(inst[ii].field, eps_min, cp_min, t0, dt, r.kx, r.ky, r.kz, r.xb, r.bs);
+               ? kWinEmpty
+               : pack_window(photon_window(inst[ii].field, eps_min, cp_min, t0, dt, r.kx, r.ky, r.kz, r.xb, r.bs));
   }
 }
 
@@ -1385,14 +1393,14 @@ void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixe
   else hipLaunchKernelGGL(k_ledger<false>, dim3(128, 3 * n_inst), dim3(256), 0, s, inst, acc);
 }
 
-void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, int2* win, PhotonRec* rec,
+void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, uint32_t* win, void* rec,
                            double t0, double dt, double cp_min, bool mixed, hipStream_t s) {
   const dim3 g(n_inst == 1 ? 2048 : 64, n_inst);
   if (mixed) hipLaunchKernelGGL(k_photon_windows<true>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
   else hipLaunchKernelGGL(k_photon_windows<false>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
 }
 
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, int2* win, PhotonRec* rec,
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, uint32_t* win, void* rec,
                     bool mixed, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   // blocks per instance: enough to stream one large instance at full bandwidth; blocks past an
