@@ -187,7 +187,8 @@ qed_status qed_set_kernel_launch(qed_workspace* ws, int32_t kernel, int32_t bloc
 qed_status qed_set_event_queue(qed_workspace* ws, int64_t capacity);
 
 /* Sec. 3: every macro-particle starts with a sampled optical depth, tau = -ln U with U from the
- * particle's stream at counter (uid, 0, INIT, 0), for every particle in [0, count).  Async. */
+ * particle's stream at counter (uid, 0, INIT, 0), for every particle in [0, count) except the
+ * converted photons still waiting for qed_compact (tau = -1), which stay converted.  Async. */
 qed_status qed_init_optical_depth(qed_workspace* ws, qed_stream stream);
 
 /* Sets the index of the next step (device-resident clock; graph-capturable).  Async. */

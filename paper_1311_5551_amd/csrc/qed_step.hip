@@ -1058,6 +1058,7 @@ __global__ void k_init_tau(const qed_instance* __restrict__ inst) {
   int64_t n = *S.count_dev;
   if (n > S.capacity) n = S.capacity;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    if (s == 2 && S.tau_dev[k] < kTauPendingMin) continue;  // a converted photon keeps its mark
     uint64_t r[4];
     philox4x64_10(S.uid_dev[k], 0, KIND_INIT, 0, I.seed, I.key_instance, r);
     S.tau_dev[k] = optical_depth(r[0]);

@@ -331,3 +331,19 @@ def test_radiation_reaction_fp32_mixed(shared_tables):
     assert rec["gamma_rel_max"] < 4e-5
     assert rec["radiated_rel"] < 1e-7
     assert l32["drift"] < 1e-9
+
+
+def test_init_optical_depth_keeps_converted_photons(shared_tables):
+    # a second qed_init_optical_depth in the middle of a run redraws the live particles' depths
+    # and leaves the photons converted since the last compaction converted
+    w, r = _collision_run(shared_tables, n=1500)
+    r.step(1800)
+    before = r.species(0, "photon", live_only=False)
+    gone = before["tau"] < 0
+    assert gone.any()
+    capi.qed_init_optical_depth(r.ws, r._s())
+    after = r.species(0, "photon", live_only=False)
+    np.testing.assert_array_equal(after["tau"] < 0, gone)
+    assert (after["tau"][~gone] > 0).all()
+    r.step(10)
+    assert r.ledger()[0]["status"] == "QED_OK"
