@@ -309,3 +309,32 @@ def test_photon_windows_fp32_mixed(shared_tables):
     assert rec["in_field_32"] <= rec["in_field_64"] <= rec["active_64"]
     assert abs(rec["pairs_32"] - rec["pairs_64"]) <= 0.02 * rec["pairs_64"] + 5
     assert l32["drift"] < 1e-9
+
+
+def test_photon_windows_past_16_bit_steps(shared_tables, oracle_tables):
+    # the packed windows hold 16-bit step indices: from step 65535 on they saturate (cull less,
+    # never wrongly).  The same photon population as above, started at step 68000 with the
+    # collision shifted with it, against the oracle.
+    s0, n = 68000, 5000
+    w = W.collision(1, a0=200.0, n_steps=s0 + 2600, meet_step=s0 + 1300, seed=9,
+                    flags=W.FLAG_PAIRS | W.FLAG_PROPAGATE)
+    w.electrons = {k: v[:0] for k, v in w.electrons.items()}
+    w.capacity = dict(electron=2 * n + 1024, positron=2 * n + 1024, photon=n + 1024)
+    w.n_steps = 2600
+    psi_len, psi0 = w.field[1], w.field[2]
+    beta = math.sqrt(1.0 - 1.0 / 2000.0 ** 2)
+    shift = beta * s0 * w.dt  # where the beam of the collision preset is at step s0
+    ph = W.photon_population(n, comoving_x=(-psi0 - psi_len - 20.0 + s0 * w.dt, -psi0 + 20.0 + s0 * w.dt), seed=9)
+    head_on = ph["ux"] < 0.999 * np.sqrt(ph["ux"] ** 2 + ph["uy"] ** 2 + ph["uz"] ** 2)
+    ph["x"] = np.where(head_on, ph["x"] - shift, ph["x"])
+    ph["birth_step"] = np.full(n, s0, dtype=np.int64)
+    cfg = oracle.RunConfig(field_kind=w.field_kind, field=w.field, dt=w.dt, n_steps=w.n_steps, flags=w.flags,
+                           seed=w.seed, instance=w.instance, step0=s0)
+    o_res, o_led = oracle.run(cfg, oracle_tables, electrons=w.electrons, photons=ph)
+    r = Run(w, shared_tables, photons=ph, step0=s0)
+    r.step(w.n_steps)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK"
+    _check_parity(r, w, o_res, o_led, label="photon_windows_past_16_bit")
+    assert o_led["n_pair"] > 20
+    assert led["n_pair"] == o_led["n_pair"]
