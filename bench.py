@@ -35,9 +35,9 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     """Algorithmic HBM bytes of one kernel class over the timed region.
 
     grid=True (the 2-D grid workload, FP64): lepton full step 48 B read (x, y, u, tau) + 48 B
-    written; photon slot 4 B (pair window) + 44 B per photon inside its window (k, x and y at
-    birth, birth step), the gather of the FP32 grid not counted (the 201 MB grid is read from
-    the cache hierarchy, its refresh is the set-up class).
+    written; photon: 4 B per window and per group summary read + 44 B per photon inside its
+    window (k, x and y at birth, birth step), the gather of the FP32 grid not counted (the
+    201 MB grid is read from the cache hierarchy, its refresh is the set-up class).
 
     Lepton sweep, per particle-step in 3-D: with the full push 56 B read (x, u, tau) + 56 B
     written in FP64 (FP32-mixed: the same 112 B as hi/lo words of position and momentum plus
@@ -45,7 +45,9 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     72 B in FP64, 60 B in FP32-mixed (hi/lo position, high words of u); + 16 B per queued
     emission event.  The emission pass (separate class) reads the event's lepton and writes the
     photon.
-    Photon sweep, per photon slot-step: its pair window (4 B); per photon inside its window, with
+    Photon sweep: 4 B per summary window of a group of 64 slots that was read, and 4 B per slot
+    whose pair window was read (every slot, except in groups whose summary excludes the step);
+    per photon inside its window, with
     a field that depends on x only (the plane-wave pulse), k (3 words), x at birth (1 word) and
     the birth step (4 B): 36 B in FP64, 20 B in FP32-mixed; + 16 B (tau read and written) for
     the photons that see a non-zero pair rate; + 8 B per queued pair event.  The pair pass
@@ -54,16 +56,16 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     if grid:
         if kind == "lepton":
             return (d("particle_steps", 0) + d("particle_steps", 1)) * 96 + (d("n_emit") + d("n_null")) * 16
-        return (d("particle_steps", 2) * 4 + d("photon_steps_active") * 44 + d("photon_steps_in_field") * 16
-                + d("n_pair") * 8)
+        return ((d("photon_window_reads") + d("photon_group_reads")) * 4 + d("photon_steps_active") * 44
+                + d("photon_steps_in_field") * 16 + d("n_pair") * 8)
     if kind == "lepton":
         steps = d("particle_steps", 0) + d("particle_steps", 1)
         full = d("lepton_steps_in_field")
         drift = 72 if form == "fp64" else 60
         return full * 112 + (steps - full) * drift + (d("n_emit") + d("n_null")) * 16
     full = 36 if form == "fp64" else 20
-    return (d("particle_steps", 2) * 4 + d("photon_steps_active") * full + d("photon_steps_in_field") * 16
-            + d("n_pair") * 8)
+    return ((d("photon_window_reads") + d("photon_group_reads")) * 4 + d("photon_steps_active") * full
+            + d("photon_steps_in_field") * 16 + d("n_pair") * 8)
 
 
 def source_hash():
@@ -312,6 +314,8 @@ def run_form(form, args, tables, tuned):
                photon_steps_in_field=int(agg1["photon_steps_in_field"] - agg0["photon_steps_in_field"]),
                photon_steps_active=int(agg1["photon_steps_active"] - agg0["photon_steps_active"]),
                lepton_steps_in_field=int(agg1["lepton_steps_in_field"] - agg0["lepton_steps_in_field"]),
+               photon_window_reads=int(agg1["photon_window_reads"] - agg0["photon_window_reads"]),
+               photon_group_reads=int(agg1["photon_group_reads"] - agg0["photon_group_reads"]),
                dropped=int(sum(l["n_dropped"] for l in led1)), status=status,
                launch={k: (tuned.get(k) if tuned else None) for k in ("lepton", "photon")})
     if graphs:
@@ -335,7 +339,8 @@ def run_form(form, args, tables, tuned):
 
 def _aggregate(leds):
     out = {"particle_steps": [0, 0, 0], "count": [0, 0, 0]}
-    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field", "photon_steps_active", "lepton_steps_in_field"):
+    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field", "photon_steps_active", "lepton_steps_in_field",
+              "photon_window_reads", "photon_group_reads"):
         out[k] = sum(l[k] for l in leds)
     for i in range(3):
         out["particle_steps"][i] = sum(l["particle_steps"][i] for l in leds)

@@ -242,6 +242,10 @@ typedef struct {
                                       window (the steps in which its pair rate can be non-zero) */
   int64_t lepton_steps_in_field;   /* lepton steps with the full push (all of them, except outside a
                                       plane-wave pulse, where the push is the field-free drift) */
+  int64_t photon_window_reads;     /* photon slot-steps whose pair window was read: all slots, except
+                                      in groups of 64 slots whose summary window excludes the step */
+  int64_t photon_group_reads;      /* summary windows read (groups of 64 photon slots present at the
+                                      last compaction or window build) */
   int64_t particle_steps[3];       /* particles present at the start of each step, summed over the
                                       steps since qed_bind (photons: buffer slots, incl. dead ones
                                       not yet compacted, counted in steps with QED_PAIRS, the steps

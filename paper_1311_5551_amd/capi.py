@@ -66,7 +66,8 @@ class qed_ledger(C.Structure):
                 ("radiated", C.c_double), ("count", C.c_int64 * 3), ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
                 ("n_dropped", C.c_int64), ("n_range", C.c_int64), ("n_nonfinite", C.c_int64),
                 ("photon_steps_in_field", C.c_int64), ("photon_steps_active", C.c_int64),
-                ("lepton_steps_in_field", C.c_int64),
+                ("lepton_steps_in_field", C.c_int64), ("photon_window_reads", C.c_int64),
+                ("photon_group_reads", C.c_int64),
                 ("particle_steps", C.c_int64 * 3), ("drift", C.c_double)]
 
     def as_dict(self) -> dict:

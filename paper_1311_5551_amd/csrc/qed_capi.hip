@@ -118,6 +118,8 @@ struct qed_workspace {
   uint32_t* d_win = nullptr;
   void* d_rec = nullptr;     // PhotonRec (FP64) or PhotonRec32 (FP32-mixed) per photon slot
   size_t win_len = 0;
+  uint32_t* d_wsum = nullptr;  // window-group summaries (kWinGroup slots each), instances at acc.wsum_off
+  size_t wsum_len = 0;
   bool win_valid = false;
   double win_t0 = 0.0, win_dt = 0.0, win_cp_min = 0.0;
   int block[2] = {256, 256}, ppt[2] = {4, 4};  // launch shapes: [0] lepton sweep, [1] photon sweep
@@ -341,6 +343,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.qe.cap = ws->emq_cap;
   a.win = ws->d_win;
   a.rec = ws->d_rec;
+  a.wsum = ws->d_wsum;
   // persistent grids: 2048 threads per CU, blocks taking contiguous runs of the chunk list.
   // The passes run in order on `stream`: the photon sweep alone saturates HBM, so running the
   // lepton passes beside it on a second stream (their data are disjoint) shares bandwidth
@@ -380,7 +383,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
 qed_status ensure_windows(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
   const double cp_min = device_tabs(tb).cp_min;
   if (ws->win_valid && ws->win_t0 == p->t0 && ws->win_dt == p->dt && ws->win_cp_min == cp_min) return QED_OK;
-  launch_photon_windows(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_win, ws->d_rec, p->t0, p->dt, cp_min,
+  launch_photon_windows(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_win, ws->d_rec, ws->d_wsum, p->t0, p->dt, cp_min,
                         ws->prec == QED_FP32_MIXED, s);
   HIP_TRY(hipGetLastError());
   ws->win_valid = true;
@@ -565,6 +568,7 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->d_movers);
   hipFree(ws->d_win);
   hipFree(ws->d_rec);
+  hipFree(ws->d_wsum);
   delete ws;
 }
 
@@ -654,11 +658,20 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
   // compaction scratch: one mover index per photon slot
   std::vector<InstAcc> acc0(n_inst);
   std::memset(acc0.data(), 0, n_inst * sizeof(InstAcc));
-  size_t off = 0;
+  size_t off = 0, goff = 0;
   for (int i = 0; i < n_inst; ++i) {
     acc0[i].n_pair_compacted = ~0ull;  // the first compaction after a bind always runs
     acc0[i].mover_off = (int64_t)off;
+    acc0[i].wsum_off = (int64_t)goff;  // n_sealed = 0: no summary until the windows are made
     off += (size_t)inst[i].s[2].capacity;
+    goff += ((size_t)inst[i].s[2].capacity + kWinGroup - 1) / kWinGroup;
+  }
+  if (goff > ws->wsum_len || !ws->d_wsum) {
+    hipFree(ws->d_wsum);
+    ws->d_wsum = nullptr;
+    ws->wsum_len = 0;
+    HIP_TRY(hipMalloc((void**)&ws->d_wsum, (goff ? goff : 1) * sizeof(uint32_t)));
+    ws->wsum_len = goff ? goff : 1;
   }
   if (movers > ws->movers_len) {
     hipFree(ws->d_movers);
@@ -859,7 +872,8 @@ qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches) {
 qed_status qed_compact(qed_workspace* ws, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
-  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_movers, ws->d_win, ws->d_rec, ws->prec == QED_FP32_MIXED,
+  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_movers, ws->d_win, ws->d_rec, ws->d_wsum,
+                 ws->prec == QED_FP32_MIXED,
                  (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return QED_OK;
@@ -897,6 +911,8 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
     L.n_nonfinite = (int64_t)A.n_nonfinite;
     L.photon_steps_in_field = (int64_t)A.n_field;
     L.photon_steps_active = (int64_t)A.n_active;
+    L.photon_window_reads = (int64_t)A.n_win_reads;
+    L.photon_group_reads = (int64_t)A.n_group_reads;
     L.lepton_steps_in_field = (int64_t)A.n_field_lepton;
     for (int s = 0; s < 3; ++s) L.particle_steps[s] = (int64_t)A.particle_steps[s];
     const double resid = tot - L.energy0 - L.work - L.defect_emit - L.defect_pair + L.dropped_energy + L.radiated;

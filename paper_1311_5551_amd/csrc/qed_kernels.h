@@ -21,6 +21,7 @@ struct StepArgs {
   EmitQueue qe;               // emission events of the step (lepton passes)
   uint32_t* win;              // per-photon pair windows (pack_window); instance i's slots from acc[i].mover_off
   void* rec;                  // per-photon records (PhotonRecT<MIXED>) for the in-window evaluation
+  const uint32_t* wsum;       // window-group summaries; instance i's from acc[i].wsum_off
 };
 
 // scratch of the spatial sort (sized by the caller for the largest species and tile count)
@@ -49,8 +50,8 @@ void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mix
 void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s);
 void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s);
 void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, uint32_t* win, void* rec,
-                    bool mixed, hipStream_t s);
-void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, uint32_t* win, void* rec,
-                           double t0, double dt, double cp_min, bool mixed, hipStream_t s);
+                    uint32_t* wsum, bool mixed, hipStream_t s);
+void launch_photon_windows(const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
+                           uint32_t* wsum, double t0, double dt, double cp_min, bool mixed, hipStream_t s);
 
 }  // namespace qedk

@@ -54,6 +54,8 @@ __global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restri
         if (c < 0) c = 0;
       }
       acc[i].n_start[s] = c;
+      // a count that fell without a compaction (set by the caller) unseals the slots above it
+      if (s == 2 && acc[i].n_sealed > c / kWinGroup * kWinGroup) acc[i].n_sealed = c / kWinGroup * kWinGroup;
       // particle-steps: leptons every step; photon slots in steps that run the photon pass
       if (advance_clock && (s < 2 || count_photons)) acc[i].particle_steps[s] += (unsigned long long)c;
       if (s < 2) sl += (c + chunk_lep - 1) / chunk_lep;
@@ -723,8 +725,15 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   gptr<double> TAU = nullptr;
   gptr<uint32_t> WIN = nullptr;
   gptr<const PhotonRecT<MIXED>> REC = nullptr;
+  gptr<const uint32_t> WSUM = nullptr;
+  int64_t nseal = 0;
+  // group summaries of the current run of chunks, read in one load per wave: bit r PPT + j is
+  // set when group j of the wave in chunk m0 + r is sealed and its summary excludes the step
+  int64_t m0 = -1;
+  uint64_t mskip = 0;
   FieldK fK{0.0};
-  unsigned uacc[4] = {0, 0, 0, 0};  // in-field steps, chi above the table, non-finite tau, in-window steps
+  // in-field steps, chi above the table, non-finite tau, in-window steps, window reads, summary reads
+  unsigned uacc[6] = {0, 0, 0, 0, 0, 0};
   auto flush = [&](int ii) {
     block_sum_u(uacc, sredu);
     if (threadIdx.x == 0) {
@@ -733,8 +742,10 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       if (uacc[1]) atomicAdd(&A.n_range, (unsigned long long)uacc[1]);
       if (uacc[2]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[2]);
       if (uacc[3]) atomicAdd(&A.n_active, (unsigned long long)uacc[3]);
+      if (uacc[4]) atomicAdd(&A.n_win_reads, (unsigned long long)uacc[4]);
+      if (uacc[5]) atomicAdd(&A.n_group_reads, (unsigned long long)uacc[5]);
     }
-    uacc[0] = uacc[1] = uacc[2] = uacc[3] = 0;
+    uacc[0] = uacc[1] = uacc[2] = uacc[3] = uacc[4] = uacc[5] = 0;
   };
 
   // the chunk list is dealt to the blocks in runs of kPhotonRun chunks, round robin: the photons
@@ -753,6 +764,9 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       TAU = as_global(uni_ptr(S.tau_dev));
       WIN = as_global(uni_ptr(a.win)) + uni64(a.acc[ii].mover_off);
       REC = as_global((const PhotonRecT<MIXED>*)uni_ptr(a.rec)) + uni64(a.acc[ii].mover_off);
+      WSUM = as_global(uni_ptr(a.wsum)) + uni64(a.acc[ii].wsum_off);
+      nseal = uni64(a.acc[ii].n_sealed);
+      m0 = -1;
       n = uni64(a.acc[ii].n_start[2]);
       __syncthreads();  // the previous field copy is no longer read
       const uint64_t* src = (const uint64_t*)&a.inst[ii].field;
@@ -824,15 +838,43 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       }
     };
 
-    // phase 1: the window of every slot (4 B); a photon outside its window has no pair rate in
-    // this step (photon_window), so nothing else of it is read
+    // phase 0: in each chunk a wave loads the windows of PPT whole groups (slots
+    // k0 + 64 w + j B + [0, 64)).  Where those groups are sealed their summaries are read first,
+    // for the whole run of chunks at once (lane r PPT + j: chunk m0 + r, group j; PPT <= 16 and
+    // kPhotonRun = 4 fit a wave), and the groups whose summary excludes this step are not read
+    // further (after the photons have left the field, that is every group)
+    constexpr unsigned kAll = (1u << PPT) - 1u;
+    static_assert(PPT * kPhotonRun <= 64, "one summary per lane for a run of chunks");
+    if (m0 < 0 || c / kPhotonRun != m0 / kPhotonRun) {  // first chunk of a run in this instance
+      m0 = c;
+      const int lane = threadIdx.x & 63;
+      const int64_t cc = c + lane / PPT;
+      const int64_t cend = min(ce, (c / kPhotonRun + 1) * kPhotonRun);  // end of the run
+      bool skip = false;
+      if (lane < PPT * kPhotonRun && cc < cend) {
+        const int64_t g = (cc - cb) * (CH / kWinGroup) + (threadIdx.x >> 6) + (int64_t)(lane % PPT) * (B / kWinGroup);
+        if ((g + 1) * kWinGroup <= nseal) {
+          skip = !in_window(WSUM[g], step);
+          ++uacc[5];
+        }
+      }
+      mskip = __ballot(skip);
+    }
+    const unsigned live = ~(unsigned)(mskip >> ((c - m0) * PPT)) & kAll;  // wave-uniform
+    if (live == 0) continue;
+    // phase 1: the window of every slot of the live groups (4 B); a photon outside its window
+    // has no pair rate in this step (photon_window), so nothing else of it is read
     uint32_t wv[PPT];
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) wv[j] = (uint32_t)buf_ld<int32_t>(rwin, (threadIdx.x + j * B) * 4u);
+    for (int j = 0; j < PPT; ++j)
+      wv[j] = (live >> j) & 1u ? (uint32_t)buf_ld<int32_t>(rwin, (threadIdx.x + j * B) * 4u) : kWinEmpty;
     unsigned gmask = 0;
 #pragma unroll
-    for (int j = 0; j < PPT; ++j)
-      if ((int64_t)(threadIdx.x + j * B) < rem && in_window(wv[j], step)) gmask |= 1u << j;
+    for (int j = 0; j < PPT; ++j) {
+      const bool exists = (int64_t)(threadIdx.x + j * B) < rem;
+      if (exists && ((live >> j) & 1u)) ++uacc[4];
+      if (exists && in_window(wv[j], step)) gmask |= 1u << j;
+    }
     // phase 2: the photons inside their windows, packed densely across the wave through a
     // per-wave LDS list (so the in-field code runs on full waves however the photons are
     // spread); one copy of the in-field code holds registers.  Most waves have none.
@@ -1224,6 +1266,51 @@ __global__ void k_compact_finish(const qed_instance* __restrict__ inst, int n_in
   }
 }
 
+// Window-group summaries of the full groups of every instance's photons, from group
+// acc.n_sealed / kWinGroup on for an instance whose compaction removed nothing (its windows
+// below that only changed by becoming empty, which keeps the old summaries valid), else from 0.
+// One wave per group; grid: x strides groups, y = instance.
+__global__ __launch_bounds__(256) void k_window_summary(const qed_instance* __restrict__ inst,
+                                                        const InstAcc* __restrict__ acc,
+                                                        const uint32_t* __restrict__ win, uint32_t* __restrict__ wsum,
+                                                        int after_compaction) {
+  const int ii = blockIdx.y;
+  const qed_species& S = inst[ii].s[2];
+  if (S.capacity == 0 || !S.count_dev) return;
+  int64_t n = *S.count_dev;
+  if (n > S.capacity) n = S.capacity;
+  if (n < 0) n = 0;
+  const int64_t ng = n / kWinGroup;
+  const int64_t g_first = after_compaction && acc[ii].compact_skip ? acc[ii].n_sealed / kWinGroup : 0;
+  const uint32_t* W = win + acc[ii].mover_off;
+  uint32_t* G = wsum + acc[ii].wsum_off;
+  const int lane = threadIdx.x & 63;
+  const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
+  // the loop bound is wave-uniform, so every lane reaches the shuffles
+  for (int64_t g = g_first + blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); g < ng; g += wstride) {
+    const uint32_t w = W[g * kWinGroup + lane];
+    const bool any = (w & 0xFFFFu) <= (w >> 16);  // a non-empty window (pack_window)
+    uint32_t lo = any ? (w & 0xFFFFu) : 0xFFFFu, hi = any ? (w >> 16) : 0u;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = min(lo, (uint32_t)__shfl_xor((int)lo, o));
+      hi = max(hi, (uint32_t)__shfl_xor((int)hi, o));
+    }
+    if (lane == 0) G[g] = lo <= hi ? (lo | (hi << 16)) : kWinEmpty;
+  }
+}
+
+// the slots with a summary: every full group (after k_window_summary)
+__global__ void k_window_sealed(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+    const qed_species& S = inst[i].s[2];
+    int64_t n = S.count_dev ? *S.count_dev : 0;
+    if (n > S.capacity) n = S.capacity;
+    if (n < 0) n = 0;
+    acc[i].n_sealed = n / kWinGroup * kWinGroup;
+  }
+}
+
 // Pair windows of every photon present (after a bind, or when the step's t0, dt or tables
 // change); grid: x strides photons, y = instance.
 template <bool MIXED>
@@ -1394,15 +1481,17 @@ void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixe
   else hipLaunchKernelGGL(k_ledger<false>, dim3(128, 3 * n_inst), dim3(256), 0, s, inst, acc);
 }
 
-void launch_photon_windows(const qed_instance* inst, int n_inst, const InstAcc* acc, uint32_t* win, void* rec,
-                           double t0, double dt, double cp_min, bool mixed, hipStream_t s) {
+void launch_photon_windows(const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
+                           uint32_t* wsum, double t0, double dt, double cp_min, bool mixed, hipStream_t s) {
   const dim3 g(n_inst == 1 ? 2048 : 64, n_inst);
   if (mixed) hipLaunchKernelGGL(k_photon_windows<true>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
   else hipLaunchKernelGGL(k_photon_windows<false>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
+  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum, 0);
+  hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
 }
 
 void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, uint32_t* win, void* rec,
-                    bool mixed, hipStream_t s) {
+                    uint32_t* wsum, bool mixed, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   // blocks per instance: enough to stream one large instance at full bandwidth; blocks past an
   // instance's photons (or of an instance with nothing to remove) return at once
@@ -1412,6 +1501,8 @@ void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t*
   if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers, win, rec);
   else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers, win, rec);
   hipLaunchKernelGGL(k_compact_finish, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
+  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum, 1);
+  hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
 }
 
 }  // namespace qedk

@@ -13,7 +13,7 @@ import oracle
 from paper_1311_5551_amd import capi, workloads as W
 from paper_1311_5551_amd.sim import Run, Tables
 
-from parity import (E_TOL, STRADDLE, TAU_TOL, U_CAP, U_FRAC, U_TOL, X_TOL, compare_species, oracle_run,
+from parity import (E_TOL, STRADDLE, TAU_TOL, U_CAP, U_FRAC, U_TOL, X_TOL, compare_species, match, oracle_run,
                     record as _record, straddle_uids)
 
 pytestmark = pytest.mark.gpu
@@ -287,6 +287,51 @@ def test_photon_windows_parity(shared_tables, oracle_tables):
     # the windows hold every step with a pair rate and leave out the photons below the energy cut
     # (~8% of this population) and the co-moving ones outside the pulse (~15%)
     assert led["photon_steps_in_field"] <= led["photon_steps_active"] < 0.8 * slots
+
+
+@pytest.mark.parametrize("precision", [capi.QED_FP64, capi.QED_FP32_MIXED])
+def test_photon_window_groups_with_compaction(precision, shared_tables, oracle_tables):
+    # groups of 64 photon slots carry a summary window (made at each compaction and window
+    # build); a wave reads no window of a group whose summary excludes the step.  The collision
+    # of the test above, compacted every 100 steps as the production runs are: the photons born
+    # in the collision are summarised at the compactions and skipped once the pulse has passed
+    # them.  FP64 against the oracle per uid; FP32-mixed against its own run without summaries
+    # (no compaction: slots appended since the window build are read one by one).
+    w = W.collision(1500, a0=200.0, n_steps=2600, meet_step=1300, seed=11)
+    r = Run(w, shared_tables, precision=precision)
+    for _ in range(w.n_steps // 100):
+        r.step(100)
+        r.compact()
+    r.step(w.n_steps % 100)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK"
+    slots = led["particle_steps"][2]
+    _record("photon_window_groups_%s" % ("fp64" if precision == capi.QED_FP64 else "fp32"),
+            {"slot_steps": slots, "window_reads": led["photon_window_reads"],
+             "group_reads": led["photon_group_reads"], "active": led["photon_steps_active"], "pairs": led["n_pair"]})
+    assert led["photon_group_reads"] > 0
+    # a head-on photon takes ~2500 steps to cross the pulse, so in this short run only the
+    # photons born early have left it (0.80 of the slot-steps are read); the bench's 20000 steps
+    # skip the whole second half
+    assert led["photon_steps_active"] <= led["photon_window_reads"] < 0.9 * slots
+    if precision == capi.QED_FP64:
+        o_res, o_led = oracle_run(w, oracle_tables)
+        assert o_led["n_pair"] > 20
+        _check_parity(r, w, o_res, o_led, label="photon_window_groups")
+        if not straddle_uids(o_res).size:
+            assert led["n_pair"] == o_led["n_pair"]
+            assert led["n_emit"] == o_led["n_emit"]
+        return
+    ref = _gpu_run(w, shared_tables, precision=precision)
+    lr = ref.ledger()[0]
+    assert lr["photon_window_reads"] == lr["particle_steps"][2]
+    assert (led["n_pair"], led["n_emit"]) == (lr["n_pair"], lr["n_emit"])
+    for name in ("electron", "positron", "photon"):
+        a, b = r.species(0, name), ref.species(0, name)
+        ia, ib, only_a, only_b = match(a["uid"], b["uid"])
+        assert len(only_a) == 0 and len(only_b) == 0, name
+        for k in ("ux", "uy", "uz", "x", "tau"):
+            assert np.array_equal(a[k][ia], b[k][ib]), (name, k)
 
 
 def test_photon_windows_fp32_mixed(shared_tables):
