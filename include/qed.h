@@ -202,8 +202,10 @@ qed_status qed_set_step(qed_workspace* ws, int64_t step, qed_stream stream);
  * in the next step.  Never allocates; async on `stream`; device-side conditions (full buffers,
  * non-finite state) are reported by the next qed_energy_ledger.  The first step after qed_bind,
  * and any step whose t0, dt or tables differ from the previous one's, also enqueues a pass that
- * sets every photon's pair window (the steps in which its pair rate can be non-zero); a caller
- * capturing qed_step into its own graph should run one step before capturing. */
+ * sets every photon's pair window (the steps in which its pair rate can be non-zero) and the
+ * summary window of every full group of 64 photon slots; a caller capturing qed_step into its
+ * own graph should run one step before capturing.  Photons appended after that pass (or the
+ * last qed_compact) are read slot by slot until the next qed_compact summarises them. */
 qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params,
                     qed_stream stream);
 
@@ -222,7 +224,10 @@ qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_p
 qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream stream);
 
 /* Removes dead photons (tau < 0) from every bound photon species by moving live photons from
- * the tail into the holes (order is not preserved).  Async. */
+ * the tail into the holes (order is not preserved), then rebuilds the summary windows of the
+ * photon slot groups (from the last summarised group on where nothing was removed).  Call it
+ * periodically (e.g. every 100 steps): it also lets the photon sweep skip the groups whose
+ * photons are outside their pair windows.  Async. */
 qed_status qed_compact(qed_workspace* ws, qed_stream stream);
 
 /* Energy account of one instance (Sec. 3.1 and Table 2), in m c^2 times the weight. */
