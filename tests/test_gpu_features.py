@@ -160,12 +160,22 @@ def test_graph_replay_matches_plain_launches(shared_tables):
         assert la[k] == lb[k]
 
 
-def test_batched_instances_equal_single_runs(shared_tables):
+@pytest.mark.parametrize("compact", [False, True])
+def test_batched_instances_equal_single_runs(compact, shared_tables):
+    # compact=True: the batched run compacts every 100 steps, which also summarises each
+    # instance's photon slot groups (the sweep then skips groups outside their pair windows);
+    # the single runs never compact
     ws = [W.collision(n, a0=a0, gamma_mean=g0, n_steps=2400, meet_step=1200, seed=1, instance=i, uid0=0)
           for i, (n, a0, g0) in enumerate([(1000, 200.0, 2000.0), (17, 450.0, 800.0), (3001, 60.0, 4500.0),
                                            (1, 300.0, 1500.0), (650, 120.0, 3000.0)])]
     rb = Run(ws, shared_tables)
-    rb.step(2400)
+    if compact:
+        for _ in range(24):
+            rb.step(100)
+            rb.compact()
+        assert sum(l["photon_group_reads"] for l in rb.ledger()) > 0
+    else:
+        rb.step(2400)
     for i, w in enumerate(ws):
         rs = Run(w, shared_tables)
         rs.step(2400)
