@@ -872,7 +872,7 @@ qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches) {
 qed_status qed_compact(qed_workspace* ws, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
-  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_movers, ws->d_win, ws->d_rec, ws->d_wsum,
+  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_movers, ws->d_win, ws->d_rec, ws->d_wsum,
                  ws->prec == QED_FP32_MIXED,
                  (hipStream_t)stream);
   HIP_TRY(hipGetLastError());

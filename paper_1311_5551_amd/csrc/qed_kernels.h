@@ -49,8 +49,8 @@ void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mix
 void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s);
 void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s);
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, uint32_t* win, void* rec,
-                    uint32_t* wsum, bool mixed, hipStream_t s);
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
+                    uint32_t* win, void* rec, uint32_t* wsum, bool mixed, hipStream_t s);
 void launch_photon_windows(const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
                            uint32_t* wsum, double t0, double dt, double cp_min, bool mixed, hipStream_t s);
 

@@ -1266,6 +1266,109 @@ __global__ void k_compact_finish(const qed_instance* __restrict__ inst, int n_in
   }
 }
 
+// ---------------------------------------------------------------------------
+// partition of the photons by pair window (after the compaction): the photons that can have no
+// pair rate from the next step on (an empty window, or one that ended before that step) go to
+// the front [0, D), the others to the back.  The photons the sweep evaluates in a step then sit
+// together, and the front's groups are skipped by their summaries.  Photons of the back that
+// belong to the front swap places with front photons that belong to the back (per-uid results
+// do not depend on the order).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool window_over(uint32_t w, int64_t s) {
+  const uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+  return lo > hi || (hi != 65535u && (int64_t)hi < s);
+}
+
+__global__ void k_part_prep(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
+    const qed_species& S = inst[i].s[2];
+    int64_t n = S.count_dev ? *S.count_dev : 0;
+    if (n > S.capacity) n = S.capacity;
+    if (n < 0) n = 0;
+    acc[i].n_start[2] = n;
+    acc[i].n_live = 0;  // here: photons whose window is over (the size D of the front)
+    acc[i].hole_ctr = 0;
+    acc[i].mover_ctr = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_part_count(InstAcc* __restrict__ acc, const Glob* __restrict__ glob,
+                                                    const uint32_t* __restrict__ win) {
+  __shared__ double sred[16];
+  __shared__ unsigned sredu[16];
+  const int ii = blockIdx.y;
+  const int64_t n = acc[ii].n_start[2], s = glob->step_next;
+  const uint32_t* W = win + acc[ii].mover_off;
+  double d[1] = {0.0};
+  unsigned u[1] = {0};
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    if (window_over(W[k], s)) ++u[0];
+  block_sum(d, u, sred, sredu);
+  if (threadIdx.x == 0 && u[0]) atomicAdd((unsigned long long*)&acc[ii].n_live, (unsigned long long)u[0]);
+}
+
+// the photons of [D, n) whose window is over, listed in the mover array
+__global__ __launch_bounds__(256) void k_part_movers(InstAcc* __restrict__ acc, const Glob* __restrict__ glob,
+                                                     const uint32_t* __restrict__ win, int64_t* __restrict__ movers) {
+  const int ii = blockIdx.y;
+  const int64_t n = acc[ii].n_start[2], D = acc[ii].n_live, s = glob->step_next;
+  const uint32_t* W = win + acc[ii].mover_off;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  // loop bounds are identical across a wave so that every lane reaches the ballot
+  for (int64_t k0 = D + blockIdx.x * (int64_t)blockDim.x; k0 < n; k0 += stride) {
+    const int64_t k = k0 + threadIdx.x;
+    const bool mv = k < n && window_over(W[k], s);
+    const long long slot = wave_reserve(mv, (int64_t*)&acc[ii].mover_ctr);
+    if (mv) movers[acc[ii].mover_off + slot] = k;
+  }
+}
+
+template <class T>
+__device__ __forceinline__ void swap_at(void* a, int64_t i, int64_t j) {
+  T* p = (T*)a;
+  const T t = p[i];
+  p[i] = p[j];
+  p[j] = t;
+}
+
+// every photon of [0, D) whose window is not over swaps with one listed by k_part_movers
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
+                                                   const Glob* __restrict__ glob, const int64_t* __restrict__ movers,
+                                                   uint32_t* __restrict__ win, void* __restrict__ rec_v) {
+  using Real = typename std::conditional<MIXED, float, double>::type;
+  const int ii = blockIdx.y;
+  const qed_species& S = inst[ii].s[2];
+  const int64_t n = acc[ii].n_start[2], D = acc[ii].n_live, s = glob->step_next;
+  const long long n_movers = (long long)acc[ii].mover_ctr;
+  uint32_t* W = win + acc[ii].mover_off;
+  PhotonRecT<MIXED>* R = (PhotonRecT<MIXED>*)rec_v + acc[ii].mover_off;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool d3 = inst[ii].dims == 3;
+  for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < D; k0 += stride) {
+    const int64_t k = k0 + threadIdx.x;
+    const bool sw = k < D && !window_over(W[k], s);
+    const long long slot = wave_reserve(sw, (int64_t*)&acc[ii].hole_ctr);
+    // the two counts are equal (both are D minus the front's photons that stay); the bounds
+    // below only guard that invariant
+    if (sw && slot < n_movers) {
+      const int64_t j = movers[acc[ii].mover_off + slot];
+      if (j < D || j >= n) continue;
+      swap_at<Real>(S.x_dev, k, j);
+      swap_at<Real>(S.y_dev, k, j);
+      if (d3) swap_at<Real>(S.z_dev, k, j);
+      swap_at<Real>(S.ux_dev, k, j);
+      swap_at<Real>(S.uy_dev, k, j);
+      swap_at<Real>(S.uz_dev, k, j);
+      swap_at<double>(S.tau_dev, k, j);
+      swap_at<uint64_t>(S.uid_dev, k, j);
+      swap_at<int32_t>(S.birth_step_dev, k, j);
+      swap_at<uint32_t>(W, k, j);
+      swap_at<PhotonRecT<MIXED>>(R, k, j);
+    }
+  }
+}
+
 // Window-group summaries of the full groups of every instance's photons, from group
 // acc.n_sealed / kWinGroup on for an instance whose compaction removed nothing (its windows
 // below that only changed by becoming empty, which keeps the old summaries valid), else from 0.
@@ -1490,8 +1593,8 @@ void launch_photon_windows(const qed_instance* inst, int n_inst, InstAcc* acc, u
   hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
 }
 
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t* movers, uint32_t* win, void* rec,
-                    uint32_t* wsum, bool mixed, hipStream_t s) {
+void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
+                    uint32_t* win, void* rec, uint32_t* wsum, bool mixed, hipStream_t s) {
   hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   // blocks per instance: enough to stream one large instance at full bandwidth; blocks past an
   // instance's photons (or of an instance with nothing to remove) return at once
@@ -1501,7 +1604,12 @@ void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, int64_t*
   if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers, win, rec);
   else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers, win, rec);
   hipLaunchKernelGGL(k_compact_finish, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
-  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum, 1);
+  hipLaunchKernelGGL(k_part_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
+  hipLaunchKernelGGL(k_part_count, g, dim3(256), 0, s, acc, glob, win);
+  hipLaunchKernelGGL(k_part_movers, g, dim3(256), 0, s, acc, glob, win, movers);
+  if (mixed) hipLaunchKernelGGL(k_part_swap<true>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec);
+  else hipLaunchKernelGGL(k_part_swap<false>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec);
+  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum, 0);
   hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
 }
 
