@@ -130,6 +130,10 @@ struct InstAcc {
   int64_t wsum_off;            // offset of this instance's window-group summaries
   int64_t n_sealed;            // photon slots [0, n_sealed) have a current group summary (multiple of
                                // kWinGroup); slots appended since are scanned one by one
+  int64_t n_front;             // photons [0, n_front) have no pair rate in any later step (their window
+                               // is over; set by the partition at compaction)
+  int64_t ph_first;            // first photon slot of the photon sweep's chunk list (n_front rounded
+                               // down to a chunk)
   unsigned long long hole_ctr, mover_ctr;
   double work, defect_emit, defect_pair, dropped_energy, radiated;
   double led_energy[3];

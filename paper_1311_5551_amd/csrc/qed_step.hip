@@ -56,10 +56,13 @@ __global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restri
       acc[i].n_start[s] = c;
       // a count that fell without a compaction (set by the caller) unseals the slots above it
       if (s == 2 && acc[i].n_sealed > c / kWinGroup * kWinGroup) acc[i].n_sealed = c / kWinGroup * kWinGroup;
+      if (s == 2 && acc[i].n_front > c) acc[i].n_front = c;
+      // the photon sweep's chunks start after the front, at a chunk boundary
+      if (s == 2) acc[i].ph_first = acc[i].n_front / chunk_ph * chunk_ph;
       // particle-steps: leptons every step; photon slots in steps that run the photon pass
       if (advance_clock && (s < 2 || count_photons)) acc[i].particle_steps[s] += (unsigned long long)c;
       if (s < 2) sl += (c + chunk_lep - 1) / chunk_lep;
-      else sp += (c + chunk_ph - 1) / chunk_ph;
+      else sp += (c - acc[i].ph_first + chunk_ph - 1) / chunk_ph;
     }
   }
   s_lep[threadIdx.x] = sl;
@@ -80,7 +83,7 @@ __global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restri
       rl += (acc[i].n_start[s] + chunk_lep - 1) / chunk_lep;
     }
     base_ph[i] = rp;
-    rp += (acc[i].n_start[2] + chunk_ph - 1) / chunk_ph;
+    rp += (acc[i].n_start[2] - acc[i].ph_first + chunk_ph - 1) / chunk_ph;
   }
   if (threadIdx.x == blockDim.x - 1) {
     glob->n_chunks[0] = s_lep[threadIdx.x];
@@ -726,7 +729,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   gptr<uint32_t> WIN = nullptr;
   gptr<const PhotonRecT<MIXED>> REC = nullptr;
   gptr<const uint32_t> WSUM = nullptr;
-  int64_t nseal = 0;
+  int64_t nseal = 0, pfirst = 0;
   // group summaries of the current run of chunks, read in one load per wave: bit r PPT + j is
   // set when group j of the wave in chunk m0 + r is sealed and its summary excludes the step
   int64_t m0 = -1;
@@ -766,6 +769,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       REC = as_global((const PhotonRecT<MIXED>*)uni_ptr(a.rec)) + uni64(a.acc[ii].mover_off);
       WSUM = as_global(uni_ptr(a.wsum)) + uni64(a.acc[ii].wsum_off);
       nseal = uni64(a.acc[ii].n_sealed);
+      pfirst = uni64(a.acc[ii].ph_first);
       m0 = -1;
       n = uni64(a.acc[ii].n_start[2]);
       __syncthreads();  // the previous field copy is no longer read
@@ -774,7 +778,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       __syncthreads();
       fK.pi_over_len = uni_f64(field_k(sF).pi_over_len);
     }
-    const int64_t k0 = uni64((c - cb) * CH);  // first slot of the chunk
+    const int64_t k0 = uni64(pfirst + (c - cb) * CH);  // first slot of the chunk
     const int64_t rem = n - k0;               // slots of the chunk that exist: min(rem, CH)
 
     // buffer resources over the chunk's live slots (uniform); lane offsets in bytes
@@ -852,7 +856,8 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       const int64_t cend = min(ce, (c / kPhotonRun + 1) * kPhotonRun);  // end of the run
       bool skip = false;
       if (lane < PPT * kPhotonRun && cc < cend) {
-        const int64_t g = (cc - cb) * (CH / kWinGroup) + (threadIdx.x >> 6) + (int64_t)(lane % PPT) * (B / kWinGroup);
+        const int64_t g = (pfirst + (cc - cb) * CH) / kWinGroup + (threadIdx.x >> 6) +
+                          (int64_t)(lane % PPT) * (B / kWinGroup);
         if ((g + 1) * kWinGroup <= nseal) {
           skip = !in_window(WSUM[g], step);
           ++uacc[5];
@@ -1403,14 +1408,18 @@ __global__ __launch_bounds__(256) void k_window_summary(const qed_instance* __re
   }
 }
 
-// the slots with a summary: every full group (after k_window_summary)
-__global__ void k_window_sealed(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc) {
+// the slots with a summary: every full group (after k_window_summary); the front is the
+// partition's (after_partition), else none (the windows were just rebuilt)
+__global__ void k_window_sealed(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
+                                int after_partition) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
     const qed_species& S = inst[i].s[2];
     int64_t n = S.count_dev ? *S.count_dev : 0;
     if (n > S.capacity) n = S.capacity;
     if (n < 0) n = 0;
     acc[i].n_sealed = n / kWinGroup * kWinGroup;
+    const int64_t D = after_partition ? acc[i].n_live : 0;
+    acc[i].n_front = D < 0 ? 0 : (D > n ? n : D);
   }
 }
 
@@ -1590,7 +1599,7 @@ void launch_photon_windows(const qed_instance* inst, int n_inst, InstAcc* acc, u
   if (mixed) hipLaunchKernelGGL(k_photon_windows<true>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
   else hipLaunchKernelGGL(k_photon_windows<false>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
   hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum, 0);
-  hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
+  hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 0);
 }
 
 void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
@@ -1610,7 +1619,7 @@ void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, const Gl
   if (mixed) hipLaunchKernelGGL(k_part_swap<true>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec);
   else hipLaunchKernelGGL(k_part_swap<false>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec);
   hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum, 0);
-  hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
+  hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 1);
 }
 
 }  // namespace qedk
