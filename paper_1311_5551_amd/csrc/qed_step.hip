@@ -685,11 +685,13 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
 // ---------------------------------------------------------------------------
 // photons, both precisions.  Position at the start of step n: x_b + (n - b) dt k/|k|.
 //
-// The sweep (k_photon) is the bandwidth-bound part: every photon slot, every step.  Each photon
-// carries a window of steps outside which it has no pair rate (photon_window: below the energy
-// that can reach chi_min in the field, or outside a pulse's support); it is set when the photon
-// is appended and moves with it.  A thread reads the windows of the PPT photons it owns in the
-// chunk; only the photons inside their window are read in full and evaluate chi and T(chi), with
+// Each photon carries a window of steps outside which it has no pair rate (photon_window: below
+// the energy that can reach chi_min in the field, or outside a pulse's support); it is set when
+// the photon is appended and moves with it.  The sweep (k_photon) skips three ways: it starts
+// after the front that the partition at compaction fills with photons whose window is over; it
+// skips the groups of 64 slots whose summary window excludes the step; in the other groups a
+// thread reads the windows of the PPT photons it owns in the chunk.  Only the photons inside
+// their window are read in full and evaluate chi and T(chi), with
 // the device library's trigonometry and log, and, where T > 0, decrement the optical depth (these
 // values only decide the event step).  A photon whose depth reaches zero is queued; the event
 // pass (k_pair_events) recomputes chi from the stored photon with correctly rounded functions,
@@ -1374,14 +1376,12 @@ __global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restric
   }
 }
 
-// Window-group summaries of the full groups of every instance's photons, from group
-// acc.n_sealed / kWinGroup on for an instance whose compaction removed nothing (its windows
-// below that only changed by becoming empty, which keeps the old summaries valid), else from 0.
-// One wave per group; grid: x strides groups, y = instance.
+// Window-group summaries of the full groups of every instance's photons (after a window build,
+// and after the partition at compaction, which moves photons across all groups).  One wave per
+// group; grid: x strides groups, y = instance.
 __global__ __launch_bounds__(256) void k_window_summary(const qed_instance* __restrict__ inst,
                                                         const InstAcc* __restrict__ acc,
-                                                        const uint32_t* __restrict__ win, uint32_t* __restrict__ wsum,
-                                                        int after_compaction) {
+                                                        const uint32_t* __restrict__ win, uint32_t* __restrict__ wsum) {
   const int ii = blockIdx.y;
   const qed_species& S = inst[ii].s[2];
   if (S.capacity == 0 || !S.count_dev) return;
@@ -1389,13 +1389,12 @@ __global__ __launch_bounds__(256) void k_window_summary(const qed_instance* __re
   if (n > S.capacity) n = S.capacity;
   if (n < 0) n = 0;
   const int64_t ng = n / kWinGroup;
-  const int64_t g_first = after_compaction && acc[ii].compact_skip ? acc[ii].n_sealed / kWinGroup : 0;
   const uint32_t* W = win + acc[ii].mover_off;
   uint32_t* G = wsum + acc[ii].wsum_off;
   const int lane = threadIdx.x & 63;
   const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
   // the loop bound is wave-uniform, so every lane reaches the shuffles
-  for (int64_t g = g_first + blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); g < ng; g += wstride) {
+  for (int64_t g = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); g < ng; g += wstride) {
     const uint32_t w = W[g * kWinGroup + lane];
     const bool any = (w & 0xFFFFu) <= (w >> 16);  // a non-empty window (pack_window)
     uint32_t lo = any ? (w & 0xFFFFu) : 0xFFFFu, hi = any ? (w >> 16) : 0u;
@@ -1598,7 +1597,7 @@ void launch_photon_windows(const qed_instance* inst, int n_inst, InstAcc* acc, u
   const dim3 g(n_inst == 1 ? 2048 : 64, n_inst);
   if (mixed) hipLaunchKernelGGL(k_photon_windows<true>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
   else hipLaunchKernelGGL(k_photon_windows<false>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
-  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum, 0);
+  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum);
   hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 0);
 }
 
@@ -1618,7 +1617,7 @@ void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, const Gl
   hipLaunchKernelGGL(k_part_movers, g, dim3(256), 0, s, acc, glob, win, movers);
   if (mixed) hipLaunchKernelGGL(k_part_swap<true>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec);
   else hipLaunchKernelGGL(k_part_swap<false>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec);
-  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum, 0);
+  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum);
   hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 1);
 }
 
