@@ -1,21 +1,31 @@
 #!/usr/bin/env python3
 """Throughput of the QED Monte-Carlo step (push + emission + pairs) on one MI355X.
 
-Workload (default): the head-on collision of 1e6 electrons (gamma ~ N(2000, 10%),
+Workload (main line): the head-on collision of 1e6 electrons (gamma ~ N(2000, 10%),
 sigma = 2 um) with a linearly polarised a0 = 200, lambda = 1 um, 30 fs sin^2 pulse,
-dt = lambda/(200 c), 20000 steps, photon emission and pair creation on, dead photons
-compacted every 100 steps, FP64.  `warmup` untimed steps, then exactly `steps` timed
-steps of the same run.  value = particle-steps (every electron, positron and photon
-slot present at the start of a step) per second of the timed region.
+dt = lambda/(200 c), a 20000-step schedule whose pulse peak meets the beam centre at step
+10000; photon emission and pair creation on, dead photons compacted every 100 steps, FP64.
 
-Also printed on the same JSON line: the roofline of the dominant kernel (algorithmic
-bytes per launch / its mean HIP-event duration over the timed region, against 8 TB/s),
-and the FP64 oracle timed on the host cores over a bounded sample of the same workload.
+Timed window: when `warmup + steps` is shorter than the schedule, the run is advanced
+untimed to `meet - steps/2 - warmup`, then `warmup` untimed steps run, then exactly `steps`
+timed steps centred on the collision (the steps where the pulse drives emission and pairs).
+Otherwise the window is steps [warmup, warmup + steps) of the schedule.
+
+value = evaluated particle-steps per second of the timed window: every electron and positron
+present at the start of a step (each is pushed), plus every photon step evaluated in full (a
+photon inside its pair window: the steps in which its pair rate can be non-zero).  Photon slots
+outside their window, whose position is the closed form of their birth record, are not counted;
+their count is reported apart (`photon_slot_steps`).
+
+Also on the same JSON line: the roofline of the dominant kernel (algorithmic bytes per launch /
+its mean HIP-event duration over the same window, against 8 TB/s), and the FP64 oracle timed on
+the host cores over a bounded sample of the same workload.  `detail` holds the other forms
+(FP32-mixed, batched instances, the 2-D grid workload, the uniform-field workload) and the
+value of the whole 20000-step schedule.
 """
 import argparse
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -25,6 +35,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "particle-steps/s (push+QED MC) FP64 vs FP32-mixed vs batched; % HBM peak"
 HBM_PEAK_GBS = 8000.0
+SCHEDULE = 20000   # steps of the collision schedule
+MEET = 10000       # step at which the pulse peak meets the beam centre
 
 
 def log(msg):
@@ -32,40 +44,36 @@ def log(msg):
 
 
 def kernel_bytes(form, kind, led0, led1, grid=False):
-    """Algorithmic HBM bytes of one kernel class over the timed region.
+    """Algorithmic HBM bytes of one kernel class between two ledgers.
 
-    grid=True (the 2-D grid workload, FP64): lepton full step 48 B read (x, y, u, tau) + 48 B
-    written; photon: 4 B per window and per group summary read + 44 B per photon inside its
-    window (k, x and y at birth, birth step), the gather of the FP32 grid not counted (the
-    201 MB grid is read from the cache hierarchy, its refresh is the set-up class).
-
-    Lepton sweep, per particle-step in 3-D: with the full push 56 B read (x, u, tau) + 56 B
-    written in FP64 (FP32-mixed: the same 112 B as hi/lo words of position and momentum plus
-    the FP64 tau); outside the plane-wave pulse (field-free drift) x and u read, x written:
-    72 B in FP64, 60 B in FP32-mixed (hi/lo position, high words of u); + 16 B per queued
-    emission event.  The emission pass (separate class) reads the event's lepton and writes the
-    photon.
+    Lepton sweep, per lepton step in 3-D: with the full push 56 B read (x, u, tau) + 56 B
+    written in FP64 (FP32-mixed: the stored words of position and momentum, 4 B each, plus the
+    FP64 tau); outside the plane-wave pulse (field-free drift) x and u read, x written: 72 B in
+    FP64; + 16 B per queued emission event.  2-D grid workload: 48 + 48 B per step (x, y, u, tau).
     Photon sweep: 4 B per summary window of a group of 64 slots that was read, and 4 B per slot
-    whose pair window was read (every slot, except in groups whose summary excludes the step);
-    per photon inside its window, with
-    a field that depends on x only (the plane-wave pulse), k (3 words), x at birth (1 word) and
-    the birth step (4 B): 36 B in FP64, 20 B in FP32-mixed; + 16 B (tau read and written) for
-    the photons that see a non-zero pair rate; + 8 B per queued pair event.  The pair pass
-    (separate class) reads the event's photon and writes the two leptons."""
+    whose pair window was read; per photon inside its window the state its record copies (k,
+    x at birth, birth step: 36 B in FP64, 20 B in FP32-mixed; with y at birth, 44 B, on the
+    grid); + 16 B (tau read and written) for the photons that see a non-zero pair rate; + 8 B per
+    queued pair event.  The event passes (separate classes) read the event's particle and write
+    the children."""
     d = lambda k, i=None: (led1[k][i] - led0[k][i]) if i is not None else (led1[k] - led0[k])
-    if grid:
-        if kind == "lepton":
-            return (d("particle_steps", 0) + d("particle_steps", 1)) * 96 + (d("n_emit") + d("n_null")) * 16
-        return ((d("photon_window_reads") + d("photon_group_reads")) * 4 + d("photon_steps_active") * 44
-                + d("photon_steps_in_field") * 16 + d("n_pair") * 8)
     if kind == "lepton":
         steps = d("particle_steps", 0) + d("particle_steps", 1)
         full = d("lepton_steps_in_field")
-        drift = 72 if form == "fp64" else 60
-        return full * 112 + (steps - full) * drift + (d("n_emit") + d("n_null")) * 16
-    full = 36 if form == "fp64" else 20
-    return ((d("photon_window_reads") + d("photon_group_reads")) * 4 + d("photon_steps_active") * full
+        if grid:
+            per_full = per_drift = 96
+        elif form == "fp64":
+            per_full, per_drift = 112, 72
+        else:
+            per_full, per_drift = LEPTON_BYTES_FP32
+        return full * per_full + (steps - full) * per_drift + (d("n_emit") + d("n_null")) * 16
+    rec = 44 if grid else (36 if form == "fp64" else 20)
+    return ((d("photon_window_reads") + d("photon_group_reads")) * 4 + d("photon_steps_active") * rec
             + d("photon_steps_in_field") * 16 + d("n_pair") * 8)
+
+
+# FP32-mixed lepton bytes per step (full push, drift); set from the stored layout below
+LEPTON_BYTES_FP32 = (112, 60)
 
 
 def source_hash():
@@ -78,34 +86,38 @@ def source_hash():
 
 def measured_traffic(kernel, form):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken on
-    the current kernel sources (else None)."""
+    the current kernel sources with the same bench window (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic_%s_%s.json" % (kernel, form))
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("source_hash") != source_hash():
+    if d.get("source_hash") != source_hash() or d.get("bench_window") != WINDOW_KEY.get(form):
         return None
     return d.get("bytes_per_launch")
+
+
+WINDOW_KEY = {}
 
 
 def tune_launch(form, args, tables):
     """Autotuned sweep launch shapes for a form: the tuner runs on a separate run of the same
     collision (tune_scale times the electrons; the best shape depends on the population size, so
-    full size by default), at points spread over the run (before, during and after the
-    collision), and each kernel gets the shape with the smallest population-weighted sum of its
-    per-particle times over the points, an estimate of its total time in the run."""
+    full size by default), at points of the timed window, and each kernel gets the shape with the
+    smallest population-weighted sum of its per-particle times over the points, an estimate of
+    its total time in the window."""
     from paper_1311_5551_amd import autotune, capi, workloads as W
     from paper_1311_5551_amd.sim import Run
     prec = capi.QED_FP64 if form == "fp64" else capi.QED_FP32_MIXED
-    w = W.collision_config2(n=max(int(args.electrons * args.tune_scale), 1000), n_steps=20000)
+    w = W.collision_config2(n=max(int(args.electrons * args.tune_scale), 1000), n_steps=SCHEDULE)
     run = Run(w, tables, precision=prec)
     points = [int(x) for x in args.tune_at.split(",")]
     log("%s: autotuning launch shapes on a %d-electron replica at steps %s" % (form, w.n, points))
     results = []
     for p in points:
         while run.step_index < p:
-            run.step(1)
+            n = min(args.compact_every - run.step_index % args.compact_every, p - run.step_index)
+            run.run(n, graph_steps=n if n == args.compact_every else 0)
             if run.step_index % args.compact_every == 0:
                 run.compact()
         results.append(autotune.tune(run, steps_per_trial=6, rounds=2, min_particles=1000))
@@ -121,8 +133,8 @@ TUNED_CACHE = os.path.join(ROOT, "paper_1311_5551_amd", "tuned_launch.json")
 
 def tuned_launch(form, args, tables):
     """Cached tuned shapes for (device, form, collision workload size, kernel sources), else a
-    fresh tuning whose result is written to gpurun_out/tuned_launch.json (entries of that file
-    are what the package's cache holds)."""
+    fresh tuning whose result is written to gpurun_out/tuned_launch.json (the tuner's output
+    file; the package's cache holds its entries)."""
     import torch
     from paper_1311_5551_amd import autotune, capi
     prec = capi.QED_FP64 if form == "fp64" else capi.QED_FP32_MIXED
@@ -167,10 +179,10 @@ def size_grid(w, tables, args, probe_n=100_000):
     return k
 
 
-def size_batched(ws, tables, args, probe_n=64):
+def size_batched(ws, tables, args, last_step, probe_n=64):
     """Buffer capacities of the batched instances from a probe run: the first `probe_n`
-    electrons of every instance (the same families as in the full run) through the whole
-    schedule; each species gets 1.3x its probe yield per initial electron plus a margin."""
+    electrons of every instance (the same families as in the full run) through the schedule up
+    to `last_step`; each species gets 1.3x its probe yield per initial electron plus a margin."""
     from paper_1311_5551_amd import capi, workloads as W
     from paper_1311_5551_amd.sim import Run
     probe = []
@@ -180,9 +192,12 @@ def size_batched(ws, tables, args, probe_n=64):
         probe.append(p)
     run = Run(probe, tables, precision=capi.QED_FP32_MIXED)
     log("batched: sizing buffers from a %d-electron probe run" % sum(p.n for p in probe))
-    for i in range(ws[0].n_steps):
-        run.step(1)
-        if (i + 1) % args.compact_every == 0:
+    step = 0
+    while step < last_step:
+        n = min(args.compact_every - step % args.compact_every, last_step - step)
+        run.run(n, graph_steps=n if n == args.compact_every else 0)
+        step += n
+        if step % args.compact_every == 0:
             run.compact()
     led = run.ledger()
     run.close()
@@ -196,46 +211,79 @@ def size_batched(ws, tables, args, probe_n=64):
                           photon=int(1.3 * y_g * w.n) + 16384)
 
 
+def window(total, warmup, steps, meet):
+    """(first untimed step, first timed step) of a window of `steps` steps after `warmup` untimed
+    ones: centred on `meet` when the schedule is longer than warmup + steps."""
+    if warmup + steps >= total:
+        return 0, warmup
+    s0 = min(max(meet - steps // 2, warmup), total - steps)
+    return s0 - warmup, s0
+
+
+def _aggregate(leds):
+    out = {"particle_steps": [0, 0, 0], "count": [0, 0, 0]}
+    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field", "photon_steps_active", "lepton_steps_in_field",
+              "photon_window_reads", "photon_group_reads"):
+        out[k] = sum(l[k] for l in leds)
+    for i in range(3):
+        out["particle_steps"][i] = sum(l["particle_steps"][i] for l in leds)
+        out["count"][i] = sum(l["count"][i] for l in leds)
+    return out
+
+
+def evaluated_steps(a0, a1):
+    """Evaluated particle-steps between two aggregated ledgers: lepton steps plus photon steps
+    inside the photon's pair window."""
+    return (a1["particle_steps"][0] - a0["particle_steps"][0] + a1["particle_steps"][1] - a0["particle_steps"][1]
+            + a1["photon_steps_active"] - a0["photon_steps_active"])
+
+
 def run_form(form, args, tables, tuned):
     import torch
     from paper_1311_5551_amd import autotune, capi, workloads as W
     from paper_1311_5551_amd.sim import Run
 
-    batched = form == "batched"
+    graphs = form not in ("grid",) and not args.no_graphs
     if form == "grid":
         w = W.grid_config3(n=args.grid_electrons)
-        steps = size_grid(w, tables, args)
-        ws, warmup = [w], 0
+        total = size_grid(w, tables, args)
+        ws, pre, s0, steps = [w], 0, 0, total
         workload = ("grid_cp_standing_a500: %d electrons at rest, uniform over a periodic 4096x2048 FP32 Yee grid "
                     "(dx = lambda/128), standing wave of two CP lasers a0=500 refreshed analytically each step, "
                     "first-order gather, 2D3V, FP64 particles, dt=lambda/400c, steps 0..%d (until the population "
                     "reaches 4x), particles sorted by 8x8-cell tile every %d steps"
-                    % (w.n, steps, args.grid_sort_every))
-    elif not batched:
-        total = args.warmup + args.steps
-        w = W.collision_config2(n=args.electrons, n_steps=max(total, 20000))
-        ws = [w]
-        workload = ("collision_lp_a200: %d electrons gamma~N(2000,10%%) sigma 2um vs LP a0=200 lambda 1um "
-                    "30fs sin^2, dt=lambda/200c, steps %d..%d of 20000, emission+pairs, compaction every %d"
-                    % (w.n, args.warmup, total, args.compact_every))
-        warmup, steps = args.warmup, args.steps
-    else:
-        # the C5 instance mix with every N_i scaled by batched_scale, on the collision schedule of
-        # the FP64 line (dt = lambda/200c, the pulse meets each beam at the middle step); at full
-        # size the collisions emit ~4.5e9 photons (~200 GB) and the run would take minutes
-        total = args.batched_steps
-        ws = W.batched_config5(n_steps=total, n_scale=args.batched_scale)
-        size_batched(ws, tables, args)
-        warmup, steps = args.batched_warmup, total - args.batched_warmup
+                    % (w.n, total, args.grid_sort_every))
+    elif form == "uniform":
+        w = W.uniform_b_config1()
+        total = w.n_steps
+        ws, pre, s0, steps = [w], 0, 0, total
+        workload = ("uniform_b_1e4: 10000 electrons gamma0=1000 perpendicular to a uniform B (eta0=1), dt=0.01 "
+                    "gyro-periods, steps 0..%d, photons recorded (not propagated), FP64, hipGraph replay of "
+                    "100-step graphs" % total)
+    elif form == "batched":
+        ws = W.batched_config5(n_steps=SCHEDULE, n_scale=args.batched_scale)
+        pre, s0 = window(SCHEDULE, args.batched_warmup, args.batched_window, MEET)
+        steps = min(args.batched_window, SCHEDULE - s0)
+        size_batched(ws, tables, args, s0 + steps)
+        total = s0 + steps
         workload = ("batched_collisions: 256 instances, N_i=floor(%g*10^U(3,6)) (total %d electrons), a0~U(50,500), "
-                    "gamma0 log-U[500,5000], FP32-mixed, dt=lambda/200c, steps %d..%d of %d (collisions at step "
-                    "%d), hipGraph replay of %d-step graphs, compaction every %d"
-                    % (args.batched_scale, sum(w.n for w in ws), warmup, total, total, total // 2,
-                       args.compact_every, args.compact_every))
-    prec = capi.QED_FP64 if form in ("fp64", "grid") else capi.QED_FP32_MIXED
-    # the grid form reorders its particles between steps (qed_sort); --no-graphs runs every step
-    # eagerly with the kernel timers on (for profilers that cannot follow graph replay)
-    graphs = form != "grid" and not args.no_graphs
+                    "gamma0 log-U[500,5000], FP32-mixed, dt=lambda/200c, steps %d..%d of %d (window centred on the "
+                    "collisions at step %d; %d untimed steps before), hipGraph replay of %d-step graphs, "
+                    "compaction every %d" % (args.batched_scale, sum(w.n for w in ws), s0, s0 + steps, SCHEDULE,
+                                             MEET, s0, args.compact_every, args.compact_every))
+    else:
+        w = W.collision_config2(n=args.electrons, n_steps=SCHEDULE)
+        ws = [w]
+        pre, s0 = window(SCHEDULE, args.warmup, args.steps, MEET)
+        steps = min(args.steps, SCHEDULE - s0)
+        total = s0 + steps
+        workload = ("collision_lp_a200: %d electrons gamma~N(2000,10%%) sigma 2um vs LP a0=200 lambda 1um 30fs "
+                    "sin^2, dt=lambda/200c, timed steps %d..%d of %d (the pulse meets the beam at step %d; steps "
+                    "0..%d untimed), emission+pairs, compaction every %d"
+                    % (w.n, s0, s0 + steps, SCHEDULE, MEET, s0, args.compact_every))
+    WINDOW_KEY[form if form != "grid" else "grid"] = "%d..%d" % (s0, s0 + steps)
+    prec = capi.QED_FP64 if form in ("fp64", "grid", "uniform") else capi.QED_FP32_MIXED
+    compact = form not in ("uniform",)
 
     def make_run():
         r = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
@@ -257,99 +305,108 @@ def run_form(form, args, tables, tuned):
                     run.step(1)
             step += n
             done += n
-            if step % args.compact_every == 0:
+            if compact and step % args.compact_every == 0:
                 run.compact()
             if done % 2000 < n and done < k:
                 log("%s: step %d" % (form, step))
         return step
 
+    res = dict(form=form, workload=workload, n_inst=len(ws), window=[s0, s0 + steps])
+    # the whole schedule once (collision forms): evaluated particle-steps per second over all steps
+    if form in ("fp64", "fp32") and args.full_run:
+        log("%s: whole schedule (%d steps)" % (form, SCHEDULE))
+        run = make_run()
+        led0 = _aggregate(run.ledger())
+        run.synchronize()
+        t0 = time.perf_counter()
+        advance(run, 0, SCHEDULE, graphs)
+        run.synchronize()
+        t1 = time.perf_counter()
+        led1 = _aggregate(run.ledger())
+        ev = evaluated_steps(led0, led1)
+        res["whole_schedule"] = {"steps": SCHEDULE, "seconds": t1 - t0, "evaluated_particle_steps": int(ev),
+                                 "value": ev / (t1 - t0),
+                                 "photon_slot_steps": int(led1["particle_steps"][2] - led0["particle_steps"][2])}
+        run.close()
+        del run
+        torch.cuda.empty_cache()
+
     log("%s: allocating and binding (%s)" % (form, workload[:60]))
     run = make_run()
-    log("%s: %d warmup steps" % (form, warmup))
-    step = advance(run, 0, warmup, graphs)
+    if pre:
+        log("%s: %d untimed steps to the window" % (form, pre))
+    step = advance(run, 0, pre, graphs)
+    warm = s0 - pre
+    log("%s: %d warmup steps" % (form, warm))
+    step = advance(run, step, warm, graphs)
     led0 = run.ledger()
-    if not graphs:
-        run.profile(True)
     run.synchronize()
-    log("%s: timing %d steps" % (form, steps))
+    log("%s: timing steps %d..%d" % (form, s0, s0 + steps))
     t0 = time.perf_counter()
     step = advance(run, step, steps, graphs)
     run.synchronize()
     t1 = time.perf_counter()
     led1 = run.ledger()
+    run.close()
+    del run
+    torch.cuda.empty_cache()
     # kernel times: HIP events around every kernel class on the run's stream, over the same
     # steps replayed eagerly from the same initial state (graph replay records no per-kernel
-    # events, and the events would add launch gaps to the timed run)
-    if graphs:
-        run.close()
-        del run
-        torch.cuda.empty_cache()
-        log("%s: kernel timing pass (eager, %d + %d steps)" % (form, warmup, steps))
-        run = make_run()
-        step = advance(run, 0, warmup, True)
-        lk0 = run.ledger()
-        run.profile(True)
-        step = advance(run, step, steps, False)
-        ms, launches = run.profile_read()
-        run.profile(False)
-        lk1 = run.ledger()
-        lk0, lk1 = _aggregate(lk0), _aggregate(lk1)
-    else:
-        ms, launches = run.profile_read()
-        run.profile(False)
-    n_inst = len(ws)
-    agg0 = _aggregate(led0)
-    agg1 = _aggregate(led1)
-    if not graphs:
-        lk0, lk1 = agg0, agg1
-    psteps = sum(agg1["particle_steps"]) - sum(agg0["particle_steps"])
+    # events, and the event records would add launch gaps to the timed run)
+    log("%s: kernel timing pass (HIP events, steps %d..%d, eager)" % (form, s0, s0 + steps))
+    run = make_run()
+    step = advance(run, 0, s0, graphs)
+    lk0 = _aggregate(run.ledger())
+    run.profile(True)
+    step = advance(run, step, steps, False)
+    ms, launches = run.profile_read()
+    run.profile(False)
+    lk1 = _aggregate(run.ledger())
+    run.close()
+    del run
+    torch.cuda.empty_cache()
+
+    agg0, agg1 = _aggregate(led0), _aggregate(led1)
+    ev = evaluated_steps(agg0, agg1)
     status = sorted(set(l["status"] for l in led1))
-    res = dict(form=form, workload=workload, n_inst=n_inst, seconds=t1 - t0, particle_steps=int(psteps),
-               value=psteps / (t1 - t0), ms_per_step=1e3 * (t1 - t0) / steps,
+    d = lambda k: int(agg1[k] - agg0[k])
+    res.update(seconds=t1 - t0, steps=steps, evaluated_particle_steps=int(ev), value=ev / (t1 - t0),
+               ms_per_step=1e3 * (t1 - t0) / steps,
+               lepton_steps=int(agg1["particle_steps"][0] + agg1["particle_steps"][1]
+                                - agg0["particle_steps"][0] - agg0["particle_steps"][1]),
+               photon_slot_steps=int(agg1["particle_steps"][2] - agg0["particle_steps"][2]),
                kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2], pair_events=ms[3], emit_events=ms[4]),
                launches=dict(setup=launches[0], lepton=launches[1], photon=launches[2], pair_events=launches[3],
                              emit_events=launches[4]),
-               photons_end=int(agg1["count"][2]), pairs=int(agg1["n_pair"] - agg0["n_pair"]),
-               emissions=int(agg1["n_emit"] - agg0["n_emit"]), drift_max=max(l["drift"] for l in led1),
-               photon_steps_in_field=int(agg1["photon_steps_in_field"] - agg0["photon_steps_in_field"]),
-               photon_steps_active=int(agg1["photon_steps_active"] - agg0["photon_steps_active"]),
-               lepton_steps_in_field=int(agg1["lepton_steps_in_field"] - agg0["lepton_steps_in_field"]),
-               photon_window_reads=int(agg1["photon_window_reads"] - agg0["photon_window_reads"]),
-               photon_group_reads=int(agg1["photon_group_reads"] - agg0["photon_group_reads"]),
+               photons_end=int(agg1["count"][2]), pairs=d("n_pair"), emissions=d("n_emit"),
+               drift_max=max(l["drift"] for l in led1),
+               photon_steps_in_field=d("photon_steps_in_field"), photon_steps_active=d("photon_steps_active"),
+               lepton_steps_in_field=d("lepton_steps_in_field"), photon_window_reads=d("photon_window_reads"),
+               photon_group_reads=d("photon_group_reads"),
                dropped=int(sum(l["n_dropped"] for l in led1)), status=status,
-               launch={k: (tuned.get(k) if tuned else None) for k in ("lepton", "photon")})
-    if graphs:
-        res["kernel_timing"] = ("HIP events per kernel class over the same steps replayed eagerly from the same "
-                                "initial state (the timed run replays captured HIP graphs)")
+               launch={k: (tuned.get(k) if tuned else None) for k in ("lepton", "photon")},
+               kernel_timing="HIP events per kernel class on the run's stream over the same steps replayed eagerly "
+                             "from the same initial state" + (" (the timed run replays captured HIP graphs)"
+                                                               if graphs else ""))
+    # the kernel that takes the most time in the window bounds the step
     kind = "photon" if ms[2] >= ms[1] else "lepton"
-    byts = kernel_bytes("fp64" if form in ("fp64", "grid") else "fp32", kind, lk0, lk1, grid=form == "grid")
+    byts = kernel_bytes("fp64" if prec == capi.QED_FP64 else "fp32", kind, lk0, lk1, grid=form == "grid")
     n_l = launches[2] if kind == "photon" else launches[1]
     avg_s = (ms[2] if kind == "photon" else ms[1]) / max(n_l, 1) * 1e-3
-    achieved = byts / max(n_l, 1) / avg_s / 1e9
+    achieved = byts / max(n_l, 1) / avg_s / 1e9 if avg_s > 0 else 0.0
     traffic = measured_traffic(kind, form)
     res["roofline"] = {"kernel": "k_%s (%s)" % (kind, form), "bound": "hbm",
                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                        "traffic": traffic, "algorithmic_bytes_per_launch": byts / max(n_l, 1),
                        "mean_launch_us": avg_s * 1e6}
-    run.close()
-    del run
-    torch.cuda.empty_cache()
+    if form in ("fp64", "fp32") and res["emissions"] == 0 and res["lepton_steps_in_field"] == 0:
+        log("%s: WARNING: the timed window has no in-field step: it measures a field-free drift" % form)
+        res["note"] = "no in-field step in the timed window: a field-free drift, not the QED step"
     return res
 
 
-def _aggregate(leds):
-    out = {"particle_steps": [0, 0, 0], "count": [0, 0, 0]}
-    for k in ("n_emit", "n_null", "n_pair", "photon_steps_in_field", "photon_steps_active", "lepton_steps_in_field",
-              "photon_window_reads", "photon_group_reads"):
-        out[k] = sum(l[k] for l in leds)
-    for i in range(3):
-        out["particle_steps"][i] = sum(l["particle_steps"][i] for l in leds)
-        out["count"][i] = sum(l["count"][i] for l in leds)
-    return out
-
-
 def cpu_baseline(args):
-    """The FP64 oracle on the host cores over the first `families` electrons of the same
+    """The FP64 oracle on the host cores over the first `families` electrons of the collision
     workload (their whole families, all 20000 steps)."""
     import oracle
     from paper_1311_5551_amd import workloads as W
@@ -364,39 +421,42 @@ def cpu_baseline(args):
     return {"value": led["particle_steps"] / (t1 - t0), "unit": "particle-steps/s", "cores": oracle.num_threads(),
             "kind": "oracle",
             "sample": "first %d electrons of the 1e6-electron collision and all their descendants, all 20000 steps "
-                      "(%d particle-steps, %.1f s); oracle tables built beforehand" % (w.n, led["particle_steps"],
-                                                                                         t1 - t0)}
+                      "(%d particle-steps, %.1f s; the oracle evaluates every live particle in every step, so every "
+                      "one of its particle-steps is an evaluated one); oracle tables built beforehand"
+                      % (w.n, led["particle_steps"], t1 - t0)}
 
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=19800)
-    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--electrons", type=int, default=1_000_000)
     ap.add_argument("--compact-every", type=int, default=100)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--ppt", type=int, default=4)
-    ap.add_argument("--forms", default="fp64,fp32,batched,grid",
-                    help="comma list of fp64, fp32, batched, grid; the first gives `value` and `roofline`")
+    ap.add_argument("--forms", default="fp64,fp32,batched,grid,uniform",
+                    help="comma list of fp64, fp32, batched, grid, uniform; the first gives `value` and `roofline`")
+    ap.add_argument("--no-full-run", dest="full_run", action="store_false",
+                    help="skip the whole-schedule value of the collision forms")
     ap.add_argument("--cpu-families", type=int, default=1500)
     ap.add_argument("--tune", choices=("auto", "replica", "none"), default="auto",
                     help="sweep launch shapes per form: auto = the tuned shapes cached in "
                          "paper_1311_5551_amd/tuned_launch.json for this device, form, workload and kernel sources, "
                          "else tune; replica = tune now; none = --block/--ppt")
     ap.add_argument("--tune-scale", type=float, default=1.0, help="electrons of the tuning run / --electrons")
-    ap.add_argument("--tune-at", default="5000,10000,11500,13000,14500,16000,17500,19000",
+    ap.add_argument("--tune-at", default="9000,9500,10000,10500,11000",
                     help="steps of the tuning run at which trials run (population-weighted sum)")
     ap.add_argument("--batched-scale", type=float, default=0.1)
+    ap.add_argument("--batched-window", type=int, default=4000)
+    ap.add_argument("--batched-warmup", type=int, default=50)
     ap.add_argument("--grid-electrons", type=int, default=16_000_000)
     ap.add_argument("--grid-sort-every", type=int, default=10, help="grid form: steps between spatial sorts")
-    ap.add_argument("--batched-warmup", type=int, default=200)
     ap.add_argument("--no-graphs", action="store_true",
-                    help="time eager launches with per-kernel HIP events instead of graph replay")
-    ap.add_argument("--batched-steps", type=int, default=20000)
+                    help="time eager launches instead of graph replay")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
-                    help="only run a plain device copy of 1 GiB, 20 times (reference for HBM byte counters)")
+                    help="only run plain device copies of 1 GiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the QED step shards by particle family with no per-step "
@@ -410,7 +470,9 @@ def main():
         src = torch.ones(n, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
         for _ in range(20):
-            dst.copy_(src)
+            dst.copy_(src)                 # the runtime's copy kernel
+        for _ in range(20):
+            torch.mul(src, 1.0, out=dst)   # an elementwise kernel: 8 B read + 8 B written per element
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes_read": 8 * n, "bytes_written": 8 * n, "launches": 20}))
         return
@@ -422,10 +484,10 @@ def main():
     tuned = {}
     results = []
     for f in forms:
-        key = "fp64" if f in ("fp64", "grid") else "fp32"
-        if args.tune != "none" and key not in tuned:
+        key = "fp64" if f in ("fp64", "grid", "uniform") else "fp32"
+        if args.tune != "none" and key not in tuned and f in ("fp64", "fp32", "batched"):
             tuned[key] = tuned_launch(key, args, tables)
-        results.append(run_form(f, args, tables, tuned.get(key)))
+        results.append(run_form(f, args, tables, tuned.get(key) if f in ("fp64", "fp32", "batched") else None))
     main_r = results[0]
     cpu = None if args.no_cpu_baseline else cpu_baseline(args)
     out = {
@@ -433,15 +495,16 @@ def main():
         "value": main_r["value"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": main_r["steps"],
         "warmup": args.warmup,
         "ms_per_step": main_r["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if main_r["form"] == "fp64" else "f32+f64",
+        "dtype": "f64" if main_r["form"] in ("fp64", "grid", "uniform") else "f32+f64",
         "data": "synthetic",
         "config": {"workload": main_r["workload"], "form": main_r["form"], "instances": main_r["n_inst"],
+                   "counted": "evaluated particle-steps: lepton steps + photon steps inside the photon's pair window",
                    # the shapes the run used: tuned (cache or replica) per sweep, else the command line
                    "launch": ({k: {"block": v["block"], "particles_per_thread": v["ppt"]}
                                for k, v in main_r["launch"].items() if v}

@@ -51,6 +51,20 @@ qed_status check_device(int* dev_out, int* cus_out) {
 
 bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
 
+// Value of fixed-point words (weights 2^-64, 2^-32, 2^0, 2^32; see fix_split): carries moved up,
+// then the integer part (exact in 128 bits) plus the fraction, rounded once per part.
+double fix_value(const long long* w_in) {
+  long long w[4] = {w_in[0], w_in[1], w_in[2], w_in[3]};
+  for (int k = 0; k < 3; ++k) {
+    const long long c = w[k] >> 32;
+    w[k] -= (long long)((unsigned long long)c << 32);
+    w[k + 1] += c;
+  }
+  const __int128 ip = ((__int128)w[3] << 32) + w[2];
+  const double frac = (double)w[1] * 0x1p-32 + (double)w[0] * 0x1p-64;  // in [0, 1)
+  return (double)ip + frac;
+}
+
 // device memory check: `p` must lie in a device allocation with room for `bytes`
 qed_status check_dev_range(const void* p, size_t bytes, const char* what, int inst, int sp) {
   if (!p) return fail(QED_ERR_ARG, "instance %d species %d: %s is NULL", inst, sp, what);
@@ -116,7 +130,8 @@ struct qed_workspace {
   // pair windows of the photons (one int2 per photon slot, instances at acc.mover_off), valid
   // for the step constants and table they were computed with
   uint32_t* d_win = nullptr;
-  void* d_rec = nullptr;     // PhotonRec (FP64) or PhotonRec32 (FP32-mixed) per photon slot
+  void* d_rec = nullptr;     // one record per photon slot (PhotonRecT: photon_rec_bytes each)
+  int rec_bytes = 0;
   size_t win_len = 0;
   uint32_t* d_wsum = nullptr;  // window-group summaries (kWinGroup slots each), instances at acc.wsum_off
   size_t wsum_len = 0;
@@ -383,7 +398,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
 qed_status ensure_windows(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
   const double cp_min = device_tabs(tb).cp_min;
   if (ws->win_valid && ws->win_t0 == p->t0 && ws->win_dt == p->dt && ws->win_cp_min == cp_min) return QED_OK;
-  launch_photon_windows(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_win, ws->d_rec, ws->d_wsum, p->t0, p->dt, cp_min,
+  launch_photon_windows(ws->field_kind, ws->d_inst, ws->n_inst, ws->d_acc, ws->d_win, ws->d_rec, ws->d_wsum, p->t0, p->dt, cp_min,
                         ws->prec == QED_FP32_MIXED, s);
   HIP_TRY(hipGetLastError());
   ws->win_valid = true;
@@ -680,15 +695,18 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
     HIP_TRY(hipMalloc((void**)&ws->d_movers, (movers ? movers : 1) * sizeof(int64_t)));
     ws->movers_len = movers;
   }
-  if (movers > ws->win_len || !ws->d_win) {
+  const int rec_bytes = photon_rec_bytes(params->precision == QED_FP32_MIXED, inst[0].field.kind);
+  if (movers > ws->win_len || !ws->d_win || rec_bytes > ws->rec_bytes) {
     hipFree(ws->d_win);
     hipFree(ws->d_rec);
     ws->d_win = nullptr;
     ws->d_rec = nullptr;
     ws->win_len = 0;
+    ws->rec_bytes = 0;
     HIP_TRY(hipMalloc((void**)&ws->d_win, (movers ? movers : 1) * sizeof(uint32_t)));
-    HIP_TRY(hipMalloc((void**)&ws->d_rec, (movers ? movers : 1) * sizeof(PhotonRec)));  // either record kind
+    HIP_TRY(hipMalloc((void**)&ws->d_rec, (movers ? movers : 1) * (size_t)rec_bytes));
     ws->win_len = movers ? movers : 1;
+    ws->rec_bytes = rec_bytes;
   }
   ws->win_valid = false;  // computed by the first step, which knows t0, dt and the tables
   // emission queue: one entry per lepton slot (a lepton emits at most once per step)
@@ -708,7 +726,8 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
   if ((st = run_ledger(ws, acc, nullptr))) return st;
   ws->e0.resize(n_inst);
   for (int i = 0; i < n_inst; ++i)
-    ws->e0[i] = (acc[i].led_energy[0] + acc[i].led_energy[1] + acc[i].led_energy[2]) * inst[i].weight;
+    ws->e0[i] = (fix_value(acc[i].fx[FX_ENERGY]) + fix_value(acc[i].fx[FX_ENERGY + 1]) +
+                 fix_value(acc[i].fx[FX_ENERGY + 2])) * inst[i].weight;
   ws->bound = true;
   return QED_OK;
 }
@@ -724,7 +743,7 @@ qed_status qed_init_optical_depth(qed_workspace* ws, qed_stream stream) {
 qed_status qed_set_step(qed_workspace* ws, int64_t step, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (step < 0 || step > ((int64_t)1 << 31)) return fail(QED_ERR_ARG, "step = %lld outside [0, 2^31]", (long long)step);
-  launch_set_step(ws->d_glob, step, (hipStream_t)stream);
+  launch_set_step(ws->d_glob, ws->d_acc, ws->n_inst, step, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return QED_OK;
 }
@@ -872,7 +891,7 @@ qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches) {
 qed_status qed_compact(qed_workspace* ws, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
-  launch_compact(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_movers, ws->d_win, ws->d_rec, ws->d_wsum,
+  launch_compact(ws->field_kind, ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_movers, ws->d_win, ws->d_rec, ws->d_wsum,
                  ws->prec == QED_FP32_MIXED,
                  (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
@@ -893,16 +912,16 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
     std::memset(&L, 0, sizeof(L));
     double tot = 0.0;
     for (int s = 0; s < 3; ++s) {
-      L.energy[s] = A.led_energy[s] * w;
+      L.energy[s] = fix_value(A.fx[FX_ENERGY + s]) * w;
       L.count[s] = (int64_t)A.led_count[s];
       tot += L.energy[s];
     }
     L.energy0 = ws->e0[i];
-    L.work = A.work * w;
-    L.defect_emit = A.defect_emit * w;
-    L.defect_pair = A.defect_pair * w;
-    L.dropped_energy = A.dropped_energy * w;
-    L.radiated = A.radiated * w;
+    L.work = fix_value(A.fx[FX_WORK]) * w;
+    L.defect_emit = fix_value(A.fx[FX_DEFECT_EMIT]) * w;
+    L.defect_pair = fix_value(A.fx[FX_DEFECT_PAIR]) * w;
+    L.dropped_energy = fix_value(A.fx[FX_DROPPED]) * w;
+    L.radiated = fix_value(A.fx[FX_RADIATED]) * w;
     L.n_emit = (int64_t)A.n_emit;
     L.n_null = (int64_t)A.n_null;
     L.n_pair = (int64_t)A.n_pair;

@@ -135,8 +135,9 @@ struct InstAcc {
   int64_t ph_first;            // first photon slot of the photon sweep's chunk list (n_front rounded
                                // down to a chunk)
   unsigned long long hole_ctr, mover_ctr;
-  double work, defect_emit, defect_pair, dropped_energy, radiated;
-  double led_energy[3];
+  // energy sums of the ledger as exact fixed-point words (fix_split): field work, emission and
+  // pair defects, dropped energy, radiated energy, then the three species energies
+  long long fx[8][4];
   unsigned long long led_count[3];
   unsigned long long n_emit, n_null, n_pair, n_dropped, n_range, n_nonfinite, n_field, n_field_lepton;
   unsigned long long n_active;           // photon steps inside the photon's window (evaluated in full)
@@ -147,6 +148,48 @@ struct InstAcc {
   int32_t compact_skip;                  // this compaction has nothing to remove
   int32_t pad_;
 };
+
+// ---------------------------------------------------------------------------
+// Exact, order-independent energy sums for the ledger.  A term v is cut into integer limbs of
+// v 2^64 with weights 2^-64, 2^-32, 2^0 and 2^32 (bits below 2^-64 truncated toward zero; every
+// limb carries the sign of v; |v| < 2^62), and limbs are added into 64-bit integer words.
+// Integer addition is associative, so a sum does not depend on the order of its terms: not on
+// the launch shape, the block schedule or the order of an event queue.  The words are
+// normalised once per step (carries moved up), so each word stays far from overflow.
+// ---------------------------------------------------------------------------
+enum { FX_WORK = 0, FX_DEFECT_EMIT = 1, FX_DEFECT_PAIR = 2, FX_DROPPED = 3, FX_RADIATED = 4, FX_ENERGY = 5 };
+constexpr int kFixRunning = 5;  // FX_WORK..FX_RADIATED accumulate over the run
+
+__device__ __forceinline__ void fix_split(double v, long long l[4]) {
+  v = v > 0x1p62 ? 0x1p62 : v < -0x1p62 ? -0x1p62 : v == v ? v : 0.0;  // non-finite state is counted apart
+  double a = v * 0x1p64;                // exact scaling
+  const double t3 = trunc(a * 0x1p-96);
+  a -= t3 * 0x1p96;                     // exact: the bits of a below 2^96
+  const double t2 = trunc(a * 0x1p-64);
+  a -= t2 * 0x1p64;
+  const double t1 = trunc(a * 0x1p-32);
+  a -= t1 * 0x1p32;
+  l[0] = (long long)trunc(a);
+  l[1] = (long long)t1;
+  l[2] = (long long)t2;
+  l[3] = (long long)t3;
+}
+
+__device__ __forceinline__ void fix_atomic_add(long long* w, const long long l[4]) {
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (l[k]) atomicAdd((unsigned long long*)&w[k], (unsigned long long)l[k]);
+}
+
+// carries of words 0..2 moved up: afterwards words 0..2 lie in [0, 2^32)
+__device__ __forceinline__ void fix_normalise(long long* w) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const long long c = w[k] >> 32;  // floor division by 2^32
+    w[k] -= (long long)((unsigned long long)c << 32);
+    w[k + 1] += c;
+  }
+}
 
 // Workspace-global device state.
 struct Glob {
@@ -404,8 +447,70 @@ struct __attribute__((aligned(32))) PhotonRec32 {
   int32_t bs;
   int32_t pad[2];
 };
-template <bool MIXED>
-using PhotonRecT = typename std::conditional<MIXED, PhotonRec32, PhotonRec>::type;
+// In the plane-wave pulse the field at a photon depends only on psi = t - x - psi0, which is
+// linear in the step index along the photon's straight path: psi(n) = A + n S with
+// A = t0 - x_b - psi0 + b dt n_x and S = dt (1 - n_x).  The pulse's E and B give
+// chi = (eps/2)(1 - n_x)|e(psi)| = c |e(psi)|, and the decrement of eq. 3,
+// a_pair chi T(chi)/eps dt, is a_pair |e| T(chi) S / 2.  So the record holds A, S and c:
+// 32 bytes in FP64 (one word of padding), 16 in the FP32-mixed form (A in FP64).
+struct __attribute__((aligned(32))) PhotonRecPW {
+  double A, S, c, pad;
+};
+struct __attribute__((aligned(16))) PhotonRecPW32 {
+  double A;
+  float S, c;
+};
+template <bool MIXED, int FK>
+using PhotonRecT = typename std::conditional<
+    FK == QED_FIELD_LP_PULSE, typename std::conditional<MIXED, PhotonRecPW32, PhotonRecPW>::type,
+    typename std::conditional<MIXED, PhotonRec32, PhotonRec>::type>::type;
+
+// bytes of one record for a precision and field kind (a multiple of 16)
+__host__ __device__ constexpr int photon_rec_bytes(bool mixed, int fk) {
+  return fk == QED_FIELD_LP_PULSE ? (mixed ? 16 : 32) : (mixed ? 32 : 64);
+}
+
+// 1 - n_x of a direction k (|k| = eps) without cancellation for photons moving along +x
+__device__ __forceinline__ double one_minus_nx(double kx, double ky, double kz, double eps) {
+  return kx > 0.0 ? (ky * ky + kz * kz) / (eps * (eps + kx)) : 1.0 - kx / eps;
+}
+
+// The record of a photon from its stored state (momentum k, birth position and step).
+template <bool MIXED, int FK>
+__device__ inline void make_photon_rec(PhotonRecT<MIXED, FK>& R, const qed_field& F, double t0, double dt,
+                                       double kx, double ky, double kz, double xb, double yb, int32_t bs) {
+  if constexpr (FK == QED_FIELD_LP_PULSE) {
+    const double eps = sqrt(kx * kx + ky * ky + kz * kz);
+    const double omn = eps > 0.0 ? one_minus_nx(kx, ky, kz, eps) : 0.0;
+    const double nx = eps > 0.0 ? kx / eps : 0.0;
+    const double A = (t0 - xb - F.p[2]) + (double)bs * dt * nx;
+    R.A = A;
+    R.S = dt * omn;
+    R.c = 0.5 * eps * omn;
+    (void)yb;
+  } else {
+    R.kx = kx;
+    R.ky = ky;
+    R.kz = kz;
+    R.xb = xb;
+    R.yb = yb;
+    R.bs = bs;
+  }
+}
+
+// Copies a record of `words16` 16-byte words (photon_rec_bytes / 16) from slot `src` to `dst`.
+__device__ __forceinline__ void move_rec(void* base, int words16, int64_t dst, int64_t src) {
+  uint4* b = (uint4*)base;
+  for (int w = 0; w < words16; ++w) b[dst * words16 + w] = b[src * words16 + w];
+}
+__device__ __forceinline__ void swap_rec(void* base, int words16, int64_t i, int64_t j) {
+  uint4* b = (uint4*)base;
+  for (int w = 0; w < words16; ++w) {
+    const uint4 t = b[i * words16 + w];
+    b[i * words16 + w] = b[j * words16 + w];
+    b[j * words16 + w] = t;
+  }
+}
 
 // A window is stored in 32 bits: first and last step as 16-bit fields (lo | hi << 16), saturated
 // so that the stored window always holds the exact one: lo at 65535 stands for "from 65535 or
@@ -446,7 +551,7 @@ __device__ inline int2 photon_window(const qed_field& F, double eps_min, double 
   if (!(eps >= eps_min)) return none;
   if (F.kind != QED_FIELD_LP_PULSE && F.kind != QED_FIELD_CP_WAVE) return all;
   // 1 - n_x without cancellation for photons moving along +x
-  const double omn = kx > 0.0 ? (ky * ky + kz * kz) / (eps * (eps + kx)) : 1.0 - kx / eps;
+  const double omn = one_minus_nx(kx, ky, kz, eps);
   // FP32: e - n_x e and the rounding of |a|^2 - (n.e)^2 (whose parts are up to 2 (1 - n_x) e^2)
   // add at most ~1e-7 + sqrt(1.2e-7 (1 - n_x)) to (1 - n_x); eps, E0 and sin^2 ~1e-6 relative
   const double cmax = 0.5 * eps * (omn + 1e-6 + sqrt(1e-6 * omn)) * fabs(F.p[0]) * (1.0 + 1e-5);
@@ -733,33 +838,82 @@ __device__ __forceinline__ unsigned wave_sum_u(unsigned v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
   return v;
 }
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
 
 // Event statistics of the lanes of a wave added to the accumulators of each lane's instance:
 // one group of atomics per instance present in the wave.  kind 0: emission, 1: pair creation.
+// The energies go in as exact fixed-point limbs (fix_split), summed over the lanes as integers.
 // Every lane of the wave must call it, all lanes active.
 __device__ inline void add_event_stats(int kind, bool has, int ii, InstAcc* acc, double defect, double dropped_e,
                                        unsigned n_ev, unsigned n_null, unsigned n_drop) {
+  long long ld[4], le[4];
+  fix_split(has ? defect : 0.0, ld);
+  fix_split(has ? dropped_e : 0.0, le);
   bool left = has;
   unsigned long long mask;
   while ((mask = __ballot(left)) != 0ull) {
     const int leader = __ffsll((long long)mask) - 1;
     const int lk = __shfl(ii, leader);
     const bool mine = left && ii == lk;
-    const double sd = wave_sum(mine ? defect : 0.0);
-    const double se = wave_sum(mine ? dropped_e : 0.0);
+    long long sd[4], se[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      sd[k] = wave_sum_ll(mine ? ld[k] : 0ll);
+      se[k] = wave_sum_ll(mine ? le[k] : 0ll);
+    }
     const unsigned sv = wave_sum_u(mine ? n_ev : 0u);
     const unsigned sn = wave_sum_u(mine ? n_null : 0u);
     const unsigned sp = wave_sum_u(mine ? n_drop : 0u);
     if (__lane_id() == leader) {
       InstAcc& A = acc[lk];
-      if (sd != 0.0) atomicAdd(kind == 0 ? &A.defect_emit : &A.defect_pair, sd);
-      if (se != 0.0) atomicAdd(&A.dropped_energy, se);
+      fix_atomic_add(A.fx[kind == 0 ? FX_DEFECT_EMIT : FX_DEFECT_PAIR], sd);
+      fix_atomic_add(A.fx[FX_DROPPED], se);
       if (sv) atomicAdd(kind == 0 ? &A.n_emit : &A.n_pair, (unsigned long long)sv);
       if (sn) atomicAdd(&A.n_null, (unsigned long long)sn);
       if (sp) atomicAdd(&A.n_dropped, (unsigned long long)sp);
     }
     if (mine) left = false;
   }
+}
+
+// Sum of the 64 lanes' values of one group of 64 consecutive particle slots (a wave's share of
+// a chunk), converted to fixed point and added by lane 0 to the wave's words in LDS (`w`, four
+// words).  The butterfly order depends only on the lane positions, i.e. on the slots, so the
+// group sum is the same for any launch shape.  Every lane of the wave must call it.
+__device__ __forceinline__ void fix_group_add(double v, long long* w) {
+  const double s = wave_sum(v);
+  if (__lane_id() == 0) {
+    long long l[4];
+    fix_split(s, l);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) w[k] += l[k];
+  }
+}
+
+// The block's per-wave LDS words (s_w[(wave * NQ + q) * 4 + k]) summed and added by thread 0 to
+// the words of dst[q], then cleared.  Every thread of the block must call it.
+template <int NQ>
+__device__ inline void fix_block_flush(long long* s_w, long long* const (&dst)[NQ]) {
+  const int nw = blockDim.x >> 6;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      long long t[4] = {0, 0, 0, 0};
+      for (int v = 0; v < nw; ++v)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          t[k] += s_w[(v * NQ + q) * 4 + k];
+          s_w[(v * NQ + q) * 4 + k] = 0;
+        }
+      fix_atomic_add(dst[q], t);
+    }
+  }
+  __syncthreads();
 }
 
 // block-wide sums of a few accumulators; result valid in thread 0.  Every thread must call.

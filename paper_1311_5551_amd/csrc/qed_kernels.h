@@ -20,7 +20,7 @@ struct StepArgs {
   EvQueue q;                  // pair events of the step (photon passes)
   EmitQueue qe;               // emission events of the step (lepton passes)
   uint32_t* win;              // per-photon pair windows (pack_window); instance i's slots from acc[i].mover_off
-  void* rec;                  // per-photon records (PhotonRecT<MIXED>) for the in-window evaluation
+  void* rec;                  // per-photon records (PhotonRecT<MIXED, FK>) for the in-window evaluation
   const uint32_t* wsum;       // window-group summaries; instance i's from acc[i].wsum_off
 };
 
@@ -41,7 +41,7 @@ hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnc
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,
                        int64_t* base_lep, int64_t* base_ph, int chunk_lep, int chunk_ph, int advance,
                        int count_photons, hipStream_t s);
-void launch_set_step(Glob* glob, int64_t step, hipStream_t s);
+void launch_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step, hipStream_t s);
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s);
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
@@ -49,9 +49,9 @@ void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mix
 void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s);
 void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s);
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
+void launch_compact(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
                     uint32_t* win, void* rec, uint32_t* wsum, bool mixed, hipStream_t s);
-void launch_photon_windows(const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
+void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
                            uint32_t* wsum, double t0, double dt, double cp_min, bool mixed, hipStream_t s);
 
 }  // namespace qedk

@@ -54,6 +54,8 @@ __global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restri
         if (c < 0) c = 0;
       }
       acc[i].n_start[s] = c;
+      if (s == 0 && advance_clock)
+        for (int q = 0; q < kFixRunning; ++q) fix_normalise(acc[i].fx[q]);
       // a count that fell without a compaction (set by the caller) unseals the slots above it
       if (s == 2 && acc[i].n_sealed > c / kWinGroup * kWinGroup) acc[i].n_sealed = c / kWinGroup * kWinGroup;
       if (s == 2 && acc[i].n_front > c) acc[i].n_front = c;
@@ -99,8 +101,12 @@ __global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restri
   }
 }
 
-__global__ void k_set_step(Glob* glob, int64_t step) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) glob->step_next = step;
+// Sets the next step.  The partition's front holds photons whose window ended before the step of
+// the last compaction; at an earlier step they may be inside it again, so the front is emptied
+// (the next compaction rebuilds it) and the sweep reads those photons through their summaries.
+__global__ void k_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) glob->step_next = step;
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) acc[i].n_front = 0;
 }
 
 // largest idx with base[idx] <= c (lands on a non-empty entry; see the chunk-list layout)
@@ -186,8 +192,8 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   __shared__ long long s_base;
   double* sh = smem;
   float* sh32 = (float*)smem;
-  double* sred = smem + a.tb.n_eta;
-  unsigned* sredu = (unsigned*)(sred + 16);
+  long long* s_ll = (long long*)(smem + a.tb.n_eta);  // 16 waves x 2 sums x 4 words
+  unsigned* sredu = (unsigned*)(s_ll + 16 * 2 * 4);
   // deterministic radiation reaction (QED_RR_*) replaces emission; its g table takes h's place
   const bool rr = (a.sc.flags & (QED_RR_QUANTUM | QED_RR_CLASSICAL)) != 0;
   const bool rr_q = (a.sc.flags & QED_RR_QUANTUM) != 0;
@@ -196,6 +202,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
     else if (MIXED) sh32[i] = a.tb.h32[i];
     else sh[i] = a.tb.h[i];
   }
+  for (int i = threadIdx.x; i < 16 * 2 * 4; i += blockDim.x) s_ll[i] = 0;
 
   const int64_t step = uni64(a.glob->step_cur);
   const double t = a.sc.t0 + (double)step * a.sc.dt;
@@ -214,19 +221,22 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   double hq = 0.0;
   float tpf0 = 0.0f, psif_max = 0.0f;
   FieldK fK{0.0};
-  double dacc[2] = {0.0, 0.0};         // field work, energy radiated (deterministic reaction)
+  // field work and energy radiated (deterministic reaction): exact fixed-point words per wave in
+  // LDS, fed with the sum of each group of 64 slots (fix_group_add), so the totals do not depend
+  // on the launch shape
+  long long* const fx_work = s_ll + (threadIdx.x >> 6) * 8;
+  long long* const fx_rad = fx_work + 4;
   unsigned uacc[3] = {0, 0, 0};        // in-field steps, eta above the table, non-finite state
   auto flush = [&](int entry) {
-    block_sum(dacc, uacc, sred, sredu);
+    InstAcc& A = a.acc[entry >> 1];
+    long long* const dst[2] = {A.fx[FX_WORK], A.fx[FX_RADIATED]};
+    fix_block_flush<2>(s_ll, dst);
+    block_sum_u(uacc, sredu);
     if (threadIdx.x == 0) {
-      InstAcc& A = a.acc[entry >> 1];
-      if (dacc[0] != 0.0) atomicAdd(&A.work, dacc[0]);
-      if (dacc[1] != 0.0) atomicAdd(&A.radiated, dacc[1]);
       if (uacc[0]) atomicAdd(&A.n_field_lepton, (unsigned long long)uacc[0]);
       if (uacc[1]) atomicAdd(&A.n_range, (unsigned long long)uacc[1]);
       if (uacc[2]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[2]);
     }
-    dacc[0] = 0.0;
     uacc[0] = uacc[1] = uacc[2] = 0;
   };
 
@@ -296,7 +306,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
     constexpr uint32_t SR = sizeof(Real);
 
     // full step of one lepton; returns true (and its eta) when its optical depth reached zero
-    auto full = [&](unsigned off, double* eta_out) -> bool {
+    auto full = [&](unsigned off, double* eta_out, double* wk, double* rd) -> bool {
       bool pend = false;
       if (!MIXED) {
         double x = buf_ld<Real>(C.x, off * SR), y = buf_ld<Real>(C.y, off * SR), z = d3 ? buf_ld<Real>(C.z, off * SR) : 0.0;
@@ -316,7 +326,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
                      ulz = umz + (upx * sy - upy * sx);
         const double u1x = ulx + hq * E[0], u1y = uly + hq * E[1], u1z = ulz + hq * E[2];
         const double g1 = sqrt(1.0 + (u1x * u1x + u1y * u1y + u1z * u1z));
-        dacc[0] += 2.0 * hq * (E[0] * (ulx + umx) + E[1] * (uly + umy) + E[2] * (ulz + umz)) / (g1 + g0);
+        *wk = 2.0 * hq * (E[0] * (ulx + umx) + E[1] * (uly + umy) + E[2] * (ulz + umz)) / (g1 + g0);
         x += dt * u1x / g1;
         y += dt * u1y / g1;
         if (d3) z += dt * u1z / g1;
@@ -338,7 +348,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
             wx = sc * u1x;
             wy = sc * u1y;
             wz = sc * u1z;
-            dacc[1] += g1 - sqrt(1.0 + (wx * wx + wy * wy + wz * wz));
+            *rd = g1 - sqrt(1.0 + (wx * wx + wy * wy + wz * wz));
           }
         }
         if (emit) {
@@ -395,7 +405,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
         // field work from the stored states (FP64), so the ledger closes on what is stored
         const double ux1 = (double)uxh + uxl, uy1 = (double)uyh + uyl, uz1 = (double)uzh + uzl;
         const double g1d = sqrt(1.0 + (ux1 * ux1 + uy1 * uy1 + uz1 * uz1));
-        dacc[0] += g1d - g0d;
+        *wk = g1d - g0d;
         if (rr) {
           // continuous reaction with eta in FP32 (as for emission) and the energy update in
           // FP64 on the stored momentum; the energy removed is what the stored pairs lost
@@ -414,7 +424,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
             split_double(sc * uy1, uyh, uyl);
             split_double(sc * uz1, uzh, uzl);
             const double vx = (double)uxh + uxl, vy = (double)uyh + uyl, vz = (double)uzh + uzl;
-            dacc[1] += g1d - sqrt(1.0 + (vx * vx + vy * vy + vz * vz));
+            *rd = g1d - sqrt(1.0 + (vx * vx + vy * vy + vz * vz));
           }
         }
         if (emit) {
@@ -426,7 +436,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
           const float eta = sqrtf(r2 > 0.0f ? r2 : 0.0f);
           if (eta > 0.0f) {
             const float h = lookup32(sh32, a.tb.n_eta, a.tb.le0, a.tb.dle, eta, uacc[1], false);
-            tau -= (double)((float)agdt * (eta / g1) * h);
+            tau -= agdt * ((double)eta / (double)g1) * (double)h;  // FP32 look-up, FP64 decrement
             if (tau <= 0.0) {
               pend = true;
               *eta_out = (double)eta;
@@ -529,10 +539,15 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
       for (int j = 0; j < PPT; ++j) {
         const unsigned off = threadIdx.x + j * B;
         bool pend = false;
-        double eta = 0.0;
-        if (gmask & (1u << j)) {
+        double eta = 0.0, wk = 0.0, rd = 0.0;
+        const bool in = (gmask >> j) & 1u;
+        if (in) {
           ++uacc[0];
-          pend = full(off, &eta);
+          pend = full(off, &eta, &wk, &rd);
+        }
+        if (__ballot(in)) {  // wave-uniform: the energy sums of the wave's group of 64 slots
+          fix_group_add(wk, fx_work);
+          if (rr) fix_group_add(rd, fx_rad);
         }
         if (emit) enqueue(off, pend, eta);  // emit is uniform over the block
       }
@@ -541,10 +556,15 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
       for (int j = 0; j < PPT; ++j) {
         const unsigned off = threadIdx.x + j * B;
         bool pend = false;
-        double eta = 0.0;
-        if ((int64_t)off < rem) {
+        double eta = 0.0, wk = 0.0, rd = 0.0;
+        const bool in = (int64_t)off < rem;
+        if (in) {
           ++uacc[0];
-          pend = full(off, &eta);
+          pend = full(off, &eta, &wk, &rd);
+        }
+        if (__ballot(in)) {
+          fix_group_add(wk, fx_work);
+          if (rr) fix_group_add(rd, fx_rad);
         }
         if (emit) enqueue(off, pend, eta);  // emit is uniform over the block
       }
@@ -666,13 +686,8 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
         const int64_t pk = a.acc[ii].mover_off + slot;
         a.win[pk] = pack_window(photon_window(I.field, pair_eps_min(I.field, a.tb.cp_min), a.tb.cp_min, a.sc.t0,
                                               a.sc.dt, skx, sky, skz, sx, (int32_t)(step + 1)));
-        PhotonRecT<MIXED>& R = ((PhotonRecT<MIXED>*)a.rec)[pk];
-        R.kx = skx;
-        R.ky = sky;
-        R.kz = skz;
-        R.xb = sx;
-        R.yb = sy;
-        R.bs = (int32_t)(step + 1);
+        make_photon_rec<MIXED, FK>(((PhotonRecT<MIXED, FK>*)a.rec)[pk], I.field, a.sc.t0, a.sc.dt, skx, sky, skz, sx,
+                                   sy, (int32_t)(step + 1));
       } else {
         n_drop = 1;
         dropped_e = sqrt(ckx * ckx + cky * cky + ckz * ckz);
@@ -729,7 +744,8 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   int64_t cb = 0, ce = 0, n = 0;
   gptr<double> TAU = nullptr;
   gptr<uint32_t> WIN = nullptr;
-  gptr<const PhotonRecT<MIXED>> REC = nullptr;
+  using Rec = PhotonRecT<MIXED, FK>;
+  gptr<const Rec> REC = nullptr;
   gptr<const uint32_t> WSUM = nullptr;
   int64_t nseal = 0, pfirst = 0;
   // group summaries of the current run of chunks, read in one load per wave: bit r PPT + j is
@@ -768,7 +784,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       const qed_species& S = a.inst[ii].s[2];
       TAU = as_global(uni_ptr(S.tau_dev));
       WIN = as_global(uni_ptr(a.win)) + uni64(a.acc[ii].mover_off);
-      REC = as_global((const PhotonRecT<MIXED>*)uni_ptr(a.rec)) + uni64(a.acc[ii].mover_off);
+      REC = as_global((const Rec*)uni_ptr(a.rec)) + uni64(a.acc[ii].mover_off);
       WSUM = as_global(uni_ptr(a.wsum)) + uni64(a.acc[ii].wsum_off);
       nseal = uni64(a.acc[ii].n_sealed);
       pfirst = uni64(a.acc[ii].ph_first);
@@ -786,7 +802,24 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     // buffer resources over the chunk's live slots (uniform); lane offsets in bytes
     const uint32_t nlive = (uint32_t)(rem < CH ? rem : CH);
     const bufres rtau = make_buf(TAU + k0, nlive * 8u), rwin = make_buf(WIN + k0, nlive * 4u);
-    const gptr<const PhotonRecT<MIXED>> rrec = REC + k0;
+    const gptr<const Rec> rrec = REC + k0;
+    // the optical-depth step of a photon with pair rate T > 0; true when its depth reached zero
+    auto decrement = [&](unsigned off, double T, double dtau, double tau) -> bool {
+      bool pend = false;
+      if (T > 0.0) {
+        if (!(tau < 0.0)) {  // tau < 0: converted in an earlier step
+          ++uacc[0];
+          tau -= dtau;
+          if (tau <= 0.0) {
+            pend = true;
+            tau = fmax(tau, kTauPendingMin);
+          }
+          if (!isfinite(tau)) ++uacc[2];
+          buf_st(rtau, off * 8u, tau);
+        }
+      }
+      return pend;
+    };
     // in-field part for one photon; true when its optical depth reached zero
     auto infield = [&](unsigned off, Real kx, Real ky, Real kz, Real xb, Real yb, int32_t bs, double tau) -> bool {
       const Real eps = sqrt(kx * kx + ky * ky + kz * kz);
@@ -821,20 +854,28 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
         chi = 0.5 * (double)eps * sqrt(r2 > 0.0 ? r2 : 0.0);
         T = lookup_T(sT, a.tb, chi, uacc[1]);
       }
-      bool pend = false;
-      if (T > 0.0) {
-        if (!(tau < 0.0)) {  // tau < 0: converted in an earlier step
-          ++uacc[0];
-          tau -= MIXED ? (double)((float)rate * (float)chi * (float)T * (float)inv) : rate * chi * T * (double)inv;
-          if (tau <= 0.0) {
-            pend = true;
-            tau = fmax(tau, kTauPendingMin);
-          }
-          if (!isfinite(tau)) ++uacc[2];
-          buf_st(rtau, off * 8u, tau);
+      return decrement(off, T, rate * chi * T * (double)inv, tau);  // FP64 (chi, T, 1/eps FP32 if mixed)
+    };
+    // the plane-wave pulse from the photon's record: psi(n) = A + n S, chi = c |e(psi)|, and the
+    // decrement a_pair |e| T(chi) S / 2 (PhotonRecPW)
+    auto infield_pw = [&](unsigned off, double A, double S, double cr, double tau) -> bool {
+      const double psi = A + (double)step * S;
+      double T = 0.0, ae = 0.0;
+      if (psi >= 0.0 && psi <= sF.p[1]) {
+        if (MIXED) {
+          float sn, cs, d;
+          fast_sincosf((float)(psi * fK.pi_over_len), &sn, &d);
+          fast_sincosf(reduce_phase(psi + sF.p[3]), &d, &cs);
+          const float e = fabsf((float)sF.p[0] * sn * sn * cs);
+          ae = e;
+          T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.dlc, (float)cr * e, uacc[1], true);
+        } else {
+          const double sn = fast_sin(psi * fK.pi_over_len), cs = fast_cos(psi + sF.p[3]);
+          ae = fabs(sF.p[0] * sn * sn * cs);
+          T = lookup_T(sT, a.tb, cr * ae, uacc[1]);
         }
       }
-      return pend;
+      return decrement(off, T, 0.5 * a.sc.a_pair * ae * T * S, tau);
     };
     auto enqueue = [&](unsigned off, bool pend) {
       const long long slot = wave_reserve(pend, &a.q.ctl->count);
@@ -913,7 +954,19 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
         off = list[e];
         // one line per photon: the record holds the stored values exactly
         const double tau = buf_ld<double>(rtau, off * 8u);
-        if (MIXED) {
+        if constexpr (FK == QED_FIELD_LP_PULSE) {
+          if (MIXED) {  // {A, S, c}: A in FP64
+            typedef unsigned u4 __attribute__((ext_vector_type(4)));
+            const u4 q = *(gptr<const u4>)(rrec + off);
+            const double A = __hiloint2double((int)q.y, (int)q.x);
+            pend = infield_pw(off, A, (double)__uint_as_float(q.z), (double)__uint_as_float(q.w), tau);
+          } else {
+            const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
+            const dbl2 q0 = q[0];
+            const double cr = ((gptr<const double>)(rrec + off))[2];
+            pend = infield_pw(off, q0.x, q0.y, cr, tau);
+          }
+        } else if (MIXED) {
           typedef float flt4 __attribute__((ext_vector_type(4)));
           const gptr<const flt4> q = (gptr<const flt4>)(rrec + off);
           const flt4 q0 = q[0], q1 = q[1];
@@ -1120,20 +1173,27 @@ __global__ void k_init_tau(const qed_instance* __restrict__ inst) {
 __global__ void k_ledger_zero(InstAcc* acc, int n_inst) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
     for (int s = 0; s < 3; ++s) {
-      acc[i].led_energy[s] = 0.0;
+      for (int k = 0; k < 4; ++k) acc[i].fx[FX_ENERGY + s][k] = 0;
       acc[i].led_count[s] = 0;
     }
+    for (int q = 0; q < kFixRunning; ++q) fix_normalise(acc[i].fx[q]);
   }
 }
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_ledger(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc) {
-  __shared__ double sred[16 * 1];
+  __shared__ long long s_ll[16 * 4];
   __shared__ unsigned sredu[16 * 1];
   const int ii = blockIdx.y / 3, s = blockIdx.y % 3;
   const qed_species& S = inst[ii].s[s];
-  double d[1] = {0.0};
+  long long fw[4] = {0, 0, 0, 0};  // energy, exact fixed point per lane
   unsigned u[1] = {0};
+  auto add = [&](double e) {
+    long long l[4];
+    fix_split(e, l);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fw[k] += l[k];
+  };
   if (S.count_dev) {
     int64_t n = *S.count_dev;
     if (n > S.capacity) n = S.capacity;
@@ -1155,18 +1215,23 @@ __global__ __launch_bounds__(256) void k_ledger(const qed_instance* __restrict__
       }
       if (s == 2) {
         if (S.tau_dev[k] < 0.0) continue;
-        d[0] += sqrt(ux * ux + uy * uy + uz * uz);
+        add(sqrt(ux * ux + uy * uy + uz * uz));
       } else {
-        d[0] += sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
+        add(sqrt(1.0 + (ux * ux + uy * uy + uz * uz)));
       }
       ++u[0];
     }
   }
-  block_sum(d, u, sred, sredu);
-  if (threadIdx.x == 0) {
-    if (d[0] != 0.0) atomicAdd(&acc[ii].led_energy[s], d[0]);
-    if (u[0]) atomicAdd(&acc[ii].led_count[s], (unsigned long long)u[0]);
+  // per-lane words to wave sums (integers: any order), then the block's sum by thread 0
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    fw[k] = wave_sum_ll(fw[k]);
+    if ((threadIdx.x & 63) == 0) s_ll[(threadIdx.x >> 6) * 4 + k] = fw[k];
   }
+  long long* const dst[1] = {acc[ii].fx[FX_ENERGY + s]};
+  fix_block_flush<1>(s_ll, dst);
+  block_sum_u(u, sredu);
+  if (threadIdx.x == 0 && u[0]) atomicAdd(&acc[ii].led_count[s], (unsigned long long)u[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1225,8 +1290,7 @@ __global__ __launch_bounds__(256) void k_compact_movers(const qed_instance* __re
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
                                                       const int64_t* __restrict__ movers, uint32_t* __restrict__ win,
-                                                      void* __restrict__ rec_v) {
-  PhotonRecT<MIXED>* rec = (PhotonRecT<MIXED>*)rec_v;
+                                                      void* __restrict__ rec, int rec_words) {
   const int ii = blockIdx.y;
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
@@ -1261,7 +1325,7 @@ __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __rest
       S.uid_dev[k] = S.uid_dev[src];
       S.birth_step_dev[k] = S.birth_step_dev[src];
       win[acc[ii].mover_off + k] = win[acc[ii].mover_off + src];
-      rec[acc[ii].mover_off + k] = rec[acc[ii].mover_off + src];
+      move_rec(rec, rec_words, acc[ii].mover_off + k, acc[ii].mover_off + src);
     }
   }
 }
@@ -1342,14 +1406,14 @@ __device__ __forceinline__ void swap_at(void* a, int64_t i, int64_t j) {
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
                                                    const Glob* __restrict__ glob, const int64_t* __restrict__ movers,
-                                                   uint32_t* __restrict__ win, void* __restrict__ rec_v) {
+                                                   uint32_t* __restrict__ win, void* __restrict__ rec, int rec_words) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   const int ii = blockIdx.y;
   const qed_species& S = inst[ii].s[2];
   const int64_t n = acc[ii].n_start[2], D = acc[ii].n_live, s = glob->step_next;
   const long long n_movers = (long long)acc[ii].mover_ctr;
   uint32_t* W = win + acc[ii].mover_off;
-  PhotonRecT<MIXED>* R = (PhotonRecT<MIXED>*)rec_v + acc[ii].mover_off;
+  const int64_t ro = acc[ii].mover_off;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const bool d3 = inst[ii].dims == 3;
   for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < D; k0 += stride) {
@@ -1371,7 +1435,7 @@ __global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restric
       swap_at<uint64_t>(S.uid_dev, k, j);
       swap_at<int32_t>(S.birth_step_dev, k, j);
       swap_at<uint32_t>(W, k, j);
-      swap_at<PhotonRecT<MIXED>>(R, k, j);
+      swap_rec(rec, rec_words, ro + k, ro + j);
     }
   }
 }
@@ -1424,7 +1488,7 @@ __global__ void k_window_sealed(const qed_instance* __restrict__ inst, int n_ins
 
 // Pair windows of every photon present (after a bind, or when the step's t0, dt or tables
 // change); grid: x strides photons, y = instance.
-template <bool MIXED>
+template <bool MIXED, int FK>
 __global__ __launch_bounds__(256) void k_photon_windows(const qed_instance* __restrict__ inst,
                                                         const InstAcc* __restrict__ acc, uint32_t* __restrict__ win,
                                                         void* __restrict__ rec_v, double t0, double dt,
@@ -1436,21 +1500,19 @@ __global__ __launch_bounds__(256) void k_photon_windows(const qed_instance* __re
   const int64_t n = min(*S.count_dev, S.capacity);
   const double eps_min = pair_eps_min(inst[ii].field, cp_min);
   uint32_t* W = win + acc[ii].mover_off;
-  PhotonRecT<MIXED>* R = (PhotonRecT<MIXED>*)rec_v + acc[ii].mover_off;
+  PhotonRecT<MIXED, FK>* R = (PhotonRecT<MIXED, FK>*)rec_v + acc[ii].mover_off;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += stride) {
-    PhotonRecT<MIXED> r{};
-    r.kx = ((const Real*)S.ux_dev)[k];
-    r.ky = ((const Real*)S.uy_dev)[k];
-    r.kz = ((const Real*)S.uz_dev)[k];
-    r.xb = ((const Real*)S.x_dev)[k];
-    r.yb = ((const Real*)S.y_dev)[k];
-    r.bs = S.birth_step_dev[k];
+    const double kx = ((const Real*)S.ux_dev)[k], ky = ((const Real*)S.uy_dev)[k], kz = ((const Real*)S.uz_dev)[k];
+    const double xb = ((const Real*)S.x_dev)[k], yb = ((const Real*)S.y_dev)[k];
+    const int32_t bs = S.birth_step_dev[k];
+    PhotonRecT<MIXED, FK> r{};
+    make_photon_rec<MIXED, FK>(r, inst[ii].field, t0, dt, kx, ky, kz, xb, yb, bs);
     R[k] = r;
     // converted photons (waiting for compaction) have no window
     W[k] = S.tau_dev[k] < kTauPendingMin
                ? kWinEmpty
-               : pack_window(photon_window(inst[ii].field, eps_min, cp_min, t0, dt, r.kx, r.ky, r.kz, r.xb, r.bs));
+               : pack_window(photon_window(inst[ii].field, eps_min, cp_min, t0, dt, kx, ky, kz, xb, bs));
   }
 }
 
@@ -1526,8 +1588,8 @@ void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob*
                      chunk_lep, chunk_ph, advance, count_photons);
 }
 
-void launch_set_step(Glob* glob, int64_t step, hipStream_t s) {
-  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(64), 0, s, glob, step);
+void launch_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_step, dim3(1), dim3(256), 0, s, glob, acc, n_inst, step);
 }
 
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s) {
@@ -1546,7 +1608,7 @@ void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mix
 }
 
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
-  const size_t shm = (size_t)a.tb.n_eta * sizeof(double) + 16 * sizeof(double) + 16 * 3 * sizeof(unsigned) + 64;
+  const size_t shm = (size_t)a.tb.n_eta * sizeof(double) + 16 * 2 * 4 * sizeof(long long) + 16 * 3 * sizeof(unsigned) + 64;
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_lepton_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;
@@ -1592,31 +1654,38 @@ void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixe
   else hipLaunchKernelGGL(k_ledger<false>, dim3(128, 3 * n_inst), dim3(256), 0, s, inst, acc);
 }
 
-void launch_photon_windows(const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
+void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
                            uint32_t* wsum, double t0, double dt, double cp_min, bool mixed, hipStream_t s) {
   const dim3 g(n_inst == 1 ? 2048 : 64, n_inst);
-  if (mixed) hipLaunchKernelGGL(k_photon_windows<true>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
-  else hipLaunchKernelGGL(k_photon_windows<false>, g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
+  constexpr int LP = QED_FIELD_LP_PULSE, GEN = QED_FIELD_UNIFORM;  // record layouts: plane wave, general
+  if (fk == LP) {
+    if (mixed) hipLaunchKernelGGL((k_photon_windows<true, LP>), g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
+    else hipLaunchKernelGGL((k_photon_windows<false, LP>), g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
+  } else {
+    if (mixed) hipLaunchKernelGGL((k_photon_windows<true, GEN>), g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
+    else hipLaunchKernelGGL((k_photon_windows<false, GEN>), g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
+  }
   hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum);
   hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 0);
 }
 
-void launch_compact(const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
+void launch_compact(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
                     uint32_t* win, void* rec, uint32_t* wsum, bool mixed, hipStream_t s) {
+  const int rw = photon_rec_bytes(mixed, fk) / 16;
   hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   // blocks per instance: enough to stream one large instance at full bandwidth; blocks past an
   // instance's photons (or of an instance with nothing to remove) return at once
   const dim3 g(n_inst == 1 ? 2048 : 256, n_inst);
   hipLaunchKernelGGL(k_compact_count, g, dim3(256), 0, s, inst, acc);
   hipLaunchKernelGGL(k_compact_movers, g, dim3(256), 0, s, inst, acc, movers);
-  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers, win, rec);
-  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers, win, rec);
+  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers, win, rec, rw);
+  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers, win, rec, rw);
   hipLaunchKernelGGL(k_compact_finish, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   hipLaunchKernelGGL(k_part_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   hipLaunchKernelGGL(k_part_count, g, dim3(256), 0, s, acc, glob, win);
   hipLaunchKernelGGL(k_part_movers, g, dim3(256), 0, s, acc, glob, win, movers);
-  if (mixed) hipLaunchKernelGGL(k_part_swap<true>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec);
-  else hipLaunchKernelGGL(k_part_swap<false>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec);
+  if (mixed) hipLaunchKernelGGL(k_part_swap<true>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec, rw);
+  else hipLaunchKernelGGL(k_part_swap<false>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec, rw);
   hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum);
   hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 1);
 }

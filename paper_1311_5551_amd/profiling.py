@@ -4,7 +4,7 @@ of a kernel in the profiled bench command.
 
   python -m paper_1311_5551_amd.profiling trace   --csv T --kernel NAME --last N
   python -m paper_1311_5551_amd.profiling traffic --fetch F --write W --copy-fetch CF --copy-write CW \\
-         --kernel NAME --last N [--out JSON --source-hash H]
+         --kernel NAME --last N [--out JSON --source-hash H --bench-window A..B]
 
 HBM traffic: FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the kernel, each divided by the
 ratio the same counter reads for a plain device copy of known size (the runtime's copy kernel,
@@ -63,12 +63,14 @@ def main(argv=None):
     c.add_argument("--copy-bytes", type=int, default=1 << 30)
     c.add_argument("--out")
     c.add_argument("--source-hash")
+    c.add_argument("--bench-window", help="the bench's timed steps, e.g. 9990..10010")
+    c.add_argument("--copy-kernel", default="copyBuffer", help="name of the plain copy kernel in the copy runs")
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(json.dumps(trace_window(a.csv, a.kernel, a.last), indent=1))
         return
-    ff = copy_factor(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
-    fw = copy_factor(a.copy_write, "WRITE_SIZE", a.copy_bytes)
+    ff = copy_factor(a.copy_fetch, "FETCH_SIZE", a.copy_bytes, a.copy_kernel)
+    fw = copy_factor(a.copy_write, "WRITE_SIZE", a.copy_bytes, a.copy_kernel)
     fe = counter_window(a.fetch, "FETCH_SIZE", a.kernel, a.last)
     wr = counter_window(a.write, "WRITE_SIZE", a.kernel, a.last)
     res = {"kernel": a.kernel, "window": fe["window"], "fetch_kib_per_launch": fe["mean"],
@@ -78,6 +80,8 @@ def main(argv=None):
     res["bytes_per_launch"] = res["bytes_read_per_launch"] + res["bytes_written_per_launch"]
     if a.source_hash:
         res["source_hash"] = a.source_hash
+    if a.bench_window:
+        res["bench_window"] = a.bench_window
     print(json.dumps(res, indent=1))
     if a.out:
         with open(a.out, "w") as f:

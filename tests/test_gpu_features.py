@@ -357,3 +357,36 @@ def test_init_optical_depth_keeps_converted_photons(shared_tables):
     assert (after["tau"][~gone] > 0).all()
     r.step(10)
     assert r.ledger()[0]["status"] == "QED_OK"
+
+
+@pytest.mark.parametrize("flags", [W.FLAG_EMIT | W.FLAG_PAIRS | W.FLAG_PROPAGATE, capi.QED_RR_QUANTUM])
+def test_ledger_is_independent_of_launch_shape(flags, shared_tables):
+    # every energy sum of the ledger is an exact fixed-point sum, so runs whose sweeps have
+    # different launch shapes (hence other blocks, waves and atomic orders) give bit-identical
+    # ledgers as well as identical particles
+    shapes = [((64, 1), (64, 1)), ((256, 8), (256, 16)), ((128, 2), (192, 4))]
+    leds, runs = [], []
+    for (bl, pl), (bp, pp) in shapes:
+        w = W.collision(2000, n_steps=2600, meet_step=1300, seed=21, flags=flags)
+        if flags == capi.QED_RR_QUANTUM:
+            w.capacity = dict(electron=w.n + 1024, positron=1024, photon=1024)
+        r = Run(w, shared_tables)
+        r.set_kernel_launch(capi.QED_KERNEL_LEPTON, bl, pl)
+        r.set_kernel_launch(capi.QED_KERNEL_PHOTON, bp, pp)
+        for _ in range(26):
+            r.step(100)
+            r.compact()
+        leds.append(r.ledger()[0])
+        runs.append(r)
+    assert leds[0]["status"] == "QED_OK"
+    keys = ("energy", "energy0", "work", "defect_emit", "defect_pair", "dropped_energy", "radiated", "drift",
+            "count", "n_emit", "n_null", "n_pair")
+    for l in leds[1:]:
+        for k in keys:
+            assert l[k] == leds[0][k], k
+    if flags == capi.QED_RR_QUANTUM:
+        assert leds[0]["radiated"] > 0
+    else:
+        assert leds[0]["n_pair"] > 0 and leds[0]["defect_emit"] != 0.0
+    for r in runs[1:]:
+        _states_equal(runs[0], r)

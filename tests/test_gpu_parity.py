@@ -383,3 +383,36 @@ def test_photon_windows_past_16_bit_steps(shared_tables, oracle_tables):
     _check_parity(r, w, o_res, o_led, label="photon_windows_past_16_bit")
     assert o_led["n_pair"] > 20
     assert led["n_pair"] == o_led["n_pair"]
+
+
+def test_set_step_back_after_compaction(shared_tables, oracle_tables):
+    # qed_compact puts the photons whose pair window is over in front of the others, and the
+    # photon sweep starts after that front.  Setting the clock back empties the front: at an
+    # earlier step those photons can be inside their windows again.  Particles at step 1800
+    # (compacted every 100 steps), clock set back to 1200, then 600 steps: per uid against the
+    # oracle started from the same particles at step 1200 (it evaluates every photon every step).
+    w = W.collision(1500, a0=200.0, n_steps=2600, meet_step=1300, seed=11)
+    r = Run(w, shared_tables)
+    for _ in range(18):
+        r.step(100)
+        r.compact()
+    # new uids for every particle, so that the children made again in steps 1200..1800 (keyed by
+    # uid and step) do not repeat uids made the first time
+    r.synchronize()
+    for name in ("electron", "positron", "photon"):
+        n = r.count(0, name)
+        r.bufs[0][name]["uid"][:n] ^= 0x5DEECE66D
+    st = r.state()[0]
+    ph = {k: v[st["photon"]["tau"] >= 0] for k, v in st["photon"].items()}
+    capi.qed_set_step(r.ws, 1200, r._s())
+    r.step_index = 1200
+    r.step(600)
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK"
+    cfg = oracle.RunConfig(field_kind=w.field_kind, field=w.field, dt=w.dt, n_steps=600, flags=w.flags,
+                           seed=w.seed, instance=w.instance, step0=1200, draw_initial_tau=False)
+    o_res, o_led = oracle.run(cfg, oracle_tables, electrons=st["electron"], positrons=st["positron"], photons=ph)
+    assert o_led["n_pair"] > 0
+    _check_parity(r, w, o_res, o_led, label="set_step_back")
+    if not straddle_uids(o_res).size:
+        assert led["n_pair"] >= o_led["n_pair"]  # the ledger also holds the pairs of steps 0..1800
