@@ -122,6 +122,8 @@ struct qed_workspace {
   int64_t evq_cap = 0;
   EmitEv* d_emq = nullptr;
   int64_t emq_cap = 0;
+  int32_t* d_wave_cnt = nullptr;  // emission events per wave of the lepton sweep (cus * 32 waves)
+  int64_t lep_cap = 0;            // bound lepton slots (both species, all instances)
   SortScratch sort;  // allocated by the first qed_sort that needs it
   int64_t sort_cap = 0;
   int64_t* d_base = nullptr;  // 3 * max_inst: leptons (2 per instance) then photons
@@ -356,6 +358,10 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.qe.ctl = ws->d_evc + 1;
   a.qe.ent = ws->d_emq;
   a.qe.cap = ws->emq_cap;
+  a.qe.wave_cnt = ws->d_wave_cnt;
+  a.qe.grid = ws->cus * (2048 / BL);
+  a.qe.waves = BL / 64;
+  a.qe.ppt = ws->ppt[0];
   a.win = ws->d_win;
   a.rec = ws->d_rec;
   a.wsum = ws->d_wsum;
@@ -405,6 +411,23 @@ qed_status ensure_windows(const qed_tables* tb, qed_workspace* ws, const qed_ste
   ws->win_t0 = p->t0;
   ws->win_dt = p->dt;
   ws->win_cp_min = cp_min;
+  return QED_OK;
+}
+
+// The emission queue holds every wave segment of the lepton sweep (EmitQueue): the bound lepton
+// slots plus the rounding of the chunk list (a partial chunk per species list) and of the blocks'
+// runs of chunks (up to one chunk per block).  Synchronises the device when it reallocates.
+qed_status ensure_emit_queue(qed_workspace* ws) {
+  const int64_t ch = (int64_t)ws->block[0] * ws->ppt[0];
+  const int64_t grid = (int64_t)ws->cus * (2048 / ws->block[0]);
+  const int64_t need = std::max<int64_t>(1, ws->lep_cap + (2 * (int64_t)ws->n_inst + grid) * ch);
+  if (need <= ws->emq_cap && ws->d_emq) return QED_OK;
+  HIP_TRY(hipDeviceSynchronize());
+  hipFree(ws->d_emq);
+  ws->d_emq = nullptr;
+  ws->emq_cap = 0;
+  HIP_TRY(hipMalloc((void**)&ws->d_emq, (size_t)need * sizeof(EmitEv)));
+  ws->emq_cap = need;
   return QED_OK;
 }
 
@@ -554,6 +577,8 @@ qed_status qed_workspace_create(int32_t max_inst, qed_workspace** out) {
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_evq, (size_t)kDefaultEventQueue * sizeof(uint64_t));
   if (e == hipSuccess) ws->evq_cap = kDefaultEventQueue;
   if (e == hipSuccess) e = hipMalloc((void**)&ws->d_base, 3 * (size_t)max_inst * sizeof(int64_t));
+  if (e == hipSuccess) e = hipMalloc((void**)&ws->d_wave_cnt, (size_t)cus * 32 * sizeof(int32_t));
+  if (e == hipSuccess) e = hipMemset(ws->d_wave_cnt, 0, (size_t)cus * 32 * sizeof(int32_t));
   if (e == hipSuccess) e = hipMemset(ws->d_glob, 0, sizeof(Glob));
   if (e == hipSuccess) e = hipMemset(ws->d_acc, 0, max_inst * sizeof(InstAcc));
   if (e == hipSuccess) e = init_crmath();
@@ -575,6 +600,7 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->d_evc);
   hipFree(ws->d_evq);
   hipFree(ws->d_emq);
+  hipFree(ws->d_wave_cnt);
   hipFree(ws->sort.key);
   hipFree(ws->sort.dst);
   hipFree(ws->sort.hist);
@@ -598,6 +624,7 @@ qed_status qed_set_kernel_launch(qed_workspace* ws, int32_t kernel, int32_t bloc
   if (ws->block[k] != block || ws->ppt[k] != ppt) drop_graph(ws);
   ws->block[k] = block;
   ws->ppt[k] = ppt;
+  if (k == 0 && ws->bound) return ensure_emit_queue(ws);
   return QED_OK;
 }
 
@@ -709,17 +736,11 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
     ws->rec_bytes = rec_bytes;
   }
   ws->win_valid = false;  // computed by the first step, which knows t0, dt and the tables
-  // emission queue: one entry per lepton slot (a lepton emits at most once per step)
+  // emission queue: the wave segments of the lepton sweep (a lepton emits at most once per step)
   int64_t leptons = 0;
   for (int i = 0; i < n_inst; ++i) leptons += inst[i].s[0].capacity + inst[i].s[1].capacity;
-  if (leptons < 1) leptons = 1;
-  if (leptons > ws->emq_cap) {
-    hipFree(ws->d_emq);
-    ws->d_emq = nullptr;
-    ws->emq_cap = 0;
-    HIP_TRY(hipMalloc((void**)&ws->d_emq, (size_t)leptons * sizeof(EmitEv)));
-    ws->emq_cap = leptons;
-  }
+  ws->lep_cap = leptons;
+  if ((st = ensure_emit_queue(ws))) return st;
   HIP_TRY(hipMemcpy(ws->d_inst, inst, n_inst * sizeof(qed_instance), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ws->d_acc, acc0.data(), n_inst * sizeof(InstAcc), hipMemcpyHostToDevice));
   std::vector<InstAcc> acc;

@@ -210,8 +210,12 @@ struct EvQueue {
   uint64_t* ent;
   int64_t cap;
 };
-// Emission-event queue: (instance << 41 | species << 40 | slot) and the emitter's eta.  Sized to
-// the bound lepton capacity, so it cannot overflow (at most one event per lepton and step).
+// Emission-event queue: (instance << 41 | species << 40 | slot) and the emitter's eta.  Every wave
+// of the lepton sweep owns a segment of it: wave w of block b writes its events, in slot order, from
+// entry (b nw + w) seg_len on, where seg_len = per_block * ppt * 64 is the number of lepton slots the
+// wave handles in the step (per_block = chunks per block), and stores their number in
+// wave_cnt[b nw + w].  No atomics, and no overflow: a lepton emits at most once per step.  The queue
+// holds the bound leptons plus the rounding of the chunk list and of the blocks' runs of it.
 struct EmitEv {
   uint64_t key;
   double eta;
@@ -220,6 +224,10 @@ struct EmitQueue {
   EvCtl* ctl;
   EmitEv* ent;
   int64_t cap;
+  int32_t* wave_cnt;   // events per wave of the lepton sweep (its grid x blockDim / 64 entries)
+  int grid;            // lepton-sweep blocks
+  int waves;           // lepton-sweep waves per block
+  int ppt;             // lepton-sweep particles per thread
 };
 constexpr int kEvSlotBits = 40;
 // state of a photon's optical depth: >= 0 live, [kTauPendingMin, 0] converting this step, -1 gone
@@ -879,6 +887,102 @@ __device__ inline void add_event_stats(int kind, bool has, int ii, InstAcc* acc,
     if (mine) left = false;
   }
 }
+
+// The key shared by all of the block's lanes that have `want` set: true (and the key in *out) when
+// at least one lane wants and all wanting lanes hold the same key.  Every thread of the block must
+// call it; s holds 3 ints per wave.
+__device__ inline bool block_uniform_key(bool want, int key, int* s, int* out) {
+  const unsigned long long m = __ballot(want);
+  const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int k0 = 0;
+  bool uni = true;
+  if (m) {
+    k0 = __shfl(key, __ffsll((long long)m) - 1);
+    uni = __ballot(want && key != k0) == 0ull;
+  }
+  if (__lane_id() == 0) {
+    s[3 * wv] = m != 0ull;
+    s[3 * wv + 1] = k0;
+    s[3 * wv + 2] = uni;
+  }
+  __syncthreads();
+  bool any = false, ok = true;
+  int kk = 0;
+  for (int w = 0; w < nw; ++w) {
+    if (!s[3 * w]) continue;
+    if (!any) {
+      kk = s[3 * w + 1];
+      any = true;
+    } else if (s[3 * w + 1] != kk) {
+      ok = false;
+    }
+    ok = ok && s[3 * w + 2];
+  }
+  __syncthreads();
+  *out = kk;
+  return any && ok;
+}
+
+// Event statistics of one instance gathered by a block over several rounds (thread 0 holds them),
+// added to the instance's accumulators with one group of atomics at flush.
+struct BlockEventStats {
+  long long defect[4], dropped[4];
+  unsigned long long n_ev, n_null, n_drop;
+  int inst;  // -1: empty
+  __device__ void clear() {
+    for (int k = 0; k < 4; ++k) defect[k] = dropped[k] = 0;
+    n_ev = n_null = n_drop = 0;
+    inst = -1;
+  }
+  // block-wide sums of the lanes' values (every thread calls; s_ll holds 16 * 8 words, s_u 16 * 3)
+  __device__ void add(const long long ld[4], const long long le[4], unsigned ev, unsigned nul, unsigned drp,
+                      long long* s_ll, unsigned* s_u) {
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    long long wd[4], we[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      wd[k] = wave_sum_ll(ld[k]);
+      we[k] = wave_sum_ll(le[k]);
+    }
+    const unsigned sv = wave_sum_u(ev), sn = wave_sum_u(nul), sp = wave_sum_u(drp);
+    if (__lane_id() == 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        s_ll[8 * wv + k] = wd[k];
+        s_ll[8 * wv + 4 + k] = we[k];
+      }
+      s_u[3 * wv] = sv;
+      s_u[3 * wv + 1] = sn;
+      s_u[3 * wv + 2] = sp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 0; w < nw; ++w) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          defect[k] += s_ll[8 * w + k];
+          dropped[k] += s_ll[8 * w + 4 + k];
+        }
+        n_ev += s_u[3 * w];
+        n_null += s_u[3 * w + 1];
+        n_drop += s_u[3 * w + 2];
+      }
+    }
+    __syncthreads();
+  }
+  // thread 0 only
+  __device__ void flush(int kind, InstAcc* acc) {
+    if (inst >= 0) {
+      InstAcc& A = acc[inst];
+      fix_atomic_add(A.fx[kind == 0 ? FX_DEFECT_EMIT : FX_DEFECT_PAIR], defect);
+      fix_atomic_add(A.fx[FX_DROPPED], dropped);
+      if (n_ev) atomicAdd(kind == 0 ? &A.n_emit : &A.n_pair, n_ev);
+      if (n_null) atomicAdd(&A.n_null, n_null);
+      if (n_drop) atomicAdd(&A.n_dropped, n_drop);
+    }
+    clear();
+  }
+};
 
 // Sum of the 64 lanes' values of one group of 64 consecutive particle slots (a wave's share of
 // a chunk), converted to fixed point and added by lane 0 to the wave's words in LDS (`w`, four

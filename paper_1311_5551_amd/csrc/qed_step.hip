@@ -188,8 +188,6 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double smem[];
   __shared__ qed_field sF;
-  __shared__ unsigned s_wave[16];  // queue reservation: wave offsets, block base
-  __shared__ long long s_base;
   double* sh = smem;
   float* sh32 = (float*)smem;
   long long* s_ll = (long long*)(smem + a.tb.n_eta);  // 16 waves x 2 sums x 4 words
@@ -244,6 +242,10 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   // instance boundary inside its run
   const int64_t per_block = (nch + gridDim.x - 1) / gridDim.x;
   const int64_t c_end = min(nch, (int64_t)blockIdx.x * per_block + per_block);
+  // this wave's segment of the emission queue and its event count
+  const int wave_id = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int64_t q_seg = (int64_t)wave_id * (per_block * PPT * 64);
+  int64_t q_run = 0;
   for (int64_t c = (int64_t)blockIdx.x * per_block; c < c_end; ++c) {
     if (c >= ce) {
       if (cur >= 0) flush(cur);
@@ -305,12 +307,65 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
     C.tau = make_buf(P.tau + k0, nlive * 8u);
     constexpr uint32_t SR = sizeof(Real);
 
+    // position and momentum of one lepton (slots past the chunk's live ones read as zero)
+    struct LepState {
+      Real x, y, z, ux, uy, uz;
+      float xl, yl, zl, uxl, uyl, uzl;  // FP32-mixed low words
+    };
+    auto load_state = [&](unsigned off) -> LepState {
+      LepState st;
+      st.x = buf_ld<Real>(C.x, off * SR);
+      st.y = buf_ld<Real>(C.y, off * SR);
+      st.z = d3 ? buf_ld<Real>(C.z, off * SR) : Real(0);
+      st.ux = buf_ld<Real>(C.ux, off * SR);
+      st.uy = buf_ld<Real>(C.uy, off * SR);
+      st.uz = buf_ld<Real>(C.uz, off * SR);
+      if (MIXED) {
+        st.xl = buf_ld<float>(C.xl, off * 4u);
+        st.yl = buf_ld<float>(C.yl, off * 4u);
+        st.zl = d3 ? buf_ld<float>(C.zl, off * 4u) : 0.0f;
+        st.uxl = buf_ld<float>(C.uxl, off * 4u);
+        st.uyl = buf_ld<float>(C.uyl, off * 4u);
+        st.uzl = buf_ld<float>(C.uzl, off * 4u);
+      } else {
+        st.xl = st.yl = st.zl = st.uxl = st.uyl = st.uzl = 0.0f;
+      }
+      return st;
+    };
+    // field-free drift of one lepton (outside the plane-wave pulse the Boris step reduces
+    // exactly to x += dt u / gamma, with u and tau unchanged)
+    auto drift = [&](unsigned off, const LepState& st) {
+      if (!MIXED) {
+        const double g1 = sqrt(1.0 + (st.ux * st.ux + st.uy * st.uy + st.uz * st.uz));
+        buf_st(C.x, off * SR, (Real)(st.x + dt * st.ux / g1));
+        buf_st(C.y, off * SR, (Real)(st.y + dt * st.uy / g1));
+        if (d3) buf_st(C.z, off * SR, (Real)(st.z + dt * st.uz / g1));
+        if (!isfinite(g1)) ++uacc[2];
+      } else {
+        const float g1 = sqrtf(1.0f + ((float)st.ux * (float)st.ux + (float)st.uy * (float)st.uy +
+                                       (float)st.uz * (float)st.uz));
+        float xh = (float)st.x, xlo = st.xl, yh = (float)st.y, ylo = st.yl;
+        comp_add(xh, xlo, dtf * (float)st.ux / g1);
+        comp_add(yh, ylo, dtf * (float)st.uy / g1);
+        buf_st(C.x, off * SR, (Real)xh);
+        buf_st(C.xl, off * 4u, xlo);
+        buf_st(C.y, off * SR, (Real)yh);
+        buf_st(C.yl, off * 4u, ylo);
+        if (d3) {
+          float zh = (float)st.z, zlo = st.zl;
+          comp_add(zh, zlo, dtf * (float)st.uz / g1);
+          buf_st(C.z, off * SR, (Real)zh);
+          buf_st(C.zl, off * 4u, zlo);
+        }
+        if (!isfinite(g1)) ++uacc[2];
+      }
+    };
     // full step of one lepton; returns true (and its eta) when its optical depth reached zero
-    auto full = [&](unsigned off, double* eta_out, double* wk, double* rd) -> bool {
+    auto full = [&](unsigned off, const LepState& st, double* eta_out, double* wk, double* rd) -> bool {
       bool pend = false;
       if (!MIXED) {
-        double x = buf_ld<Real>(C.x, off * SR), y = buf_ld<Real>(C.y, off * SR), z = d3 ? buf_ld<Real>(C.z, off * SR) : 0.0;
-        const double ux = buf_ld<Real>(C.ux, off * SR), uy = buf_ld<Real>(C.uy, off * SR), uz = buf_ld<Real>(C.uz, off * SR);
+        double x = st.x, y = st.y, z = st.z;
+        const double ux = st.ux, uy = st.uy, uz = st.uz;
         double tau = buf_ld<double>(C.tau, off * 8u);
         double E[3], Bf[3];
         field_at<FK>(sF, x, y, t, E, Bf);
@@ -376,10 +431,8 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
         buf_st(C.uz, off * SR, (Real)(wz));
         buf_st(C.tau, off * 8u, (double)(tau));
       } else {
-        float xh = buf_ld<Real>(C.x, off * SR), xl = buf_ld<float>(C.xl, off * 4u), yh = buf_ld<Real>(C.y, off * SR), yl = buf_ld<float>(C.yl, off * 4u);
-        float zh = d3 ? buf_ld<Real>(C.z, off * SR) : 0.0f, zl = d3 ? buf_ld<float>(C.zl, off * 4u) : 0.0f;
-        float uxh = buf_ld<Real>(C.ux, off * SR), uxl = buf_ld<float>(C.uxl, off * 4u), uyh = buf_ld<Real>(C.uy, off * SR),
-              uyl = buf_ld<float>(C.uyl, off * 4u), uzh = buf_ld<Real>(C.uz, off * SR), uzl = buf_ld<float>(C.uzl, off * 4u);
+        float xh = st.x, xl = st.xl, yh = st.y, yl = st.yl, zh = st.z, zl = st.zl;
+        float uxh = st.ux, uxl = st.uxl, uyh = st.uy, uyl = st.uyl, uzh = st.uz, uzl = st.uzl;
         double tau = buf_ld<double>(C.tau, off * 8u);
         const double ux0 = (double)uxh + uxl, uy0 = (double)uyh + uyl, uz0 = (double)uzh + uzl;
         const double g0d = sqrt(1.0 + (ux0 * ux0 + uy0 * uy0 + uz0 * uz0));
@@ -463,10 +516,12 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
       return pend;
     };
     auto enqueue = [&](unsigned off, bool pend, double eta) {
-      // one atomic per block: with a few percent of leptons emitting per step nearly every wave
-      // has an event, and per-wave atomics on the one queue counter would serialise
-      const long long slot = block_reserve(pend, &a.qe.ctl->count, s_wave, &s_base);
+      // into the wave's own segment of the queue (EmitQueue): no atomics, no barriers.  (Atomics
+      // on one device-wide counter serialise at ~10 ns each, and there is an event in nearly every
+      // wave during a collision.)
+      const unsigned long long m = __ballot(pend);
       if (pend) {
+        const int64_t slot = q_seg + q_run + __popcll(m & ((1ull << __lane_id()) - 1ull));
         if (slot < a.qe.cap) {
           a.qe.ent[slot].key = ((uint64_t)(cur >> 1) << 41) | ((uint64_t)(cur & 1) << 40) | (uint64_t)(k0 + off);
           a.qe.ent[slot].eta = eta;
@@ -474,76 +529,31 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
           a.qe.ctl->overflow = 1;  // cannot happen: the queue holds one entry per lepton slot
         }
       }
+      q_run += __popcll(m);
     };
 
     if (FK == QED_FIELD_LP_PULSE) {
-      // phase 1: state of all PPT leptons; outside the pulse (FP32 phase test with a margin far
-      // above its rounding error) the drift, inside it a bit for phase 2
-      Real x[PPT], y[PPT], z[PPT], ux[PPT], uy[PPT], uz[PPT];
-      float xl[PPT], yl[PPT], zl[PPT];
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {  // slots past the chunk's live ones read as zero
-        const unsigned off = threadIdx.x + j * B;
-        x[j] = buf_ld<Real>(C.x, off * SR);
-        y[j] = buf_ld<Real>(C.y, off * SR);
-        z[j] = buf_ld<Real>(C.z, off * SR);
-        ux[j] = buf_ld<Real>(C.ux, off * SR);
-        uy[j] = buf_ld<Real>(C.uy, off * SR);
-        uz[j] = buf_ld<Real>(C.uz, off * SR);
-        if (MIXED) {
-          xl[j] = buf_ld<float>(C.xl, off * 4u);
-          yl[j] = buf_ld<float>(C.yl, off * 4u);
-          zl[j] = buf_ld<float>(C.zl, off * 4u);
-        }
-      }
+      // outside the pulse (an FP32 test of the phase with a margin far above its rounding error)
+      // the drift, inside it the full step
       const float tpf = (float)t - tpf0;
       const float mt = fabsf((float)t) + fabsf(tpf0);
-      unsigned gmask = 0;
-#pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const unsigned off = threadIdx.x + j * B;
-        if ((int64_t)off < rem) {
-          const float xf = (float)x[j];
-          const float psif = tpf - xf;
-          const float m = 1e-5f * (mt + fabsf(xf)) + 1e-30f;
-          if (psif >= -m && psif <= psif_max + m) {
-            gmask |= 1u << j;
-          } else if (!MIXED) {
-            const double g1 = sqrt(1.0 + (ux[j] * ux[j] + uy[j] * uy[j] + uz[j] * uz[j]));
-            buf_st(C.x, off * SR, (Real)(x[j] + dt * ux[j] / g1));
-            buf_st(C.y, off * SR, (Real)(y[j] + dt * uy[j] / g1));
-            if (d3) buf_st(C.z, off * SR, (Real)(z[j] + dt * uz[j] / g1));
-            if (!isfinite(g1)) ++uacc[2];
-          } else {
-            const float g1 = sqrtf(1.0f + ((float)ux[j] * (float)ux[j] + (float)uy[j] * (float)uy[j] +
-                                           (float)uz[j] * (float)uz[j]));
-            float xh = (float)x[j], xlo = xl[j], yh = (float)y[j], ylo = yl[j];
-            comp_add(xh, xlo, dtf * (float)ux[j] / g1);
-            comp_add(yh, ylo, dtf * (float)uy[j] / g1);
-            buf_st(C.x, off * SR, (Real)((Real)xh));
-            buf_st(C.xl, off * 4u, (float)(xlo));
-            buf_st(C.y, off * SR, (Real)((Real)yh));
-            buf_st(C.yl, off * 4u, (float)(ylo));
-            if (d3) {
-              float zh = (float)z[j], zlo = zl[j];
-              comp_add(zh, zlo, dtf * (float)uz[j] / g1);
-              buf_st(C.z, off * SR, (Real)((Real)zh));
-              buf_st(C.zl, off * 4u, (float)(zlo));
-            }
-            if (!isfinite(g1)) ++uacc[2];
-          }
-        }
-      }
-      // phase 2: the leptons inside the pulse, state re-read (from cache) one at a time
 #pragma unroll 1
       for (int j = 0; j < PPT; ++j) {
         const unsigned off = threadIdx.x + j * B;
-        bool pend = false;
+        bool pend = false, in = false;
         double eta = 0.0, wk = 0.0, rd = 0.0;
-        const bool in = (gmask >> j) & 1u;
-        if (in) {
-          ++uacc[0];
-          pend = full(off, &eta, &wk, &rd);
+        if ((int64_t)off < rem) {
+          const LepState st = load_state(off);
+          const float xf = (float)st.x;
+          const float psif = tpf - xf;
+          const float m = 1e-5f * (mt + fabsf(xf)) + 1e-30f;
+          in = psif >= -m && psif <= psif_max + m;
+          if (in) {
+            ++uacc[0];
+            pend = full(off, st, &eta, &wk, &rd);
+          } else {
+            drift(off, st);
+          }
         }
         if (__ballot(in)) {  // wave-uniform: the energy sums of the wave's group of 64 slots
           fix_group_add(wk, fx_work);
@@ -560,7 +570,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
         const bool in = (int64_t)off < rem;
         if (in) {
           ++uacc[0];
-          pend = full(off, &eta, &wk, &rd);
+          pend = full(off, load_state(off), &eta, &wk, &rd);
         }
         if (__ballot(in)) {
           fix_group_add(wk, fx_work);
@@ -571,24 +581,77 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
     }
   }
   if (cur >= 0) flush(cur);
+  if (emit && (threadIdx.x & 63) == 0) a.qe.wave_cnt[wave_id] = (int32_t)q_run;
 }
 
 // Emission by the queued leptons: chi from the 2-D inverse CDF at the emitter's eta, photon
 // momentum (2 chi / eta) u along the emitter's momentum, recoil, photon appended at the
 // emitter's post-push position (born at the start of the next step), new optical depth.
+//
+// The events sit in the lepton sweep's per-wave segments (EmitQueue); every block forms the prefix
+// of the per-wave counts in LDS and takes a contiguous range of the events.  A round whose events
+// all belong to one instance (the usual case: the segments follow the chunk list, which is ordered
+// by instance) reserves its photon slots and adds its statistics with one atomic per block; rounds
+// across instances use per-wave atomics.
 template <int FK, bool MIXED>
 __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
   using Real = typename std::conditional<MIXED, float, double>::type;
+  extern __shared__ int s_pref[];                  // per-wave event counts, then their prefix
+  __shared__ int s_scan[256];
+  __shared__ int s_key[48];
+  __shared__ unsigned s_wave[16];
+  __shared__ long long s_base;
+  __shared__ long long s_ll[16 * 8];
+  __shared__ unsigned s_u[16 * 3];
   const int64_t step = a.glob->step_cur;
-  const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const int64_t cnt = min(a.qe.ctl->count, a.qe.cap);
-  const int lane = threadIdx.x % 64;
-  for (int64_t e0 = gtid - lane; e0 < cnt; e0 += stride) {  // whole waves iterate together
-    const int64_t e = e0 + lane;
-    const bool want = e < cnt;
+  const int NW = a.qe.grid * a.qe.waves;
+  const int64_t nch = a.glob->n_chunks[0];
+  const int64_t seg_len = (nch + a.qe.grid - 1) / a.qe.grid * a.qe.ppt * 64;
+  // exclusive prefix of the per-wave counts: thread t sums a contiguous run, a block scan of the
+  // run totals, then the run's prefixes
+  {
+    const int per = (NW + blockDim.x - 1) / blockDim.x;
+    const int b = min(NW, (int)threadIdx.x * per), e = min(NW, b + per);
+    int loc = 0;
+    for (int i = b; i < e; ++i) {
+      const int c = a.qe.wave_cnt[i];
+      s_pref[i] = c;
+      loc += c;
+    }
+    s_scan[threadIdx.x] = loc;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+      const int v = threadIdx.x >= o ? s_scan[threadIdx.x - o] : 0;
+      __syncthreads();
+      s_scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    int run = s_scan[threadIdx.x] - loc;
+    for (int i = b; i < e; ++i) {
+      const int c = s_pref[i];
+      s_pref[i] = run;
+      run += c;
+    }
+    if (threadIdx.x == blockDim.x - 1) s_pref[NW] = s_scan[threadIdx.x];
+    __syncthreads();
+  }
+  const int total = s_pref[NW];
+  const int per = (total + gridDim.x - 1) / gridDim.x;
+  const int eb = min(total, (int)blockIdx.x * per), ee = min(total, eb + per);
+  BlockEventStats bst;
+  bst.clear();
+  for (int e0 = eb; e0 < ee; e0 += blockDim.x) {  // block-uniform trip count
+    const int e = e0 + (int)threadIdx.x;
+    const bool want = e < ee;
     EmitEv ev{0, 0.0};
-    if (want) ev = a.qe.ent[e];
+    if (want) {
+      int lo = 0, hi = NW - 1;  // the last wave segment whose prefix is <= e
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pref[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      ev = a.qe.ent[(int64_t)lo * seg_len + (e - s_pref[lo])];
+    }
     const int ii = (int)(ev.key >> 41), sp = (int)((ev.key >> 40) & 1);
     const int64_t k = (int64_t)(ev.key & ((1ull << 40) - 1));
     const qed_instance& I = a.inst[ii];
@@ -655,7 +718,10 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
       }
       S.tau_dev[k] = optical_depth(r[1]);
     }
-    const long long slot = wave_reserve_grouped(child, ii, G.count_dev);
+    int bkey = 0;
+    const bool uni = block_uniform_key(want, ii, s_key, &bkey);  // block-uniform
+    const long long slot = uni ? block_reserve(child, a.inst[bkey].s[2].count_dev, s_wave, &s_base)
+                               : wave_reserve_grouped(child, ii, G.count_dev);
     double dropped_e = 0.0;
     unsigned n_drop = 0;
     if (child) {
@@ -693,8 +759,20 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
         dropped_e = sqrt(ckx * ckx + cky * cky + ckz * ckz);
       }
     }
-    add_event_stats(0, want, ii, a.acc, defect, dropped_e, child ? 1u : 0u, n_null, n_drop);
+    if (uni) {
+      if (bkey != bst.inst && threadIdx.x == 0) {
+        bst.flush(0, a.acc);
+        bst.inst = bkey;
+      }
+      long long ld[4], le[4];
+      fix_split(defect, ld);
+      fix_split(dropped_e, le);
+      bst.add(ld, le, child ? 1u : 0u, n_null, n_drop, s_ll, s_u);
+    } else {
+      add_event_stats(0, want, ii, a.acc, defect, dropped_e, child ? 1u : 0u, n_null, n_drop);
+    }
   }
+  if (threadIdx.x == 0) bst.flush(0, a.acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -923,21 +1001,65 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       if (exists && ((live >> j) & 1u)) ++uacc[4];
       if (exists && in_window(wv[j], step)) gmask |= 1u << j;
     }
-    // phase 2: the photons inside their windows, packed densely across the wave through a
-    // per-wave LDS list (so the in-field code runs on full waves however the photons are
-    // spread); one copy of the in-field code holds registers.  Most waves have none.
-    if (__ballot(gmask != 0) == 0) continue;
+    // phase 2: the photons inside their windows.  A wave with at least half of its slots inside
+    // (the partition at compaction keeps those photons together) evaluates them in place; a
+    // sparser wave first packs its photons densely through a per-wave LDS list, so that the
+    // in-field code runs on full waves however the photons are spread.
+    unsigned total = 0;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) total += (unsigned)__popcll(__ballot((gmask >> j) & 1u));
+    if (total == 0) continue;
     const int lane = threadIdx.x & 63;
+    uacc[3] += __popc(gmask);
+    typedef double dbl2 __attribute__((ext_vector_type(2)));
+    // one photon: its record (one line; the stored values, or the plane-wave phase and chi
+    // factors) and optical depth
+    auto eval = [&](unsigned off) -> bool {
+      const double tau = buf_ld<double>(rtau, off * 8u);
+      if constexpr (FK == QED_FIELD_LP_PULSE) {
+        if (MIXED) {  // {A, S, c}: A in FP64
+          typedef unsigned u4 __attribute__((ext_vector_type(4)));
+          const u4 q = *(gptr<const u4>)(rrec + off);
+          const double A = __hiloint2double((int)q.y, (int)q.x);
+          return infield_pw(off, A, (double)__uint_as_float(q.z), (double)__uint_as_float(q.w), tau);
+        } else {
+          const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
+          const dbl2 q0 = q[0];
+          const double cr = ((gptr<const double>)(rrec + off))[2];
+          return infield_pw(off, q0.x, q0.y, cr, tau);
+        }
+      } else if (MIXED) {
+        typedef float flt4 __attribute__((ext_vector_type(4)));
+        const gptr<const flt4> q = (gptr<const flt4>)(rrec + off);
+        const flt4 q0 = q[0], q1 = q[1];
+        return infield(off, (Real)q0.x, (Real)q0.y, (Real)q0.z, NEED_X ? (Real)q0.w : Real(0),
+                       NEED_Y ? (Real)q1.x : Real(0), NEED_X ? (int32_t)__float_as_uint(q1.y) : 0, tau);
+      } else {
+        const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
+        const dbl2 q0 = q[0], q1 = q[1], q2 = q[2];
+        return infield(off, (Real)q0.x, (Real)q0.y, (Real)q1.x, NEED_X ? (Real)q1.y : Real(0),
+                       NEED_Y ? (Real)q2.x : Real(0), NEED_X ? (int32_t)(uint32_t)__double_as_longlong(q2.y) : 0,
+                       tau);
+      }
+    };
+    if (2 * total >= 64u * PPT) {
+#pragma unroll
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        bool pend = false;
+        if ((gmask >> j) & 1u) pend = eval(off);
+        enqueue(off, pend);
+      }
+      continue;
+    }
     unsigned* list = slist + (threadIdx.x >> 6) * (64 * PPT);
     const int cnt = __popc(gmask);
-    uacc[3] += cnt;
     int incl = cnt;
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const int v = __shfl_up(incl, o);
       if (lane >= o) incl += v;
     }
-    const int total = __shfl(incl, 63);
     int w = incl - cnt;
 #pragma unroll
     for (int j = 0; j < PPT; ++j)
@@ -945,40 +1067,13 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    typedef double dbl2 __attribute__((ext_vector_type(2)));
-    for (int e0 = 0; e0 < total; e0 += 64) {  // wave-uniform trip count
+    for (int e0 = 0; e0 < (int)total; e0 += 64) {  // wave-uniform trip count
       const int e = e0 + lane;
       bool pend = false;
       unsigned off = 0;
-      if (e < total) {
+      if (e < (int)total) {
         off = list[e];
-        // one line per photon: the record holds the stored values exactly
-        const double tau = buf_ld<double>(rtau, off * 8u);
-        if constexpr (FK == QED_FIELD_LP_PULSE) {
-          if (MIXED) {  // {A, S, c}: A in FP64
-            typedef unsigned u4 __attribute__((ext_vector_type(4)));
-            const u4 q = *(gptr<const u4>)(rrec + off);
-            const double A = __hiloint2double((int)q.y, (int)q.x);
-            pend = infield_pw(off, A, (double)__uint_as_float(q.z), (double)__uint_as_float(q.w), tau);
-          } else {
-            const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
-            const dbl2 q0 = q[0];
-            const double cr = ((gptr<const double>)(rrec + off))[2];
-            pend = infield_pw(off, q0.x, q0.y, cr, tau);
-          }
-        } else if (MIXED) {
-          typedef float flt4 __attribute__((ext_vector_type(4)));
-          const gptr<const flt4> q = (gptr<const flt4>)(rrec + off);
-          const flt4 q0 = q[0], q1 = q[1];
-          pend = infield(off, (Real)q0.x, (Real)q0.y, (Real)q0.z, NEED_X ? (Real)q0.w : Real(0),
-                         NEED_Y ? (Real)q1.x : Real(0), NEED_X ? (int32_t)__float_as_uint(q1.y) : 0, tau);
-        } else {
-          const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
-          const dbl2 q0 = q[0], q1 = q[1], q2 = q[2];
-          pend = infield(off, (Real)q0.x, (Real)q0.y, (Real)q1.x, NEED_X ? (Real)q1.y : Real(0),
-                         NEED_Y ? (Real)q2.x : Real(0), NEED_X ? (int32_t)(uint32_t)__double_as_longlong(q2.y) : 0,
-                         tau);
-        }
+        pend = eval(off);
       }
       enqueue(off, pend);
     }
@@ -1556,9 +1651,9 @@ static void launch_lepton_fk(const StepArgs& a, dim3 grid, dim3 block, size_t sh
 #undef QED_LEP
 }
 template <int FK>
-static void launch_emit_events_fk(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s, bool mixed) {
-  if (mixed) hipLaunchKernelGGL((k_emit_events<FK, true>), grid, block, 0, s, a);
-  else hipLaunchKernelGGL((k_emit_events<FK, false>), grid, block, 0, s, a);
+static void launch_emit_events_fk(const StepArgs& a, dim3 grid, dim3 block, size_t shm, hipStream_t s, bool mixed) {
+  if (mixed) hipLaunchKernelGGL((k_emit_events<FK, true>), grid, block, shm, s, a);
+  else hipLaunchKernelGGL((k_emit_events<FK, false>), grid, block, shm, s, a);
 }
 template <int FK>
 static void launch_pair_events_fk(const StepArgs& a, dim3 grid, dim3 block, hipStream_t s, bool mixed) {
@@ -1598,12 +1693,13 @@ void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob,
 
 void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
   const dim3 g(grid), b(block);
+  const size_t shm = ((size_t)a.qe.grid * a.qe.waves + 1) * sizeof(int);  // prefix of the per-wave counts
   switch (fk) {
-    case QED_FIELD_UNIFORM: launch_emit_events_fk<QED_FIELD_UNIFORM>(a, g, b, s, mixed); break;
-    case QED_FIELD_LP_PULSE: launch_emit_events_fk<QED_FIELD_LP_PULSE>(a, g, b, s, mixed); break;
-    case QED_FIELD_CP_WAVE: launch_emit_events_fk<QED_FIELD_CP_WAVE>(a, g, b, s, mixed); break;
-    case QED_FIELD_CP_STANDING: launch_emit_events_fk<QED_FIELD_CP_STANDING>(a, g, b, s, mixed); break;
-    default: launch_emit_events_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, s, mixed); break;
+    case QED_FIELD_UNIFORM: launch_emit_events_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_LP_PULSE: launch_emit_events_fk<QED_FIELD_LP_PULSE>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_CP_WAVE: launch_emit_events_fk<QED_FIELD_CP_WAVE>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_CP_STANDING: launch_emit_events_fk<QED_FIELD_CP_STANDING>(a, g, b, shm, s, mixed); break;
+    default: launch_emit_events_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, shm, s, mixed); break;
   }
 }
 

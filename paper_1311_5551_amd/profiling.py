@@ -3,6 +3,7 @@ one kernel over a window of its dispatches: the bench's timed region is the last
 of a kernel in the profiled bench command.
 
   python -m paper_1311_5551_amd.profiling trace   --csv T --kernel NAME --last N
+  python -m paper_1311_5551_amd.profiling counters --csv C --kernel NAME --last N
   python -m paper_1311_5551_amd.profiling traffic --fetch F --write W --copy-fetch CF --copy-write CW \\
          --kernel NAME --last N [--out JSON --source-hash H --bench-window A..B]
 
@@ -43,6 +44,22 @@ def counter_window(path: str, counter: str, kernel: str, last: int) -> dict:
     return {"counter": counter, "window": len(win), "mean": statistics.mean(v) if v else 0.0}
 
 
+def counters_window(path: str, kernel: str, last: int) -> dict:
+    """Mean per dispatch of every counter in a counter-collection CSV over the last `last`
+    dispatches of `kernel`."""
+    rows = [r for r in _rows(path) if kernel in r["Kernel_Name"]]
+    ids = sorted(set(int(r["Dispatch_Id"]) for r in rows))
+    keep = set(ids[-last:] if last else ids)
+    out = {"kernel": rows[0]["Kernel_Name"] if rows else kernel, "dispatches_total": len(ids), "window": len(keep)}
+    acc = {}
+    for r in rows:
+        if int(r["Dispatch_Id"]) in keep:
+            acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+    for k, v in sorted(acc.items()):
+        out[k] = sum(v) / len(keep)
+    return out
+
+
 def copy_factor(path: str, counter: str, bytes_per_copy: int, kernel: str = "copyBuffer") -> float:
     """Counter reading (KiB) per true byte of a plain copy: mean over the copy dispatches / size."""
     c = counter_window(path, counter, kernel, 0)
@@ -56,6 +73,10 @@ def main(argv=None):
     t.add_argument("--csv", required=True)
     t.add_argument("--kernel", required=True)
     t.add_argument("--last", type=int, default=0)
+    q = sub.add_parser("counters")
+    q.add_argument("--csv", required=True)
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--last", type=int, default=0)
     c = sub.add_parser("traffic")
     for k in ("--fetch", "--write", "--copy-fetch", "--copy-write", "--kernel"):
         c.add_argument(k, required=True)
@@ -68,6 +89,9 @@ def main(argv=None):
     a = ap.parse_args(argv)
     if a.cmd == "trace":
         print(json.dumps(trace_window(a.csv, a.kernel, a.last), indent=1))
+        return
+    if a.cmd == "counters":
+        print(json.dumps(counters_window(a.csv, a.kernel, a.last), indent=1))
         return
     ff = copy_factor(a.copy_fetch, "FETCH_SIZE", a.copy_bytes, a.copy_kernel)
     fw = copy_factor(a.copy_write, "WRITE_SIZE", a.copy_bytes, a.copy_kernel)
