@@ -109,6 +109,13 @@ def lib():
         L.oracle_build_tables.restype = C.c_int
         L.oracle_run.argtypes = [C.POINTER(_Config), C.POINTER(_Tables), C.POINTER(_Species),
                                  C.POINTER(_Species), C.POINTER(_Ledger)]
+        L.oracle_fields.argtypes = [C.POINTER(_Config)] + [C.c_double] * 4 + [_DP, _DP]
+        L.oracle_fields.restype = None
+        L.oracle_grid_gather.argtypes = [C.POINTER(_Config), C.c_int, _DP, C.c_double, C.c_double]
+        L.oracle_grid_gather.restype = C.c_double
+        for name in ("oracle_eta", "oracle_chi"):
+            getattr(L, name).argtypes = [C.POINTER(_Config)] + [C.c_double] * 7
+            getattr(L, name).restype = C.c_double
         L.oracle_run.restype = C.c_int
         L.oracle_num_threads.restype = C.c_int
         _LIB = L
@@ -270,6 +277,62 @@ def _species_in(d):
     return s, keep
 
 
+def _config(cfg: RunConfig) -> _Config:
+    conf = _Config()
+    conf.field_kind = cfg.field_kind
+    fp = list(cfg.field) + [0.0] * (16 - len(cfg.field))
+    conf.field = (C.c_double * 16)(*fp)
+    conf.grid_nx, conf.grid_ny, conf.grid_dx, conf.grid_dy, conf.grid_x0, conf.grid_y0 = cfg.grid
+    conf.dims = cfg.dims
+    conf.dt = cfg.dt
+    conf.t0 = cfg.t0
+    conf.step0 = cfg.step0
+    conf.n_steps = cfg.n_steps
+    conf.seed = cfg.seed
+    conf.instance = cfg.instance
+    conf.flags = cfg.flags
+    conf.draw_initial_tau = 1 if cfg.draw_initial_tau else 0
+    conf.lambda_L = cfg.lambda_L
+    return conf
+
+
+def fields(cfg: RunConfig, x, y, z, t):
+    """E and B (code units) that the step of `cfg` sees at the points (x, y, z) and times t
+    (broadcast); arrays of shape (..., 3)."""
+    conf = _config(cfg)
+    b = np.broadcast_arrays(*[np.asarray(a, dtype=np.float64) for a in (x, y, z, t)])
+    E = np.empty(b[0].shape + (3,))
+    B = np.empty(b[0].shape + (3,))
+    e3, b3 = np.empty(3), np.empty(3)
+    for idx in np.ndindex(b[0].shape):
+        lib().oracle_fields(C.byref(conf), *[float(a[idx]) for a in b], e3.ctypes.data_as(_DP),
+                            b3.ctypes.data_as(_DP))
+        E[idx] = e3
+        B[idx] = b3
+    return E, B
+
+
+def grid_gather(cfg: RunConfig, comp: int, nodes, x, y):
+    """First-order gather of component `comp` (0..5: Ex, Ey, Ez, Bx, By, Bz) of the grid of `cfg`
+    from the node values `nodes` (ny x nx, that component's staggered grid) at (x, y)."""
+    conf = _config(cfg)
+    n = np.ascontiguousarray(nodes, dtype=np.float64)
+    assert n.shape == (cfg.grid[1], cfg.grid[0])
+    return _vec(lambda a, b: lib().oracle_grid_gather(C.byref(conf), int(comp), n.ctypes.data_as(_DP), a, b), x, y)
+
+
+def eta(cfg: RunConfig, x, y, z, t, ux, uy, uz):
+    """eta of a lepton with momentum u at (x, y, z, t) in the fields of `cfg` (eq. 1)."""
+    conf = _config(cfg)
+    return _vec(lambda *a: lib().oracle_eta(C.byref(conf), *a), x, y, z, t, ux, uy, uz)
+
+
+def chi(cfg: RunConfig, x, y, z, t, kx, ky, kz):
+    """chi of a photon with momentum k at (x, y, z, t) in the fields of `cfg` (eq. 1)."""
+    conf = _config(cfg)
+    return _vec(lambda *a: lib().oracle_chi(C.byref(conf), *a), x, y, z, t, kx, ky, kz)
+
+
 def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=None, capacity=None):
     """Advance every family rooted at the given particles; return (species dict, ledger dict).
 
@@ -296,21 +359,7 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
     if tables.get("g") is not None:
         g_arr = np.ascontiguousarray(tables["g"], dtype=np.float64)  # held for the call
         tab.g = g_arr.ctypes.data_as(_DP)
-    conf = _Config()
-    conf.field_kind = cfg.field_kind
-    fp = list(cfg.field) + [0.0] * (16 - len(cfg.field))
-    conf.field = (C.c_double * 16)(*fp)
-    conf.grid_nx, conf.grid_ny, conf.grid_dx, conf.grid_dy, conf.grid_x0, conf.grid_y0 = cfg.grid
-    conf.dims = cfg.dims
-    conf.dt = cfg.dt
-    conf.t0 = cfg.t0
-    conf.step0 = cfg.step0
-    conf.n_steps = cfg.n_steps
-    conf.seed = cfg.seed
-    conf.instance = cfg.instance
-    conf.flags = cfg.flags
-    conf.draw_initial_tau = 1 if cfg.draw_initial_tau else 0
-    conf.lambda_L = cfg.lambda_L
+    conf = _config(cfg)
 
     ins = (_Species * 3)()
     keep = []

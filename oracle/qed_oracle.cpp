@@ -719,6 +719,21 @@ int64_t wrap(int64_t i, int n) {
   return r < 0 ? r + n : r;
 }
 
+// first-order (cloud-in-cell) gather of component comp at (x, y): bilinear weights over the four
+// nodes around the point on that component's staggered grid; node(i, j) gives a node's value
+template <class NodeFn>
+double cic_gather(const Grid& g, int comp, double x, double y, NodeFn node) {
+  const double gx = (x - g.x0) / g.dx - kYeeOx[comp];
+  const double gy = (y - g.y0) / g.dy - kYeeOy[comp];
+  const double fx = std::floor(gx), fy = std::floor(gy);
+  const double wx = gx - fx, wy = gy - fy;
+  const int64_t i0 = (int64_t)fx, j0 = (int64_t)fy;
+  const int64_t ia = wrap(i0, g.nx), ib = wrap(i0 + 1, g.nx);
+  const int64_t ja = wrap(j0, g.ny), jb = wrap(j0 + 1, g.ny);
+  return (1.0 - wx) * (1.0 - wy) * node(ia, ja) + wx * (1.0 - wy) * node(ib, ja) + (1.0 - wx) * wy * node(ia, jb) +
+         wx * wy * node(ib, jb);
+}
+
 void fields_at(const Config& c, double x, double y, double z, double t, Vec3* E, Vec3* B) {
   double f[6] = {0, 0, 0, 0, 0, 0};
   switch (c.field) {
@@ -749,18 +764,8 @@ void fields_at(const Config& c, double x, double y, double z, double t, Vec3* E,
       break;
     case FIELD_GRID_CP_STANDING: {
       // first-order (cloud-in-cell) gather from each staggered component grid
-      for (int comp = 0; comp < 6; ++comp) {
-        const double gx = (x - c.grid.x0) / c.grid.dx - kYeeOx[comp];
-        const double gy = (y - c.grid.y0) / c.grid.dy - kYeeOy[comp];
-        const double fx = std::floor(gx), fy = std::floor(gy);
-        const double wx = gx - fx, wy = gy - fy;
-        const int64_t i0 = (int64_t)fx, j0 = (int64_t)fy;
-        const int64_t ia = wrap(i0, c.grid.nx), ib = wrap(i0 + 1, c.grid.nx);
-        const int64_t ja = wrap(j0, c.grid.ny), jb = wrap(j0 + 1, c.grid.ny);
-        f[comp] = (1.0 - wx) * (1.0 - wy) * grid_node(c, comp, ia, ja, t) +
-                  wx * (1.0 - wy) * grid_node(c, comp, ib, ja, t) +
-                  (1.0 - wx) * wy * grid_node(c, comp, ia, jb, t) + wx * wy * grid_node(c, comp, ib, jb, t);
-      }
+      for (int comp = 0; comp < 6; ++comp)
+        f[comp] = cic_gather(c.grid, comp, x, y, [&](int64_t i, int64_t j) { return grid_node(c, comp, i, j, t); });
       break;
     }
     default:
@@ -908,6 +913,22 @@ void draw(const Config& c, uint64_t uid, int64_t step, uint64_t kind, uint64_t s
 
 double gamma_of(double ux, double uy, double uz) { return std::sqrt(1.0 + ux * ux + uy * uy + uz * uz); }
 
+// eta = |F_{mu nu} p^nu| / (m c E_s) = sqrt(|gamma E + u x B|^2 - (u.E)^2) of a lepton with
+// momentum u (gamma = g) in the fields E, B (Sec. 2.1, eq. 1)
+double eta_of(Vec3 E, Vec3 B, Vec3 u, double g) {
+  const Vec3 a = g * E + cross(u, B);
+  const double ue = dot(u, E);
+  return std::sqrt(std::max(0.0, dot(a, a) - ue * ue));
+}
+
+// chi = (eps/2) sqrt(|E + n x B|^2 - (n.E)^2) of a photon with momentum k = eps n (the chi of
+// eq. 1, half the usual chi_gamma)
+double chi_of(Vec3 E, Vec3 B, Vec3 nh, double eps) {
+  const Vec3 a = E + cross(nh, B);
+  const double ne = dot(nh, E);
+  return 0.5 * eps * std::sqrt(std::max(0.0, dot(a, a) - ne * ne));
+}
+
 // one step of an electron (q = -1) or positron (q = +1); children are appended to `fam`
 void step_lepton(Particle& p, const Config& c, const Tables& tb, int64_t n, std::vector<Particle>& fam,
                  Tally& tl) {
@@ -941,9 +962,7 @@ void step_lepton(Particle& p, const Config& c, const Tables& tb, int64_t n, std:
     // continuous radiation reaction: the lepton loses the radiated power P_c g(eta)
     // (eqs. 8 and 9 with Appendix A's g; g = 1 for the classical power) over dt,
     // dgamma = -(2/3) alpha kappa eta^2 g dt, along its momentum and never below rest
-    const Vec3 a = g1 * E + cross(u1, B);
-    const double ue = dot(u1, E);
-    const double eta = std::sqrt(std::max(0.0, dot(a, a) - ue * ue));
+    const double eta = eta_of(E, B, u1, g1);
     if (eta > 0.0) {
       const double gfac = (c.flags & FLAG_RR_QUANTUM) ? lookup_g(tb, eta, &tl.n_range) : 1.0;
       const double g2 = std::max(g1 - c.a_rr * eta * eta * gfac * c.dt, 1.0);
@@ -957,10 +976,7 @@ void step_lepton(Particle& p, const Config& c, const Tables& tb, int64_t n, std:
   }
 
   if (c.flags & FLAG_EMIT) {
-    // eta = |F_{mu nu} p^nu| / (m c E_s) = sqrt(|gamma E + u x B|^2 - (u.E)^2)
-    const Vec3 a = g1 * E + cross(u1, B);
-    const double ue = dot(u1, E);
-    const double eta = std::sqrt(std::max(0.0, dot(a, a) - ue * ue));
+    const double eta = eta_of(E, B, u1, g1);
     if (eta > 0.0) {
       const double h = lookup_h(tb, eta, &tl.n_range);
       p.tau -= c.a_gamma * (eta / g1) * h * c.dt;  // first-order Euler in the optical depth
@@ -1018,10 +1034,7 @@ void step_photon(Particle& p, const Config& c, const Tables& tb, int64_t n, std:
   Vec3 E, B;
   fields_at(c, xn.x, xn.y, xn.z, t, &E, &B);
   if (c.flags & FLAG_PAIRS) {
-    // chi = (eps/2) sqrt(|E + n x B|^2 - (n.E)^2)
-    const Vec3 a = E + cross(nh, B);
-    const double ne = dot(nh, E);
-    const double chi = 0.5 * eps * std::sqrt(std::max(0.0, dot(a, a) - ne * ne));
+    const double chi = chi_of(E, B, nh, eps);
     const double T = lookup_T(tb, chi, &tl.n_range);
     if (T > 0.0) {
       p.tau -= c.a_pair * chi * T / eps * c.dt;
@@ -1127,8 +1140,7 @@ typedef struct {
 // first move in the following step.  Outputs are written family by family in input
 // order, each family in creation order.  Returns -1 if an output array is too small
 // (the counts then hold the required sizes).
-int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_species* in,
-               oracle_species* out, oracle_ledger* led) {
+static Config config_of(const oracle_config* cfg) {
   Config c;
   c.field = cfg->field_kind;
   std::memcpy(c.fp, cfg->field, sizeof(c.fp));
@@ -1145,6 +1157,50 @@ int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_
   c.a_gamma = std::sqrt(3.0) * kAlpha * c.kappa / (2.0 * kPi);
   c.a_pair = kAlpha * c.kappa;
   c.a_rr = 2.0 / 3.0 * kAlpha * c.kappa;
+  return c;
+}
+
+// The fields of the configuration at (x, y, z, t) (Sec. 3.2: the fields the step sees), and the
+// eta of a lepton / chi of a photon with the given momentum there.
+void oracle_fields(const oracle_config* cfg, double x, double y, double z, double t, double* E, double* B) {
+  const Config c = config_of(cfg);
+  Vec3 e, b;
+  fields_at(c, x, y, z, t, &e, &b);
+  E[0] = e.x;
+  E[1] = e.y;
+  E[2] = e.z;
+  B[0] = b.x;
+  B[1] = b.y;
+  B[2] = b.z;
+}
+
+// The gather of the configuration's grid for component comp from caller-given node values
+// (nodes[j * nx + i], the component's own staggered grid), at (x, y).
+double oracle_grid_gather(const oracle_config* cfg, int comp, const double* nodes, double x, double y) {
+  const Config c = config_of(cfg);
+  return cic_gather(c.grid, comp, x, y, [&](int64_t i, int64_t j) { return nodes[j * c.grid.nx + i]; });
+}
+
+double oracle_eta(const oracle_config* cfg, double x, double y, double z, double t, double ux, double uy,
+                  double uz) {
+  const Config c = config_of(cfg);
+  Vec3 E, B;
+  fields_at(c, x, y, z, t, &E, &B);
+  return eta_of(E, B, {ux, uy, uz}, gamma_of(ux, uy, uz));
+}
+
+double oracle_chi(const oracle_config* cfg, double x, double y, double z, double t, double kx, double ky,
+                  double kz) {
+  const Config c = config_of(cfg);
+  Vec3 E, B;
+  fields_at(c, x, y, z, t, &E, &B);
+  const double eps = std::sqrt(kx * kx + ky * ky + kz * kz);
+  return chi_of(E, B, {kx / eps, ky / eps, kz / eps}, eps);
+}
+
+int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_species* in,
+               oracle_species* out, oracle_ledger* led) {
+  const Config c = config_of(cfg);
   if ((c.flags & FLAG_RR_QUANTUM) && (c.flags & FLAG_RR_CLASSICAL)) return -2;
   if ((c.flags & (FLAG_RR_QUANTUM | FLAG_RR_CLASSICAL)) && (c.flags & FLAG_EMIT)) return -2;
   if ((c.flags & FLAG_RR_QUANTUM) && !tab->g) return -2;
