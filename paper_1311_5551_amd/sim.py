@@ -257,16 +257,6 @@ class Run:
         the whole state of the run."""
         return [{name: self.species(i, name, live_only=False) for name in SPECIES} for i in range(len(self.insts))]
 
-    def photon_positions(self, ph: dict, step: int) -> dict:
-        """Positions of photons at the start of `step`: x_b + (step - b) dt k/|k|."""
-        k = np.stack([ph["ux"], ph["uy"], ph["uz"]])
-        nrm = k / np.sqrt((k * k).sum(0))
-        age = (step - ph["birth_step"].astype(np.float64)) * self.dt
-        out = {"x": ph["x"] + age * nrm[0], "y": ph["y"] + age * nrm[1]}
-        if "z" in ph:
-            out["z"] = ph["z"] + age * nrm[2]
-        return out
-
     def close(self):
         if getattr(self, "ws", None):
             capi.qed_workspace_destroy(self.ws)

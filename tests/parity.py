@@ -42,10 +42,11 @@ TAU_TOL = 1e-10
 STRADDLE = 1e-9
 
 
-def oracle_run(w, tables, electrons=None, photons=None):
+def oracle_run(w, tables, electrons=None, photons=None, capacity=None):
     cfg = oracle.RunConfig(field_kind=w.field_kind, field=w.field, dt=w.dt, n_steps=w.n_steps, flags=w.flags,
                            seed=w.seed, instance=w.instance, dims=w.dims, grid=w.grid, t0=w.t0)
-    return oracle.run(cfg, tables, electrons=electrons if electrons is not None else w.electrons, photons=photons)
+    return oracle.run(cfg, tables, electrons=electrons if electrons is not None else w.electrons, photons=photons,
+                      capacity=capacity)
 
 
 def match(a_uid, b_uid):

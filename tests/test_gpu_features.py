@@ -160,15 +160,17 @@ def test_graph_replay_matches_plain_launches(shared_tables):
         assert la[k] == lb[k]
 
 
+@pytest.mark.parametrize("precision", [capi.QED_FP64, capi.QED_FP32_MIXED])
 @pytest.mark.parametrize("compact", [False, True])
-def test_batched_instances_equal_single_runs(compact, shared_tables):
+def test_batched_instances_equal_single_runs(compact, precision, shared_tables):
     # compact=True: the batched run compacts every 100 steps, which also summarises each
     # instance's photon slot groups (the sweep then skips groups outside their pair windows);
-    # the single runs never compact
+    # the single runs never compact.  Both precisions: the FP32-mixed batched form of
+    # configuration 5 equals its single runs bit for bit
     ws = [W.collision(n, a0=a0, gamma_mean=g0, n_steps=2400, meet_step=1200, seed=1, instance=i, uid0=0)
           for i, (n, a0, g0) in enumerate([(1000, 200.0, 2000.0), (17, 450.0, 800.0), (3001, 60.0, 4500.0),
                                            (1, 300.0, 1500.0), (650, 120.0, 3000.0)])]
-    rb = Run(ws, shared_tables)
+    rb = Run(ws, shared_tables, precision=precision)
     if compact:
         for _ in range(24):
             rb.step(100)
@@ -177,7 +179,7 @@ def test_batched_instances_equal_single_runs(compact, shared_tables):
     else:
         rb.step(2400)
     for i, w in enumerate(ws):
-        rs = Run(w, shared_tables)
+        rs = Run(w, shared_tables, precision=precision)
         rs.step(2400)
         _states_equal(rb, rs, ia=i, ib=0)
         lb, ls = rb.ledger()[i], rs.ledger()[0]
@@ -390,3 +392,126 @@ def test_ledger_is_independent_of_launch_shape(flags, shared_tables):
         assert leds[0]["n_pair"] > 0 and leds[0]["defect_emit"] != 0.0
     for r in runs[1:]:
         _states_equal(runs[0], r)
+
+
+def _photon_energies(ph):
+    return np.sqrt(ph["ux"] ** 2 + ph["uy"] ** 2 + ph["uz"] ** 2)
+
+
+def _ensemble_errors(g, o, n_electrons, bins=np.logspace(-3, 4, 65), min_count=10000):
+    """Ensemble errors of an FP32-mixed run against the FP64 oracle on the same random streams.
+
+    The two sides reproduce almost every particle per uid; the rest belong to families in which
+    FP32 rounding moved an event by a step, after which the family is a different Monte-Carlo
+    realisation.  Those particles make sampling noise, not a precision bias, so each error is
+    returned with the 3-sigma noise that the particles not reproduced per uid can make: a bin's
+    photons, and the electrons whose final energy differs."""
+    eg, eo = _photon_energies(g["photon"]), _photon_energies(o["photon"])
+    hg, ho = np.histogram(eg, bins)[0], np.histogram(eo, bins)[0]
+    ug = np.histogram(eg[~np.isin(g["photon"]["uid"], o["photon"]["uid"])], bins)[0]
+    uo = np.histogram(eo[~np.isin(o["photon"]["uid"], g["photon"]["uid"])], bins)[0]
+    sel = ho >= min_count
+    spec_rel = np.abs(hg[sel] - ho[sel]) / ho[sel]
+    spec_noise = 3.0 * np.sqrt(ug[sel] + uo[sel]) / ho[sel]
+    ge = np.sqrt(1 + g["electron"]["ux"] ** 2 + g["electron"]["uy"] ** 2 + g["electron"]["uz"] ** 2)
+    oe = np.sqrt(1 + o["electron"]["ux"] ** 2 + o["electron"]["uy"] ** 2 + o["electron"]["uz"] ** 2)
+    common, ig, io = np.intersect1d(g["electron"]["uid"], o["electron"]["uid"], return_indices=True)
+    differs = np.abs(ge[ig] - oe[io]) > 1e-3 * oe[io]  # FP32 rounding alone moves gamma by ~1e-5
+    n_div = int(differs.sum()) + (len(ge) - len(common)) + (len(oe) - len(common))
+    loss_noise = 3.0 * np.std(oe) * np.sqrt(2.0 * n_div) / n_electrons
+    return dict(bins_used=int(sel.sum()), spectrum_rel_err_max=float(spec_rel.max()) if sel.any() else 0.0,
+                spectrum_excess_max=float(np.max(spec_rel - spec_noise)) if sel.any() else 0.0,
+                electrons_diverged=n_div, loss_noise=float(loss_noise))
+
+
+def test_fp32_mixed_against_fp64_oracle(shared_tables, oracle_tables):
+    # configuration 4 (the precision form of the collision) against the FP64 oracle on the same
+    # electrons and random streams: per-bin photon spectrum (64 log bins on [1e-3, 1e4]), mean
+    # energy loss of the electrons, pair yield, the fraction of oracle particles reproduced per uid,
+    # and the ledger closure.  The oracle's tables are loaded, so only precision separates them.
+    n, steps = 10000, 2600
+    w = W.collision(n, n_steps=steps, meet_step=steps // 2, seed=31)
+    r32 = Run(w, shared_tables, precision=capi.QED_FP32_MIXED)
+    for _ in range(steps // 100):
+        r32.step(100)
+        r32.compact()
+    l32 = r32.ledger()[0]
+    print("[fp32 vs oracle] GPU run done; oracle on %d electrons x %d steps" % (n, steps), flush=True)
+    o_res, o_led = oracle_run(w, oracle_tables, capacity=[4 * n, 2 * n, 200 * n])
+    print("[fp32 vs oracle] oracle done", flush=True)
+    assert l32["status"] == "QED_OK"
+    g = {name: r32.species(0, name) for name in ("electron", "positron", "photon")}
+    from scipy import stats
+    p_ks = stats.ks_2samp(_photon_energies(g["photon"]), _photon_energies(o_res["photon"])).pvalue
+    g0 = o_led["energy0"][0] / n
+    loss_o = g0 - o_led["energy"][0] / n
+    loss_g = l32["energy0"] / n - l32["energy"][0] / n
+    uid_match = {name: float(np.mean(np.isin(o_res[name]["uid"], g[name]["uid"]))) for name in g}
+    rec = _ensemble_errors(g, o_res, n)
+    rec.update(ks_p=float(p_ks), energy_loss_oracle=loss_o, energy_loss_rel_err=abs(loss_g - loss_o) / loss_o,
+               pair_yield_oracle=o_led["n_pair"] / n, pair_yield_fp32=l32["n_pair"] / n,
+               photons_oracle=len(o_res["photon"]["uid"]), photons_fp32=len(g["photon"]["uid"]),
+               uid_reproduced=uid_match, drift_32=l32["drift"])
+    record("fp32_mixed_vs_oracle", rec)
+    assert rec["bins_used"] >= 10
+    assert rec["spectrum_excess_max"] <= 1e-3          # per bin: 1e-3 beyond the diverged families' noise
+    assert p_ks > 0.01
+    assert rec["energy_loss_rel_err"] <= 1e-3 + rec["loss_noise"] / loss_o
+    assert abs(l32["n_pair"] - o_led["n_pair"]) <= 0.05 * o_led["n_pair"] + 3
+    assert uid_match["photon"] > 0.99
+    assert l32["drift"] <= 1e-9
+
+
+def _c5_like_instances(n_steps=2400):
+    # a spread of configuration 5's instance parameters: counts, a0 and gamma0 from its ranges
+    return [W.collision(nn, a0=a0, gamma_mean=g0, n_steps=n_steps, meet_step=n_steps // 2, seed=1, instance=i)
+            for i, (nn, a0, g0) in enumerate([(1000, 480.0, 600.0), (2500, 60.0, 4800.0), (1, 250.0, 2000.0),
+                                              (1800, 300.0, 1200.0), (700, 150.0, 3500.0)])]
+
+
+@pytest.mark.parametrize("precision", [capi.QED_FP64, capi.QED_FP32_MIXED])
+def test_batched_instances_against_oracle(precision, shared_tables, oracle_tables):
+    # configuration 5's batched form (several instances of uneven sizes in one launch, compaction
+    # every 100 steps) against the oracle instance by instance: FP64 per uid at the strict bars,
+    # FP32-mixed by the ensemble bars of the precision form
+    ws = _c5_like_instances()
+    rb = Run(ws, shared_tables, precision=precision)
+    for _ in range(ws[0].n_steps // 100):
+        rb.step(100)
+        rb.compact()
+    leds = rb.ledger()
+    summary = {}
+    for i, w in enumerate(ws):
+        o_res, o_led = oracle_run(w, oracle_tables, capacity=[4 * w.n + 64, 2 * w.n + 64, 300 * w.n + 1024])
+        print("[batched vs oracle] instance %d: oracle done" % i, flush=True)
+        assert leds[i]["status"] == "QED_OK"
+        if precision == capi.QED_FP64:
+            for name in ("electron", "positron", "photon"):
+                rep = compare_species(rb.species(i, name), o_res[name], photon=name == "photon")
+                flagged = (o_res[name]["margin"] < 1e-9).any()
+                assert flagged or (len(rep["only_gpu"]) == 0 and len(rep["only_oracle"]) == 0), (i, name)
+                assert (rep["u_err"] <= 1e-10).all() and (rep["e_err"] <= 1e-12).all(), (i, name)
+                assert (rep["tau_err"] <= 1e-10).all(), (i, name)
+                summary["%d_%s_u_err_max" % (i, name)] = float(rep["u_err"].max(initial=0.0))
+            assert leds[i]["n_emit"] == o_led["n_emit"] and leds[i]["n_pair"] == o_led["n_pair"]
+        else:
+            # mean electron energy at the end (the pulse may still be on the beam, so the mean loss
+            # can be small or of either sign; the energy is the well-defined ensemble number)
+            e_o, e_g = o_led["energy"][0] / w.n, leds[i]["energy"][0] / w.n
+            loss_o = o_led["energy0"][0] / w.n - e_o
+            loss_g = leds[i]["energy0"] / w.n - e_g
+            g = {name: rb.species(i, name) for name in ("electron", "positron", "photon")}
+            ph_match = float(np.mean(np.isin(o_res["photon"]["uid"], g["photon"]["uid"])))
+            ens = _ensemble_errors(g, o_res, w.n, min_count=1000)
+            summary[i] = dict(energy_rel_err=abs(e_g - e_o) / e_o, loss_oracle=loss_o, loss_fp32=loss_g,
+                              loss_noise=ens["loss_noise"] / e_o,
+                              spectrum_rel_err_max=ens["spectrum_rel_err_max"],
+                              spectrum_excess_max=ens["spectrum_excess_max"],
+                              photons=(leds[i]["count"][2], o_led["count"][2]),
+                              pairs=(leds[i]["n_pair"], o_led["n_pair"]), uid_reproduced=ph_match)
+            if w.n >= 500:
+                assert summary[i]["energy_rel_err"] <= 1e-3 + summary[i]["loss_noise"], (i, summary[i])
+                assert summary[i]["spectrum_excess_max"] <= 1e-3, (i, summary[i])
+                assert ph_match > 0.98, (i, summary[i])
+            assert leds[i]["drift"] <= 1e-9
+    record("batched_vs_oracle_%s" % ("fp64" if precision == capi.QED_FP64 else "fp32"), summary)
