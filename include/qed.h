@@ -223,6 +223,16 @@ qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_p
  * (QED_ERR_ARG beyond).  Instances with analytic fields are left as they are. */
 qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream stream);
 
+/* qed_sort without allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same reordering, with its
+ * scratch (tile keys, destination slots, staging, tile histogram) in a fixed array of 32.25 MB
+ * that the library holds in device memory on every GPU it runs on until the process ends.
+ * Species of up to 2^21 slots (capacity) and grids of up to 2^16 tiles of 8 x 8 cells; larger
+ * ones return QED_ERR_ARG before anything is enqueued.  Async on `stream`; never allocates.
+ * All calls on one GPU share that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads, other workspaces) race and must be ordered by the caller. */
+qed_status qed_sort_static(qed_workspace* ws, const qed_step_params* params, qed_stream stream);
+
 /* Removes dead photons (tau < 0) from every bound photon species by moving live photons from
  * the tail into the holes (order is not preserved), then rebuilds the summary windows of the
  * photon slot groups (from the last summarised group on where nothing was removed).  Call it

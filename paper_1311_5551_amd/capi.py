@@ -96,6 +96,7 @@ _SIGNATURES = {
     "qed_run": (C.c_int, [_vp, _vp, C.POINTER(qed_step_params), C.c_int64, C.c_int32, _vp]),
     "qed_compact": (C.c_int, [_vp, _vp]),
     "qed_sort": (C.c_int, [_vp, C.POINTER(qed_step_params), _vp]),
+    "qed_sort_static": (C.c_int, [_vp, C.POINTER(qed_step_params), _vp]),
     "qed_energy_ledger": (C.c_int, [_vp, C.POINTER(qed_ledger), _vp]),
     "qed_profile": (C.c_int, [_vp, C.c_int32]),
     "qed_profile_read": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
@@ -206,6 +207,10 @@ def qed_run(tables, ws, params: qed_step_params, n_steps: int, graph_steps: int 
 
 def qed_sort(ws, params: qed_step_params, stream=None):
     return check(lib().qed_sort(ws, C.byref(params), stream))
+
+
+def qed_sort_static(ws, params: qed_step_params, stream=None):
+    return check(lib().qed_sort_static(ws, C.byref(params), stream))
 
 
 def qed_compact(ws, stream=None):

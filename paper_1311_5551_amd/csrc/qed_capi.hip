@@ -876,6 +876,43 @@ qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream
   return QED_OK;
 }
 
+qed_status qed_sort_static(qed_workspace* ws, const qed_step_params* params, qed_stream stream) {
+  if (!ws || !params) return fail(QED_ERR_ARG, "NULL argument");
+  if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
+  if (!(params->dt > 0.0) || !std::isfinite(params->dt)) return fail(QED_ERR_ARG, "dt must be positive");
+  int64_t cap = 0;
+  int tiles = 0;
+  for (const qed_instance& I : ws->inst) {
+    if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    for (int s = 0; s < 3; ++s) cap = std::max<int64_t>(cap, I.s[s].capacity);
+    tiles = std::max(tiles, ((I.field.nx + 7) / 8) * ((I.field.ny + 7) / 8));
+  }
+  if (cap == 0) return QED_OK;
+  if (cap > kStaticSortSlots)
+    return fail(QED_ERR_ARG, "qed_sort_static handles species of up to %lld slots (capacity %lld here); use qed_sort",
+                (long long)kStaticSortSlots, (long long)cap);
+  if (tiles > kStaticSortTiles)
+    return fail(QED_ERR_ARG, "qed_sort_static handles grids of up to %d tiles of 8 x 8 cells (%d here); use qed_sort",
+                kStaticSortTiles, tiles);
+  int cur = 0;
+  HIP_TRY(hipGetDevice(&cur));
+  if (cur != ws->device) return fail(QED_ERR_STATE, "workspace belongs to device %d, current is %d", ws->device, cur);
+  SortScratch w;
+  HIP_TRY(static_sort_scratch(&w));
+  const bool mixed = ws->prec == QED_FP32_MIXED;
+  for (int ii = 0; ii < ws->n_inst; ++ii) {
+    const qed_instance& I = ws->inst[ii];
+    if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    for (int s = 0; s < 3; ++s) {
+      if (I.s[s].capacity == 0) continue;
+      HIP_TRY(launch_sort_species(ws->d_inst, I, ii, s, ws->d_glob, params->dt, mixed, w, ws->cus * 8,
+                                  (hipStream_t)stream));
+    }
+  }
+  ws->win_valid = false;
+  return QED_OK;
+}
+
 qed_status qed_set_event_queue(qed_workspace* ws, int64_t capacity) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (capacity < 1 || capacity > (int64_t(1) << 32))

@@ -33,6 +33,14 @@ struct SortScratch {
   void* stage = nullptr;  // 8 bytes per slot
 };
 
+// the fixed scratch of qed_sort_static: up to 2^21 slots per species and 2^16 tiles of 8 x 8 cells
+constexpr int64_t kStaticSortSlots = int64_t(1) << 21;
+constexpr int kStaticSortTiles = 1 << 16;
+constexpr size_t kStaticSortBytes = (size_t)kStaticSortSlots * 16 + (size_t)kStaticSortTiles * 4;
+constexpr int kMaxDevices = 64;
+// the device address of that scratch on the current device, split into the sort's arrays
+hipError_t static_sort_scratch(SortScratch* out);
+
 hipError_t init_crmath();
 hipError_t launch_sort_species(const qed_instance* inst_dev, const qed_instance& inst_host, int ii, int s,
                                const Glob* glob, double dt, bool mixed, const SortScratch& w, int grid, hipStream_t st);

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "qed_device.h"
@@ -158,6 +159,38 @@ hipError_t launch_sort_species(const qed_instance* inst_dev, const qed_instance&
   permute<uint64_t>(sp_dev, S.uid_dev, w.stage, w.dst, grid, st);
   if (s == 2) permute<int32_t>(sp_dev, S.birth_step_dev, w.stage, w.dst, grid, st);
   return hipGetLastError();
+}
+
+// Scratch of qed_sort_static: a fixed array in device memory (each GPU holds its own copy from
+// the load of the library to the end of the process), laid out as the staging words (8 B per
+// slot), the tile keys and destination slots (4 B per slot each), then the tile histogram.  In
+// host code its name is not a device address: the address comes from hipGetSymbolAddress, taken
+// once per device with that device current, and only that address is handed to kernels.
+static __device__ __align__(256) unsigned char scratch[kStaticSortBytes];
+
+hipError_t static_sort_scratch(SortScratch* out) {
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+      void* p = nullptr;
+      e = hipGetSymbolAddress((void**)&p, HIP_SYMBOL(scratch));
+      if (e != hipSuccess) return e;
+      addr[dev] = p;
+    }
+  }
+  char* base = (char*)addr[dev];
+  out->stage = base;
+  out->key = (int32_t*)(base + kStaticSortSlots * 8);
+  out->dst = (uint32_t*)(base + kStaticSortSlots * 12);
+  out->hist = (uint32_t*)(base + kStaticSortSlots * 16);
+  out->hist_len = kStaticSortTiles;
+  return hipSuccess;
 }
 
 }  // namespace qedk

@@ -207,6 +207,10 @@ class Run:
     def sort(self):
         capi.qed_sort(self.ws, self.params, self._s())
 
+    def sort_static(self):
+        """qed_sort_static: the same reordering with the library's fixed scratch (no allocation)."""
+        capi.qed_sort_static(self.ws, self.params, self._s())
+
     def ledger(self):
         st, led = capi.qed_energy_ledger(self.ws, len(self.insts), self._s())
         for d in led:
