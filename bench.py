@@ -26,6 +26,7 @@ value of the whole 20000-step schedule.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -43,7 +44,7 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(form, kind, led0, led1, grid=False):
+def kernel_bytes(form, kind, led0, led1, grid=False, pulse=True):
     """Algorithmic HBM bytes of one kernel class between two ledgers.
 
     Lepton sweep, per lepton step in 3-D: with the full push 56 B read (x, u, tau) + 56 B
@@ -51,10 +52,11 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
     FP64 tau); outside the plane-wave pulse (field-free drift) x and u read, x written: 72 B in
     FP64; + 16 B per queued emission event.  2-D grid workload: 48 + 48 B per step (x, y, u, tau).
     Photon sweep: 4 B per summary window of a group of 64 slots that was read, and 4 B per slot
-    whose pair window was read; per photon inside its window the state its record copies (k,
-    x at birth, birth step: 36 B in FP64, 20 B in FP32-mixed; with y at birth, 44 B, on the
-    grid); + 16 B (tau read and written) for the photons that see a non-zero pair rate; + 8 B per
-    queued pair event.  The event passes (separate classes) read the event's particle and write
+    whose pair window was read; per photon inside its window what its record holds: in the
+    plane-wave pulse the phase at step 0, its rate per step and the chi scale (24 B in FP64, 16 B
+    in FP32-mixed), in a general field the momentum, the birth position and the birth step (44 B
+    in FP64, 24 B in FP32-mixed); + 16 B (tau read and written) for the photons that see a
+    non-zero pair rate; + 8 B per queued pair event.  The event passes (separate classes) read the event's particle and write
     the children."""
     d = lambda k, i=None: (led1[k][i] - led0[k][i]) if i is not None else (led1[k] - led0[k])
     if kind == "lepton":
@@ -67,7 +69,10 @@ def kernel_bytes(form, kind, led0, led1, grid=False):
         else:
             per_full, per_drift = LEPTON_BYTES_FP32
         return full * per_full + (steps - full) * per_drift + (d("n_emit") + d("n_null")) * 16
-    rec = 44 if grid else (36 if form == "fp64" else 20)
+    if pulse:
+        rec = 24 if form == "fp64" else 16
+    else:
+        rec = 44 if form == "fp64" else 24
     return ((d("photon_window_reads") + d("photon_group_reads")) * 4 + d("photon_steps_active") * rec
             + d("photon_steps_in_field") * 16 + d("n_pair") * 8)
 
@@ -179,10 +184,14 @@ def size_grid(w, tables, args, probe_n=100_000):
     return k
 
 
-def size_batched(ws, tables, args, last_step, probe_n=64):
+def size_batched(ws, tables, args, last_step, probe_n=256):
     """Buffer capacities of the batched instances from a probe run: the first `probe_n`
     electrons of every instance (the same families as in the full run) through the schedule up
-    to `last_step`; each species gets 1.3x its probe yield per initial electron plus a margin."""
+    to `last_step`, retiring photons at each compaction as the full run does; each species gets
+    1.3x the largest population per initial electron the probe held (photons: just before a
+    compaction) plus a margin.  Family sizes scatter widely at the strongest fields, so the
+    probe takes 256 electrons per instance and the margin is 1.5x plus four standard errors of the
+    probe's per-electron mean (counted as if families were independent Poisson sources)."""
     from paper_1311_5551_amd import capi, workloads as W
     from paper_1311_5551_amd.sim import Run
     probe = []
@@ -191,24 +200,34 @@ def size_batched(ws, tables, args, last_step, probe_n=64):
         p.capacity = dict(electron=2000 * p.n + 4096, positron=2000 * p.n + 4096, photon=4000 * p.n + 8192)
         probe.append(p)
     run = Run(probe, tables, precision=capi.QED_FP32_MIXED)
+    if args.batched_retire:
+        run.set_retire(RETIRE_BINS, RETIRE_EMIN, RETIRE_EMAX)
     log("batched: sizing buffers from a %d-electron probe run" % sum(p.n for p in probe))
     step = 0
+    peak = [[0, 0, 0] for _ in probe]
     while step < last_step:
         n = min(args.compact_every - step % args.compact_every, last_step - step)
         run.run(n, graph_steps=n if n == args.compact_every else 0)
         step += n
         if step % args.compact_every == 0:
+            for pk, l in zip(peak, run.ledger()):
+                for s_ in range(3):
+                    pk[s_] = max(pk[s_], l["count"][s_])
             run.compact()
     led = run.ledger()
     run.close()
     if any(l["status"] != "QED_OK" for l in led):
         raise RuntimeError("batched probe run: %s" % sorted(set(l["status"] for l in led)))
-    for w, p, l in zip(ws, probe, led):
-        y_e = l["count"][0] / p.n
-        y_p = l["count"][1] / p.n
-        y_g = (l["n_emit"] + l["n_pair"]) / p.n  # photons emitted (an upper bound of the live ones)
-        w.capacity = dict(electron=int(1.3 * y_e * w.n) + 4096, positron=int(1.3 * y_p * w.n) + 4096,
-                          photon=int(1.3 * y_g * w.n) + 16384)
+    for w, p, l, pk in zip(ws, probe, led, peak):
+        y = [max(pk[s_], l["count"][s_]) / p.n for s_ in range(3)]
+        cap = [int(1.5 * y[s_] * w.n + 4.0 * w.n * math.sqrt(max(y[s_], 1.0) / p.n)) for s_ in range(3)]
+        w.capacity = dict(electron=cap[0] + 4096, positron=cap[1] + 4096, photon=cap[2] + 16384)
+    tot = [sum(w.capacity[k] for w in ws) for k in ("electron", "positron", "photon")]
+    log("batched: capacities %d electrons, %d positrons, %d photons" % tuple(tot))
+
+
+# photon spectrum of the retired photons (batched form)
+RETIRE_BINS, RETIRE_EMIN, RETIRE_EMAX = 64, 1e-3, 1e4
 
 
 def window(total, warmup, steps, meet):
@@ -266,11 +285,13 @@ def run_form(form, args, tables, tuned):
         steps = min(args.batched_window, SCHEDULE - s0)
         size_batched(ws, tables, args, s0 + steps)
         total = s0 + steps
-        workload = ("batched_collisions: 256 instances, N_i=floor(%g*10^U(3,6)) (total %d electrons), a0~U(50,500), "
+        workload = ("batched_collisions: 256 instances, N_i=floor(%s10^U(3,6)) (total %d electrons), a0~U(50,500), "
                     "gamma0 log-U[500,5000], FP32-mixed, dt=lambda/200c, steps %d..%d of %d (window centred on the "
                     "collisions at step %d; %d untimed steps before), hipGraph replay of %d-step graphs, "
-                    "compaction every %d" % (args.batched_scale, sum(w.n for w in ws), s0, s0 + steps, SCHEDULE,
-                                             MEET, s0, args.compact_every, args.compact_every))
+                    "compaction every %d%s"
+                    % ("" if args.batched_scale == 1.0 else "%g*" % args.batched_scale, sum(w.n for w in ws), s0,
+                       s0 + steps, SCHEDULE, MEET, s0, args.compact_every, args.compact_every,
+                       " retiring the photons whose pair window is over" if args.batched_retire else ""))
     else:
         w = W.collision_config2(n=args.electrons, n_steps=SCHEDULE)
         ws = [w]
@@ -289,6 +310,8 @@ def run_form(form, args, tables, tuned):
         r = Run(ws, tables, precision=prec, block=args.block, ppt=args.ppt)
         if tuned is not None:
             autotune.apply(r, tuned)
+        if form == "batched" and args.batched_retire:
+            r.set_retire(RETIRE_BINS, RETIRE_EMIN, RETIRE_EMAX)
         return r
 
     def advance(run, step, k, graph):
@@ -384,13 +407,17 @@ def run_form(form, args, tables, tuned):
                lepton_steps_in_field=d("lepton_steps_in_field"), photon_window_reads=d("photon_window_reads"),
                photon_group_reads=d("photon_group_reads"),
                dropped=int(sum(l["n_dropped"] for l in led1)), status=status,
+               overflowed=[dict(instance=i, dropped=int(l["n_dropped"]), count=[int(c) for c in l["count"]])
+                           for i, l in enumerate(led1) if l["n_dropped"] > 0][:16],
+               photons_retired=int(sum(l["n_retired"] for l in led1)),
                launch={k: (tuned.get(k) if tuned else None) for k in ("lepton", "photon")},
                kernel_timing="HIP events per kernel class on the run's stream over the same steps replayed eagerly "
                              "from the same initial state" + (" (the timed run replays captured HIP graphs)"
                                                                if graphs else ""))
     # the kernel that takes the most time in the window bounds the step
     kind = "photon" if ms[2] >= ms[1] else "lepton"
-    byts = kernel_bytes("fp64" if prec == capi.QED_FP64 else "fp32", kind, lk0, lk1, grid=form == "grid")
+    byts = kernel_bytes("fp64" if prec == capi.QED_FP64 else "fp32", kind, lk0, lk1, grid=form == "grid",
+                        pulse=form not in ("grid", "uniform"))
     n_l = launches[2] if kind == "photon" else launches[1]
     avg_s = (ms[2] if kind == "photon" else ms[1]) / max(n_l, 1) * 1e-3
     achieved = byts / max(n_l, 1) / avg_s / 1e9 if avg_s > 0 else 0.0
@@ -447,7 +474,9 @@ def main():
     ap.add_argument("--tune-scale", type=float, default=1.0, help="electrons of the tuning run / --electrons")
     ap.add_argument("--tune-at", default="9000,9500,10000,10500,11000",
                     help="steps of the tuning run at which trials run (population-weighted sum)")
-    ap.add_argument("--batched-scale", type=float, default=0.1)
+    ap.add_argument("--batched-scale", type=float, default=1.0, help="factor on every instance's electrons")
+    ap.add_argument("--no-batched-retire", dest="batched_retire", action="store_false",
+                    help="keep the photons whose pair window is over (they then need ~3x the memory)")
     ap.add_argument("--batched-window", type=int, default=4000)
     ap.add_argument("--batched-warmup", type=int, default=50)
     ap.add_argument("--grid-electrons", type=int, default=16_000_000)

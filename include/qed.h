@@ -233,12 +233,26 @@ qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream
  * other threads, other workspaces) race and must be ordered by the caller. */
 qed_status qed_sort_static(qed_workspace* ws, const qed_step_params* params, qed_stream stream);
 
-/* Removes dead photons (tau < 0) from every bound photon species by moving live photons from
- * the tail into the holes (order is not preserved), then rebuilds the summary windows of the
- * photon slot groups (from the last summarised group on where nothing was removed).  Call it
- * periodically (e.g. every 100 steps): it also lets the photon sweep skip the groups whose
- * photons are outside their pair windows.  Async. */
+/* Removes the photons that pair creation annihilated (Sec. 3: the photon is deleted when it
+ * creates a pair; tau < 0 marks it until then) from every bound photon species, by moving live
+ * photons from the tail into the holes (order is not preserved).  With retirement on
+ * (qed_set_retire) it also removes the photons whose pair window is over: they can never create
+ * a pair again (the paper deletes photons that cannot matter for pair creation, Sec. 3.1); their
+ * energy goes to the ledger's retired_energy and each is counted in its instance's photon
+ * spectrum.  Then it puts the photons whose window is over in front of the others (the photon
+ * sweep starts after them) and rebuilds the summary windows of the groups of 64 photon slots.
+ * Call it periodically (e.g. every 100 steps).  Async; graph-capturable. */
 qed_status qed_compact(qed_workspace* ws, qed_stream stream);
+
+/* Retirement of photons at compaction (see qed_compact): n_bins > 0 turns it on, with a photon
+ * spectrum of n_bins log-spaced bins of photon energy |k| over [eps_min, eps_max] (m c^2) per
+ * instance, plus an underflow and an overflow bin; n_bins = 0 turns it off.  Allocates and
+ * zeroes the spectra (synchronous); a new qed_bind zeroes them again. */
+qed_status qed_set_retire(qed_workspace* ws, int32_t n_bins, double eps_min, double eps_max);
+
+/* The retired-photon spectrum of instance `inst`: counts[0] below eps_min, counts[1..n_bins]
+ * the bins, counts[n_bins + 1] at or above eps_max.  Synchronises `stream`. */
+qed_status qed_retired_spectrum(qed_workspace* ws, int32_t inst, int64_t* counts, qed_stream stream);
 
 /* Energy account of one instance (Sec. 3.1 and Table 2), in m c^2 times the weight. */
 typedef struct {
@@ -249,6 +263,8 @@ typedef struct {
   double defect_pair;     /* sum over pair creations of gamma_- + gamma_+ - |k| */
   double dropped_energy;  /* energy of children that did not fit their buffer */
   double radiated;        /* energy removed by deterministic radiation reaction (QED_RR_*) */
+  double retired_energy;  /* energy of the photons retired at compaction (qed_set_retire) */
+  int64_t n_retired;      /* photons retired */
   int64_t count[3];
   int64_t n_emit, n_null, n_pair;  /* emissions, draws below the cut-off, pair creations */
   int64_t n_dropped, n_range, n_nonfinite;
@@ -265,7 +281,7 @@ typedef struct {
                                       steps since qed_bind (photons: buffer slots, incl. dead ones
                                       not yet compacted, counted in steps with QED_PAIRS, the steps
                                       in which photons are advanced) */
-  double drift;           /* |sum energy - energy0 - work - defects + dropped + radiated| / energy0 */
+  double drift;           /* |sum energy + retired - energy0 - work - defects + dropped + radiated| / energy0 */
 } qed_ledger;
 
 /* Fills out[0..n_inst-1] for the bound instances.  Synchronises `stream`.  Returns

@@ -63,7 +63,8 @@ class qed_step_params(C.Structure):
 class qed_ledger(C.Structure):
     _fields_ = [("energy", C.c_double * 3), ("energy0", C.c_double), ("work", C.c_double),
                 ("defect_emit", C.c_double), ("defect_pair", C.c_double), ("dropped_energy", C.c_double),
-                ("radiated", C.c_double), ("count", C.c_int64 * 3), ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
+                ("radiated", C.c_double), ("retired_energy", C.c_double), ("n_retired", C.c_int64),
+                ("count", C.c_int64 * 3), ("n_emit", C.c_int64), ("n_null", C.c_int64), ("n_pair", C.c_int64),
                 ("n_dropped", C.c_int64), ("n_range", C.c_int64), ("n_nonfinite", C.c_int64),
                 ("photon_steps_in_field", C.c_int64), ("photon_steps_active", C.c_int64),
                 ("lepton_steps_in_field", C.c_int64), ("photon_window_reads", C.c_int64),
@@ -98,6 +99,8 @@ _SIGNATURES = {
     "qed_sort": (C.c_int, [_vp, C.POINTER(qed_step_params), _vp]),
     "qed_sort_static": (C.c_int, [_vp, C.POINTER(qed_step_params), _vp]),
     "qed_energy_ledger": (C.c_int, [_vp, C.POINTER(qed_ledger), _vp]),
+    "qed_set_retire": (C.c_int, [_vp, C.c_int32, C.c_double, C.c_double]),
+    "qed_retired_spectrum": (C.c_int, [_vp, C.c_int32, C.POINTER(C.c_int64), _vp]),
     "qed_profile": (C.c_int, [_vp, C.c_int32]),
     "qed_profile_read": (C.c_int, [_vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "qed_last_error": (C.c_char_p, []),
@@ -211,6 +214,16 @@ def qed_sort(ws, params: qed_step_params, stream=None):
 
 def qed_sort_static(ws, params: qed_step_params, stream=None):
     return check(lib().qed_sort_static(ws, C.byref(params), stream))
+
+
+def qed_set_retire(ws, n_bins: int, eps_min: float, eps_max: float):
+    return check(lib().qed_set_retire(ws, n_bins, eps_min, eps_max))
+
+
+def qed_retired_spectrum(ws, inst: int, n_bins: int, stream=None):
+    out = (C.c_int64 * (n_bins + 2))()
+    check(lib().qed_retired_spectrum(ws, inst, out, stream))
+    return list(out)
 
 
 def qed_compact(ws, stream=None):

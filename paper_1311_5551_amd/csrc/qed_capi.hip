@@ -123,6 +123,8 @@ struct qed_workspace {
   EmitEv* d_emq = nullptr;
   int64_t emq_cap = 0;
   int32_t* d_wave_cnt = nullptr;  // emission events per wave of the lepton sweep (cus * 32 waves)
+  RetireSpec retire;              // retirement of photons at compaction, and its spectra
+  size_t spec_len = 0;
   int64_t lep_cap = 0;            // bound lepton slots (both species, all instances)
   SortScratch sort;  // allocated by the first qed_sort that needs it
   int64_t sort_cap = 0;
@@ -601,6 +603,7 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->d_evq);
   hipFree(ws->d_emq);
   hipFree(ws->d_wave_cnt);
+  hipFree(ws->retire.spec);
   hipFree(ws->sort.key);
   hipFree(ws->sort.dst);
   hipFree(ws->sort.hist);
@@ -736,6 +739,7 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
     ws->rec_bytes = rec_bytes;
   }
   ws->win_valid = false;  // computed by the first step, which knows t0, dt and the tables
+  if (ws->retire.spec) HIP_TRY(hipMemset(ws->retire.spec, 0, ws->spec_len * sizeof(unsigned long long)));
   // emission queue: the wave segments of the lepton sweep (a lepton emits at most once per step)
   int64_t leptons = 0;
   for (int i = 0; i < n_inst; ++i) leptons += inst[i].s[0].capacity + inst[i].s[1].capacity;
@@ -949,10 +953,47 @@ qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches) {
 qed_status qed_compact(qed_workspace* ws, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
-  launch_compact(ws->field_kind, ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_movers, ws->d_win, ws->d_rec, ws->d_wsum,
-                 ws->prec == QED_FP32_MIXED,
-                 (hipStream_t)stream);
+  launch_compact(ws->field_kind, ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_movers, ws->d_win, ws->d_rec,
+                 ws->d_wsum, ws->prec == QED_FP32_MIXED, ws->retire, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
+  return QED_OK;
+}
+
+qed_status qed_set_retire(qed_workspace* ws, int32_t n_bins, double eps_min, double eps_max) {
+  if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
+  if (n_bins == 0) {
+    ws->retire.on = 0;
+    return QED_OK;
+  }
+  if (n_bins < 1 || n_bins > 4096) return fail(QED_ERR_ARG, "n_bins = %d outside [1, 4096]", n_bins);
+  if (!finite_pos(eps_min) || !finite_pos(eps_max) || !(eps_max > eps_min))
+    return fail(QED_ERR_ARG, "photon energy range [%g, %g] invalid", eps_min, eps_max);
+  const size_t len = (size_t)ws->max_inst * (n_bins + 2);
+  HIP_TRY(hipSetDevice(ws->device));
+  HIP_TRY(hipDeviceSynchronize());
+  if (len > ws->spec_len || !ws->retire.spec) {
+    hipFree(ws->retire.spec);
+    ws->retire.spec = nullptr;
+    ws->spec_len = 0;
+    HIP_TRY(hipMalloc((void**)&ws->retire.spec, len * sizeof(unsigned long long)));
+    ws->spec_len = len;
+  }
+  HIP_TRY(hipMemset(ws->retire.spec, 0, len * sizeof(unsigned long long)));
+  ws->retire.on = 1;
+  ws->retire.n_bins = n_bins;
+  ws->retire.e_min = eps_min;
+  ws->retire.e_max = eps_max;
+  return QED_OK;
+}
+
+qed_status qed_retired_spectrum(qed_workspace* ws, int32_t inst, int64_t* counts, qed_stream stream) {
+  if (!ws || !counts) return fail(QED_ERR_ARG, "NULL argument");
+  if (!ws->retire.spec || ws->retire.n_bins < 1) return fail(QED_ERR_STATE, "retirement was never enabled");
+  if (inst < 0 || inst >= ws->max_inst) return fail(QED_ERR_ARG, "instance %d outside [0, %d)", inst, ws->max_inst);
+  const int nb = ws->retire.n_bins + 2;
+  HIP_TRY(hipMemcpyAsync(counts, ws->retire.spec + (size_t)inst * nb, nb * sizeof(int64_t), hipMemcpyDeviceToHost,
+                         (hipStream_t)stream));
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return QED_OK;
 }
 
@@ -980,6 +1021,8 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
     L.defect_pair = fix_value(A.fx[FX_DEFECT_PAIR]) * w;
     L.dropped_energy = fix_value(A.fx[FX_DROPPED]) * w;
     L.radiated = fix_value(A.fx[FX_RADIATED]) * w;
+    L.retired_energy = fix_value(A.fx[FX_RETIRED]) * w;
+    L.n_retired = (int64_t)A.n_retired;
     L.n_emit = (int64_t)A.n_emit;
     L.n_null = (int64_t)A.n_null;
     L.n_pair = (int64_t)A.n_pair;
@@ -992,7 +1035,8 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
     L.photon_group_reads = (int64_t)A.n_group_reads;
     L.lepton_steps_in_field = (int64_t)A.n_field_lepton;
     for (int s = 0; s < 3; ++s) L.particle_steps[s] = (int64_t)A.particle_steps[s];
-    const double resid = tot - L.energy0 - L.work - L.defect_emit - L.defect_pair + L.dropped_energy + L.radiated;
+    const double resid = tot + L.retired_energy - L.energy0 - L.work - L.defect_emit - L.defect_pair +
+                         L.dropped_energy + L.radiated;
     L.drift = L.energy0 > 0.0 ? std::fabs(resid) / L.energy0 : std::fabs(resid);
     dropped |= A.n_dropped > 0;
     nonfinite |= A.n_nonfinite > 0;

@@ -136,8 +136,9 @@ struct InstAcc {
                                // down to a chunk)
   unsigned long long hole_ctr, mover_ctr;
   // energy sums of the ledger as exact fixed-point words (fix_split): field work, emission and
-  // pair defects, dropped energy, radiated energy, then the three species energies
-  long long fx[8][4];
+  // pair defects, dropped energy, radiated energy, retired photons' energy, then the three species
+  long long fx[9][4];
+  unsigned long long n_retired;          // photons retired at compaction (pair window over)
   unsigned long long led_count[3];
   unsigned long long n_emit, n_null, n_pair, n_dropped, n_range, n_nonfinite, n_field, n_field_lepton;
   unsigned long long n_active;           // photon steps inside the photon's window (evaluated in full)
@@ -157,8 +158,9 @@ struct InstAcc {
 // the launch shape, the block schedule or the order of an event queue.  The words are
 // normalised once per step (carries moved up), so each word stays far from overflow.
 // ---------------------------------------------------------------------------
-enum { FX_WORK = 0, FX_DEFECT_EMIT = 1, FX_DEFECT_PAIR = 2, FX_DROPPED = 3, FX_RADIATED = 4, FX_ENERGY = 5 };
-constexpr int kFixRunning = 5;  // FX_WORK..FX_RADIATED accumulate over the run
+enum { FX_WORK = 0, FX_DEFECT_EMIT = 1, FX_DEFECT_PAIR = 2, FX_DROPPED = 3, FX_RADIATED = 4, FX_RETIRED = 5,
+       FX_ENERGY = 6 };
+constexpr int kFixRunning = 6;  // FX_WORK..FX_RETIRED accumulate over the run
 
 __device__ __forceinline__ void fix_split(double v, long long l[4]) {
   v = v > 0x1p62 ? 0x1p62 : v < -0x1p62 ? -0x1p62 : v == v ? v : 0.0;  // non-finite state is counted apart

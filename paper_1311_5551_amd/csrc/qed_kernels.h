@@ -24,6 +24,14 @@ struct StepArgs {
   const uint32_t* wsum;       // window-group summaries; instance i's from acc[i].wsum_off
 };
 
+// retirement of photons at compaction (pair window over): the photon spectrum they are counted in
+struct RetireSpec {
+  int on = 0;
+  int n_bins = 0;
+  double e_min = 0.0, e_max = 0.0;      // log-spaced bins of photon energy (m c^2)
+  unsigned long long* spec = nullptr;   // per instance n_bins + 2 counts (below, bins, above)
+};
+
 // scratch of the spatial sort (sized by the caller for the largest species and tile count)
 struct SortScratch {
   int32_t* key = nullptr;
@@ -58,7 +66,7 @@ void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mix
 void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s);
 void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s);
 void launch_compact(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
-                    uint32_t* win, void* rec, uint32_t* wsum, bool mixed, hipStream_t s);
+                    uint32_t* win, void* rec, uint32_t* wsum, bool mixed, const RetireSpec& rs, hipStream_t s);
 void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
                            uint32_t* wsum, double t0, double dt, double cp_min, bool mixed, hipStream_t s);
 

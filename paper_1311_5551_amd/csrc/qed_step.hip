@@ -1332,7 +1332,22 @@ __global__ __launch_bounds__(256) void k_ledger(const qed_instance* __restrict__
 // ---------------------------------------------------------------------------
 // compaction of dead photons (tau < 0): live photons from [n_live, n) fill the holes in [0, n_live)
 // ---------------------------------------------------------------------------
-__global__ void k_compact_prep(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc) {
+// A photon leaves the arrays at compaction when it converted to a pair (tau < 0) or, with
+// retirement on, when its pair window is over (it can never convert: it only moves ballistically,
+// so it is booked into the ledger and the instance's photon spectrum and dropped).
+__device__ __forceinline__ bool window_over(uint32_t w, int64_t s);
+
+struct RetireArgs {
+  int on;                       // retirement enabled
+  int n_bins;                   // spectrum bins, log-spaced in photon energy over [e_min, e_max]
+  double le_min, inv_dle;       // ln e_min and 1 / ln-width of a bin
+  unsigned long long* spec;     // per instance n_bins + 2 counts (below, bins, above)
+  int64_t step;                 // the step after the compaction (windows over before it): set by
+                                // each kernel from the device clock
+};
+
+__global__ void k_compact_prep(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
+                               int retire) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
     const qed_species& S = inst[i].s[2];
     int64_t n = S.count_dev ? *S.count_dev : 0;
@@ -1344,39 +1359,89 @@ __global__ void k_compact_prep(const qed_instance* __restrict__ inst, int n_inst
     acc[i].mover_ctr = 0;
     // photons are removed only by pair creation: with no pair event since the last compaction
     // there is nothing to remove (the first compaction after a bind always runs)
-    const bool skip = acc[i].n_pair_compacted == acc[i].n_pair;
+    const bool skip = !retire && acc[i].n_pair_compacted == acc[i].n_pair;
     acc[i].compact_skip = skip ? 1 : 0;
     acc[i].n_live = skip ? n : 0;
     acc[i].n_pair_compacted = acc[i].n_pair;
   }
 }
 
-__global__ __launch_bounds__(256) void k_compact_count(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc) {
-  __shared__ double sred[16];
-  __shared__ unsigned sredu[16];
+__device__ __forceinline__ bool photon_leaves(const qed_species& S, const uint32_t* W, int64_t k, const RetireArgs& r) {
+  return S.tau_dev[k] < 0.0 || (r.on && window_over(W[k], r.step));
+}
+
+// live photons per instance; retired photons' energy, count and spectrum bin
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_compact_count(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
+                                                       const Glob* __restrict__ glob, const uint32_t* __restrict__ win,
+                                                       RetireArgs r) {
+  r.step = glob->step_next;
+  using Real = typename std::conditional<MIXED, float, double>::type;
+  __shared__ unsigned sredu[16 * 2];
+  __shared__ long long s_ll[16 * 4];
+  extern __shared__ unsigned s_hist[];  // n_bins + 2 with retirement on
   const int ii = blockIdx.y;
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
+  const uint32_t* W = win + acc[ii].mover_off;
   const int64_t n = acc[ii].n_start[2];
-  double d[1] = {0.0};
-  unsigned u[1] = {0};
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-    if (!(S.tau_dev[k] < 0.0)) ++u[0];
-  block_sum(d, u, sred, sredu);
-  if (threadIdx.x == 0 && u[0]) atomicAdd((unsigned long long*)&acc[ii].n_live, (unsigned long long)u[0]);
+  if (r.on)
+    for (int b = threadIdx.x; b < r.n_bins + 2; b += blockDim.x) s_hist[b] = 0u;
+  __syncthreads();
+  unsigned u[2] = {0, 0};  // live, retired
+  long long fe[4] = {0, 0, 0, 0};
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const double tau = S.tau_dev[k];
+    if (tau < 0.0) continue;
+    if (r.on && window_over(W[k], r.step)) {
+      const double kx = ((const Real*)S.ux_dev)[k], ky = ((const Real*)S.uy_dev)[k], kz = ((const Real*)S.uz_dev)[k];
+      const double e = sqrt(kx * kx + ky * ky + kz * kz);
+      long long l[4];
+      fix_split(e, l);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) fe[q] += l[q];
+      ++u[1];
+      const double sb = e > 0.0 ? (log(e) - r.le_min) * r.inv_dle : -1.0;  // bin of the spectrum
+      const int b = !(sb >= 0.0) ? 0 : sb >= (double)r.n_bins ? r.n_bins + 1 : 1 + (int)sb;
+      atomicAdd(&s_hist[b], 1u);
+    } else {
+      ++u[0];
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    fe[q] = wave_sum_ll(fe[q]);
+    if ((threadIdx.x & 63) == 0) s_ll[(threadIdx.x >> 6) * 4 + q] = fe[q];
+  }
+  long long* const dst[1] = {acc[ii].fx[FX_RETIRED]};
+  fix_block_flush<1>(s_ll, dst);
+  block_sum_u(u, sredu);
+  if (threadIdx.x == 0) {
+    if (u[0]) atomicAdd((unsigned long long*)&acc[ii].n_live, (unsigned long long)u[0]);
+    if (u[1]) atomicAdd(&acc[ii].n_retired, (unsigned long long)u[1]);
+  }
+  if (r.on) {
+    __syncthreads();
+    unsigned long long* H = r.spec + (size_t)ii * (r.n_bins + 2);
+    for (int b = threadIdx.x; b < r.n_bins + 2; b += blockDim.x)
+      if (s_hist[b]) atomicAdd(&H[b], (unsigned long long)s_hist[b]);
+  }
 }
 
 __global__ __launch_bounds__(256) void k_compact_movers(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
-                                                        int64_t* __restrict__ movers) {
+                                                        const Glob* __restrict__ glob, int64_t* __restrict__ movers,
+                                                        const uint32_t* __restrict__ win, RetireArgs r) {
+  r.step = glob->step_next;
   const int ii = blockIdx.y;
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
+  const uint32_t* W = win + acc[ii].mover_off;
   const int64_t n = acc[ii].n_start[2], L = acc[ii].n_live;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   // loop bounds are identical across a wave so that every lane reaches the ballot
   for (int64_t k0 = L + blockIdx.x * (int64_t)blockDim.x; k0 < n; k0 += stride) {
     const int64_t k = k0 + threadIdx.x;
-    const bool mv = k < n && !(S.tau_dev[k] < 0.0);
+    const bool mv = k < n && !photon_leaves(S, W, k, r);
     const long long slot = wave_reserve(mv, (int64_t*)&acc[ii].mover_ctr);
     if (mv) movers[acc[ii].mover_off + slot] = k;
   }
@@ -1384,8 +1449,10 @@ __global__ __launch_bounds__(256) void k_compact_movers(const qed_instance* __re
 
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
-                                                      const int64_t* __restrict__ movers, uint32_t* __restrict__ win,
-                                                      void* __restrict__ rec, int rec_words) {
+                                                      const Glob* __restrict__ glob, const int64_t* __restrict__ movers,
+                                                      uint32_t* __restrict__ win, void* __restrict__ rec, int rec_words,
+                                                      RetireArgs r) {
+  r.step = glob->step_next;
   const int ii = blockIdx.y;
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
@@ -1395,7 +1462,7 @@ __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __rest
   const bool d3 = inst[ii].dims == 3;
   for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < L; k0 += stride) {
     const int64_t k = k0 + threadIdx.x;
-    const bool hole = k < L && S.tau_dev[k] < 0.0;
+    const bool hole = k < L && photon_leaves(S, win + acc[ii].mover_off, k, r);
     const long long slot = wave_reserve(hole, (int64_t*)&acc[ii].hole_ctr);
     // every hole in [0, L) has a mover in [L, n); the bounds below only guard that invariant
     if (hole && slot < n_movers) {
@@ -1766,16 +1833,25 @@ void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc
 }
 
 void launch_compact(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
-                    uint32_t* win, void* rec, uint32_t* wsum, bool mixed, hipStream_t s) {
+                    uint32_t* win, void* rec, uint32_t* wsum, bool mixed, const RetireSpec& rs, hipStream_t s) {
   const int rw = photon_rec_bytes(mixed, fk) / 16;
-  hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
+  RetireArgs r{};
+  r.on = rs.on;
+  r.n_bins = rs.n_bins;
+  r.le_min = rs.on ? std::log(rs.e_min) : 0.0;
+  r.inv_dle = rs.on ? rs.n_bins / (std::log(rs.e_max) - std::log(rs.e_min)) : 0.0;
+  r.spec = rs.spec;
+  r.step = 0;
+  hipLaunchKernelGGL(k_compact_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc, r.on);
   // blocks per instance: enough to stream one large instance at full bandwidth; blocks past an
   // instance's photons (or of an instance with nothing to remove) return at once
   const dim3 g(n_inst == 1 ? 2048 : 256, n_inst);
-  hipLaunchKernelGGL(k_compact_count, g, dim3(256), 0, s, inst, acc);
-  hipLaunchKernelGGL(k_compact_movers, g, dim3(256), 0, s, inst, acc, movers);
-  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, movers, win, rec, rw);
-  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, movers, win, rec, rw);
+  const size_t shm = r.on ? (size_t)(r.n_bins + 2) * sizeof(unsigned) : 0;
+  if (mixed) hipLaunchKernelGGL(k_compact_count<true>, g, dim3(256), shm, s, inst, acc, glob, win, r);
+  else hipLaunchKernelGGL(k_compact_count<false>, g, dim3(256), shm, s, inst, acc, glob, win, r);
+  hipLaunchKernelGGL(k_compact_movers, g, dim3(256), 0, s, inst, acc, glob, movers, win, r);
+  if (mixed) hipLaunchKernelGGL(k_compact_fill<true>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec, rw, r);
+  else hipLaunchKernelGGL(k_compact_fill<false>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec, rw, r);
   hipLaunchKernelGGL(k_compact_finish, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   hipLaunchKernelGGL(k_part_prep, dim3(1), dim3(256), 0, s, inst, n_inst, acc);
   hipLaunchKernelGGL(k_part_count, g, dim3(256), 0, s, acc, glob, win);

@@ -204,6 +204,15 @@ class Run:
     def compact(self):
         capi.qed_compact(self.ws, self._s())
 
+    def set_retire(self, n_bins: int, eps_min: float = 1e-3, eps_max: float = 1e4):
+        """Retire photons whose pair window is over at each compaction (n_bins = 0: off)."""
+        capi.qed_set_retire(self.ws, n_bins, eps_min, eps_max)
+        self.retire_bins = n_bins
+
+    def retired_spectrum(self, inst: int = 0):
+        """Counts of retired photons: [below, bins..., above]."""
+        return capi.qed_retired_spectrum(self.ws, inst, self.retire_bins, self._s())
+
     def sort(self):
         capi.qed_sort(self.ws, self.params, self._s())
 

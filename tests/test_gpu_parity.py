@@ -416,3 +416,38 @@ def test_set_step_back_after_compaction(shared_tables, oracle_tables):
     _check_parity(r, w, o_res, o_led, label="set_step_back")
     if not straddle_uids(o_res).size:
         assert led["n_pair"] >= o_led["n_pair"]  # the ledger also holds the pairs of steps 0..1800
+
+
+def test_retirement_books_the_photons_the_oracle_keeps(shared_tables, oracle_tables):
+    # with retirement on, each compaction removes the photons whose pair window is over (they can
+    # never create a pair again) and books them in the ledger and the instance's photon spectrum.
+    # The oracle keeps every photon: its photons not left in the GPU arrays must be exactly the
+    # retired ones, in number, energy and spectrum, and everything else matches per uid
+    w = W.collision(1500, a0=200.0, n_steps=2600, meet_step=1300, seed=11)
+    r = Run(w, shared_tables)
+    nb, lo, hi = 64, 1e-3, 1e4
+    r.set_retire(nb, lo, hi)
+    for _ in range(26):
+        r.step(100)
+        r.compact()
+    led = r.ledger()[0]
+    assert led["status"] == "QED_OK"
+    o_res, o_led = oracle_run(w, oracle_tables)
+    g_ph = r.species(0, "photon")
+    o_ph = o_res["photon"]
+    gone = ~np.isin(o_ph["uid"], g_ph["uid"])
+    assert np.isin(g_ph["uid"], o_ph["uid"]).all()
+    eo = np.sqrt(o_ph["ux"] ** 2 + o_ph["uy"] ** 2 + o_ph["uz"] ** 2)
+    assert led["n_retired"] == int(gone.sum()) > 0.5 * len(o_ph["uid"])
+    assert led["retired_energy"] == pytest.approx(eo[gone].sum(), rel=1e-12)
+    edges = np.exp(np.linspace(math.log(lo), math.log(hi), nb + 1))
+    ref = np.concatenate([[np.sum(eo[gone] < lo)], np.histogram(eo[gone], edges)[0], [np.sum(eo[gone] >= hi)]])
+    spec = np.array(r.retired_spectrum(0))
+    # bin edges of the kernel (ln e scaled in FP64) and of numpy can differ by an ulp at an edge
+    assert np.abs(spec - ref).sum() <= 2 and spec.sum() == led["n_retired"]
+    # the photons still in the arrays, and every lepton, per uid against the oracle
+    keep = {k: v[~gone] for k, v in o_ph.items()}
+    o_kept = dict(o_res, photon=keep)
+    _check_parity(r, w, o_kept, o_led, label="retirement")
+    assert led["drift"] < 1e-12
+    assert led["count"][2] == len(g_ph["uid"]) < 0.5 * len(o_ph["uid"])
