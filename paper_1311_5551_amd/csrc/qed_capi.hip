@@ -136,6 +136,10 @@ struct qed_workspace {
   uint32_t* d_win = nullptr;
   void* d_rec = nullptr;     // one record per photon slot (PhotonRecT: photon_rec_bytes each)
   int rec_bytes = 0;
+  // blocks of the lepton [0] and photon [1] sweeps resident per CU for the shape in fit_key
+  // (field kind, particles per thread, block, precision, table rows)
+  int fit[2] = {0, 0};
+  int fit_key[2][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}};
   size_t win_len = 0;
   uint32_t* d_wsum = nullptr;  // window-group summaries (kWinGroup slots each), instances at acc.wsum_off
   size_t wsum_len = 0;
@@ -266,6 +270,7 @@ Tabs device_tabs(const qed_tables* t) {
   tb.n_eta = p.n_eta;
   tb.le0 = std::log(p.eta_min);
   tb.dle = (std::log(p.eta_max) - tb.le0) / (p.n_eta - 1);
+  tb.idle = 1.0 / tb.dle;
   tb.h = t->h;
   tb.h32 = t->h32;
   tb.g = t->has_g ? t->g : nullptr;
@@ -277,6 +282,7 @@ Tabs device_tabs(const qed_tables* t) {
   tb.lc0 = std::log(p.chi_pair_min);
   tb.cp_min = p.chi_pair_min;
   tb.dlc = (std::log(p.chi_pair_max) - tb.lc0) / (p.n_chi_pair - 1);
+  tb.idlc = 1.0 / tb.dlc;
   tb.T = t->T;
   tb.T32 = t->T32;
   tb.n_f = p.n_f;
@@ -339,6 +345,20 @@ void mark_end(qed_workspace* ws, int slot, hipStream_t s) {
   if (slot >= 0) hipEventRecord(ws->ev_marks[slot].second.second, s);
 }
 
+// Persistent grid of sweep `w` (0 lepton, 1 photon): one resident round of blocks.  The chunk
+// deal gives every block the same share, so blocks beyond what fits at once would only form a
+// second round that starts late.  At most 2048 threads per CU (the emission queue's bound).
+int sweep_grid(qed_workspace* ws, int w, int n_tab) {
+  const bool mixed = ws->prec == QED_FP32_MIXED;
+  const int key[5] = {ws->field_kind, ws->ppt[w], ws->block[w], (int)mixed, n_tab};
+  if (std::memcmp(key, ws->fit_key[w], sizeof(key)) != 0) {
+    ws->fit[w] = w ? photon_blocks_per_cu(ws->field_kind, ws->ppt[1], ws->block[1], n_tab, mixed)
+                   : lepton_blocks_per_cu(ws->field_kind, ws->ppt[0], ws->block[0], n_tab, mixed);
+    std::memcpy(ws->fit_key[w], key, sizeof(key));
+  }
+  return ws->cus * std::max(1, std::min(ws->fit[w], 2048 / ws->block[w]));
+}
+
 qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
   const int BL = ws->block[0], BP = ws->block[1];
   const StepConst sc = step_const(p);
@@ -361,13 +381,13 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.qe.ent = ws->d_emq;
   a.qe.cap = ws->emq_cap;
   a.qe.wave_cnt = ws->d_wave_cnt;
-  a.qe.grid = ws->cus * (2048 / BL);
+  a.qe.grid = sweep_grid(ws, 0, a.tb.n_eta);
   a.qe.waves = BL / 64;
   a.qe.ppt = ws->ppt[0];
   a.win = ws->d_win;
   a.rec = ws->d_rec;
   a.wsum = ws->d_wsum;
-  // persistent grids: 2048 threads per CU, blocks taking contiguous runs of the chunk list.
+  // persistent grids (sweep_grid), blocks taking runs of the chunk list.
   // The passes run in order on `stream`: the photon sweep alone saturates HBM, so running the
   // lepton passes beside it on a second stream (their data are disjoint) shares bandwidth
   // rather than adding any.
@@ -377,7 +397,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.n_base = 2 * ws->n_inst;
   a.ppt = ws->ppt[0];
   m = mark_begin(ws, 1, sl);
-  launch_lepton(ws->field_kind, a, ws->cus * (2048 / BL), BL, mixed, sl);
+  launch_lepton(ws->field_kind, a, a.qe.grid, BL, mixed, sl);
   mark_end(ws, m, sl);
   if (p->flags & QED_EMIT) {
     m = mark_begin(ws, 4, sl);
@@ -391,7 +411,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
     a.n_base = ws->n_inst;
     a.ppt = ws->ppt[1];
     m = mark_begin(ws, 2, s);
-    launch_photon(ws->field_kind, a, ws->cus * (2048 / BP), BP, mixed, s);
+    launch_photon(ws->field_kind, a, sweep_grid(ws, 1, a.tb.n_cp), BP, mixed, s);
     mark_end(ws, m, s);
     m = mark_begin(ws, 3, s);
     launch_pair_events(ws->field_kind, a, ws->cus, 256, mixed, s);
@@ -421,7 +441,7 @@ qed_status ensure_windows(const qed_tables* tb, qed_workspace* ws, const qed_ste
 // runs of chunks (up to one chunk per block).  Synchronises the device when it reallocates.
 qed_status ensure_emit_queue(qed_workspace* ws) {
   const int64_t ch = (int64_t)ws->block[0] * ws->ppt[0];
-  const int64_t grid = (int64_t)ws->cus * (2048 / ws->block[0]);
+  const int64_t grid = (int64_t)ws->cus * (2048 / ws->block[0]);  // bound of sweep_grid
   const int64_t need = std::max<int64_t>(1, ws->lep_cap + (2 * (int64_t)ws->n_inst + grid) * ch);
   if (need <= ws->emq_cap && ws->d_emq) return QED_OK;
   HIP_TRY(hipDeviceSynchronize());

@@ -82,6 +82,25 @@ template <>
 __device__ __forceinline__ int32_t buf_ld<int32_t>(bufres r, uint32_t o) {
   return (int32_t)__builtin_amdgcn_raw_buffer_load_b32(r, o, 0, 0);
 }
+// N consecutive dwords from byte offset o (128-bit pieces, then a 64- and a 32-bit tail)
+template <int N>
+__device__ __forceinline__ void load_dwords(bufres r, uint32_t o, uint32_t* q) {
+#pragma unroll
+  for (int w = 0; w + 4 <= N; w += 4) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, o + 4u * w, 0, 0);
+    q[w] = v[0];
+    q[w + 1] = v[1];
+    q[w + 2] = v[2];
+    q[w + 3] = v[3];
+  }
+  constexpr int w4 = N / 4 * 4;
+  if constexpr (N - w4 >= 2) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, o + 4u * w4, 0, 0);
+    q[w4] = v[0];
+    q[w4 + 1] = v[1];
+  }
+  if constexpr ((N - w4) % 2 == 1) q[N - 1] = __builtin_amdgcn_raw_buffer_load_b32(r, o + 4u * (N - 1), 0, 0);
+}
 __device__ __forceinline__ void buf_st(bufres r, uint32_t o, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, o, 0, 0);
 }
@@ -94,6 +113,7 @@ __device__ __forceinline__ void buf_st(bufres r, uint32_t o, float v) {
 struct Tabs {
   int n_eta;
   double le0, dle;             // ln eta_min, ln-spacing of the eta rows
+  double idle;                 // 1 / dle (rate look-ups only; the sampling divides)
   const double* h;
   const float* h32;
   const double* g;             // quantum reduction of the radiated power, per eta row (or NULL)
@@ -103,6 +123,7 @@ struct Tabs {
   const double* P;             // [n_eta][n_chi]
   int n_cp;
   double lc0, dlc;             // ln chi_pair_min, ln-spacing of the pair rows
+  double idlc;                 // 1 / dlc (rate look-up only)
   double cp_min;               // chi_pair_min
   const double* T;
   const float* T32;
@@ -282,8 +303,6 @@ __device__ __forceinline__ int64_t wrap_index(int64_t i, int n) {
   return r < 0 ? r + n : r;
 }
 
-// EXACT selects correctly rounded trigonometry (bit-reproducible momenta); the fast variant
-// (device library, <= 1 ulp) serves quantities that only feed an optical-depth decrement.
 // ---------------------------------------------------------------------------
 // Compact sin/cos and log for values that only set optical-depth decrements (the step decided
 // by a decrement is insensitive to their last bits; momenta always use the correctly rounded
@@ -300,113 +319,105 @@ constexpr double f2 = 1.0 / 2.0, f3 = 1.0 / 6.0, f4 = 1.0 / 24.0, f5 = 1.0 / 120
 
 // sin and cos of x, |x| < 2^20: x = k pi/2 + r by Cody-Waite reduction (pi/2 in three parts, the
 // first with 33 bits so that k times it is exact), |r| <= pi/4, Taylor polynomials to r^17 and
-// r^18 (truncation below 1e-19); quadrant from k mod 4.  Error a few ulp.
-__device__ __forceinline__ void fast_sincos(double x, double* sn, double* cs) {
+// r^18 (truncation below 1e-19) in fused multiply-adds; quadrant from k mod 4.  Error a few ulp.
+// Both polynomials are evaluated and the quadrant selects (no divergent branch).
+__device__ __forceinline__ void fast_sincos_r(double x, double* sv, double* cv, int* q) {
   using namespace fastm;
   const double k = rint(x * kTwoOverPi);
-  const double r = ((x - k * kPio2A) - k * kPio2B) - k * kPio2C;
+  double r = fma(-k, kPio2A, x);
+  r = fma(-k, kPio2B, r);
+  r = fma(-k, kPio2C, r);
   const double r2 = r * r;
-  double ps = f17;
-  ps = ps * r2 - f15;
-  ps = ps * r2 + f13;
-  ps = ps * r2 - f11;
-  ps = ps * r2 + f9;
-  ps = ps * r2 - f7;
-  ps = ps * r2 + f5;
-  ps = ps * r2 - f3;
-  const double sv = r + r * (r2 * ps);
-  double pc = f18;
-  pc = pc * r2 - f16;
-  pc = pc * r2 + f14;
-  pc = pc * r2 - f12;
-  pc = pc * r2 + f10;
-  pc = pc * r2 - f8;
-  pc = pc * r2 + f6;
-  pc = pc * r2 - f4;
-  const double cv = (1.0 - f2 * r2) - r2 * (r2 * pc);
-  const int q = (int)(int64_t)k & 3;
-  *sn = q == 0 ? sv : q == 1 ? cv : q == 2 ? -sv : -cv;
-  *cs = q == 0 ? cv : q == 1 ? -sv : q == 2 ? -cv : sv;
+  double ps = fma(f17, r2, -f15);
+  double pc = fma(f18, r2, -f16);
+  ps = fma(ps, r2, f13);
+  pc = fma(pc, r2, f14);
+  ps = fma(ps, r2, -f11);
+  pc = fma(pc, r2, -f12);
+  ps = fma(ps, r2, f9);
+  pc = fma(pc, r2, f10);
+  ps = fma(ps, r2, -f7);
+  pc = fma(pc, r2, -f8);
+  ps = fma(ps, r2, f5);
+  pc = fma(pc, r2, f6);
+  ps = fma(ps, r2, -f3);
+  pc = fma(pc, r2, -f4);
+  *sv = fma(r * r2, ps, r);                          // r + r^3 (-1/3! + ...)
+  *cv = fma(r2 * r2, -pc, fma(-f2, r2, 1.0));        // 1 - r^2/2 + r^4 (1/4! - ...)
+  *q = (int)(int64_t)k;
 }
-
-// sin(x + qs pi/2) alone (same reduction and polynomials as fast_sincos, one of the two
-// evaluated): qs = 0 sin, qs = 1 cos
+__device__ __forceinline__ void fast_sincos(double x, double* sn, double* cs) {
+  double sv, cv;
+  int k;
+  fast_sincos_r(x, &sv, &cv, &k);
+  const int q = k & 3;
+  *sn = (q & 1) ? cv : sv;
+  *cs = (q & 1) ? sv : cv;
+  if (q == 1 || q == 2) *cs = -*cs;
+  if (q & 2) *sn = -*sn;
+}
+// sin(x + qs pi/2): qs = 0 sin, qs = 1 cos
 __device__ __forceinline__ double fast_sinq(double x, int qs) {
-  using namespace fastm;
-  const double k = rint(x * kTwoOverPi);
-  const double r = ((x - k * kPio2A) - k * kPio2B) - k * kPio2C;
-  const double r2 = r * r;
-  const int q = ((int)(int64_t)k + qs) & 3;
-  double v;
-  if (q & 1) {  // +-cos r
-    double pc = f18;
-    pc = pc * r2 - f16;
-    pc = pc * r2 + f14;
-    pc = pc * r2 - f12;
-    pc = pc * r2 + f10;
-    pc = pc * r2 - f8;
-    pc = pc * r2 + f6;
-    pc = pc * r2 - f4;
-    v = (1.0 - f2 * r2) - r2 * (r2 * pc);
-  } else {  // +-sin r
-    double ps = f17;
-    ps = ps * r2 - f15;
-    ps = ps * r2 + f13;
-    ps = ps * r2 - f11;
-    ps = ps * r2 + f9;
-    ps = ps * r2 - f7;
-    ps = ps * r2 + f5;
-    ps = ps * r2 - f3;
-    v = r + r * (r2 * ps);
-  }
+  double sv, cv;
+  int k;
+  fast_sincos_r(x, &sv, &cv, &k);
+  const int q = (k + qs) & 3;
+  const double v = (q & 1) ? cv : sv;
   return (q & 2) ? -v : v;
 }
 __device__ __forceinline__ double fast_sin(double x) { return fast_sinq(x, 0); }
 __device__ __forceinline__ double fast_cos(double x) { return fast_sinq(x, 1); }
 
-// natural log of a finite x > 0: x = m 2^e with m in [1/sqrt2, sqrt2), log m = 2 atanh(s),
-// s = (m - 1)/(m + 1), |s| <= 0.172, by its odd series to s^25 (truncation below 1e-19).
-__device__ __forceinline__ double fast_log(double x) {
+// Natural log of a finite x > 0 with a table of kLogTab reciprocals: x = m 2^e with m in
+// [1/2, 1); j = the 7 mantissa bits after the leading one picks c_j ~ 1/m (the centre of the
+// j-th of 128 equal sub-intervals) and L_j = -log c_j (both rounded to double, computed on the
+// host); r = m c_j - 1 (one rounding, |r| <= 2^-8) and log x = e log 2 + L_j + log1p(r), the
+// series of log1p to r^7 (truncation below 1e-20).  Absolute error ~1e-16: the value only
+// places a look-up between table rows.  `tab` holds c_j, L_j interleaved (an LDS copy).
+constexpr int kLogTab = 128;
+static __constant__ double c_logtab[2 * kLogTab];  // c_j, L_j (uploaded with the device math constants)
+// LDS copy of the log table for a block (every thread calls this, then a barrier follows)
+__device__ __forceinline__ void stage_logtab(double* dst) {
+  for (int i = threadIdx.x; i < 2 * kLogTab; i += blockDim.x) dst[i] = c_logtab[i];
+}
+__device__ __forceinline__ double fast_log(double x, const double* tab) {
   int e;
-  double m = frexp(x, &e);
-  if (m < 0.70710678118654752) {
-    m += m;
-    e -= 1;
-  }
-  const double f = m - 1.0;
-  const double s = f / (2.0 + f);
-  const double s2 = s * s;
-  double p = 2.0 / 25.0;
-  p = p * s2 + 2.0 / 23.0;
-  p = p * s2 + 2.0 / 21.0;
-  p = p * s2 + 2.0 / 19.0;
-  p = p * s2 + 2.0 / 17.0;
-  p = p * s2 + 2.0 / 15.0;
-  p = p * s2 + 2.0 / 13.0;
-  p = p * s2 + 2.0 / 11.0;
-  p = p * s2 + 2.0 / 9.0;
-  p = p * s2 + 2.0 / 7.0;
-  p = p * s2 + 2.0 / 5.0;
-  p = p * s2 + 2.0 / 3.0;
+  const double m = frexp(x, &e);
+  const int j = (int)((uint32_t)(__double_as_longlong(m) >> 45) & (kLogTab - 1));
+  const double2 cl = ((const double2*)tab)[j];
+  const double r = fma(m, cl.x, -1.0);
+  double p = fma(1.0 / 7.0, r, -1.0 / 6.0);
+  p = fma(p, r, 1.0 / 5.0);
+  p = fma(p, r, -1.0 / 4.0);
+  p = fma(p, r, 1.0 / 3.0);
+  p = fma(p, r, -1.0 / 2.0);
+  const double l1p = fma(r * r, p, r);
   const double ed = (double)e;
-  return ed * kLn2Hi + (ed * kLn2Lo + (2.0 * s + s * (s2 * p)));
+  return fma(ed, kLn2Hi, cl.y) + fma(ed, kLn2Lo, l1p);
 }
 
 // FP32 sin and cos of |x| <= 4 (phases already reduced in FP64): Cody-Waite by pi/2 in two FP32
-// parts, Taylor polynomials to r^11 and r^10.
+// parts, Taylor polynomials to r^11 and r^10 in fused multiply-adds, quadrant by selection.
 __device__ __forceinline__ void fast_sincosf(float x, float* sn, float* cs) {
   const float k = rintf(x * 0.636619772f);
-  const float r = (x - k * 1.57079637f) - k * -4.37113883e-8f;
+  const float r = fmaf(-k, -4.37113883e-8f, fmaf(-k, 1.57079637f, x));
   const float r2 = r * r;
-  const float ps = ((((-2.50521084e-8f * r2 + 2.75573192e-6f) * r2 - 1.98412698e-4f) * r2 + 8.33333333e-3f) * r2 -
-                    1.66666667e-1f);
-  const float sv = r + r * (r2 * ps);
-  const float pc = ((((2.08767570e-9f * r2 - 2.75573192e-7f) * r2 + 2.48015873e-5f) * r2 - 1.38888889e-3f) * r2 +
-                    4.16666667e-2f);
-  const float cv = (1.0f - 0.5f * r2) + r2 * (r2 * pc);
+  float ps = fmaf(-2.50521084e-8f, r2, 2.75573192e-6f);
+  float pc = fmaf(2.08767570e-9f, r2, -2.75573192e-7f);
+  ps = fmaf(ps, r2, -1.98412698e-4f);
+  pc = fmaf(pc, r2, 2.48015873e-5f);
+  ps = fmaf(ps, r2, 8.33333333e-3f);
+  pc = fmaf(pc, r2, -1.38888889e-3f);
+  ps = fmaf(ps, r2, -1.66666667e-1f);
+  pc = fmaf(pc, r2, 4.16666667e-2f);
+  const float sv = fmaf(r * r2, ps, r);
+  const float cv = fmaf(r2 * r2, pc, fmaf(-0.5f, r2, 1.0f));
   const int q = (int)k & 3;
-  *sn = q == 0 ? sv : q == 1 ? cv : q == 2 ? -sv : -cv;
-  *cs = q == 0 ? cv : q == 1 ? -sv : q == 2 ? -cv : sv;
+  float s = (q & 1) ? cv : sv, c = (q & 1) ? sv : cv;
+  if (q & 2) s = -s;
+  if (q == 1 || q == 2) c = -c;
+  *sn = s;
+  *cs = c;
 }
 
 // Per-instance constants of a field derived once per kernel and instance (fast paths only).
@@ -462,9 +473,9 @@ struct __attribute__((aligned(32))) PhotonRec32 {
 // A = t0 - x_b - psi0 + b dt n_x and S = dt (1 - n_x).  The pulse's E and B give
 // chi = (eps/2)(1 - n_x)|e(psi)| = c |e(psi)|, and the decrement of eq. 3,
 // a_pair chi T(chi)/eps dt, is a_pair |e| T(chi) S / 2.  So the record holds A, S and c:
-// 32 bytes in FP64 (one word of padding), 16 in the FP32-mixed form (A in FP64).
-struct __attribute__((aligned(32))) PhotonRecPW {
-  double A, S, c, pad;
+// 24 bytes in FP64, 16 in the FP32-mixed form (A in FP64).
+struct __attribute__((aligned(8))) PhotonRecPW {
+  double A, S, c;
 };
 struct __attribute__((aligned(16))) PhotonRecPW32 {
   double A;
@@ -475,10 +486,13 @@ using PhotonRecT = typename std::conditional<
     FK == QED_FIELD_LP_PULSE, typename std::conditional<MIXED, PhotonRecPW32, PhotonRecPW>::type,
     typename std::conditional<MIXED, PhotonRec32, PhotonRec>::type>::type;
 
-// bytes of one record for a precision and field kind (a multiple of 16)
+// bytes of one record for a precision and field kind (a multiple of 8)
 __host__ __device__ constexpr int photon_rec_bytes(bool mixed, int fk) {
-  return fk == QED_FIELD_LP_PULSE ? (mixed ? 16 : 32) : (mixed ? 32 : 64);
+  return fk == QED_FIELD_LP_PULSE ? (mixed ? 16 : 24) : (mixed ? 32 : 64);
 }
+static_assert(sizeof(PhotonRecPW) == 24 && sizeof(PhotonRecPW32) == 16 && sizeof(PhotonRec) == 64 &&
+                  sizeof(PhotonRec32) == 32,
+              "record sizes as photon_rec_bytes states them");
 
 // 1 - n_x of a direction k (|k| = eps) without cancellation for photons moving along +x
 __device__ __forceinline__ double one_minus_nx(double kx, double ky, double kz, double eps) {
@@ -508,17 +522,17 @@ __device__ inline void make_photon_rec(PhotonRecT<MIXED, FK>& R, const qed_field
   }
 }
 
-// Copies a record of `words16` 16-byte words (photon_rec_bytes / 16) from slot `src` to `dst`.
-__device__ __forceinline__ void move_rec(void* base, int words16, int64_t dst, int64_t src) {
-  uint4* b = (uint4*)base;
-  for (int w = 0; w < words16; ++w) b[dst * words16 + w] = b[src * words16 + w];
+// Copies a record of `words8` 8-byte words (photon_rec_bytes / 8) from slot `src` to `dst`.
+__device__ __forceinline__ void move_rec(void* base, int words8, int64_t dst, int64_t src) {
+  uint2* b = (uint2*)base;
+  for (int w = 0; w < words8; ++w) b[dst * words8 + w] = b[src * words8 + w];
 }
-__device__ __forceinline__ void swap_rec(void* base, int words16, int64_t i, int64_t j) {
-  uint4* b = (uint4*)base;
-  for (int w = 0; w < words16; ++w) {
-    const uint4 t = b[i * words16 + w];
-    b[i * words16 + w] = b[j * words16 + w];
-    b[j * words16 + w] = t;
+__device__ __forceinline__ void swap_rec(void* base, int words8, int64_t i, int64_t j) {
+  uint2* b = (uint2*)base;
+  for (int w = 0; w < words8; ++w) {
+    const uint2 t = b[i * words8 + w];
+    b[i * words8 + w] = b[j * words8 + w];
+    b[j * words8 + w] = t;
   }
 }
 
@@ -668,12 +682,13 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
 
 // h(eta) from an LDS copy; clamped outside [eta_min, eta_max], counting eta > eta_max.  The
 // rate only feeds the optical-depth decrement, so the device library's log serves.
-__device__ __forceinline__ double lookup_h(const double* sh, const Tabs& tb, double eta, unsigned& range) {
+__device__ __forceinline__ double lookup_h(const double* sh, const double* ltab, const Tabs& tb, double eta,
+                                           unsigned& range) {
   if (eta == INFINITY) {
     ++range;
     return sh[tb.n_eta - 1];
   }
-  const double s = (fast_log(eta) - tb.le0) / tb.dle;
+  const double s = (fast_log(eta, ltab) - tb.le0) * tb.idle;
   if (!(s > 0.0)) return sh[0];
   if (s >= tb.n_eta - 1) {
     ++range;
@@ -700,13 +715,14 @@ __device__ __forceinline__ double lookup_g(const double* sg, const Tabs& tb, dou
   return (1.0 - w) * sg[i] + w * sg[i + 1];
 }
 
-__device__ __forceinline__ double lookup_T(const double* sT, const Tabs& tb, double chi, unsigned& range) {
+__device__ __forceinline__ double lookup_T(const double* sT, const double* ltab, const Tabs& tb, double chi,
+                                           unsigned& range) {
   if (!(chi >= tb.cp_min)) return 0.0;  // below the table (T ~ 0) or NaN
   if (chi == INFINITY) {
     ++range;
     return sT[tb.n_cp - 1];
   }
-  const double s = (fast_log(chi) - tb.lc0) / tb.dlc;
+  const double s = (fast_log(chi, ltab) - tb.lc0) * tb.idlc;
   if (s < 0.0) return 0.0;
   if (s >= tb.n_cp - 1) {
     ++range;

@@ -60,6 +60,8 @@ void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob*
 void launch_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step, hipStream_t s);
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s);
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
+int photon_blocks_per_cu(int fk, int ppt, int block, int n_cp, bool mixed);
+int lepton_blocks_per_cu(int fk, int ppt, int block, int n_eta, bool mixed);
 void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);

@@ -100,10 +100,11 @@ __device__ __forceinline__ void field_at32(const qed_field& F, const FieldK& K, 
   }
 }
 
-__device__ __forceinline__ float lookup32(const float* tab, int n, double l0, double dl, float arg, unsigned& range,
+// rate look-up in FP32: `idl` is the reciprocal of the table's ln-spacing
+__device__ __forceinline__ float lookup32(const float* tab, int n, double l0, double idl, float arg, unsigned& range,
                                           bool zero_below) {
   if (!(arg > 0.0f)) return zero_below ? 0.0f : tab[0];
-  const float s = (logf(arg) - (float)l0) / (float)dl;
+  const float s = (logf(arg) - (float)l0) * (float)idl;
   if (!(s > 0.0f)) return zero_below ? (s < 0.0f ? 0.0f : tab[0]) : tab[0];
   if (s >= (float)(n - 1)) {
     ++range;

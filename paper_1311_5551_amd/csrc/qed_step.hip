@@ -188,6 +188,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double smem[];
   __shared__ qed_field sF;
+  __shared__ double sLog[2 * kLogTab];
   double* sh = smem;
   float* sh32 = (float*)smem;
   long long* s_ll = (long long*)(smem + a.tb.n_eta);  // 16 waves x 2 sums x 4 words
@@ -201,6 +202,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
     else sh[i] = a.tb.h[i];
   }
   for (int i = threadIdx.x; i < 16 * 2 * 4; i += blockDim.x) s_ll[i] = 0;
+  if (!MIXED) stage_logtab(sLog);
 
   const int64_t step = uni64(a.glob->step_cur);
   const double t = a.sc.t0 + (double)step * a.sc.dt;
@@ -414,7 +416,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
           const double r2 = (ax * ax + ay * ay + az * az) - ue * ue;
           const double eta = sqrt(r2 > 0.0 ? r2 : 0.0);
           if (eta > 0.0) {
-            const double h = lookup_h(sh, a.tb, eta, uacc[1]);
+            const double h = lookup_h(sh, sLog, a.tb, eta, uacc[1]);
             tau -= a.sc.a_gamma * (eta / g1) * h * dt;
             if (tau <= 0.0) {
               pend = true;
@@ -488,7 +490,7 @@ __global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
           const float r2 = (ax * ax + ay * ay + az * az) - ue * ue;
           const float eta = sqrtf(r2 > 0.0f ? r2 : 0.0f);
           if (eta > 0.0f) {
-            const float h = lookup32(sh32, a.tb.n_eta, a.tb.le0, a.tb.dle, eta, uacc[1], false);
+            const float h = lookup32(sh32, a.tb.n_eta, a.tb.le0, a.tb.idle, eta, uacc[1], false);
             tau -= agdt * ((double)eta / (double)g1) * (double)h;  // FP32 look-up, FP64 decrement
             if (tau <= 0.0) {
               pend = true;
@@ -800,14 +802,15 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   constexpr bool NEED_Y = FK == QED_FIELD_GRID_CP_STANDING;
   extern __shared__ double smem[];
   __shared__ qed_field sF;  // field of the instance being processed
+  __shared__ double sLog[2 * kLogTab];
   double* sT = smem;
   float* sT32 = (float*)smem;
   unsigned* sredu = (unsigned*)(smem + a.tb.n_cp);
-  unsigned* slist = sredu + 16 * 3;  // per wave: 64 * PPT slot offsets
   for (int i = threadIdx.x; i < a.tb.n_cp; i += blockDim.x) {
     if (MIXED) sT32[i] = a.tb.T32[i];
     else sT[i] = a.tb.T[i];
   }
+  if (!MIXED) stage_logtab(sLog);
 
   const int64_t step = uni64(a.glob->step_cur);
   const double t = a.sc.t0 + (double)step * a.sc.dt;
@@ -823,6 +826,8 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   gptr<double> TAU = nullptr;
   gptr<uint32_t> WIN = nullptr;
   using Rec = PhotonRecT<MIXED, FK>;
+  // dwords of a record the sweep reads: plane-wave {A, S, c}; general {k, x_b, y_b, birth step}
+  constexpr int kRecDw = FK == QED_FIELD_LP_PULSE ? (MIXED ? 4 : 6) : (MIXED ? 6 : 11);
   gptr<const Rec> REC = nullptr;
   gptr<const uint32_t> WSUM = nullptr;
   int64_t nseal = 0, pfirst = 0;
@@ -880,7 +885,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     // buffer resources over the chunk's live slots (uniform); lane offsets in bytes
     const uint32_t nlive = (uint32_t)(rem < CH ? rem : CH);
     const bufres rtau = make_buf(TAU + k0, nlive * 8u), rwin = make_buf(WIN + k0, nlive * 4u);
-    const gptr<const Rec> rrec = REC + k0;
+    const bufres rrec = make_buf(REC + k0, nlive * (uint32_t)sizeof(Rec));
     // the optical-depth step of a photon with pair rate T > 0; true when its depth reached zero
     auto decrement = [&](unsigned off, double T, double dtau, double tau) -> bool {
       bool pend = false;
@@ -920,7 +925,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
         const float r2 = (ax * ax + ay * ay + az * az) - ne * ne;
         const float chif = 0.5f * (float)eps * sqrtf(r2 > 0.0f ? r2 : 0.0f);
         chi = chif;
-        T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.dlc, chif, uacc[1], true);
+        T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.idlc, chif, uacc[1], true);
       } else {
         double E[3], Bf[3];
         field_at<FK, false>(sF, x, y, t, E, Bf, &fK);
@@ -930,7 +935,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
         const double ne = nx * E[0] + ny * E[1] + nz * E[2];
         const double r2 = (ax * ax + ay * ay + az * az) - ne * ne;
         chi = 0.5 * (double)eps * sqrt(r2 > 0.0 ? r2 : 0.0);
-        T = lookup_T(sT, a.tb, chi, uacc[1]);
+        T = lookup_T(sT, sLog, a.tb, chi, uacc[1]);
       }
       return decrement(off, T, rate * chi * T * (double)inv, tau);  // FP64 (chi, T, 1/eps FP32 if mixed)
     };
@@ -946,11 +951,11 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
           fast_sincosf(reduce_phase(psi + sF.p[3]), &d, &cs);
           const float e = fabsf((float)sF.p[0] * sn * sn * cs);
           ae = e;
-          T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.dlc, (float)cr * e, uacc[1], true);
+          T = lookup32(sT32, a.tb.n_cp, a.tb.lc0, a.tb.idlc, (float)cr * e, uacc[1], true);
         } else {
           const double sn = fast_sin(psi * fK.pi_over_len), cs = fast_cos(psi + sF.p[3]);
           ae = fabs(sF.p[0] * sn * sn * cs);
-          T = lookup_T(sT, a.tb, cr * ae, uacc[1]);
+          T = lookup_T(sT, sLog, a.tb, cr * ae, uacc[1]);
         }
       }
       return decrement(off, T, 0.5 * a.sc.a_pair * ae * T * S, tau);
@@ -988,12 +993,24 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     }
     const unsigned live = ~(unsigned)(mskip >> ((c - m0) * PPT)) & kAll;  // wave-uniform
     if (live == 0) continue;
-    // phase 1: the window of every slot of the live groups (4 B); a photon outside its window
-    // has no pair rate in this step (photon_window), so nothing else of it is read
+    // phase 1: the window, the record and the optical depth of every slot of the live groups,
+    // issued together, so that a chunk costs one memory round trip (loads past the chunk's live
+    // slots return zero).  The record and depth of a slot outside its window are read for
+    // nothing; where the partition keeps the in-window photons together that is a small share.
     uint32_t wv[PPT];
+    uint32_t q[PPT][kRecDw];
+    double tv[PPT];
 #pragma unroll
-    for (int j = 0; j < PPT; ++j)
-      wv[j] = (live >> j) & 1u ? (uint32_t)buf_ld<int32_t>(rwin, (threadIdx.x + j * B) * 4u) : kWinEmpty;
+    for (int j = 0; j < PPT; ++j) {
+      wv[j] = kWinEmpty;
+      tv[j] = 0.0;
+      if ((live >> j) & 1u) {
+        const unsigned off = threadIdx.x + j * B;
+        wv[j] = (uint32_t)buf_ld<int32_t>(rwin, off * 4u);
+        load_dwords<kRecDw>(rrec, off * (unsigned)sizeof(Rec), q[j]);
+        tv[j] = buf_ld<double>(rtau, off * 8u);
+      }
+    }
     unsigned gmask = 0;
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
@@ -1001,86 +1018,31 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       if (exists && ((live >> j) & 1u)) ++uacc[4];
       if (exists && in_window(wv[j], step)) gmask |= 1u << j;
     }
-    // phase 2: the photons inside their windows.  A wave with at least half of its slots inside
-    // (the partition at compaction keeps those photons together) evaluates them in place; a
-    // sparser wave first packs its photons densely through a per-wave LDS list, so that the
-    // in-field code runs on full waves however the photons are spread.
-    unsigned total = 0;
-#pragma unroll
-    for (int j = 0; j < PPT; ++j) total += (unsigned)__popcll(__ballot((gmask >> j) & 1u));
-    if (total == 0) continue;
-    const int lane = threadIdx.x & 63;
+    if (__ballot(gmask != 0) == 0ull) continue;
     uacc[3] += __popc(gmask);
-    typedef double dbl2 __attribute__((ext_vector_type(2)));
-    // one photon: its record (one line; the stored values, or the plane-wave phase and chi
-    // factors) and optical depth
-    auto eval = [&](unsigned off) -> bool {
-      const double tau = buf_ld<double>(rtau, off * 8u);
+    // one photon inside its window, from the dwords of its record and its optical depth
+    auto eval = [&](unsigned off, const uint32_t* w, double tau) -> bool {
+      auto dbl = [&](int i) { return __hiloint2double((int)w[i + 1], (int)w[i]); };
       if constexpr (FK == QED_FIELD_LP_PULSE) {
-        if (MIXED) {  // {A, S, c}: A in FP64
-          typedef unsigned u4 __attribute__((ext_vector_type(4)));
-          const u4 q = *(gptr<const u4>)(rrec + off);
-          const double A = __hiloint2double((int)q.y, (int)q.x);
-          return infield_pw(off, A, (double)__uint_as_float(q.z), (double)__uint_as_float(q.w), tau);
-        } else {
-          const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
-          const dbl2 q0 = q[0];
-          const double cr = ((gptr<const double>)(rrec + off))[2];
-          return infield_pw(off, q0.x, q0.y, cr, tau);
-        }
+        if (MIXED) return infield_pw(off, dbl(0), (double)__uint_as_float(w[2]), (double)__uint_as_float(w[3]), tau);
+        else return infield_pw(off, dbl(0), dbl(2), dbl(4), tau);
       } else if (MIXED) {
-        typedef float flt4 __attribute__((ext_vector_type(4)));
-        const gptr<const flt4> q = (gptr<const flt4>)(rrec + off);
-        const flt4 q0 = q[0], q1 = q[1];
-        return infield(off, (Real)q0.x, (Real)q0.y, (Real)q0.z, NEED_X ? (Real)q0.w : Real(0),
-                       NEED_Y ? (Real)q1.x : Real(0), NEED_X ? (int32_t)__float_as_uint(q1.y) : 0, tau);
+        return infield(off, (Real)__uint_as_float(w[0]), (Real)__uint_as_float(w[1]), (Real)__uint_as_float(w[2]),
+                       NEED_X ? (Real)__uint_as_float(w[3]) : Real(0), NEED_Y ? (Real)__uint_as_float(w[4]) : Real(0),
+                       NEED_X ? (int32_t)w[5] : 0, tau);
       } else {
-        const gptr<const dbl2> q = (gptr<const dbl2>)(rrec + off);
-        const dbl2 q0 = q[0], q1 = q[1], q2 = q[2];
-        return infield(off, (Real)q0.x, (Real)q0.y, (Real)q1.x, NEED_X ? (Real)q1.y : Real(0),
-                       NEED_Y ? (Real)q2.x : Real(0), NEED_X ? (int32_t)(uint32_t)__double_as_longlong(q2.y) : 0,
-                       tau);
+        return infield(off, (Real)dbl(0), (Real)dbl(2), (Real)dbl(4), NEED_X ? (Real)dbl(6) : Real(0),
+                       NEED_Y ? (Real)dbl(8) : Real(0), NEED_X ? (int32_t)w[10] : 0, tau);
       }
     };
-    if (2 * total >= 64u * PPT) {
+    // phase 2: the photons inside their windows, in place
 #pragma unroll
-      for (int j = 0; j < PPT; ++j) {
-        const unsigned off = threadIdx.x + j * B;
-        bool pend = false;
-        if ((gmask >> j) & 1u) pend = eval(off);
-        enqueue(off, pend);
-      }
-      continue;
-    }
-    unsigned* list = slist + (threadIdx.x >> 6) * (64 * PPT);
-    const int cnt = __popc(gmask);
-    int incl = cnt;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int v = __shfl_up(incl, o);
-      if (lane >= o) incl += v;
-    }
-    int w = incl - cnt;
-#pragma unroll
-    for (int j = 0; j < PPT; ++j)
-      if (gmask & (1u << j)) list[w++] = threadIdx.x + j * B;
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    for (int e0 = 0; e0 < (int)total; e0 += 64) {  // wave-uniform trip count
-      const int e = e0 + lane;
+    for (int j = 0; j < PPT; ++j) {
+      const unsigned off = threadIdx.x + j * B;
       bool pend = false;
-      unsigned off = 0;
-      if (e < (int)total) {
-        off = list[e];
-        pend = eval(off);
-      }
+      if ((gmask >> j) & 1u) pend = eval(off, q[j], tv[j]);
       enqueue(off, pend);
     }
-    // the list is rewritten for the next chunk only after every lane has read it
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
   }
   if (cur >= 0) flush(cur);
 }
@@ -1701,6 +1663,14 @@ hipError_t init_crmath() {
     f[n] = {s, q2 - (s - q1)};
   }
   e = hipMemcpyToSymbol(HIP_SYMBOL(c_inv_fact), f, sizeof(f));
+  // log table of fast_log: c_j = 1 / (centre of the j-th sub-interval of [1/2, 1)), L_j = -log c_j
+  double lt[2 * kLogTab];
+  for (int j = 0; j < kLogTab; ++j) {
+    const double c = 1.0 / (0.5 + (j + 0.5) / (2.0 * kLogTab));
+    lt[2 * j] = c;
+    lt[2 * j + 1] = -std::log(c);
+  }
+  if (e == hipSuccess) e = hipMemcpyToSymbol(HIP_SYMBOL(c_logtab), lt, sizeof(lt));
   if (e == hipSuccess && dev < 64) done |= 1ull << dev;
   return e;
 }
@@ -1770,8 +1740,39 @@ void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mix
   }
 }
 
+static size_t lepton_shm(int n_eta) {
+  return (size_t)n_eta * sizeof(double) + 16 * 2 * 4 * sizeof(long long) + 16 * 3 * sizeof(unsigned) + 64;
+}
+template <int FK, int PPT>
+static int lepton_fit_ppt(int block, size_t shm, bool mixed) {
+  int n = 0;
+  const hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_lepton<FK, PPT, true>, block, shm)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_lepton<FK, PPT, false>, block, shm);
+  return e == hipSuccess ? n : 0;
+}
+template <int FK>
+static int lepton_fit_fk(int ppt, int block, size_t shm, bool mixed) {
+  switch (ppt) {
+    case 1: return lepton_fit_ppt<FK, 1>(block, shm, mixed);
+    case 2: return lepton_fit_ppt<FK, 2>(block, shm, mixed);
+    case 8: return lepton_fit_ppt<FK, 8>(block, shm, mixed);
+    default: return lepton_fit_ppt<FK, 4>(block, shm, mixed);
+  }
+}
+// Blocks of the lepton sweep that fit on one CU at once (registers, LDS), for the shape given.
+int lepton_blocks_per_cu(int fk, int ppt, int block, int n_eta, bool mixed) {
+  const size_t shm = lepton_shm(n_eta);
+  switch (fk) {
+    case QED_FIELD_UNIFORM: return lepton_fit_fk<QED_FIELD_UNIFORM>(ppt, block, shm, mixed);
+    case QED_FIELD_LP_PULSE: return lepton_fit_fk<QED_FIELD_LP_PULSE>(ppt, block, shm, mixed);
+    case QED_FIELD_CP_WAVE: return lepton_fit_fk<QED_FIELD_CP_WAVE>(ppt, block, shm, mixed);
+    case QED_FIELD_CP_STANDING: return lepton_fit_fk<QED_FIELD_CP_STANDING>(ppt, block, shm, mixed);
+    default: return lepton_fit_fk<QED_FIELD_GRID_CP_STANDING>(ppt, block, shm, mixed);
+  }
+}
+
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
-  const size_t shm = (size_t)a.tb.n_eta * sizeof(double) + 16 * 2 * 4 * sizeof(long long) + 16 * 3 * sizeof(unsigned) + 64;
+  const size_t shm = lepton_shm(a.tb.n_eta);
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_lepton_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;
@@ -1793,10 +1794,38 @@ void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mix
   }
 }
 
+// Blocks of the photon sweep that fit on one CU at once (registers, LDS), for the shape given.
+template <int FK, int PPT>
+static int photon_fit_ppt(int block, size_t shm, bool mixed) {
+  int n = 0;
+  const hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_photon<FK, PPT, true>, block, shm)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_photon<FK, PPT, false>, block, shm);
+  return e == hipSuccess ? n : 0;
+}
+template <int FK>
+static int photon_fit_fk(int ppt, int block, size_t shm, bool mixed) {
+  switch (ppt) {
+    case 1: return photon_fit_ppt<FK, 1>(block, shm, mixed);
+    case 2: return photon_fit_ppt<FK, 2>(block, shm, mixed);
+    case 8: return photon_fit_ppt<FK, 8>(block, shm, mixed);
+    case 16: return photon_fit_ppt<FK, 16>(block, shm, mixed);
+    default: return photon_fit_ppt<FK, 4>(block, shm, mixed);
+  }
+}
+static size_t photon_shm(int n_cp) { return (size_t)n_cp * sizeof(double) + 16 * 3 * sizeof(unsigned) + 64; }
+int photon_blocks_per_cu(int fk, int ppt, int block, int n_cp, bool mixed) {
+  const size_t shm = photon_shm(n_cp);
+  switch (fk) {
+    case QED_FIELD_UNIFORM: return photon_fit_fk<QED_FIELD_UNIFORM>(ppt, block, shm, mixed);
+    case QED_FIELD_LP_PULSE: return photon_fit_fk<QED_FIELD_LP_PULSE>(ppt, block, shm, mixed);
+    case QED_FIELD_CP_WAVE: return photon_fit_fk<QED_FIELD_CP_WAVE>(ppt, block, shm, mixed);
+    case QED_FIELD_CP_STANDING: return photon_fit_fk<QED_FIELD_CP_STANDING>(ppt, block, shm, mixed);
+    default: return photon_fit_fk<QED_FIELD_GRID_CP_STANDING>(ppt, block, shm, mixed);
+  }
+}
+
 void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
-  // T table, block reduction, and the per-wave lists of in-window photon slots (64 * ppt each)
-  const size_t shm = (size_t)a.tb.n_cp * sizeof(double) + 16 * 3 * sizeof(unsigned) +
-                     (size_t)block * a.ppt * sizeof(unsigned) + 64;
+  const size_t shm = photon_shm(a.tb.n_cp);  // T table and block reduction
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_photon_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;
@@ -1834,7 +1863,7 @@ void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc
 
 void launch_compact(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
                     uint32_t* win, void* rec, uint32_t* wsum, bool mixed, const RetireSpec& rs, hipStream_t s) {
-  const int rw = photon_rec_bytes(mixed, fk) / 16;
+  const int rw = photon_rec_bytes(mixed, fk) / 8;
   RetireArgs r{};
   r.on = rs.on;
   r.n_bins = rs.n_bins;
