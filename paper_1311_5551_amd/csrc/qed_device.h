@@ -834,6 +834,33 @@ __device__ inline long long block_reserve(bool want, int64_t* counter, unsigned*
   return r;
 }
 
+// Rank of a wanting thread among the wanting threads of its block (in thread order), and the
+// block's total in *total; every thread of the block calls it (it holds two barriers).
+__device__ inline unsigned block_rank(bool want, unsigned* s_wave, unsigned* total) {
+  const unsigned long long m = __ballot(want);
+  const int lane = __lane_id(), wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  if (lane == 0) s_wave[wv] = (unsigned)__popcll(m);
+  __syncthreads();
+  unsigned before = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    const unsigned c = s_wave[w];
+    if (w < wv) before += c;
+    tot += c;
+  }
+  __syncthreads();  // s_wave is rewritten by the next call
+  *total = tot;
+  return before + (unsigned)__popcll(m & ((1ull << lane) - 1ull));
+}
+
+// The contiguous range [b0, b1) of [lo, hi) that block `blk` of `nblk` takes: equal shares,
+// each a multiple of the block size (so that every pass of the block covers whole blocks).
+__device__ __forceinline__ void block_range(int64_t lo, int64_t hi, int blk, int nblk, int64_t* b0, int64_t* b1) {
+  const int64_t len = hi > lo ? hi - lo : 0;
+  const int64_t per = ((len + nblk - 1) / nblk + blockDim.x - 1) / blockDim.x * blockDim.x;
+  *b0 = min(hi, lo + (int64_t)blk * per);
+  *b1 = min(hi, *b0 + per);
+}
+
 // wave_reserve for lanes whose counters may differ: lanes are served one key (counter) at a time.
 // Every lane of the wave must call it.
 __device__ inline long long wave_reserve_grouped(bool want, int key, int64_t* counter) {

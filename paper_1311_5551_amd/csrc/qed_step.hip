@@ -1502,19 +1502,34 @@ __global__ __launch_bounds__(256) void k_part_count(InstAcc* __restrict__ acc, c
   if (threadIdx.x == 0 && u[0]) atomicAdd((unsigned long long*)&acc[ii].n_live, (unsigned long long)u[0]);
 }
 
-// the photons of [D, n) whose window is over, listed in the mover array
+// the photons of [D, n) whose window is over, listed in the mover array.  Each block takes a
+// contiguous range: it counts its movers, reserves their places with one atomic, then lists
+// them in order (one contended atomic per block rather than per wave).
 __global__ __launch_bounds__(256) void k_part_movers(InstAcc* __restrict__ acc, const Glob* __restrict__ glob,
                                                      const uint32_t* __restrict__ win, int64_t* __restrict__ movers) {
+  __shared__ unsigned sredu[16];
+  __shared__ long long s_base;
   const int ii = blockIdx.y;
   const int64_t n = acc[ii].n_start[2], D = acc[ii].n_live, s = glob->step_next;
   const uint32_t* W = win + acc[ii].mover_off;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // loop bounds are identical across a wave so that every lane reaches the ballot
-  for (int64_t k0 = D + blockIdx.x * (int64_t)blockDim.x; k0 < n; k0 += stride) {
+  int64_t b0, b1;
+  block_range(D, n, blockIdx.x, gridDim.x, &b0, &b1);
+  if (b0 >= b1) return;  // the whole block
+  unsigned u[1] = {0};
+  for (int64_t k = b0 + threadIdx.x; k < b1; k += blockDim.x)
+    if (window_over(W[k], s)) ++u[0];
+  block_sum_u(u, sredu);
+  if (threadIdx.x == 0) s_base = u[0] ? (long long)atomicAdd((unsigned long long*)&acc[ii].mover_ctr, (unsigned long long)u[0]) : 0;
+  __syncthreads();
+  long long run = s_base;
+  int64_t* M = movers + acc[ii].mover_off;
+  for (int64_t k0 = b0; k0 < b1; k0 += blockDim.x) {  // block-uniform trip count
     const int64_t k = k0 + threadIdx.x;
-    const bool mv = k < n && window_over(W[k], s);
-    const long long slot = wave_reserve(mv, (int64_t*)&acc[ii].mover_ctr);
-    if (mv) movers[acc[ii].mover_off + slot] = k;
+    const bool mv = k < b1 && window_over(W[k], s);
+    unsigned tot;
+    const unsigned r = block_rank(mv, sredu, &tot);
+    if (mv) M[run + r] = k;
+    run += tot;
   }
 }
 
@@ -1538,12 +1553,26 @@ __global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restric
   const long long n_movers = (long long)acc[ii].mover_ctr;
   uint32_t* W = win + acc[ii].mover_off;
   const int64_t ro = acc[ii].mover_off;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const bool d3 = inst[ii].dims == 3;
-  for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < D; k0 += stride) {
+  // a contiguous range of [0, D) per block, its holes' places reserved with one atomic
+  __shared__ unsigned sredu[16];
+  __shared__ long long s_base;
+  int64_t b0, b1;
+  block_range(0, D, blockIdx.x, gridDim.x, &b0, &b1);
+  if (b0 >= b1) return;  // the whole block
+  unsigned u[1] = {0};
+  for (int64_t k = b0 + threadIdx.x; k < b1; k += blockDim.x)
+    if (!window_over(W[k], s)) ++u[0];
+  block_sum_u(u, sredu);
+  if (threadIdx.x == 0) s_base = u[0] ? (long long)atomicAdd((unsigned long long*)&acc[ii].hole_ctr, (unsigned long long)u[0]) : 0;
+  __syncthreads();
+  long long run = s_base;
+  for (int64_t k0 = b0; k0 < b1; k0 += blockDim.x) {  // block-uniform trip count
     const int64_t k = k0 + threadIdx.x;
-    const bool sw = k < D && !window_over(W[k], s);
-    const long long slot = wave_reserve(sw, (int64_t*)&acc[ii].hole_ctr);
+    const bool sw = k < b1 && !window_over(W[k], s);
+    unsigned tot;
+    const long long slot = run + block_rank(sw, sredu, &tot);
+    run += tot;
     // the two counts are equal (both are D minus the front's photons that stay); the bounds
     // below only guard that invariant
     if (sw && slot < n_movers) {
