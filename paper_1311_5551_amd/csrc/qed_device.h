@@ -318,8 +318,10 @@ constexpr double f2 = 1.0 / 2.0, f3 = 1.0 / 6.0, f4 = 1.0 / 24.0, f5 = 1.0 / 120
 }  // namespace fastm
 
 // sin and cos of x, |x| < 2^20: x = k pi/2 + r by Cody-Waite reduction (pi/2 in three parts, the
-// first with 33 bits so that k times it is exact), |r| <= pi/4, Taylor polynomials to r^17 and
-// r^18 (truncation below 1e-19) in fused multiply-adds; quadrant from k mod 4.  Error a few ulp.
+// first with 33 bits so that k times it is exact), |r| <= pi/4, Taylor polynomials to r^13 and
+// r^14 in fused multiply-adds (truncation below 3e-14 and 1e-15 relative); quadrant from k mod 4.
+// These values only set optical-depth decrements, where the parity bars allow 1e-10 in the
+// depth; the short polynomials keep the kernels' 64-bit constants (scalar registers) few.
 // Both polynomials are evaluated and the quadrant selects (no divergent branch).
 __device__ __forceinline__ void fast_sincos_r(double x, double* sv, double* cv, int* q) {
   using namespace fastm;
@@ -328,12 +330,8 @@ __device__ __forceinline__ void fast_sincos_r(double x, double* sv, double* cv, 
   r = fma(-k, kPio2B, r);
   r = fma(-k, kPio2C, r);
   const double r2 = r * r;
-  double ps = fma(f17, r2, -f15);
-  double pc = fma(f18, r2, -f16);
-  ps = fma(ps, r2, f13);
-  pc = fma(pc, r2, f14);
-  ps = fma(ps, r2, -f11);
-  pc = fma(pc, r2, -f12);
+  double ps = fma(f13, r2, -f11);
+  double pc = fma(f14, r2, -f12);
   ps = fma(ps, r2, f9);
   pc = fma(pc, r2, f10);
   ps = fma(ps, r2, -f7);
@@ -342,8 +340,8 @@ __device__ __forceinline__ void fast_sincos_r(double x, double* sv, double* cv, 
   pc = fma(pc, r2, f6);
   ps = fma(ps, r2, -f3);
   pc = fma(pc, r2, -f4);
-  *sv = fma(r * r2, ps, r);                          // r + r^3 (-1/3! + ...)
-  *cv = fma(r2 * r2, -pc, fma(-f2, r2, 1.0));        // 1 - r^2/2 + r^4 (1/4! - ...)
+  *sv = fma(r * r2, ps, r);                    // r + r^3 (-1/3! + ...)
+  *cv = fma(r2 * r2, -pc, fma(-0.5, r2, 1.0));  // 1 - r^2/2 + r^4 (1/4! - ...)
   *q = (int)(int64_t)k;
 }
 __device__ __forceinline__ void fast_sincos(double x, double* sn, double* cs) {
@@ -372,8 +370,8 @@ __device__ __forceinline__ double fast_cos(double x) { return fast_sinq(x, 1); }
 // [1/2, 1); j = the 7 mantissa bits after the leading one picks c_j ~ 1/m (the centre of the
 // j-th of 128 equal sub-intervals) and L_j = -log c_j (both rounded to double, computed on the
 // host); r = m c_j - 1 (one rounding, |r| <= 2^-8) and log x = e log 2 + L_j + log1p(r), the
-// series of log1p to r^7 (truncation below 1e-20).  Absolute error ~1e-16: the value only
-// places a look-up between table rows.  `tab` holds c_j, L_j interleaved (an LDS copy).
+// series of log1p to r^5 (truncation below 1e-17 absolute).  Absolute error ~1e-16: the value
+// only places a look-up between table rows.  `tab` holds c_j, L_j interleaved (an LDS copy).
 constexpr int kLogTab = 128;
 static __constant__ double c_logtab[2 * kLogTab];  // c_j, L_j (uploaded with the device math constants)
 // LDS copy of the log table for a block (every thread calls this, then a barrier follows)
@@ -386,11 +384,9 @@ __device__ __forceinline__ double fast_log(double x, const double* tab) {
   const int j = (int)((uint32_t)(__double_as_longlong(m) >> 45) & (kLogTab - 1));
   const double2 cl = ((const double2*)tab)[j];
   const double r = fma(m, cl.x, -1.0);
-  double p = fma(1.0 / 7.0, r, -1.0 / 6.0);
-  p = fma(p, r, 1.0 / 5.0);
-  p = fma(p, r, -1.0 / 4.0);
+  double p = fma(1.0 / 5.0, r, -0.25);
   p = fma(p, r, 1.0 / 3.0);
-  p = fma(p, r, -1.0 / 2.0);
+  p = fma(p, r, -0.5);
   const double l1p = fma(r * r, p, r);
   const double ed = (double)e;
   return fma(ed, kLn2Hi, cl.y) + fma(ed, kLn2Lo, l1p);

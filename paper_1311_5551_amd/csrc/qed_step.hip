@@ -184,7 +184,9 @@ struct LepPtr {
 };
 
 template <int FK, int PPT, bool MIXED>
-__global__ __launch_bounds__(256) void k_lepton(StepArgs a) {
+// (three waves per SIMD: the register budget of 168 that allows it costs at most a few spilled
+// words in the larger instantiations, and the sweep is latency-bound)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_lepton(StepArgs a) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double smem[];
   __shared__ qed_field sF;
@@ -838,17 +840,22 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   FieldK fK{0.0};
   // in-field steps, chi above the table, non-finite tau, in-window steps, window reads, summary reads
   unsigned uacc[6] = {0, 0, 0, 0, 0, 0};
+  // the counters of the instance just left: lane sums through LDS atomics (few registers on
+  // this rare path), then one global atomic per counter
   auto flush = [&](int ii) {
-    block_sum_u(uacc, sredu);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < 6) sredu[threadIdx.x] = 0u;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+      if (uacc[c]) atomicAdd(&sredu[c], uacc[c]);
+    __syncthreads();
+    if (threadIdx.x < 6 && sredu[threadIdx.x]) {
       InstAcc& A = a.acc[ii];
-      if (uacc[0]) atomicAdd(&A.n_field, (unsigned long long)uacc[0]);
-      if (uacc[1]) atomicAdd(&A.n_range, (unsigned long long)uacc[1]);
-      if (uacc[2]) atomicAdd(&A.n_nonfinite, (unsigned long long)uacc[2]);
-      if (uacc[3]) atomicAdd(&A.n_active, (unsigned long long)uacc[3]);
-      if (uacc[4]) atomicAdd(&A.n_win_reads, (unsigned long long)uacc[4]);
-      if (uacc[5]) atomicAdd(&A.n_group_reads, (unsigned long long)uacc[5]);
+      unsigned long long* const dst[6] = {&A.n_field,  &A.n_range,     &A.n_nonfinite,
+                                          &A.n_active, &A.n_win_reads, &A.n_group_reads};
+      atomicAdd(dst[threadIdx.x], (unsigned long long)sredu[threadIdx.x]);
     }
+    __syncthreads();  // sredu is reused by the next flush
     uacc[0] = uacc[1] = uacc[2] = uacc[3] = uacc[4] = uacc[5] = 0;
   };
 
