@@ -30,6 +30,7 @@ FIELD_LP_PULSE = 1
 FIELD_CP_WAVE = 2
 FIELD_CP_STANDING = 3
 FIELD_GRID_CP_STANDING = 4
+FIELD_GRID_FDTD = 5      # p = {Q}: Yee grid advanced by Maxwell's equations with the leptons' current
 
 SPECIES = ("electron", "positron", "photon")
 
@@ -117,6 +118,13 @@ def lib():
             getattr(L, name).argtypes = [C.POINTER(_Config)] + [C.c_double] * 7
             getattr(L, name).restype = C.c_double
         L.oracle_run.restype = C.c_int
+        L.oracle_run_pic.argtypes = [C.POINTER(_Config), C.POINTER(_Tables), C.POINTER(_Species),
+                                     C.POINTER(_Species), C.POINTER(_Ledger), _DP]
+        L.oracle_run_pic.restype = C.c_int
+        L.oracle_deposit.argtypes = [C.POINTER(_Config)] + [C.c_double] * 6 + [_DP]
+        L.oracle_deposit.restype = None
+        L.oracle_fdtd_step.argtypes = [C.POINTER(_Config), _DP]
+        L.oracle_fdtd_step.restype = None
         L.oracle_num_threads.restype = C.c_int
         _LIB = L
     return _LIB
@@ -333,8 +341,33 @@ def chi(cfg: RunConfig, x, y, z, t, kx, ky, kz):
     return _vec(lambda *a: lib().oracle_chi(C.byref(conf), *a), x, y, z, t, kx, ky, kz)
 
 
-def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=None, capacity=None):
+def deposit(cfg: RunConfig, Q, x0, y0, x1, y1, vz, J=None):
+    """The current planes (3, ny, nx: Jx, Jy, Jz) of one macro-particle of charge Q moving in one
+    step of cfg.dt from (x0, y0) to (x1, y1) with z velocity vz, added to J (zeros if None)."""
+    conf = _config(cfg)
+    nx, ny = cfg.grid[0], cfg.grid[1]
+    out = np.zeros((3, ny, nx)) if J is None else np.ascontiguousarray(J, dtype=np.float64).copy()
+    lib().oracle_deposit(C.byref(conf), float(Q), float(x0), float(y0), float(x1), float(y1), float(vz),
+                         out.ctypes.data_as(_DP))
+    return out
+
+
+def fdtd_step(cfg: RunConfig, F):
+    """One step of the Yee solver on the nine planes F (9, ny, nx: Ex Ey Ez Bx By Bz Jx Jy Jz);
+    returns the advanced planes (the current planes unchanged)."""
+    conf = _config(cfg)
+    out = np.ascontiguousarray(F, dtype=np.float64).copy()
+    assert out.shape == (9, cfg.grid[1], cfg.grid[0])
+    lib().oracle_fdtd_step(C.byref(conf), out.ctypes.data_as(_DP))
+    return out
+
+
+def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=None, capacity=None, fields=None):
     """Advance every family rooted at the given particles; return (species dict, ledger dict).
+
+    With ``cfg.field_kind == FIELD_GRID_FDTD`` the run couples the particles to the grid
+    (field feedback): ``fields`` holds the nine planes (9, ny, nx) at the start, and the planes
+    at the end are returned in the ledger as ``fields``.
 
     Each species input is a dict of arrays x, y, z, ux, uy, uz, uid (and tau when
     ``cfg.draw_initial_tau`` is False; photons may carry ``birth_step``).  Outputs hold
@@ -387,11 +420,17 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
             o.birth = b["birth_step"].ctypes.data_as(C.POINTER(C.c_int64))
             outs[i] = o
         led = _Ledger()
-        rc = L.oracle_run(C.byref(conf), C.byref(tab), ins, outs, C.byref(led))
+        if cfg.field_kind == FIELD_GRID_FDTD:
+            F = np.ascontiguousarray(fields, dtype=np.float64).copy()  # a fresh copy for each attempt
+            assert F.shape == (9, cfg.grid[1], cfg.grid[0])
+            rc = L.oracle_run_pic(C.byref(conf), C.byref(tab), ins, outs, C.byref(led), F.ctypes.data_as(_DP))
+        else:
+            rc = L.oracle_run(C.byref(conf), C.byref(tab), ins, outs, C.byref(led))
         if rc == 0:
             break
         if rc == -2:
-            raise ValueError("oracle_run: inconsistent radiation-reaction flags (or no g table)")
+            raise ValueError("oracle_run: inconsistent flags (radiation reaction without its table, or "
+                             "field feedback outside 2-D or with radiation reaction)")
         # outputs did not fit: retry with the sizes the oracle reported (same result, deterministic)
         cap = [int(outs[i].count) + 1 for i in range(3)]
     else:
@@ -408,6 +447,8 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
                   radiated=led.radiated,
                   n_emit=led.n_emit, n_null=led.n_null, n_pair=led.n_pair, n_range=led.n_range,
                   n_nonfinite=led.n_nonfinite, particle_steps=led.particle_steps)
+    if cfg.field_kind == FIELD_GRID_FDTD:
+        ledger["fields"] = F
     return res, ledger
 
 

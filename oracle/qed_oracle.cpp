@@ -642,7 +642,9 @@ enum : int32_t {
   FIELD_LP_PULSE = 1,     // p = {E0, Psi, psi0, phase}: E_y = B_z = E0 env(psi) cos(psi + phase)
   FIELD_CP_WAVE = 2,      // p = {E0, phase}: E = E0 (cos, sin) in (y, z), B = x_hat cross E
   FIELD_CP_STANDING = 3,  // p = {E0}: two counter-propagating circularly polarised waves
-  FIELD_GRID_CP_STANDING = 4  // same source sampled on a 2-D Yee grid (FP32) and gathered (CIC)
+  FIELD_GRID_CP_STANDING = 4,  // same source sampled on a 2-D Yee grid (FP32) and gathered (CIC)
+  FIELD_GRID_FDTD = 5  // p = {Q}: the fields of a 2-D Yee grid (FP64) advanced by Maxwell's equations
+                       // with the current of the leptons (charge q Q per macro-particle); gathered (CIC)
 };
 
 struct Tables {
@@ -677,6 +679,7 @@ struct Config {
   uint64_t seed, instance;
   uint32_t flags;
   double kappa, a_gamma, a_pair, a_rr;
+  double* fdtd = nullptr;  // FIELD_GRID_FDTD: 9 planes of ny x nx nodes, Ex Ey Ez Bx By Bz Jx Jy Jz
 };
 
 struct Vec3 {
@@ -734,6 +737,113 @@ double cic_gather(const Grid& g, int comp, double x, double y, NodeFn node) {
          wx * wy * node(ib, jb);
 }
 
+// --- field feedback (Sec. 3.2: charge and current of the macro-particles on the grid, then
+// Maxwell's equations for E and B).  Code units: dE/dt = curl B - J, dB/dt = -curl E, and
+// div E = rho; a macro-particle of charge Q (per unit length along z) has the density
+// Q S_x S_y / (dx dy) with the first-order (cloud-in-cell) shape S of the gather.
+
+// Current of one macro-particle of charge Q moving in one step from (x0, y0) to (x1, y1), less
+// than a cell in each direction, with out-of-plane velocity vz: the charge-conserving split of
+// Esirkepov (Comput. Phys. Commun. 135, 144, 2001) for first-order shapes in 2-D.  With the
+// old and new shape factors S0, S1 of the (up to) three nodes per direction the particle
+// touches and D = S1 - S0:
+//   Wx = Dx (S0y + Dy/2),   Wy = Dy (S0x + Dx/2),
+//   Wz = S0x S0y + Dx S0y / 2 + S0x Dy / 2 + Dx Dy / 3,
+//   Jx(i+1/2, j) = -Q/(dy dt) sum_{i' <= i} Wx(i', j),   Jy(i, j+1/2) = -Q/(dx dt) sum_{j' <= j} Wy(i, j'),
+//   Jz(i, j) = Q vz Wz(i, j) / (dx dy),
+// so that (rho1 - rho0)/dt + (Jx(i+1/2) - Jx(i-1/2))/dx + (Jy(j+1/2) - Jy(j-1/2))/dy = 0 node by
+// node.  J holds the planes Jx, Jy, Jz (ny x nx each, Jx at Ex's nodes, Jy at Ey's, Jz at Ez's).
+void deposit_current(const Grid& g, double Q, double dt, double x0, double y0, double x1, double y1, double vz,
+                     double* J) {
+  const double gx0 = (x0 - g.x0) / g.dx, gy0 = (y0 - g.y0) / g.dy;
+  const double gx1 = (x1 - g.x0) / g.dx, gy1 = (y1 - g.y0) / g.dy;
+  const double bx = std::floor(std::min(gx0, gx1)), by = std::floor(std::min(gy0, gy1));
+  const int64_t I = (int64_t)bx, Jn = (int64_t)by;
+  double S0x[3], S1x[3], S0y[3], S1y[3];
+  for (int a = 0; a < 3; ++a) {
+    S0x[a] = std::max(0.0, 1.0 - std::fabs(gx0 - (bx + a)));
+    S1x[a] = std::max(0.0, 1.0 - std::fabs(gx1 - (bx + a)));
+    S0y[a] = std::max(0.0, 1.0 - std::fabs(gy0 - (by + a)));
+    S1y[a] = std::max(0.0, 1.0 - std::fabs(gy1 - (by + a)));
+  }
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  const double cx = -Q / (g.dy * dt), cy = -Q / (g.dx * dt), cz = Q * vz / (g.dx * g.dy);
+  for (int b = 0; b < 3; ++b) {
+    const int64_t j = wrap(Jn + b, g.ny);
+    double run = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t i = wrap(I + a, g.nx);
+      const double dxa = S1x[a] - S0x[a], dyb = S1y[b] - S0y[b];
+      run += dxa * (S0y[b] + 0.5 * dyb);
+      J[j * g.nx + i] += cx * run;
+      const double wz = S0x[a] * S0y[b] + 0.5 * dxa * S0y[b] + 0.5 * S0x[a] * dyb + dxa * dyb / 3.0;
+      J[2 * plane + j * g.nx + i] += cz * wz;
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    const int64_t i = wrap(I + a, g.nx);
+    double run = 0.0;
+    for (int b = 0; b < 3; ++b) {
+      const int64_t j = wrap(Jn + b, g.ny);
+      const double dxa = S1x[a] - S0x[a], dyb = S1y[b] - S0y[b];
+      run += dyb * (S0x[a] + 0.5 * dxa);
+      J[plane + j * g.nx + i] += cy * run;
+    }
+  }
+}
+
+// One step of Maxwell's equations on the Yee grid (periodic), leapfrog in the form that keeps E
+// and B at the same time level: B advanced half a step with E^n, E a full step with that B and
+// the current J^{n+1/2}, B the second half step with E^{n+1}.  In cell indices (each component
+// stored at its own staggered node, index (i, j)):
+//   Bx(i,j) -= (dt/2) (Ez(i,j+1) - Ez(i,j))/dy
+//   By(i,j) += (dt/2) (Ez(i+1,j) - Ez(i,j))/dx
+//   Bz(i,j) -= (dt/2) ((Ey(i+1,j) - Ey(i,j))/dx - (Ex(i,j+1) - Ex(i,j))/dy)
+//   Ex(i,j) += dt ((Bz(i,j) - Bz(i,j-1))/dy - Jx(i,j))
+//   Ey(i,j) += dt (-(Bz(i,j) - Bz(i-1,j))/dx - Jy(i,j))
+//   Ez(i,j) += dt ((By(i,j) - By(i-1,j))/dx - (Bx(i,j) - Bx(i,j-1))/dy - Jz(i,j))
+// F holds the nine planes Ex Ey Ez Bx By Bz Jx Jy Jz.
+void fdtd_half_b(const Grid& g, double dt, double* F) {
+  const int64_t P = (int64_t)g.nx * g.ny;
+  const double h = 0.5 * dt;
+  std::vector<double> bx(P), by(P), bz(P);
+  for (int64_t j = 0; j < g.ny; ++j)
+    for (int64_t i = 0; i < g.nx; ++i) {
+      const int64_t k = j * g.nx + i, ip = j * g.nx + wrap(i + 1, g.nx), jp = wrap(j + 1, g.ny) * g.nx + i;
+      const double* Ex = F;
+      const double* Ey = F + P;
+      const double* Ez = F + 2 * P;
+      bx[k] = F[3 * P + k] - h * ((Ez[jp] - Ez[k]) / g.dy);
+      by[k] = F[4 * P + k] + h * ((Ez[ip] - Ez[k]) / g.dx);
+      bz[k] = F[5 * P + k] - h * ((Ey[ip] - Ey[k]) / g.dx - (Ex[jp] - Ex[k]) / g.dy);
+    }
+  std::copy(bx.begin(), bx.end(), F + 3 * P);
+  std::copy(by.begin(), by.end(), F + 4 * P);
+  std::copy(bz.begin(), bz.end(), F + 5 * P);
+}
+void fdtd_full_e(const Grid& g, double dt, double* F) {
+  const int64_t P = (int64_t)g.nx * g.ny;
+  std::vector<double> ex(P), ey(P), ez(P);
+  for (int64_t j = 0; j < g.ny; ++j)
+    for (int64_t i = 0; i < g.nx; ++i) {
+      const int64_t k = j * g.nx + i, im = j * g.nx + wrap(i - 1, g.nx), jm = wrap(j - 1, g.ny) * g.nx + i;
+      const double* Bx = F + 3 * P;
+      const double* By = F + 4 * P;
+      const double* Bz = F + 5 * P;
+      ex[k] = F[k] + dt * ((Bz[k] - Bz[jm]) / g.dy - F[6 * P + k]);
+      ey[k] = F[P + k] + dt * (-(Bz[k] - Bz[im]) / g.dx - F[7 * P + k]);
+      ez[k] = F[2 * P + k] + dt * ((By[k] - By[im]) / g.dx - (Bx[k] - Bx[jm]) / g.dy - F[8 * P + k]);
+    }
+  std::copy(ex.begin(), ex.end(), F);
+  std::copy(ey.begin(), ey.end(), F + P);
+  std::copy(ez.begin(), ez.end(), F + 2 * P);
+}
+void fdtd_step(const Grid& g, double dt, double* F) {
+  fdtd_half_b(g, dt, F);
+  fdtd_full_e(g, dt, F);
+  fdtd_half_b(g, dt, F);
+}
+
 void fields_at(const Config& c, double x, double y, double z, double t, Vec3* E, Vec3* B) {
   double f[6] = {0, 0, 0, 0, 0, 0};
   switch (c.field) {
@@ -766,6 +876,14 @@ void fields_at(const Config& c, double x, double y, double z, double t, Vec3* E,
       // first-order (cloud-in-cell) gather from each staggered component grid
       for (int comp = 0; comp < 6; ++comp)
         f[comp] = cic_gather(c.grid, comp, x, y, [&](int64_t i, int64_t j) { return grid_node(c, comp, i, j, t); });
+      break;
+    }
+    case FIELD_GRID_FDTD: {
+      // the same gather from the solver's grid as it stands at this step
+      const int64_t plane = (int64_t)c.grid.nx * c.grid.ny;
+      for (int comp = 0; comp < 6; ++comp)
+        f[comp] = cic_gather(c.grid, comp, x, y,
+                             [&](int64_t i, int64_t j) { return c.fdtd[comp * plane + j * c.grid.nx + i]; });
       break;
     }
     default:
@@ -929,9 +1047,10 @@ double chi_of(Vec3 E, Vec3 B, Vec3 nh, double eps) {
   return 0.5 * eps * std::sqrt(std::max(0.0, dot(a, a) - ne * ne));
 }
 
-// one step of an electron (q = -1) or positron (q = +1); children are appended to `fam`
+// one step of an electron (q = -1) or positron (q = +1); children are appended to `fam`.
+// vz_push (optional) receives the z velocity u1z/gamma1 of the push (the one that moved it).
 void step_lepton(Particle& p, const Config& c, const Tables& tb, int64_t n, std::vector<Particle>& fam,
-                 Tally& tl) {
+                 Tally& tl, double* vz_push = nullptr) {
   const double t = c.t0 + (double)n * c.dt;
   Vec3 E, B;
   fields_at(c, p.x, p.y, p.z, t, &E, &B);
@@ -954,6 +1073,7 @@ void step_lepton(Particle& p, const Config& c, const Tables& tb, int64_t n, std:
   p.x += c.dt * u1.x / g1;
   p.y += c.dt * u1.y / g1;
   if (c.dims == 3) p.z += c.dt * u1.z / g1;
+  if (vz_push) *vz_push = u1.z / g1;
   p.ux = u1.x;
   p.uy = u1.y;
   p.uz = u1.z;
@@ -1331,6 +1451,149 @@ int oracle_run(const oracle_config* cfg, const oracle_tables* tab, const oracle_
   }
   for (int s = 0; s < 3; ++s) out[s].count = need[s];
   return fits ? 0 : -1;
+}
+
+// Runs n_steps steps of configuration FIELD_GRID_FDTD with field feedback (Sec. 3.2): every
+// step, each particle present at its start is advanced with the fields of the grid as they
+// stand (leptons first pushed, then the emission step; photons the pair step), each lepton's
+// current is deposited from its positions before and after the push, and then the grid
+// advances one step of Maxwell's equations with that current.  Families are coupled through
+// the grid, so the run goes step by step over all particles (one thread).  `fields` holds the
+// nine planes Ex Ey Ez Bx By Bz Jx Jy Jz (ny x nx each) in and out; the current planes on
+// return hold the last step's current.  Outputs and ledger as oracle_run.
+int oracle_run_pic(const oracle_config* cfg, const oracle_tables* tab, const oracle_species* in,
+                   oracle_species* out, oracle_ledger* led, double* fields) {
+  Config c = config_of(cfg);
+  if (c.field != FIELD_GRID_FDTD || c.dims != 2) return -2;
+  if (c.flags & (FLAG_RR_QUANTUM | FLAG_RR_CLASSICAL)) return -2;
+  c.fdtd = fields;
+  Tables tb;
+  tb.n_eta = tab->n_eta;
+  tb.le0 = std::log(tab->eta_min);
+  tb.dle = (std::log(tab->eta_max) - tb.le0) / (tab->n_eta - 1);
+  tb.h = tab->h;
+  tb.g = tab->g;
+  tb.n_chi = tab->n_chi;
+  tb.lnchi_min = tab->lnchi_min;
+  tb.dlnchi = tab->dlnchi;
+  tb.P = tab->P_chi;
+  tb.n_cp = tab->n_chi_pair;
+  tb.lc0 = std::log(tab->chi_pair_min);
+  tb.dlc = (std::log(tab->chi_pair_max) - tb.lc0) / (tab->n_chi_pair - 1);
+  tb.T = tab->T;
+  tb.n_f = tab->n_f;
+  tb.f = tab->f_grid;
+  tb.Pf = tab->P_f;
+
+  std::vector<Particle> all;
+  std::vector<int64_t> family;
+  std::memset(led, 0, sizeof(*led));
+  for (int s = 0; s < 3; ++s) {
+    for (int64_t i = 0; i < in[s].count; ++i) {
+      Particle p;
+      p.x = in[s].x[i];
+      p.y = in[s].y[i];
+      p.z = 0.0;
+      p.ux = in[s].ux[i];
+      p.uy = in[s].uy[i];
+      p.uz = in[s].uz[i];
+      p.uid = in[s].uid[i];
+      p.birth = in[s].birth ? in[s].birth[i] : 0;
+      p.species = s;
+      p.margin = INFINITY;
+      p.alive = true;
+      if (cfg->draw_initial_tau) {
+        uint64_t r[4];
+        draw(c, p.uid, 0, KIND_INIT, 0, r);
+        p.tau = optical_depth_draw(r[0]);
+      } else {
+        p.tau = in[s].tau[i];
+      }
+      led->energy0[s] += (s == 2) ? std::sqrt(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz) : gamma_of(p.ux, p.uy, p.uz);
+      family.push_back((int64_t)all.size());
+      all.push_back(p);
+    }
+  }
+  const int64_t plane = (int64_t)c.grid.nx * c.grid.ny;
+  double* J = fields + 6 * plane;
+  Tally tl;
+  for (int64_t n = c.step0; n < c.step0 + c.n_steps; ++n) {
+    std::fill(J, J + 3 * plane, 0.0);
+    const size_t present = all.size();
+    for (size_t i = 0; i < present; ++i) {
+      if (!all[i].alive) continue;
+      Particle p = all[i];  // copy: push_back may reallocate while the particle is advanced
+      const size_t before = all.size();
+      if (p.species == 2) {
+        if (c.flags & FLAG_PROPAGATE) {
+          step_photon(p, c, tb, n, all, tl);
+          ++tl.particle_steps;
+        }
+      } else {
+        const double x0 = p.x, y0 = p.y;
+        double vz = 0.0;
+        step_lepton(p, c, tb, n, all, tl, &vz);
+        ++tl.particle_steps;
+        const double Q = (p.species == 0 ? -1.0 : 1.0) * c.fp[0];
+        deposit_current(c.grid, Q, c.dt, x0, y0, p.x, p.y, vz, J);
+      }
+      all[i] = p;
+      for (size_t k = before; k < all.size(); ++k) family.push_back(family[i]);
+    }
+    fdtd_step(c.grid, c.dt, fields);
+  }
+
+  led->work = tl.work;
+  led->defect_emit = tl.defect_emit;
+  led->defect_pair = tl.defect_pair;
+  led->n_emit = tl.n_emit;
+  led->n_null = tl.n_null;
+  led->n_pair = tl.n_pair;
+  led->n_range = tl.n_range;
+  led->n_nonfinite = tl.n_nonfinite;
+  led->particle_steps = tl.particle_steps;
+  int64_t need[3] = {0, 0, 0};
+  for (const Particle& p : all)
+    if (p.alive) ++need[p.species];
+  bool fits = true;
+  for (int s = 0; s < 3; ++s)
+    if (need[s] > out[s].capacity) fits = false;
+  int64_t w[3] = {0, 0, 0};
+  for (size_t i = 0; i < all.size(); ++i) {
+    const Particle& p = all[i];
+    if (!p.alive) continue;
+    const int s = p.species;
+    led->energy[s] += (s == 2) ? std::sqrt(p.ux * p.ux + p.uy * p.uy + p.uz * p.uz) : gamma_of(p.ux, p.uy, p.uz);
+    led->count[s] += 1;
+    if (fits) {
+      const int64_t k = w[s]++;
+      out[s].x[k] = p.x;
+      out[s].y[k] = p.y;
+      if (out[s].z) out[s].z[k] = p.z;
+      out[s].ux[k] = p.ux;
+      out[s].uy[k] = p.uy;
+      out[s].uz[k] = p.uz;
+      out[s].tau[k] = p.tau;
+      out[s].uid[k] = p.uid;
+      if (out[s].margin) out[s].margin[k] = p.margin;
+      if (out[s].family) out[s].family[k] = family[i];
+      if (out[s].birth) out[s].birth[k] = p.birth;
+    }
+  }
+  for (int s = 0; s < 3; ++s) out[s].count = need[s];
+  return fits ? 0 : -1;
+}
+
+// The current of one macro-particle move (deposit_current) added to the three planes J, and one
+// step of the Yee solver on the nine planes F, for tests of the two pieces alone.
+void oracle_deposit(const oracle_config* cfg, double Q, double x0, double y0, double x1, double y1, double vz,
+                    double* J) {
+  const Config c = config_of(cfg);
+  deposit_current(c.grid, Q, c.dt, x0, y0, x1, y1, vz, J);
+}
+void oracle_fdtd_step(const oracle_config* cfg, double* F) {
+  const Config c = config_of(cfg);
+  fdtd_step(c.grid, c.dt, F);
 }
 
 int oracle_num_threads(void) {
