@@ -60,8 +60,16 @@ enum {
                                     B = x_hat x E (Sec. 2.4 test configuration) */
   QED_FIELD_CP_STANDING = 3,     /* p = {E0}: two counter-propagating CP waves, E_y = 2E0 cos t cos x,
                                     E_z = 2E0 sin t cos x, B_y = 2E0 cos t sin x, B_z = 2E0 sin t sin x */
-  QED_FIELD_GRID_CP_STANDING = 4 /* the standing wave written each step onto a 2-D Yee grid (FP32) and
+  QED_FIELD_GRID_CP_STANDING = 4, /* the standing wave written each step onto a 2-D Yee grid (FP32) and
                                     gathered with first-order (cloud-in-cell) weights (Sec. 3.2) */
+  QED_FIELD_GRID_FDTD = 5        /* p = {Q}: field feedback (Sec. 3.2, the coupling to a PIC code): the
+                                    fields of a 2-D Yee grid (FP64, fdtd_dev) gathered as above; after
+                                    each step the leptons' current (charge -Q electrons, +Q positrons
+                                    per macro-particle, code units, per unit length along z) is
+                                    deposited with the charge-conserving split of Esirkepov for
+                                    first-order shapes, and the grid advances one step of Maxwell's
+                                    equations (dE/dt = curl B - J, dB/dt = -curl E; B half a step,
+                                    E a full step, B half a step).  FP64 only, 2-D only. */
 };
 
 /* ---------------------------------------------------------------------------
@@ -139,6 +147,12 @@ typedef struct {
                                        Bx(i, j+1/2), By(i+1/2, j), Bz(i+1/2, j+1/2); periodic */
   int32_t nx, ny;
   double dx, dy, x0, y0;
+  double* fdtd_dev;                 /* QED_FIELD_GRID_FDTD: 9 x ny x nx doubles, caller-owned, read and
+                                       written by qed_step: Ex, Ey, Ez, Bx, By, Bz at the staggered
+                                       nodes above (E and B both at the start of the next step), then
+                                       Jx, Jy, Jz at the nodes of Ex, Ey, Ez (zero between steps: the
+                                       library clears them once the step's field update has used
+                                       them; the caller passes them zeroed).  Else NULL. */
 } qed_field;
 
 typedef struct {
@@ -214,7 +228,8 @@ qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_
 qed_status qed_run(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params,
                    int64_t n_steps, int32_t graph_steps, qed_stream stream);
 
-/* Reorders the particles of every bound instance with a grid field (QED_FIELD_GRID_CP_STANDING)
+/* Reorders the particles of every bound instance with a grid field (QED_FIELD_GRID_CP_STANDING,
+ * QED_FIELD_GRID_FDTD)
  * by 8 x 8-cell tile of their position (photons: position at the start of the next step, using
  * params->dt), so that neighbouring particles gather from the same grid cache lines.  A counting
  * sort and a permutation of every array of each species; the order within a tile is not
@@ -291,10 +306,10 @@ qed_status qed_energy_ledger(qed_workspace* ws, qed_ledger* out, qed_stream stre
 /* Kernel timing with HIP events recorded around each kernel of qed_step on its stream (not
  * available inside qed_run's graph replay).  qed_profile_read synchronises and writes, for the
  * QED_PROFILE_CLASSES kernel classes [0] step set-up (snapshot, grid refresh), [1] lepton
- * sweep, [2] photon sweep, [3] pair-creation pass, [4] photon-emission pass, the summed
- * durations in milliseconds and the launch counts since qed_profile(ws, 1) or the previous
- * read, and keeps timing. */
-#define QED_PROFILE_CLASSES 5
+ * sweep, [2] photon sweep, [3] pair-creation pass, [4] photon-emission pass, [5] field solver
+ * (QED_FIELD_GRID_FDTD), the summed durations in milliseconds and the launch counts since
+ * qed_profile(ws, 1) or the previous read, and keeps timing. */
+#define QED_PROFILE_CLASSES 6
 qed_status qed_profile(qed_workspace* ws, int32_t enable);
 qed_status qed_profile_read(qed_workspace* ws, double* ms, int64_t* launches);
 

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libqed.so")
-SOURCES = ["qed_capi.hip", "qed_tables.hip", "qed_step.hip", "qed_sort.hip"]
+SOURCES = ["qed_capi.hip", "qed_tables.hip", "qed_step.hip", "qed_sort.hip", "qed_fdtd.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

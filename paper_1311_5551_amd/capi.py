@@ -16,10 +16,11 @@ STATUS_NAMES = {0: "QED_OK", -1: "QED_ERR_ARG", -2: "QED_ERR_HIP", -3: "QED_ERR_
 QED_FP64, QED_FP32_MIXED = 0, 1
 QED_EMIT, QED_PAIRS, QED_PROPAGATE = 1, 2, 4
 QED_RR_QUANTUM, QED_RR_CLASSICAL = 8, 16
-QED_PROFILE_CLASSES = 5
+QED_PROFILE_CLASSES = 6
 QED_KERNEL_LEPTON, QED_KERNEL_PHOTON = 1, 2
 QED_FIELD_UNIFORM, QED_FIELD_LP_PULSE, QED_FIELD_CP_WAVE, QED_FIELD_CP_STANDING, QED_FIELD_GRID_CP_STANDING = \
     0, 1, 2, 3, 4
+QED_FIELD_GRID_FDTD = 5
 
 _vp = C.c_void_p
 _DP = C.POINTER(C.c_double)
@@ -47,7 +48,7 @@ class qed_species(C.Structure):
 
 class qed_field(C.Structure):
     _fields_ = [("kind", C.c_int32), ("p", C.c_double * 16), ("grid_dev", _vp), ("nx", C.c_int32), ("ny", C.c_int32),
-                ("dx", C.c_double), ("dy", C.c_double), ("x0", C.c_double), ("y0", C.c_double)]
+                ("dx", C.c_double), ("dy", C.c_double), ("x0", C.c_double), ("y0", C.c_double), ("fdtd_dev", _vp)]
 
 
 class qed_instance(C.Structure):

@@ -112,6 +112,7 @@ struct qed_workspace {
   qed_precision prec = QED_FP64;
   int field_kind = 0;
   bool any_grid = false;
+  int64_t fdtd_work = 0;  // field-feedback kind: work items of the largest grid's solver pass (0: none)
   std::vector<qed_instance> inst;
   std::vector<double> e0;
   qed_instance* d_inst = nullptr;
@@ -417,6 +418,11 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
     launch_pair_events(ws->field_kind, a, ws->cus, 256, mixed, s);
     mark_end(ws, m, s);
   }
+  if (ws->fdtd_work) {  // field feedback: the grid advances with the current the step deposited
+    m = mark_begin(ws, 5, s);
+    launch_fdtd(ws->d_inst, ws->n_inst, (int)std::min<int64_t>(ws->fdtd_work, 1 << 30), p->dt, s);
+    mark_end(ws, m, s);
+  }
   HIP_TRY(hipGetLastError());
   return QED_OK;
 }
@@ -435,6 +441,8 @@ qed_status ensure_windows(const qed_tables* tb, qed_workspace* ws, const qed_ste
   ws->win_cp_min = cp_min;
   return QED_OK;
 }
+
+static bool grid_kind(int kind) { return kind == QED_FIELD_GRID_CP_STANDING || kind == QED_FIELD_GRID_FDTD; }
 
 // The emission queue holds every wave segment of the lepton sweep (EmitQueue): the bound lepton
 // slots plus the rounding of the chunk list (a partial chunk per species list) and of the blocks'
@@ -673,7 +681,7 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
     if (I.dims != 2 && I.dims != 3) return fail(QED_ERR_ARG, "instance %d: dims = %d (2 or 3)", i, I.dims);
     if (!finite_pos(I.weight)) return fail(QED_ERR_ARG, "instance %d: weight must be finite and positive", i);
     const qed_field& F = I.field;
-    if (F.kind < QED_FIELD_UNIFORM || F.kind > QED_FIELD_GRID_CP_STANDING)
+    if (F.kind < QED_FIELD_UNIFORM || F.kind > QED_FIELD_GRID_FDTD)
       return fail(QED_ERR_ARG, "instance %d: unknown field kind %d", i, F.kind);
     if (F.kind != inst[0].field.kind)
       return fail(QED_ERR_ARG, "instance %d: all bound instances must share one field kind", i);
@@ -681,10 +689,21 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
       if (!std::isfinite(F.p[k])) return fail(QED_ERR_ARG, "instance %d: field parameter %d not finite", i, k);
     if (F.kind == QED_FIELD_LP_PULSE && !finite_pos(F.p[1]))
       return fail(QED_ERR_ARG, "instance %d: pulse length must be positive", i);
-    if (F.kind == QED_FIELD_GRID_CP_STANDING) {
+    if (grid_kind(F.kind)) {
       if (F.nx < 2 || F.ny < 2 || !finite_pos(F.dx) || !finite_pos(F.dy) || !std::isfinite(F.x0) || !std::isfinite(F.y0))
         return fail(QED_ERR_ARG, "instance %d: grid shape invalid", i);
-      if ((st = check_dev_range(F.grid_dev, (size_t)6 * F.nx * F.ny * 4, "grid_dev", i, -1))) return st;
+      if ((int64_t)F.nx * F.ny > ((int64_t)1 << 31)) return fail(QED_ERR_ARG, "instance %d: grid above 2^31 nodes", i);
+    }
+    if (F.kind == QED_FIELD_GRID_CP_STANDING &&
+        (st = check_dev_range(F.grid_dev, (size_t)6 * F.nx * F.ny * 4, "grid_dev", i, -1)))
+      return st;
+    if (F.kind == QED_FIELD_GRID_FDTD) {
+      // the deposit assumes moves below a cell per step, which the solver's Courant condition
+      // (dt < 1/sqrt(1/dx^2 + 1/dy^2)) implies for particles slower than light
+      if (mixed || I.dims != 2) return fail(QED_ERR_ARG, "instance %d: the field-feedback kind runs in FP64, 2-D", i);
+      if (!(params->dt * std::sqrt(1.0 / (F.dx * F.dx) + 1.0 / (F.dy * F.dy)) < 1.0))
+        return fail(QED_ERR_ARG, "instance %d: dt above the Yee Courant limit of the grid", i);
+      if ((st = check_dev_range(F.fdtd_dev, (size_t)9 * F.nx * F.ny * 8, "fdtd_dev", i, -1))) return st;
     }
     for (int s = 0; s < 3; ++s) {
       const qed_species& S = I.s[s];
@@ -720,6 +739,10 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
   ws->prec = params->precision;
   ws->field_kind = inst[0].field.kind;
   ws->any_grid = inst[0].field.kind == QED_FIELD_GRID_CP_STANDING;
+  ws->fdtd_work = 0;
+  for (int i = 0; i < n_inst; ++i)
+    if (inst[i].field.kind == QED_FIELD_GRID_FDTD)
+      ws->fdtd_work = std::max<int64_t>(ws->fdtd_work, (int64_t)inst[i].field.ny * ((inst[i].field.nx + 255) / 256));
   // compaction scratch: one mover index per photon slot
   std::vector<InstAcc> acc0(n_inst);
   std::memset(acc0.data(), 0, n_inst * sizeof(InstAcc));
@@ -864,7 +887,7 @@ qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream
   int64_t cap = 0;
   int tiles = 0;
   for (const qed_instance& I : ws->inst) {
-    if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    if (!grid_kind(I.field.kind)) continue;
     for (int s = 0; s < 3; ++s) cap = std::max<int64_t>(cap, I.s[s].capacity);
     tiles = std::max(tiles, ((I.field.nx + 7) / 8) * ((I.field.ny + 7) / 8));
   }
@@ -889,7 +912,7 @@ qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream
   const bool mixed = ws->prec == QED_FP32_MIXED;
   for (int ii = 0; ii < ws->n_inst; ++ii) {
     const qed_instance& I = ws->inst[ii];
-    if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    if (!grid_kind(I.field.kind)) continue;
     for (int s = 0; s < 3; ++s) {
       if (I.s[s].capacity == 0) continue;
       HIP_TRY(launch_sort_species(ws->d_inst, I, ii, s, ws->d_glob, params->dt, mixed, ws->sort, ws->cus * 8,
@@ -907,7 +930,7 @@ qed_status qed_sort_static(qed_workspace* ws, const qed_step_params* params, qed
   int64_t cap = 0;
   int tiles = 0;
   for (const qed_instance& I : ws->inst) {
-    if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    if (!grid_kind(I.field.kind)) continue;
     for (int s = 0; s < 3; ++s) cap = std::max<int64_t>(cap, I.s[s].capacity);
     tiles = std::max(tiles, ((I.field.nx + 7) / 8) * ((I.field.ny + 7) / 8));
   }
@@ -926,7 +949,7 @@ qed_status qed_sort_static(qed_workspace* ws, const qed_step_params* params, qed
   const bool mixed = ws->prec == QED_FP32_MIXED;
   for (int ii = 0; ii < ws->n_inst; ++ii) {
     const qed_instance& I = ws->inst[ii];
-    if (I.field.kind != QED_FIELD_GRID_CP_STANDING) continue;
+    if (!grid_kind(I.field.kind)) continue;
     for (int s = 0; s < 3; ++s) {
       if (I.s[s].capacity == 0) continue;
       HIP_TRY(launch_sort_species(ws->d_inst, I, ii, s, ws->d_glob, params->dt, mixed, w, ws->cus * 8,

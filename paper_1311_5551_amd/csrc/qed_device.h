@@ -439,6 +439,8 @@ __device__ __forceinline__ double field_bound(const qed_field& F) {
     case QED_FIELD_LP_PULSE:
     case QED_FIELD_CP_WAVE:
       return 2.0 * fabs(F.p[0]);
+    case QED_FIELD_GRID_FDTD:  // evolving fields: no bound
+      return INFINITY;
     default:  // standing waves: |E|, |B| <= 2 a each
       return 4.0 * fabs(F.p[0]);
   }
@@ -593,6 +595,99 @@ __device__ inline int2 photon_window(const qed_field& F, double eps_min, double 
   return make_int2(ilo, ihi);
 }
 
+// First-order (cloud-in-cell) gather of the six components at (x, y): bilinear weights over the
+// four nodes around the point on each component's staggered grid (Yee offsets), periodic; node
+// values of type T (FP32 refreshed grid, FP64 solver grid).
+template <class T>
+__device__ __forceinline__ void cic_gather6(const qed_field& F, const T* base, double x, double y, double E[3],
+                                            double B[3]) {
+  const double ox[6] = {0.5, 0.0, 0.0, 0.0, 0.5, 0.5};
+  const double oy[6] = {0.0, 0.5, 0.0, 0.5, 0.0, 0.5};
+  const int64_t plane = (int64_t)F.nx * F.ny;
+  double v[6];
+#pragma unroll
+  for (int c = 0; c < 6; ++c) {
+    const double gx = (x - F.x0) / F.dx - ox[c];
+    const double gy = (y - F.y0) / F.dy - oy[c];
+    const double fx = floor(gx), fy = floor(gy);
+    const double wx = gx - fx, wy = gy - fy;
+    const int64_t i0 = (int64_t)fx, j0 = (int64_t)fy;
+    const int64_t ia = wrap_index(i0, F.nx), ib = wrap_index(i0 + 1, F.nx);
+    const int64_t ja = wrap_index(j0, F.ny), jb = wrap_index(j0 + 1, F.ny);
+    gptr<const T> g = as_global(base + c * plane);
+    const double g00 = g[ja * F.nx + ia], g10 = g[ja * F.nx + ib];
+    const double g01 = g[jb * F.nx + ia], g11 = g[jb * F.nx + ib];
+    v[c] = (1.0 - wx) * (1.0 - wy) * g00 + wx * (1.0 - wy) * g10 + (1.0 - wx) * wy * g01 + wx * wy * g11;
+  }
+  E[0] = v[0];
+  E[1] = v[1];
+  E[2] = v[2];
+  B[0] = v[3];
+  B[1] = v[4];
+  B[2] = v[5];
+}
+
+// Current of one macro-particle of charge Q moving in one step (dt) from (x0, y0) to (x1, y1),
+// less than a cell in each direction, with z velocity vz, added to the planes J (Jx, Jy, Jz at
+// the nodes of Ex, Ey, Ez): the charge-conserving split of Esirkepov for first-order shapes in
+// 2-D.  With the old and new shape factors S0, S1 of the (up to) three nodes per direction the
+// particle touches and D = S1 - S0: Wx = Dx (S0y + Dy/2), Wy = Dy (S0x + Dx/2),
+// Wz = S0x S0y + Dx S0y/2 + S0x Dy/2 + Dx Dy/3; Jx(i+1/2, j) = -Q/(dy dt) sum_{i'<=i} Wx,
+// Jy(i, j+1/2) = -Q/(dx dt) sum_{j'<=j} Wy, Jz = Q vz Wz/(dx dy).  The discrete continuity
+// equation then holds node by node for the cloud-in-cell density.  FP64 atomic adds (the
+// order of the sums over particles is not fixed).
+__device__ __forceinline__ void deposit_current(const qed_field& F, double Q, double dt, double x0, double y0,
+                                                double x1, double y1, double vz) {
+  const double gx0 = (x0 - F.x0) / F.dx, gy0 = (y0 - F.y0) / F.dy;
+  const double gx1 = (x1 - F.x0) / F.dx, gy1 = (y1 - F.y0) / F.dy;
+  const double bx = floor(fmin(gx0, gx1)), by = floor(fmin(gy0, gy1));
+  const int64_t I = (int64_t)bx, Jn = (int64_t)by;
+  double S0x[3], S1x[3], S0y[3], S1y[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    S0x[a] = fmax(0.0, 1.0 - fabs(gx0 - (bx + a)));
+    S1x[a] = fmax(0.0, 1.0 - fabs(gx1 - (bx + a)));
+    S0y[a] = fmax(0.0, 1.0 - fabs(gy0 - (by + a)));
+    S1y[a] = fmax(0.0, 1.0 - fabs(gy1 - (by + a)));
+  }
+  const int64_t plane = (int64_t)F.nx * F.ny;
+  double* const Jx = F.fdtd_dev + 6 * plane;
+  double* const Jy = Jx + plane;
+  double* const Jz = Jy + plane;
+  const double cx = -Q / (F.dy * dt), cy = -Q / (F.dx * dt), cz = Q * vz / (F.dx * F.dy);
+  int64_t ii[3], jj[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    ii[a] = wrap_index(I + a, F.nx);
+    jj[a] = wrap_index(Jn + a, F.ny);
+  }
+#pragma unroll
+  for (int b = 0; b < 3; ++b) {
+    double run = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const double dxa = S1x[a] - S0x[a], dyb = S1y[b] - S0y[b];
+      run += dxa * (S0y[b] + 0.5 * dyb);
+      const double wz = S0x[a] * S0y[b] + 0.5 * dxa * S0y[b] + 0.5 * S0x[a] * dyb + dxa * dyb / 3.0;
+      const int64_t k = jj[b] * F.nx + ii[a];
+      const double jx = cx * run, jz = cz * wz;
+      if (jx != 0.0) unsafeAtomicAdd(Jx + k, jx);
+      if (jz != 0.0) unsafeAtomicAdd(Jz + k, jz);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double run = 0.0;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const double dxa = S1x[a] - S0x[a], dyb = S1y[b] - S0y[b];
+      run += dyb * (S0x[a] + 0.5 * dxa);
+      const double jy = cy * run;
+      if (jy != 0.0) unsafeAtomicAdd(Jy + jj[b] * F.nx + ii[a], jy);
+    }
+  }
+}
+
 template <int FK, bool EXACT = true>
 __device__ __forceinline__ void field_at(const qed_field& F, double x, double y, double t, double E[3],
                                          double B[3], const FieldK* K = nullptr) {
@@ -644,31 +739,9 @@ __device__ __forceinline__ void field_at(const qed_field& F, double x, double y,
     B[1] = 2.0 * F.p[0] * ct * sx;
     B[2] = 2.0 * F.p[0] * st * sx;
   } else if (FK == QED_FIELD_GRID_CP_STANDING) {
-    // first-order shape: bilinear weights on each staggered component grid
-    const double ox[6] = {0.5, 0.0, 0.0, 0.0, 0.5, 0.5};
-    const double oy[6] = {0.0, 0.5, 0.0, 0.5, 0.0, 0.5};
-    const int64_t plane = (int64_t)F.nx * F.ny;
-    double v[6];
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      const double gx = (x - F.x0) / F.dx - ox[c];
-      const double gy = (y - F.y0) / F.dy - oy[c];
-      const double fx = floor(gx), fy = floor(gy);
-      const double wx = gx - fx, wy = gy - fy;
-      const int64_t i0 = (int64_t)fx, j0 = (int64_t)fy;
-      const int64_t ia = wrap_index(i0, F.nx), ib = wrap_index(i0 + 1, F.nx);
-      const int64_t ja = wrap_index(j0, F.ny), jb = wrap_index(j0 + 1, F.ny);
-      gptr<const float> g = as_global((const float*)F.grid_dev + c * plane);
-      const double g00 = g[ja * F.nx + ia], g10 = g[ja * F.nx + ib];
-      const double g01 = g[jb * F.nx + ia], g11 = g[jb * F.nx + ib];
-      v[c] = (1.0 - wx) * (1.0 - wy) * g00 + wx * (1.0 - wy) * g10 + (1.0 - wx) * wy * g01 + wx * wy * g11;
-    }
-    E[0] = v[0];
-    E[1] = v[1];
-    E[2] = v[2];
-    B[0] = v[3];
-    B[1] = v[4];
-    B[2] = v[5];
+    cic_gather6(F, (const float*)F.grid_dev, x, y, E, B);
+  } else if (FK == QED_FIELD_GRID_FDTD) {
+    cic_gather6(F, (const double*)F.fdtd_dev, x, y, E, B);
   }
 }
 

@@ -61,6 +61,9 @@ void launch_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step, hipStre
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s);
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 int photon_blocks_per_cu(int fk, int ppt, int block, int n_cp, bool mixed);
+// one step of the field solver of every QED_FIELD_GRID_FDTD instance; max_nodes_rows: the largest
+// instance's rows times its runs of 256 columns (the work items of one pass)
+void launch_fdtd(const qed_instance* inst, int n_inst, int max_nodes_rows, double dt, hipStream_t s);
 int lepton_blocks_per_cu(int fk, int ppt, int block, int n_eta, bool mixed);
 void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);

@@ -72,6 +72,14 @@ __device__ __forceinline__ void field_at32(const qed_field& F, const FieldK& K, 
     E[2] = e2 * st * cx;
     B[1] = e2 * ct * sx;
     B[2] = e2 * st * sx;
+  } else if (FK == QED_FIELD_GRID_FDTD) {
+    // (the binding runs this kind in FP64 only; the gather is here for completeness)
+    double e[3], b[3];
+    cic_gather6(F, (const double*)F.fdtd_dev, x, y, e, b);
+    for (int k = 0; k < 3; ++k) {
+      E[k] = (float)e[k];
+      B[k] = (float)b[k];
+    }
   } else if (FK == QED_FIELD_GRID_CP_STANDING) {
     const float ox[6] = {0.5f, 0.0f, 0.0f, 0.0f, 0.5f, 0.5f};
     const float oy[6] = {0.0f, 0.5f, 0.0f, 0.5f, 0.0f, 0.5f};

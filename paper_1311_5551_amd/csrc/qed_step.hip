@@ -221,6 +221,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   LepPtr<MIXED> P{};
   bool d3 = false;
   double hq = 0.0;
+  double qch = 0.0;  // charge of the species (-1 electrons, +1 positrons)
   float tpf0 = 0.0f, psif_max = 0.0f;
   FieldK fK{0.0};
   // field work and energy radiated (deterministic reaction): exact fixed-point words per wave in
@@ -277,7 +278,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       P.tau = as_global(uni_ptr(S.tau_dev));
       n = uni64(a.acc[ii].n_start[sp]);
       d3 = uni32(I.dims) == 3;
-      hq = 0.5 * (sp == 0 ? -1.0 : 1.0) * a.sc.kappa * dt;
+      qch = sp == 0 ? -1.0 : 1.0;
+      hq = 0.5 * qch * a.sc.kappa * dt;
       __syncthreads();
       const uint64_t* src = (const uint64_t*)&I.field;
       for (int w = threadIdx.x; w < (int)(sizeof(qed_field) / 8); w += B) ((uint64_t*)&sF)[w] = src[w];
@@ -389,6 +391,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         x += dt * u1x / g1;
         y += dt * u1y / g1;
         if (d3) z += dt * u1z / g1;
+        // field feedback: the current of this move onto the solver's grid
+        if constexpr (FK == QED_FIELD_GRID_FDTD) deposit_current(sF, qch * sF.p[0], dt, st.x, st.y, x, y, u1z / g1);
         double wx = u1x, wy = u1y, wz = u1z;  // stored momentum
         if (rr) {
           // continuous reaction (eqs. 8, 9): gamma -> max(gamma - (2/3) alpha kappa eta^2 g dt, 1)
@@ -801,7 +805,7 @@ template <int FK, int PPT, bool MIXED>
 __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   constexpr bool NEED_X = FK != QED_FIELD_UNIFORM;
-  constexpr bool NEED_Y = FK == QED_FIELD_GRID_CP_STANDING;
+  constexpr bool NEED_Y = FK == QED_FIELD_GRID_CP_STANDING || FK == QED_FIELD_GRID_FDTD;
   extern __shared__ double smem[];
   __shared__ qed_field sF;  // field of the instance being processed
   __shared__ double sLog[2 * kLogTab];
@@ -1772,6 +1776,7 @@ void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mix
     case QED_FIELD_LP_PULSE: launch_emit_events_fk<QED_FIELD_LP_PULSE>(a, g, b, shm, s, mixed); break;
     case QED_FIELD_CP_WAVE: launch_emit_events_fk<QED_FIELD_CP_WAVE>(a, g, b, shm, s, mixed); break;
     case QED_FIELD_CP_STANDING: launch_emit_events_fk<QED_FIELD_CP_STANDING>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_GRID_FDTD: launch_emit_events_fk<QED_FIELD_GRID_FDTD>(a, g, b, shm, s, mixed); break;
     default: launch_emit_events_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, shm, s, mixed); break;
   }
 }
@@ -1803,6 +1808,7 @@ int lepton_blocks_per_cu(int fk, int ppt, int block, int n_eta, bool mixed) {
     case QED_FIELD_LP_PULSE: return lepton_fit_fk<QED_FIELD_LP_PULSE>(ppt, block, shm, mixed);
     case QED_FIELD_CP_WAVE: return lepton_fit_fk<QED_FIELD_CP_WAVE>(ppt, block, shm, mixed);
     case QED_FIELD_CP_STANDING: return lepton_fit_fk<QED_FIELD_CP_STANDING>(ppt, block, shm, mixed);
+    case QED_FIELD_GRID_FDTD: return lepton_fit_fk<QED_FIELD_GRID_FDTD>(ppt, block, shm, mixed);
     default: return lepton_fit_fk<QED_FIELD_GRID_CP_STANDING>(ppt, block, shm, mixed);
   }
 }
@@ -1815,6 +1821,7 @@ void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, h
     case QED_FIELD_LP_PULSE: launch_lepton_fk<QED_FIELD_LP_PULSE>(a, g, b, shm, s, mixed); break;
     case QED_FIELD_CP_WAVE: launch_lepton_fk<QED_FIELD_CP_WAVE>(a, g, b, shm, s, mixed); break;
     case QED_FIELD_CP_STANDING: launch_lepton_fk<QED_FIELD_CP_STANDING>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_GRID_FDTD: launch_lepton_fk<QED_FIELD_GRID_FDTD>(a, g, b, shm, s, mixed); break;
     default: launch_lepton_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, shm, s, mixed); break;
   }
 }
@@ -1826,6 +1833,7 @@ void launch_pair_events(int fk, const StepArgs& a, int grid, int block, bool mix
     case QED_FIELD_LP_PULSE: launch_pair_events_fk<QED_FIELD_LP_PULSE>(a, g, b, s, mixed); break;
     case QED_FIELD_CP_WAVE: launch_pair_events_fk<QED_FIELD_CP_WAVE>(a, g, b, s, mixed); break;
     case QED_FIELD_CP_STANDING: launch_pair_events_fk<QED_FIELD_CP_STANDING>(a, g, b, s, mixed); break;
+    case QED_FIELD_GRID_FDTD: launch_pair_events_fk<QED_FIELD_GRID_FDTD>(a, g, b, s, mixed); break;
     default: launch_pair_events_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, s, mixed); break;
   }
 }
@@ -1856,6 +1864,7 @@ int photon_blocks_per_cu(int fk, int ppt, int block, int n_cp, bool mixed) {
     case QED_FIELD_LP_PULSE: return photon_fit_fk<QED_FIELD_LP_PULSE>(ppt, block, shm, mixed);
     case QED_FIELD_CP_WAVE: return photon_fit_fk<QED_FIELD_CP_WAVE>(ppt, block, shm, mixed);
     case QED_FIELD_CP_STANDING: return photon_fit_fk<QED_FIELD_CP_STANDING>(ppt, block, shm, mixed);
+    case QED_FIELD_GRID_FDTD: return photon_fit_fk<QED_FIELD_GRID_FDTD>(ppt, block, shm, mixed);
     default: return photon_fit_fk<QED_FIELD_GRID_CP_STANDING>(ppt, block, shm, mixed);
   }
 }
@@ -1868,6 +1877,7 @@ void launch_photon(int fk, const StepArgs& a, int grid, int block, bool mixed, h
     case QED_FIELD_LP_PULSE: launch_photon_fk<QED_FIELD_LP_PULSE>(a, g, b, shm, s, mixed); break;
     case QED_FIELD_CP_WAVE: launch_photon_fk<QED_FIELD_CP_WAVE>(a, g, b, shm, s, mixed); break;
     case QED_FIELD_CP_STANDING: launch_photon_fk<QED_FIELD_CP_STANDING>(a, g, b, shm, s, mixed); break;
+    case QED_FIELD_GRID_FDTD: launch_photon_fk<QED_FIELD_GRID_FDTD>(a, g, b, shm, s, mixed); break;
     default: launch_photon_fk<QED_FIELD_GRID_CP_STANDING>(a, g, b, shm, s, mixed); break;
   }
 }

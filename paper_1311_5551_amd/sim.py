@@ -134,11 +134,19 @@ class Run:
             f.kind = w.field_kind
             fp = list(w.field) + [0.0] * (16 - len(w.field))
             f.p = (C.c_double * 16)(*fp)
-            if w.field_kind == capi.QED_FIELD_GRID_CP_STANDING:
+            if w.field_kind in (capi.QED_FIELD_GRID_CP_STANDING, capi.QED_FIELD_GRID_FDTD):
                 nx, ny, dx, dy, x0, y0 = w.grid
+                f.nx, f.ny, f.dx, f.dy, f.x0, f.y0 = nx, ny, dx, dy, x0, y0
+            if w.field_kind == capi.QED_FIELD_GRID_CP_STANDING:
                 b["grid"] = torch.zeros(6 * nx * ny, dtype=torch.float32, device=self.dev)
                 f.grid_dev = _ptr(b["grid"])
-                f.nx, f.ny, f.dx, f.dy, f.x0, f.y0 = nx, ny, dx, dy, x0, y0
+            elif w.field_kind == capi.QED_FIELD_GRID_FDTD:
+                # the solver's planes Ex..Bz, Jx..Jz (FP64), from the workload's initial fields
+                init = np.zeros((9, ny, nx)) if w.fields is None else np.asarray(w.fields, dtype=np.float64)
+                if init.shape != (9, ny, nx):
+                    raise ValueError("initial field planes must have shape (9, ny, nx)")
+                b["fdtd"] = torch.as_tensor(np.ascontiguousarray(init).reshape(-1)).to(self.dev)
+                f.fdtd_dev = _ptr(b["fdtd"])
             inst.weight = w.weight
             inst.seed = w.seed
             inst.key_instance = w.instance
@@ -219,6 +227,13 @@ class Run:
     def sort_static(self):
         """qed_sort_static: the same reordering with the library's fixed scratch (no allocation)."""
         capi.qed_sort_static(self.ws, self.params, self._s())
+
+    def fields(self, inst: int = 0):
+        """The solver planes (9, ny, nx) of a field-feedback instance as they stand (Ex Ey Ez Bx By
+        Bz at the start of the next step; the current planes are zero between steps)."""
+        nx, ny = self.workloads[inst].grid[:2]
+        self.synchronize()
+        return self.bufs[inst]["fdtd"].cpu().numpy().reshape(9, ny, nx)
 
     def ledger(self):
         st, led = capi.qed_energy_ledger(self.ws, len(self.insts), self._s())

@@ -28,6 +28,7 @@ FIELD_LP_PULSE = 1
 FIELD_CP_WAVE = 2
 FIELD_CP_STANDING = 3
 FIELD_GRID_CP_STANDING = 4
+FIELD_GRID_FDTD = 5
 
 FLAG_EMIT = 1
 FLAG_PAIRS = 2
@@ -58,6 +59,7 @@ class Workload:
     t0: float = 0.0
     weight: float = 1.0
     grid: tuple = (0, 0, 0.0, 0.0, 0.0, 0.0)   # nx, ny, dx, dy, x0, y0
+    fields: np.ndarray | None = None           # field feedback: initial planes (9, ny, nx), Ex..Bz, Jx..Jz
     capacity: dict = dfield(default_factory=dict)  # per species: electron, positron, photon
     notes: str = ""
 
@@ -266,6 +268,38 @@ def grid_config3(n: int = 16_000_000, nx: int = 4096, ny: int = 2048, cells_per_
     return w
 
 
+def standing_wave_planes(e0: float, nx: int, ny: int, dx: float, dy: float, x0: float = 0.0) -> np.ndarray:
+    """Initial planes (9, ny, nx) of the solver grid: the standing wave of two CP lasers at t = 0
+    (E_y = 2 e0 cos x, B_y = 2 e0 sin x, the rest zero) at the Yee nodes, zero current."""
+    F = np.zeros((9, ny, nx))
+    xa = x0 + np.arange(nx) * dx          # nodes of Ey, Ez, Bx
+    xb = x0 + (np.arange(nx) + 0.5) * dx  # nodes of Ex, By, Bz
+    F[1] = 2.0 * e0 * np.cos(xa)[None, :]
+    F[4] = 2.0 * e0 * np.sin(xb)[None, :]
+    return F
+
+
+def feedback_config(n: int = 16_000_000, nx: int = 4096, ny: int = 2048, cells_per_lambda: int = 128,
+                    a0: float = 500.0, density: float = 1e-3, dt: float = 2.0 * math.pi / 400.0,
+                    n_steps: int = 2000, seed: int = 1) -> Workload:
+    """Configuration 3 with field feedback: the electrons (at rest, uniform) are a plasma of
+    `density` times the critical density n_c whose current drives the grid's fields; the grid
+    starts with the standing wave of two CP lasers of amplitude a0 each.  An immobile ion
+    background neutralises the plasma (its charge never enters: the solver advances E with the
+    current only).  Charge per macro-particle in code units: from omega_p^2 = kappa Q n_m (n_m
+    macro-particles per unit area) and omega_p^2 / omega^2 = n / n_c, Q = (n/n_c) / (kappa n_m)."""
+    w = grid_config3(n=n, nx=nx, ny=ny, cells_per_lambda=cells_per_lambda, a0=a0, dt=dt, n_steps=n_steps, seed=seed)
+    dx = w.grid[2]
+    n_m = n / (nx * dx * ny * dx)
+    q = density / (KAPPA * n_m)
+    w.name = "feedback_cp_standing_a500"
+    w.field_kind = FIELD_GRID_FDTD
+    w.field = (q,)
+    w.fields = standing_wave_planes(a0 / KAPPA, nx, ny, dx, dx)
+    w.notes = "plasma density %g n_c, charge per macro-particle %.4g (code units)" % (density, q)
+    return w
+
+
 def subset(w: Workload, idx) -> Workload:
     """The same workload restricted to the initial electrons `idx` (uids preserved)."""
     idx = np.asarray(idx)
@@ -273,4 +307,5 @@ def subset(w: Workload, idx) -> Workload:
     return Workload(name=w.name + "_subset", field_kind=w.field_kind, field=w.field, dt=w.dt,
                     n_steps=w.n_steps, flags=w.flags, electrons=e, dims=w.dims, seed=w.seed,
                     instance=w.instance, t0=w.t0, weight=w.weight, grid=w.grid,
-                    capacity=dict(w.capacity), notes=w.notes)
+                    capacity=dict(w.capacity), notes=w.notes,
+                    fields=None if w.fields is None else w.fields.copy())
