@@ -262,8 +262,18 @@ def run_form(form, args, tables, tuned):
     from paper_1311_5551_amd import autotune, capi, workloads as W
     from paper_1311_5551_amd.sim import Run
 
-    graphs = form not in ("grid",) and not args.no_graphs
-    if form == "grid":
+    graphs = form not in ("grid", "feedback") and not args.no_graphs
+    if form == "feedback":
+        w = W.feedback_config(n=args.grid_electrons)
+        total = size_grid(w, tables, args)
+        ws, pre, s0, steps = [w], 0, 0, total
+        workload = ("feedback_cp_standing_a500: %d electrons at rest, uniform over a periodic 4096x2048 FP64 Yee grid "
+                    "(dx = lambda/128) that starts with the standing wave of two CP lasers a0=500 and is advanced "
+                    "by Maxwell's equations with the leptons' current each step (field feedback, plasma density "
+                    "1e-3 n_c), charge-conserving deposition, first-order gather, 2D3V, FP64, dt=lambda/400c, steps "
+                    "0..%d (until the population reaches 4x), particles sorted by 8x8-cell tile every %d steps"
+                    % (w.n, total, args.grid_sort_every))
+    elif form == "grid":
         w = W.grid_config3(n=args.grid_electrons)
         total = size_grid(w, tables, args)
         ws, pre, s0, steps = [w], 0, 0, total
@@ -302,8 +312,8 @@ def run_form(form, args, tables, tuned):
                     "sin^2, dt=lambda/200c, timed steps %d..%d of %d (the pulse meets the beam at step %d; steps "
                     "0..%d untimed), emission+pairs, compaction every %d"
                     % (w.n, s0, s0 + steps, SCHEDULE, MEET, s0, args.compact_every))
-    WINDOW_KEY[form if form != "grid" else "grid"] = "%d..%d" % (s0, s0 + steps)
-    prec = capi.QED_FP64 if form in ("fp64", "grid", "uniform") else capi.QED_FP32_MIXED
+    WINDOW_KEY[form] = "%d..%d" % (s0, s0 + steps)
+    prec = capi.QED_FP64 if form in ("fp64", "grid", "uniform", "feedback") else capi.QED_FP32_MIXED
     compact = form not in ("uniform",)
 
     def make_run():
@@ -323,7 +333,7 @@ def run_form(form, args, tables, tuned):
                 run.run(n, graph_steps=n if n == args.compact_every else 0)
             else:
                 for i in range(n):
-                    if form == "grid" and (done + i) % args.grid_sort_every == 0:
+                    if form in ("grid", "feedback") and (done + i) % args.grid_sort_every == 0:
                         run.sort()  # tile order for the grid gathers, inside the timed region
                     run.step(1)
             step += n
@@ -398,9 +408,10 @@ def run_form(form, args, tables, tuned):
                lepton_steps=int(agg1["particle_steps"][0] + agg1["particle_steps"][1]
                                 - agg0["particle_steps"][0] - agg0["particle_steps"][1]),
                photon_slot_steps=int(agg1["particle_steps"][2] - agg0["particle_steps"][2]),
-               kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2], pair_events=ms[3], emit_events=ms[4]),
+               kernel_ms=dict(setup=ms[0], lepton=ms[1], photon=ms[2], pair_events=ms[3], emit_events=ms[4],
+                              field_solver=ms[5]),
                launches=dict(setup=launches[0], lepton=launches[1], photon=launches[2], pair_events=launches[3],
-                             emit_events=launches[4]),
+                             emit_events=launches[4], field_solver=launches[5]),
                photons_end=int(agg1["count"][2]), pairs=d("n_pair"), emissions=d("n_emit"),
                drift_max=max(l["drift"] for l in led1),
                photon_steps_in_field=d("photon_steps_in_field"), photon_steps_active=d("photon_steps_active"),
@@ -416,8 +427,8 @@ def run_form(form, args, tables, tuned):
                                                                if graphs else ""))
     # the kernel that takes the most time in the window bounds the step
     kind = "photon" if ms[2] >= ms[1] else "lepton"
-    byts = kernel_bytes("fp64" if prec == capi.QED_FP64 else "fp32", kind, lk0, lk1, grid=form == "grid",
-                        pulse=form not in ("grid", "uniform"))
+    byts = kernel_bytes("fp64" if prec == capi.QED_FP64 else "fp32", kind, lk0, lk1, grid=form in ("grid", "feedback"),
+                        pulse=form not in ("grid", "uniform", "feedback"))
     n_l = launches[2] if kind == "photon" else launches[1]
     avg_s = (ms[2] if kind == "photon" else ms[1]) / max(n_l, 1) * 1e-3
     achieved = byts / max(n_l, 1) / avg_s / 1e9 if avg_s > 0 else 0.0
@@ -426,6 +437,16 @@ def run_form(form, args, tables, tuned):
                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                        "traffic": traffic, "algorithmic_bytes_per_launch": byts / max(n_l, 1),
                        "mean_launch_us": avg_s * 1e6}
+    if form == "feedback" and launches[5]:
+        # the Yee solver's three passes per step (B half, E, B half): 9 + 15 + 9 planes of nx x ny
+        # FP64 words read or written; one fused pass would need 15 (read E, B, J; write E, B, J)
+        nx, ny = ws[0].grid[:2]
+        plane = nx * ny * 8
+        per_step_s = ms[5] / launches[5] * 1e-3
+        res["field_solver"] = {"us_per_step": per_step_s * 1e6, "bytes_per_step": 33 * plane,
+                               "min_bytes_per_step": 15 * plane,
+                               "achieved_GBs": 33 * plane / per_step_s / 1e9,
+                               "frac": 33 * plane / per_step_s / 1e9 / HBM_PEAK_GBS}
     if form in ("fp64", "fp32") and res["emissions"] == 0 and res["lepton_steps_in_field"] == 0:
         log("%s: WARNING: the timed window has no in-field step: it measures a field-free drift" % form)
         res["note"] = "no in-field step in the timed window: a field-free drift, not the QED step"
@@ -462,7 +483,7 @@ def main():
     ap.add_argument("--compact-every", type=int, default=100)
     ap.add_argument("--block", type=int, default=256)
     ap.add_argument("--ppt", type=int, default=4)
-    ap.add_argument("--forms", default="fp64,fp32,batched,grid,uniform",
+    ap.add_argument("--forms", default="fp64,fp32,batched,grid,uniform,feedback",
                     help="comma list of fp64, fp32, batched, grid, uniform; the first gives `value` and `roofline`")
     ap.add_argument("--no-full-run", dest="full_run", action="store_false",
                     help="skip the whole-schedule value of the collision forms")
@@ -513,7 +534,7 @@ def main():
     tuned = {}
     results = []
     for f in forms:
-        key = "fp64" if f in ("fp64", "grid", "uniform") else "fp32"
+        key = "fp64" if f in ("fp64", "grid", "uniform", "feedback") else "fp32"
         if args.tune != "none" and key not in tuned and f in ("fp64", "fp32", "batched"):
             tuned[key] = tuned_launch(key, args, tables)
         results.append(run_form(f, args, tables, tuned.get(key) if f in ("fp64", "fp32", "batched") else None))
@@ -530,7 +551,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if main_r["form"] in ("fp64", "grid", "uniform") else "f32+f64",
+        "dtype": "f64" if main_r["form"] in ("fp64", "grid", "uniform", "feedback") else "f32+f64",
         "data": "synthetic",
         "config": {"workload": main_r["workload"], "form": main_r["form"], "instances": main_r["n_inst"],
                    "counted": "evaluated particle-steps: lepton steps + photon steps inside the photon's pair window",
