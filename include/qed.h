@@ -188,7 +188,8 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
  * per thread (1, 2, 4 or 8; the photon sweep also 16); qed_set_launch sets both sweeps, qed_set_kernel_launch one of
  * them (kernel = QED_KERNEL_LEPTON or QED_KERNEL_PHOTON, the profile-class indices).  Takes
  * effect from the next step; drops a captured graph.  Results do not depend on the shape
- * (per-uid random streams); only the order of floating-point sums in the ledger does. */
+ * (per-uid random streams, ledger sums in exact fixed point), except with field feedback
+ * (QED_FIELD_GRID_FDTD), whose current sums over particles have no fixed order. */
 #define QED_KERNEL_LEPTON 1
 #define QED_KERNEL_PHOTON 2
 qed_status qed_set_launch(qed_workspace* ws, int32_t block, int32_t ppt);
