@@ -97,6 +97,7 @@ struct qed_tables {
   double *h = nullptr, *lnchi_min = nullptr, *dlnchi = nullptr, *P = nullptr, *T = nullptr, *fgrid = nullptr,
          *Pf = nullptr, *knorm = nullptr, *g = nullptr;
   float *h32 = nullptr, *T32 = nullptr;
+  uint16_t *gP = nullptr, *gPf = nullptr;  // guide tables of the cumulative rows (kGuide + 1 per row)
   std::vector<double> hh, hlnchi, hdlnchi, hP, hT, hf, hPf, hk, hg;
   bool has_g = false;
 };
@@ -173,6 +174,8 @@ void free_tables(qed_tables* t) {
   hipFree(t->g);
   hipFree(t->h32);
   hipFree(t->T32);
+  hipFree(t->gP);
+  hipFree(t->gPf);
   delete t;
 }
 
@@ -209,7 +212,8 @@ qed_status alloc_tables(qed_tables* t) {
       (st = dalloc(&t->P, (size_t)p.n_eta * p.n_chi)) || (st = dalloc(&t->T, p.n_chi_pair)) ||
       (st = dalloc(&t->fgrid, p.n_f)) || (st = dalloc(&t->Pf, (size_t)p.n_chi_pair * p.n_f)) ||
       (st = dalloc(&t->knorm, p.n_chi_pair)) || (st = dalloc(&t->g, p.n_eta)) || (st = dalloc(&t->h32, p.n_eta)) ||
-      (st = dalloc(&t->T32, p.n_chi_pair)))
+      (st = dalloc(&t->T32, p.n_chi_pair)) || (st = dalloc(&t->gP, (size_t)p.n_eta * (kGuide + 1))) ||
+      (st = dalloc(&t->gPf, (size_t)p.n_chi_pair * (kGuide + 1))))
     return st;
   return QED_OK;
 }
@@ -257,6 +261,26 @@ qed_status finish_tables(qed_tables* t, bool from_device) {
         return fail(QED_ERR_STATE, "P_f row %d is not a cumulative distribution at column %d", k, l);
     if (P[0] != 0.0 || P[p.n_f - 1] != 1.0) return fail(QED_ERR_STATE, "P_f row %d does not span [0, 1]", k);
   }
+  // guide tables: for each row and u-bin g of width 1/kGuide, the largest column j <= n - 2 with
+  // P[j] < g / kGuide (0 if none); the inversion of u in bin g then searches only between the
+  // guides of bins g and g + 1 (an index structure over the rows, the same answer)
+  auto guides = [](const std::vector<double>& P, int rows, int n, std::vector<uint16_t>& out) {
+    out.assign((size_t)rows * (kGuide + 1), 0);
+    for (int r = 0; r < rows; ++r) {
+      const double* row = &P[(size_t)r * n];
+      int j = 0;
+      for (int g = 0; g <= kGuide; ++g) {
+        const double v = (double)g / kGuide;
+        while (j + 1 <= n - 2 && row[j + 1] < v) ++j;
+        out[(size_t)r * (kGuide + 1) + g] = (uint16_t)j;
+      }
+    }
+  };
+  std::vector<uint16_t> gP, gPf;
+  guides(t->hP, p.n_eta, p.n_chi, gP);
+  guides(t->hPf, p.n_chi_pair, p.n_f, gPf);
+  HIP_TRY(hipMemcpy(t->gP, gP.data(), gP.size() * 2, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(t->gPf, gPf.data(), gPf.size() * 2, hipMemcpyHostToDevice));
   std::vector<float> h32(p.n_eta), T32(p.n_chi_pair);
   for (int i = 0; i < p.n_eta; ++i) h32[i] = (float)t->hh[i];
   for (int k = 0; k < p.n_chi_pair; ++k) T32[k] = (float)t->hT[k];
@@ -279,6 +303,7 @@ Tabs device_tabs(const qed_tables* t) {
   tb.lnchi_min = t->lnchi_min;
   tb.dlnchi = t->dlnchi;
   tb.P = t->P;
+  tb.gP = t->gP;
   tb.n_cp = p.n_chi_pair;
   tb.lc0 = std::log(p.chi_pair_min);
   tb.cp_min = p.chi_pair_min;
@@ -289,6 +314,7 @@ Tabs device_tabs(const qed_tables* t) {
   tb.n_f = p.n_f;
   tb.f = t->fgrid;
   tb.Pf = t->Pf;
+  tb.gPf = t->gPf;
   return tb;
 }
 

@@ -109,6 +109,9 @@ __device__ __forceinline__ void buf_st(bufres r, uint32_t o, float v) {
 }
 
 
+// u-bins of the guide tables of the cumulative rows (a power of two, so u * kGuide is exact)
+constexpr int kGuide = 64;
+
 // Device copy of the tables plus their grid constants.
 struct Tabs {
   int n_eta;
@@ -121,6 +124,7 @@ struct Tabs {
   const double* lnchi_min;     // per row: ln chi_0 and ln-spacing of the columns
   const double* dlnchi;
   const double* P;             // [n_eta][n_chi]
+  const uint16_t* gP;          // [n_eta][kGuide + 1]: guide of each row's inversion
   int n_cp;
   double lc0, dlc;             // ln chi_pair_min, ln-spacing of the pair rows
   double idlc;                 // 1 / dlc (rate look-up only)
@@ -130,6 +134,7 @@ struct Tabs {
   int n_f;
   const double* f;             // f grid
   const double* Pf;            // [n_cp][n_f]
+  const uint16_t* gPf;         // [n_cp][kGuide + 1]
 };
 
 // Step constants derived from qed_step_params.
@@ -804,8 +809,12 @@ __device__ __forceinline__ double lookup_T(const double* sT, const double* ltab,
 
 // Largest j with P[j] < u (so P[j] < u <= P[j+1]; P[n-1] = 1 > u) and the position of u in
 // that segment.  Flat segments (P[j] == P[j+1]) are never selected.
-__device__ __forceinline__ int row_inverse(const double* __restrict__ P, int n, double u, double* frac) {
-  int lo = 0, hi = n - 1;
+__device__ __forceinline__ int row_inverse(const double* __restrict__ P, int n, double u, double* frac,
+                                           const uint16_t* __restrict__ guide) {
+  // the answer lies between the guides of u's bin and the next (guide tables: same answer as the
+  // search over the whole row, in one or two probes instead of log2 n dependent loads)
+  const int g = (int)(u * kGuide);
+  int lo = guide[g], hi = guide[g + 1] + 1;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (P[mid] < u) lo = mid; else hi = mid;
@@ -823,7 +832,7 @@ __device__ inline bool sample_chi(const Tabs& tb, double eta, double u, double* 
     const double* P = tb.P + (size_t)r * tb.n_chi;
     if (u <= P[0]) return false;
     double fr;
-    const int j = row_inverse(P, tb.n_chi, u, &fr);
+    const int j = row_inverse(P, tb.n_chi, u, &fr, tb.gP + (size_t)r * (kGuide + 1));
     *q = tb.lnchi_min[r] + (j + fr) * tb.dlnchi[r];
     return true;
   };
@@ -853,7 +862,7 @@ __device__ inline double sample_f(const Tabs& tb, double chi, double u) {
   const double s = (cr_log(chi) - tb.lc0) / tb.dlc;
   auto frow = [&](int r) {
     double fr;
-    const int j = row_inverse(tb.Pf + (size_t)r * tb.n_f, tb.n_f, u, &fr);
+    const int j = row_inverse(tb.Pf + (size_t)r * tb.n_f, tb.n_f, u, &fr, tb.gPf + (size_t)r * (kGuide + 1));
     return tb.f[j] + fr * (tb.f[j + 1] - tb.f[j]);
   };
   if (!(s > 0.0)) return frow(0);
