@@ -641,8 +641,17 @@ __device__ __forceinline__ void cic_gather6(const qed_field& F, const T* base, d
 // Jy(i, j+1/2) = -Q/(dx dt) sum_{j'<=j} Wy, Jz = Q vz Wz/(dx dy).  The discrete continuity
 // equation then holds node by node for the cloud-in-cell density.  FP64 atomic adds (the
 // order of the sums over particles is not fixed).
+// A deposit target: LDS words of a block's node box (unwrapped node indices [ox, ox + W) x
+// [oy, oy + H), three planes), or, with W = 0, the grid's current planes through global atomics.
+constexpr int kDepNodes = 2048;  // LDS budget of a lepton-sweep block's current box, in nodes
+struct DepositSink {
+  double* lds = nullptr;
+  int64_t ox = 0, oy = 0;
+  int W = 0, H = 0;
+};
+
 __device__ __forceinline__ void deposit_current(const qed_field& F, double Q, double dt, double x0, double y0,
-                                                double x1, double y1, double vz) {
+                                                double x1, double y1, double vz, const DepositSink& sink = {}) {
   const double gx0 = (x0 - F.x0) / F.dx, gy0 = (y0 - F.y0) / F.dy;
   const double gx1 = (x1 - F.x0) / F.dx, gy1 = (y1 - F.y0) / F.dy;
   const double bx = floor(fmin(gx0, gx1)), by = floor(fmin(gy0, gy1));
@@ -655,17 +664,24 @@ __device__ __forceinline__ void deposit_current(const qed_field& F, double Q, do
     S0y[a] = fmax(0.0, 1.0 - fabs(gy0 - (by + a)));
     S1y[a] = fmax(0.0, 1.0 - fabs(gy1 - (by + a)));
   }
-  const int64_t plane = (int64_t)F.nx * F.ny;
-  double* const Jx = F.fdtd_dev + 6 * plane;
+  const bool lds = sink.W > 0;
+  const int64_t plane = lds ? (int64_t)sink.W * sink.H : (int64_t)F.nx * F.ny;
+  const int64_t nxp = lds ? sink.W : F.nx;
+  double* const Jx = lds ? sink.lds : F.fdtd_dev + 6 * plane;
   double* const Jy = Jx + plane;
   double* const Jz = Jy + plane;
   const double cx = -Q / (F.dy * dt), cy = -Q / (F.dx * dt), cz = Q * vz / (F.dx * F.dy);
   int64_t ii[3], jj[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    ii[a] = wrap_index(I + a, F.nx);
-    jj[a] = wrap_index(Jn + a, F.ny);
+    ii[a] = lds ? I + a - sink.ox : wrap_index(I + a, F.nx);
+    jj[a] = lds ? Jn + a - sink.oy : wrap_index(Jn + a, F.ny);
   }
+  auto add = [&](double* w, double v) {
+    if (v == 0.0) return;
+    if (lds) atomicAdd(w, v);  // LDS
+    else unsafeAtomicAdd(w, v);
+  };
 #pragma unroll
   for (int b = 0; b < 3; ++b) {
     double run = 0.0;
@@ -674,10 +690,9 @@ __device__ __forceinline__ void deposit_current(const qed_field& F, double Q, do
       const double dxa = S1x[a] - S0x[a], dyb = S1y[b] - S0y[b];
       run += dxa * (S0y[b] + 0.5 * dyb);
       const double wz = S0x[a] * S0y[b] + 0.5 * dxa * S0y[b] + 0.5 * S0x[a] * dyb + dxa * dyb / 3.0;
-      const int64_t k = jj[b] * F.nx + ii[a];
-      const double jx = cx * run, jz = cz * wz;
-      if (jx != 0.0) unsafeAtomicAdd(Jx + k, jx);
-      if (jz != 0.0) unsafeAtomicAdd(Jz + k, jz);
+      const int64_t k = jj[b] * nxp + ii[a];
+      add(Jx + k, cx * run);
+      add(Jz + k, cz * wz);
     }
   }
 #pragma unroll
@@ -687,8 +702,7 @@ __device__ __forceinline__ void deposit_current(const qed_field& F, double Q, do
     for (int b = 0; b < 3; ++b) {
       const double dxa = S1x[a] - S0x[a], dyb = S1y[b] - S0y[b];
       run += dyb * (S0x[a] + 0.5 * dxa);
-      const double jy = cy * run;
-      if (jy != 0.0) unsafeAtomicAdd(Jy + jj[b] * F.nx + ii[a], jy);
+      add(Jy + jj[b] * nxp + ii[a], cy * run);
     }
   }
 }

@@ -186,7 +186,7 @@ struct LepPtr {
 template <int FK, int PPT, bool MIXED>
 // (three waves per SIMD: the register budget of 168 that allows it costs at most a few spilled
 // words in the larger instantiations, and the sweep is latency-bound)
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_lepton(StepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FK == QED_FIELD_GRID_FDTD ? 1 : 3))) void k_lepton(StepArgs a) {
   using Real = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double smem[];
   __shared__ qed_field sF;
@@ -195,6 +195,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   float* sh32 = (float*)smem;
   long long* s_ll = (long long*)(smem + a.tb.n_eta);  // 16 waves x 2 sums x 4 words
   unsigned* sredu = (unsigned*)(s_ll + 16 * 2 * 4);
+  // field feedback: the current of a chunk's particles is summed in LDS over the chunk's node box
+  // (3 x kDepNodes words) and added to the grid once per node
+  constexpr bool DEP = FK == QED_FIELD_GRID_FDTD;
+  double* const sJ = (double*)(sredu + 16 * 3);
   // deterministic radiation reaction (QED_RR_*) replaces emission; its g table takes h's place
   const bool rr = (a.sc.flags & (QED_RR_QUANTUM | QED_RR_CLASSICAL)) != 0;
   const bool rr_q = (a.sc.flags & QED_RR_QUANTUM) != 0;
@@ -313,6 +317,57 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     C.tau = make_buf(P.tau + k0, nlive * 8u);
     constexpr uint32_t SR = sizeof(Real);
 
+    // field feedback: the box of cells holding the chunk's particles (before the push; a move
+    // stays within a cell of it, and the deposit stencil spans cells I - 1 .. I + 2); where its
+    // nodes fit the LDS budget, the chunk deposits there, else straight to the grid
+    DepositSink sink;
+    if constexpr (DEP) {
+      __shared__ int sbox[4];
+      if (threadIdx.x == 0) {
+        sbox[0] = INT_MAX;
+        sbox[1] = INT_MIN;
+        sbox[2] = INT_MAX;
+        sbox[3] = INT_MIN;
+      }
+      __syncthreads();
+      int lx0 = INT_MAX, lx1 = INT_MIN, ly0 = INT_MAX, ly1 = INT_MIN;
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        if ((int64_t)off >= rem) continue;
+        const double gx = ((double)buf_ld<Real>(C.x, off * SR) - sF.x0) / sF.dx;
+        const double gy = ((double)buf_ld<Real>(C.y, off * SR) - sF.y0) / sF.dy;
+        if (fabs(gx) < 1e9 && fabs(gy) < 1e9) {
+          const int ix = (int)floor(gx), iy = (int)floor(gy);
+          lx0 = min(lx0, ix);
+          lx1 = max(lx1, ix);
+          ly0 = min(ly0, iy);
+          ly1 = max(ly1, iy);
+        } else {  // far or non-finite: the chunk takes the global path
+          lx0 = INT_MIN;
+          lx1 = INT_MAX;
+        }
+      }
+      atomicMin(&sbox[0], lx0);
+      atomicMax(&sbox[1], lx1);
+      atomicMin(&sbox[2], ly0);
+      atomicMax(&sbox[3], ly1);
+      __syncthreads();
+      const int bx0 = sbox[0], bx1 = sbox[1], by0 = sbox[2], by1 = sbox[3];
+      __syncthreads();  // every thread has read the box before thread 0 resets it for the next chunk
+      if (bx0 <= bx1 && by0 <= by1 && bx0 != INT_MIN && bx1 != INT_MAX) {
+        const int64_t W = (int64_t)bx1 - bx0 + 4, H = (int64_t)by1 - by0 + 4;
+        if (W * H <= kDepNodes) {
+          sink.lds = sJ;
+          sink.ox = (int64_t)bx0 - 1;
+          sink.oy = (int64_t)by0 - 1;
+          sink.W = (int)W;
+          sink.H = (int)H;
+          for (int i = threadIdx.x; i < 3 * W * H; i += B) sJ[i] = 0.0;
+          __syncthreads();
+        }
+      }
+    }
+
     // position and momentum of one lepton (slots past the chunk's live ones read as zero)
     struct LepState {
       Real x, y, z, ux, uy, uz;
@@ -391,8 +446,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         x += dt * u1x / g1;
         y += dt * u1y / g1;
         if (d3) z += dt * u1z / g1;
-        // field feedback: the current of this move onto the solver's grid
-        if constexpr (FK == QED_FIELD_GRID_FDTD) deposit_current(sF, qch * sF.p[0], dt, st.x, st.y, x, y, u1z / g1);
+        // field feedback: the current of this move onto the solver's grid (or the chunk's LDS box)
+        if constexpr (DEP) deposit_current(sF, qch * sF.p[0], dt, st.x, st.y, x, y, u1z / g1, sink);
         double wx = u1x, wy = u1y, wz = u1z;  // stored momentum
         if (rr) {
           // continuous reaction (eqs. 8, 9): gamma -> max(gamma - (2/3) alpha kappa eta^2 g dt, 1)
@@ -585,6 +640,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
           if (rr) fix_group_add(rd, fx_rad);
         }
         if (emit) enqueue(off, pend, eta);  // emit is uniform over the block
+      }
+    }
+    if constexpr (DEP) {
+      if (sink.W) {  // block-uniform: the box's sums onto the grid, one atomic per non-zero node
+        __syncthreads();
+        const int64_t WH = (int64_t)sink.W * sink.H, plane = (int64_t)sF.nx * sF.ny;
+        for (int64_t i = threadIdx.x; i < 3 * WH; i += B) {
+          const double v = sJ[i];
+          if (v == 0.0) continue;
+          const int comp = (int)(i / WH);
+          const int64_t r = i - comp * WH, ly = r / sink.W, lx = r - ly * sink.W;
+          const int64_t gi = wrap_index(sink.ox + lx, sF.nx), gj = wrap_index(sink.oy + ly, sF.ny);
+          unsafeAtomicAdd(sF.fdtd_dev + (6 + comp) * plane + gj * sF.nx + gi, v);
+        }
+        __syncthreads();  // the box is zeroed again by the next chunk
       }
     }
   }
@@ -1781,8 +1851,9 @@ void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mix
   }
 }
 
-static size_t lepton_shm(int n_eta) {
-  return (size_t)n_eta * sizeof(double) + 16 * 2 * 4 * sizeof(long long) + 16 * 3 * sizeof(unsigned) + 64;
+static size_t lepton_shm(int fk, int n_eta) {
+  return (size_t)n_eta * sizeof(double) + 16 * 2 * 4 * sizeof(long long) + 16 * 3 * sizeof(unsigned) + 64 +
+         (fk == QED_FIELD_GRID_FDTD ? 3 * (size_t)kDepNodes * sizeof(double) : 0);
 }
 template <int FK, int PPT>
 static int lepton_fit_ppt(int block, size_t shm, bool mixed) {
@@ -1802,7 +1873,7 @@ static int lepton_fit_fk(int ppt, int block, size_t shm, bool mixed) {
 }
 // Blocks of the lepton sweep that fit on one CU at once (registers, LDS), for the shape given.
 int lepton_blocks_per_cu(int fk, int ppt, int block, int n_eta, bool mixed) {
-  const size_t shm = lepton_shm(n_eta);
+  const size_t shm = lepton_shm(fk, n_eta);
   switch (fk) {
     case QED_FIELD_UNIFORM: return lepton_fit_fk<QED_FIELD_UNIFORM>(ppt, block, shm, mixed);
     case QED_FIELD_LP_PULSE: return lepton_fit_fk<QED_FIELD_LP_PULSE>(ppt, block, shm, mixed);
@@ -1814,7 +1885,7 @@ int lepton_blocks_per_cu(int fk, int ppt, int block, int n_eta, bool mixed) {
 }
 
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
-  const size_t shm = lepton_shm(a.tb.n_eta);
+  const size_t shm = lepton_shm(fk, a.tb.n_eta);
   const dim3 g(grid), b(block);
   switch (fk) {
     case QED_FIELD_UNIFORM: launch_lepton_fk<QED_FIELD_UNIFORM>(a, g, b, shm, s, mixed); break;
