@@ -972,6 +972,36 @@ __device__ inline long long wave_reserve_grouped(bool want, int key, int64_t* co
   return res;
 }
 
+// Two wave_reserve_grouped calls at once (one slot from each of two counters per wanting lane):
+// the leader's two atomics are both in flight before either result is used.
+__device__ inline void wave_reserve2_grouped(bool want, int key, int64_t* ca, int64_t* cb, long long* ra,
+                                             long long* rb) {
+  *ra = *rb = -1;
+  bool left = want;
+  unsigned long long mask;
+  while ((mask = __ballot(left)) != 0ull) {
+    const int leader = __ffsll((long long)mask) - 1;
+    const int lk = __shfl(key, leader);
+    const bool mine = left && key == lk;
+    const unsigned long long m = __ballot(mine);
+    const int lane = __lane_id();
+    const unsigned long long total = (unsigned long long)__popcll(m);
+    long long ba = 0, bb = 0;
+    if (lane == leader) {
+      ba = (long long)atomicAdd((unsigned long long*)ca, total);
+      bb = (long long)atomicAdd((unsigned long long*)cb, total);
+    }
+    ba = __shfl(ba, leader);
+    bb = __shfl(bb, leader);
+    if (mine) {
+      const int prefix = __popcll(m & ((1ull << lane) - 1ull));
+      *ra = ba + prefix;
+      *rb = bb + prefix;
+      left = false;
+    }
+  }
+}
+
 // sums over the 64 lanes of a wave, every lane active; every lane gets the result
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -41,14 +41,20 @@ __global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restri
   const int b = min(n_inst, (int)threadIdx.x * per), e = min(n_inst, b + per);
   int64_t sl = 0, sp = 0;
   for (int i = b; i < e; ++i) {
+    // the three counts are read before anything is written (one memory round trip)
+    int64_t* cp[3];
+    int64_t cv[3];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) cp[s] = inst[i].s[s].count_dev;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) cv[s] = cp[s] ? *cp[s] : 0;
     for (int s = 0; s < 3; ++s) {
       const qed_species& S = inst[i].s[s];
-      int64_t c = 0;
-      if (S.count_dev) {
-        c = *S.count_dev;
+      int64_t c = cv[s];
+      if (cp[s]) {
         if (c > S.capacity) {
           // appends past the end were dropped (and counted) by the kernel that made them
-          *S.count_dev = S.capacity;
+          *cp[s] = S.capacity;
           c = S.capacity;
         }
         if (c < 0) c = 0;
@@ -685,17 +691,29 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
   const int NW = a.qe.grid * a.qe.waves;
   const int64_t nch = a.glob->n_chunks[0];
   const int64_t seg_len = (nch + a.qe.grid - 1) / a.qe.grid * a.qe.ppt * 64;
-  // exclusive prefix of the per-wave counts: thread t sums a contiguous run, a block scan of the
-  // run totals, then the run's prefixes
+  // exclusive prefix of the per-wave counts: the counts land in LDS from coalesced loads that are
+  // all in flight together (32 per thread: the 8192 waves of 256 CUs in one memory round trip),
+  // then thread t sums a contiguous run, a block scan of the run totals, then the run's prefixes
   {
+    constexpr int kRound = 32;
+    for (int i0 = 0; i0 < NW; i0 += kRound * (int)blockDim.x) {
+      int v[kRound];
+#pragma unroll
+      for (int j = 0; j < kRound; ++j) {
+        const int i = i0 + (int)threadIdx.x + j * (int)blockDim.x;
+        v[j] = i < NW ? a.qe.wave_cnt[i] : 0;
+      }
+#pragma unroll
+      for (int j = 0; j < kRound; ++j) {
+        const int i = i0 + (int)threadIdx.x + j * (int)blockDim.x;
+        if (i < NW) s_pref[i] = v[j];
+      }
+    }
+    __syncthreads();
     const int per = (NW + blockDim.x - 1) / blockDim.x;
     const int b = min(NW, (int)threadIdx.x * per), e = min(NW, b + per);
     int loc = 0;
-    for (int i = b; i < e; ++i) {
-      const int c = a.qe.wave_cnt[i];
-      s_pref[i] = c;
-      loc += c;
-    }
+    for (int i = b; i < e; ++i) loc += s_pref[i];
     s_scan[threadIdx.x] = loc;
     __syncthreads();
     for (int o = 1; o < (int)blockDim.x; o <<= 1) {
@@ -732,28 +750,42 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
     }
     const int ii = (int)(ev.key >> 41), sp = (int)((ev.key >> 40) & 1);
     const int64_t k = (int64_t)(ev.key & ((1ull << 40) - 1));
+    int bkey = 0;
+    const bool uni = block_uniform_key(want, ii, s_key, &bkey);  // block-uniform
+    // everything the event reads besides the tables, loaded before its first store (which the
+    // compiler cannot tell apart from these words), so that the loads share a memory round trip
     const qed_instance& I = a.inst[ii];
-    const qed_species& S = I.s[sp];
-    const qed_species& G = I.s[2];
+    const qed_species S = I.s[sp], G = I.s[2];
+    const qed_field F = I.field;
+    const uint64_t seed = I.seed, key_inst = I.key_instance;
     const bool d3 = I.dims == 3;
+    const int64_t moff = a.acc[ii].mover_off;
+    int64_t* const bcount = a.inst[bkey].s[2].count_dev;
     bool child = false;
     double defect = 0.0, cx = 0, cy = 0, cz = 0, ckx = 0, cky = 0, ckz = 0, ctau = 0;
     uint64_t cuid = 0;
     unsigned n_null = 0;
     if (want) {
-      uint64_t r[4];
-      philox4x64_10(S.uid_dev[k], (uint64_t)step, KIND_EMIT, 0, I.seed, I.key_instance, r);
+      const uint64_t uid = S.uid_dev[k];
       gptr<Real> UX = as_global((Real*)S.ux_dev), UY = as_global((Real*)S.uy_dev), UZ = as_global((Real*)S.uz_dev);
       double ux1, uy1, uz1;
       if (MIXED) {
         ux1 = (double)UX[k] + S.ux_lo_dev[k];
         uy1 = (double)UY[k] + S.uy_lo_dev[k];
         uz1 = (double)UZ[k] + S.uz_lo_dev[k];
+        cx = (double)((const float*)S.x_dev)[k] + S.x_lo_dev[k];
+        cy = (double)((const float*)S.y_dev)[k] + S.y_lo_dev[k];
+        cz = d3 ? (double)((const float*)S.z_dev)[k] + S.z_lo_dev[k] : 0.0;
       } else {
         ux1 = UX[k];
         uy1 = UY[k];
         uz1 = UZ[k];
+        cx = ((const double*)S.x_dev)[k];
+        cy = ((const double*)S.y_dev)[k];
+        cz = d3 ? ((const double*)S.z_dev)[k] : 0.0;
       }
+      uint64_t r[4];
+      philox4x64_10(uid, (uint64_t)step, KIND_EMIT, 0, seed, key_inst, r);
       const double g1 = sqrt(1.0 + (ux1 * ux1 + uy1 * uy1 + uz1 * uz1));
       double chi;
       if (sample_chi(a.tb, ev.eta, unit_open(r[0]), &chi)) {
@@ -768,9 +800,6 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
           split_double(ux1 - ckx, h, l); UX[k] = h; S.ux_lo_dev[k] = l; ux = (double)h + l;
           split_double(uy1 - cky, h, l); UY[k] = h; S.uy_lo_dev[k] = l; uy = (double)h + l;
           split_double(uz1 - ckz, h, l); UZ[k] = h; S.uz_lo_dev[k] = l; uz = (double)h + l;
-          cx = (double)((const float*)S.x_dev)[k] + S.x_lo_dev[k];
-          cy = (double)((const float*)S.y_dev)[k] + S.y_lo_dev[k];
-          cz = d3 ? (double)((const float*)S.z_dev)[k] + S.z_lo_dev[k] : 0.0;
         } else {
           ckx = xi * ux1;
           cky = xi * uy1;
@@ -781,9 +810,6 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
           UX[k] = ux;
           UY[k] = uy;
           UZ[k] = uz;
-          cx = ((const double*)S.x_dev)[k];
-          cy = ((const double*)S.y_dev)[k];
-          cz = d3 ? ((const double*)S.z_dev)[k] : 0.0;
         }
         const double g2 = sqrt(1.0 + (ux * ux + uy * uy + uz * uz));
         const double eps = sqrt(ckx * ckx + cky * cky + ckz * ckz);
@@ -796,9 +822,7 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
       }
       S.tau_dev[k] = optical_depth(r[1]);
     }
-    int bkey = 0;
-    const bool uni = block_uniform_key(want, ii, s_key, &bkey);  // block-uniform
-    const long long slot = uni ? block_reserve(child, a.inst[bkey].s[2].count_dev, s_wave, &s_base)
+    const long long slot = uni ? block_reserve(child, bcount, s_wave, &s_base)
                                : wave_reserve_grouped(child, ii, G.count_dev);
     double dropped_e = 0.0;
     unsigned n_drop = 0;
@@ -827,11 +851,11 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
         const double skx = MIXED ? (double)(float)ckx : ckx, sky = MIXED ? (double)(float)cky : cky,
                      skz = MIXED ? (double)(float)ckz : ckz;
         const double sy = MIXED ? (double)(float)cy : cy;
-        const int64_t pk = a.acc[ii].mover_off + slot;
-        a.win[pk] = pack_window(photon_window(I.field, pair_eps_min(I.field, a.tb.cp_min), a.tb.cp_min, a.sc.t0,
-                                              a.sc.dt, skx, sky, skz, sx, (int32_t)(step + 1)));
-        make_photon_rec<MIXED, FK>(((PhotonRecT<MIXED, FK>*)a.rec)[pk], I.field, a.sc.t0, a.sc.dt, skx, sky, skz, sx,
-                                   sy, (int32_t)(step + 1));
+        const int64_t pk = moff + slot;
+        a.win[pk] = pack_window(photon_window(F, pair_eps_min(F, a.tb.cp_min), a.tb.cp_min, a.sc.t0, a.sc.dt, skx, sky,
+                                              skz, sx, (int32_t)(step + 1)));
+        make_photon_rec<MIXED, FK>(((PhotonRecT<MIXED, FK>*)a.rec)[pk], F, a.sc.t0, a.sc.dt, skx, sky, skz, sx, sy,
+                                   (int32_t)(step + 1));
       } else {
         n_drop = 1;
         dropped_e = sqrt(ckx * ckx + cky * cky + ckz * ckz);
@@ -1162,6 +1186,10 @@ __device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k,
   const qed_instance& I = a.inst[ii];
   const qed_species& S = I.s[2];
   const bool d3 = I.dims == 3;
+  // the children's species and the photon's record offset, read before the first store (which the
+  // compiler cannot tell apart from them), so that the loads share a memory round trip
+  const qed_species Se = I.s[0], Sp = I.s[1];
+  const int64_t moff = a.acc[ii].mover_off;
   double px = 0, py = 0, pz = 0, etau = 0, ptau = 0, ex = 0, ey = 0, ez = 0, pkx = 0, pky = 0, pkz = 0;
   double defect = 0.0, dropped_e = 0.0;
   unsigned n_drop = 0;
@@ -1225,14 +1253,12 @@ __device__ __forceinline__ void pair_event(const StepArgs& a, int ii, int64_t k,
     etau = optical_depth(r0[3]);
     ptau = optical_depth(r1[0]);
     S.tau_dev[k] = kTauGone;
-    a.win[a.acc[ii].mover_off + k] = kWinEmpty;
+    a.win[moff + k] = kWinEmpty;
     defect = gp + ge - epsd;
   }
-  // append electron and positron, one atomic per wave and instance
-  const qed_species& Se = I.s[0];
-  const qed_species& Sp = I.s[1];
-  const long long se = wave_reserve_grouped(want, ii, Se.count_dev);
-  const long long spo = wave_reserve_grouped(want, ii, Sp.count_dev);
+  // append electron and positron, one atomic per wave, instance and species
+  long long se, spo;
+  wave_reserve2_grouped(want, ii, Se.count_dev, Sp.count_dev, &se, &spo);
   if (want) {
     if (se < Se.capacity) {
       write_lepton<MIXED>(Se, se, px, py, pz, ex, ey, ez, etau, euid, d3);
@@ -1259,8 +1285,8 @@ __global__ __launch_bounds__(256) void k_pair_events(StepArgs a) {
   const double t = a.sc.t0 + (double)step * a.sc.dt;
   const int64_t gtid = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t cnt = a.q.ctl->count;  // read with the overflow flag (one round trip)
   if (!a.q.ctl->overflow) {
-    const int64_t cnt = a.q.ctl->count;
     for (int64_t e0 = gtid - threadIdx.x % 64; e0 < cnt; e0 += stride) {
       // whole waves iterate together; lanes past the end take no event
       const int64_t e = e0 + threadIdx.x % 64;
