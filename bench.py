@@ -51,8 +51,8 @@ def kernel_bytes(form, kind, led0, led1, grid=False, pulse=True):
     written in FP64 (FP32-mixed: the stored words of position and momentum, 4 B each, plus the
     FP64 tau); outside the plane-wave pulse (field-free drift) x and u read, x written: 72 B in
     FP64; + 16 B per queued emission event.  2-D grid workload: 48 + 48 B per step (x, y, u, tau).
-    Photon sweep: 4 B per summary window of a group of 64 slots that was read, and 4 B per slot
-    whose pair window was read; per photon inside its window what its record holds: in the
+    Photon sweep: 8 B per live mask of a group of 64 slots that was read, and 4 B per slot
+    whose pair window was read (its live bit was set); per photon inside its window what its record holds: in the
     plane-wave pulse the phase at step 0, its rate per step and the chi scale (24 B in FP64, 16 B
     in FP32-mixed), in a general field the momentum, the birth position and the birth step (44 B
     in FP64, 24 B in FP32-mixed); + 16 B (tau read and written) for the photons that see a
@@ -73,7 +73,7 @@ def kernel_bytes(form, kind, led0, led1, grid=False, pulse=True):
         rec = 24 if form == "fp64" else 16
     else:
         rec = 44 if form == "fp64" else 24
-    return ((d("photon_window_reads") + d("photon_group_reads")) * 4 + d("photon_steps_active") * rec
+    return (d("photon_window_reads") * 4 + d("photon_group_reads") * 8 + d("photon_steps_active") * rec
             + d("photon_steps_in_field") * 16 + d("n_pair") * 8)
 
 

@@ -218,9 +218,10 @@ qed_status qed_set_step(qed_workspace* ws, int64_t step, qed_stream stream);
  * non-finite state) are reported by the next qed_energy_ledger.  The first step after qed_bind,
  * and any step whose t0, dt or tables differ from the previous one's, also enqueues a pass that
  * sets every photon's pair window (the steps in which its pair rate can be non-zero) and the
- * summary window of every full group of 64 photon slots; a caller capturing qed_step into its
- * own graph should run one step before capturing.  Photons appended after that pass (or the
- * last qed_compact) are read slot by slot until the next qed_compact summarises them. */
+ * live mask of every group of 64 photon slots (a bit per photon whose window is not over); a
+ * caller capturing qed_step into its own graph should run one step before capturing.  The
+ * photon pass reads only the photons whose live bit is set; the emission pass sets the bits of
+ * the photons it appends and the photon pass clears those whose window is over. */
 qed_status qed_step(const qed_tables* tables, qed_workspace* ws, const qed_step_params* params,
                     qed_stream stream);
 
@@ -256,7 +257,7 @@ qed_status qed_sort_static(qed_workspace* ws, const qed_step_params* params, qed
  * a pair again (the paper deletes photons that cannot matter for pair creation, Sec. 3.1); their
  * energy goes to the ledger's retired_energy and each is counted in its instance's photon
  * spectrum.  Then it puts the photons whose window is over in front of the others (the photon
- * sweep starts after them) and rebuilds the summary windows of the groups of 64 photon slots.
+ * sweep starts after them) and rebuilds the live masks of the groups of 64 photon slots.
  * Call it periodically (e.g. every 100 steps).  Async; graph-capturable. */
 qed_status qed_compact(qed_workspace* ws, qed_stream stream);
 
@@ -289,10 +290,10 @@ typedef struct {
                                       window (the steps in which its pair rate can be non-zero) */
   int64_t lepton_steps_in_field;   /* lepton steps with the full push (all of them, except outside a
                                       plane-wave pulse, where the push is the field-free drift) */
-  int64_t photon_window_reads;     /* photon slot-steps whose pair window was read: all slots, except
-                                      in groups of 64 slots whose summary window excludes the step */
-  int64_t photon_group_reads;      /* summary windows read (groups of 64 photon slots present at the
-                                      last compaction or window build) */
+  int64_t photon_window_reads;     /* photon slot-steps whose pair window was read: the slots whose
+                                      live bit was set (a photon whose window is not over) */
+  int64_t photon_group_reads;      /* live masks read (one 64-bit mask per group of 64 photon slots
+                                      the photon sweep visits) */
   int64_t particle_steps[3];       /* particles present at the start of each step, summed over the
                                       steps since qed_bind (photons: buffer slots, incl. dead ones
                                       not yet compacted, counted in steps with QED_PAIRS, the steps

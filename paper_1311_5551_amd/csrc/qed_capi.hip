@@ -143,8 +143,8 @@ struct qed_workspace {
   int fit[2] = {0, 0};
   int fit_key[2][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}};
   size_t win_len = 0;
-  uint32_t* d_wsum = nullptr;  // window-group summaries (kWinGroup slots each), instances at acc.wsum_off
-  size_t wsum_len = 0;
+  uint64_t* d_lmask = nullptr;  // live masks of the photon slot groups (kWinGroup slots each), at acc.lmask_off
+  size_t lmask_len = 0;
   bool win_valid = false;
   double win_t0 = 0.0, win_dt = 0.0, win_cp_min = 0.0;
   int block[2] = {256, 256}, ppt[2] = {4, 4};  // launch shapes: [0] lepton sweep, [1] photon sweep
@@ -413,7 +413,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   a.qe.ppt = ws->ppt[0];
   a.win = ws->d_win;
   a.rec = ws->d_rec;
-  a.wsum = ws->d_wsum;
+  a.lmask = ws->d_lmask;
   // persistent grids (sweep_grid), blocks taking runs of the chunk list.
   // The passes run in order on `stream`: the photon sweep alone saturates HBM, so running the
   // lepton passes beside it on a second stream (their data are disjoint) shares bandwidth
@@ -458,7 +458,8 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
 qed_status ensure_windows(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
   const double cp_min = device_tabs(tb).cp_min;
   if (ws->win_valid && ws->win_t0 == p->t0 && ws->win_dt == p->dt && ws->win_cp_min == cp_min) return QED_OK;
-  launch_photon_windows(ws->field_kind, ws->d_inst, ws->n_inst, ws->d_acc, ws->d_win, ws->d_rec, ws->d_wsum, p->t0, p->dt, cp_min,
+  launch_photon_windows(ws->field_kind, ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_win, ws->d_rec, ws->d_lmask,
+                        p->t0, p->dt, cp_min,
                         ws->prec == QED_FP32_MIXED, s);
   HIP_TRY(hipGetLastError());
   ws->win_valid = true;
@@ -666,7 +667,7 @@ void qed_workspace_destroy(qed_workspace* ws) {
   hipFree(ws->d_movers);
   hipFree(ws->d_win);
   hipFree(ws->d_rec);
-  hipFree(ws->d_wsum);
+  hipFree(ws->d_lmask);
   delete ws;
 }
 
@@ -776,17 +777,19 @@ qed_status qed_bind(qed_workspace* ws, const qed_instance* inst, int32_t n_inst,
   for (int i = 0; i < n_inst; ++i) {
     acc0[i].n_pair_compacted = ~0ull;  // the first compaction after a bind always runs
     acc0[i].mover_off = (int64_t)off;
-    acc0[i].wsum_off = (int64_t)goff;  // n_sealed = 0: no summary until the windows are made
+    acc0[i].lmask_off = (int64_t)goff;  // the masks are made with the windows
     off += (size_t)inst[i].s[2].capacity;
     goff += ((size_t)inst[i].s[2].capacity + kWinGroup - 1) / kWinGroup;
   }
-  if (goff > ws->wsum_len || !ws->d_wsum) {
-    hipFree(ws->d_wsum);
-    ws->d_wsum = nullptr;
-    ws->wsum_len = 0;
-    HIP_TRY(hipMalloc((void**)&ws->d_wsum, (goff ? goff : 1) * sizeof(uint32_t)));
-    ws->wsum_len = goff ? goff : 1;
+  if (goff > ws->lmask_len || !ws->d_lmask) {
+    hipFree(ws->d_lmask);
+    ws->d_lmask = nullptr;
+    ws->lmask_len = 0;
+    HIP_TRY(hipMalloc((void**)&ws->d_lmask, (goff ? goff : 1) * sizeof(uint64_t)));
+    ws->lmask_len = goff ? goff : 1;
   }
+  // no bit for a slot no photon has held yet (the window build sets those of the bound photons)
+  HIP_TRY(hipMemset(ws->d_lmask, 0, ws->lmask_len * sizeof(uint64_t)));
   if (movers > ws->movers_len) {
     hipFree(ws->d_movers);
     ws->d_movers = nullptr;
@@ -837,7 +840,7 @@ qed_status qed_init_optical_depth(qed_workspace* ws, qed_stream stream) {
 qed_status qed_set_step(qed_workspace* ws, int64_t step, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (step < 0 || step > ((int64_t)1 << 31)) return fail(QED_ERR_ARG, "step = %lld outside [0, 2^31]", (long long)step);
-  launch_set_step(ws->d_glob, ws->d_acc, ws->n_inst, step, (hipStream_t)stream);
+  launch_set_step(ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_win, ws->d_lmask, step, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return QED_OK;
 }
@@ -1023,7 +1026,7 @@ qed_status qed_compact(qed_workspace* ws, qed_stream stream) {
   if (!ws) return fail(QED_ERR_ARG, "workspace is NULL");
   if (!ws->bound) return fail(QED_ERR_STATE, "no instances bound");
   launch_compact(ws->field_kind, ws->d_inst, ws->n_inst, ws->d_acc, ws->d_glob, ws->d_movers, ws->d_win, ws->d_rec,
-                 ws->d_wsum, ws->prec == QED_FP32_MIXED, ws->retire, (hipStream_t)stream);
+                 ws->d_lmask, ws->prec == QED_FP32_MIXED, ws->retire, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return QED_OK;
 }

@@ -153,9 +153,7 @@ struct InstAcc {
   int64_t n_live;              // compaction: live photons
   int64_t mover_off;           // offset of this instance's photon slots in the workspace's per-photon
                                // arrays (compaction movers, photon windows)
-  int64_t wsum_off;            // offset of this instance's window-group summaries
-  int64_t n_sealed;            // photon slots [0, n_sealed) have a current group summary (multiple of
-                               // kWinGroup); slots appended since are scanned one by one
+  int64_t lmask_off;           // offset of this instance's live masks (one per kWinGroup photon slots)
   int64_t n_front;             // photons [0, n_front) have no pair rate in any later step (their window
                                // is over; set by the partition at compaction)
   int64_t ph_first;            // first photon slot of the photon sweep's chunk list (n_front rounded
@@ -168,8 +166,8 @@ struct InstAcc {
   unsigned long long led_count[3];
   unsigned long long n_emit, n_null, n_pair, n_dropped, n_range, n_nonfinite, n_field, n_field_lepton;
   unsigned long long n_active;           // photon steps inside the photon's window (evaluated in full)
-  unsigned long long n_win_reads;        // photon slot-steps whose window word was read
-  unsigned long long n_group_reads;      // window-group summaries read
+  unsigned long long n_win_reads;        // photon slot-steps whose window word was read (live bit set)
+  unsigned long long n_group_reads;      // live masks read
   unsigned long long particle_steps[3];  // particles (photon slots) present at the start of each step
   unsigned long long n_pair_compacted;   // n_pair at the last compaction (~0: unknown, e.g. after bind)
   int32_t compact_skip;                  // this compaction has nothing to remove
@@ -554,10 +552,16 @@ __device__ __forceinline__ bool in_window(uint32_t w, int64_t n) {
   const int64_t lo = w & 0xFFFFu, hi = w >> 16;
   return lo <= hi && lo <= (n < 65535 ? n : 65535) && (hi == 65535 || n <= hi);
 }
-// Photon slots are grouped by kWinGroup consecutive slots (one wave's load of windows).  A group's
-// summary is a packed window whose lo is the least lo and whose hi the greatest hi over the
-// group's non-empty windows (kWinEmpty if all are empty): every step inside any member's window is
-// inside the summary, so a step outside the summary needs none of the group's windows.
+// the window has no step at or after step s (empty windows included)
+__device__ __forceinline__ bool window_over(uint32_t w, int64_t s) {
+  const uint32_t lo = w & 0xFFFFu, hi = w >> 16;
+  return lo > hi || (hi != 65535u && (int64_t)hi < s);
+}
+// Photon slots are grouped by kWinGroup consecutive slots (one wave's share of a chunk).  A group's
+// live mask has bit i set for every slot i of the group whose photon's window is not over at the
+// next step the photon sweep runs (it may have more bits set, never fewer): the sweep reads only
+// the slots whose bit is set.  Set for a new photon by the emission pass, cleared by the sweep
+// once the window is over, rebuilt from the windows after a window build or a compaction.
 constexpr int kWinGroup = 64;
 
 // The steps [lo, hi] in which a photon can have a pair rate (eq. 3 needs chi >= chi_min); in

@@ -21,7 +21,7 @@ struct StepArgs {
   EmitQueue qe;               // emission events of the step (lepton passes)
   uint32_t* win;              // per-photon pair windows (pack_window); instance i's slots from acc[i].mover_off
   void* rec;                  // per-photon records (PhotonRecT<MIXED, FK>) for the in-window evaluation
-  const uint32_t* wsum;       // window-group summaries; instance i's from acc[i].wsum_off
+  uint64_t* lmask;            // live masks of the photon slot groups; instance i's from acc[i].lmask_off
 };
 
 // retirement of photons at compaction (pair window over): the photon spectrum they are counted in
@@ -57,7 +57,8 @@ hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnc
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,
                        int64_t* base_lep, int64_t* base_ph, int chunk_lep, int chunk_ph, int advance,
                        int count_photons, hipStream_t s);
-void launch_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step, hipStream_t s);
+void launch_set_step(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, const uint32_t* win,
+                     uint64_t* lmask, int64_t step, hipStream_t s);
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s);
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 int photon_blocks_per_cu(int fk, int ppt, int block, int n_cp, bool mixed);
@@ -71,8 +72,8 @@ void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mix
 void launch_init_tau(const qed_instance* inst, int n_inst, hipStream_t s);
 void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixed, hipStream_t s);
 void launch_compact(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
-                    uint32_t* win, void* rec, uint32_t* wsum, bool mixed, const RetireSpec& rs, hipStream_t s);
-void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
-                           uint32_t* wsum, double t0, double dt, double cp_min, bool mixed, hipStream_t s);
+                    uint32_t* win, void* rec, uint64_t* lmask, bool mixed, const RetireSpec& rs, hipStream_t s);
+void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, uint32_t* win,
+                           void* rec, uint64_t* lmask, double t0, double dt, double cp_min, bool mixed, hipStream_t s);
 
 }  // namespace qedk

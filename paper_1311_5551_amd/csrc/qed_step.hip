@@ -62,8 +62,6 @@ __global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restri
       acc[i].n_start[s] = c;
       if (s == 0 && advance_clock)
         for (int q = 0; q < kFixRunning; ++q) fix_normalise(acc[i].fx[q]);
-      // a count that fell without a compaction (set by the caller) unseals the slots above it
-      if (s == 2 && acc[i].n_sealed > c / kWinGroup * kWinGroup) acc[i].n_sealed = c / kWinGroup * kWinGroup;
       if (s == 2 && acc[i].n_front > c) acc[i].n_front = c;
       // the photon sweep's chunks start after the front, at a chunk boundary
       if (s == 2) acc[i].ph_first = acc[i].n_front / chunk_ph * chunk_ph;
@@ -108,8 +106,9 @@ __global__ __launch_bounds__(256) void k_step_begin(const qed_instance* __restri
 }
 
 // Sets the next step.  The partition's front holds photons whose window ended before the step of
-// the last compaction; at an earlier step they may be inside it again, so the front is emptied
-// (the next compaction rebuilds it) and the sweep reads those photons through their summaries.
+// the last compaction, and the live masks have lost the photons whose window ended before the
+// last step swept; at an earlier step they may be inside their windows again, so the front is
+// emptied (the next compaction rebuilds it) and the launcher rebuilds the masks at the new step.
 __global__ void k_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step) {
   if (blockIdx.x == 0 && threadIdx.x == 0) glob->step_next = step;
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) acc[i].n_front = 0;
@@ -759,7 +758,7 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
     const qed_field F = I.field;
     const uint64_t seed = I.seed, key_inst = I.key_instance;
     const bool d3 = I.dims == 3;
-    const int64_t moff = a.acc[ii].mover_off;
+    const int64_t moff = a.acc[ii].mover_off, lmoff = a.acc[ii].lmask_off;
     int64_t* const bcount = a.inst[bkey].s[2].count_dev;
     bool child = false;
     double defect = 0.0, cx = 0, cy = 0, cz = 0, ckx = 0, cky = 0, ckz = 0, ctau = 0;
@@ -852,8 +851,12 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
                      skz = MIXED ? (double)(float)ckz : ckz;
         const double sy = MIXED ? (double)(float)cy : cy;
         const int64_t pk = moff + slot;
-        a.win[pk] = pack_window(photon_window(F, pair_eps_min(F, a.tb.cp_min), a.tb.cp_min, a.sc.t0, a.sc.dt, skx, sky,
-                                              skz, sx, (int32_t)(step + 1)));
+        const uint32_t wn = pack_window(photon_window(F, pair_eps_min(F, a.tb.cp_min), a.tb.cp_min, a.sc.t0, a.sc.dt,
+                                                      skx, sky, skz, sx, (int32_t)(step + 1)));
+        a.win[pk] = wn;
+        // the live bit of a photon that can still create a pair (the masks' other bits belong to
+        // other slots, some of them set by other waves)
+        if (!window_over(wn, step + 1)) atomicOr((unsigned long long*)(a.lmask + lmoff + slot / kWinGroup), 1ull << (slot % kWinGroup));
         make_photon_rec<MIXED, FK>(((PhotonRecT<MIXED, FK>*)a.rec)[pk], F, a.sc.t0, a.sc.dt, skx, sky, skz, sx, sy,
                                    (int32_t)(step + 1));
       } else {
@@ -884,9 +887,11 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
 // the energy that can reach chi_min in the field, or outside a pulse's support); it is set when
 // the photon is appended and moves with it.  The sweep (k_photon) skips three ways: it starts
 // after the front that the partition at compaction fills with photons whose window is over; it
-// skips the groups of 64 slots whose summary window excludes the step; in the other groups a
-// thread reads the windows of the PPT photons it owns in the chunk.  Only the photons inside
-// their window are read in full and evaluate chi and T(chi), with
+// skips the groups of 64 slots whose live mask is empty; in the other groups a thread reads the
+// window, record and optical depth of each photon it owns whose live bit is set (the live mask
+// holds a bit for every photon whose window is not over, so only photons in their window, and
+// the few whose window starts later, are read).  The photons inside their window evaluate chi
+// and T(chi), with
 // the device library's trigonometry and log, and, where T > 0, decrement the optical depth (these
 // values only decide the event step).  A photon whose depth reaches zero is queued; the event
 // pass (k_pair_events) recomputes chi from the stored photon with correctly rounded functions,
@@ -929,14 +934,14 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
   // dwords of a record the sweep reads: plane-wave {A, S, c}; general {k, x_b, y_b, birth step}
   constexpr int kRecDw = FK == QED_FIELD_LP_PULSE ? (MIXED ? 4 : 6) : (MIXED ? 6 : 11);
   gptr<const Rec> REC = nullptr;
-  gptr<const uint32_t> WSUM = nullptr;
-  int64_t nseal = 0, pfirst = 0;
-  // group summaries of the current run of chunks, read in one load per wave: bit r PPT + j is
-  // set when group j of the wave in chunk m0 + r is sealed and its summary excludes the step
+  gptr<uint64_t> LM = nullptr;
+  int64_t pfirst = 0;
+  // live masks of the current run of chunks, one load per wave: lane r PPT + j holds the mask of
+  // group j of the wave in chunk m0 + r (0 past the instance's chunks)
   int64_t m0 = -1;
-  uint64_t mskip = 0;
+  uint64_t mrun = 0;
   FieldK fK{0.0};
-  // in-field steps, chi above the table, non-finite tau, in-window steps, window reads, summary reads
+  // in-field steps, chi above the table, non-finite tau, in-window steps, window reads, mask reads
   unsigned uacc[6] = {0, 0, 0, 0, 0, 0};
   // the counters of the instance just left: lane sums through LDS atomics (few registers on
   // this rare path), then one global atomic per counter
@@ -973,8 +978,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       TAU = as_global(uni_ptr(S.tau_dev));
       WIN = as_global(uni_ptr(a.win)) + uni64(a.acc[ii].mover_off);
       REC = as_global((const Rec*)uni_ptr(a.rec)) + uni64(a.acc[ii].mover_off);
-      WSUM = as_global(uni_ptr(a.wsum)) + uni64(a.acc[ii].wsum_off);
-      nseal = uni64(a.acc[ii].n_sealed);
+      LM = as_global(uni_ptr(a.lmask)) + uni64(a.acc[ii].lmask_off);
       pfirst = uni64(a.acc[ii].ph_first);
       m0 = -1;
       n = uni64(a.acc[ii].n_start[2]);
@@ -1073,35 +1077,39 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
       }
     };
 
-    // phase 0: in each chunk a wave loads the windows of PPT whole groups (slots
-    // k0 + 64 w + j B + [0, 64)).  Where those groups are sealed their summaries are read first,
-    // for the whole run of chunks at once (lane r PPT + j: chunk m0 + r, group j; PPT <= 16 and
-    // kPhotonRun = 4 fit a wave), and the groups whose summary excludes this step are not read
+    // phase 0: in each chunk a wave owns PPT whole groups (slots k0 + 64 w + j B + [0, 64)).
+    // Their live masks are read for the whole run of chunks at once (lane r PPT + j: chunk m0 + r,
+    // group j; PPT <= 16 and kPhotonRun = 4 fit a wave); a group whose mask is empty is not read
     // further (after the photons have left the field, that is every group)
-    constexpr unsigned kAll = (1u << PPT) - 1u;
-    static_assert(PPT * kPhotonRun <= 64, "one summary per lane for a run of chunks");
+    static_assert(PPT * kPhotonRun <= 64, "one mask per lane for a run of chunks");
+    const int lane = threadIdx.x & 63;
     if (m0 < 0 || c / kPhotonRun != m0 / kPhotonRun) {  // first chunk of a run in this instance
       m0 = c;
-      const int lane = threadIdx.x & 63;
       const int64_t cc = c + lane / PPT;
       const int64_t cend = min(ce, (c / kPhotonRun + 1) * kPhotonRun);  // end of the run
-      bool skip = false;
+      mrun = 0;
       if (lane < PPT * kPhotonRun && cc < cend) {
         const int64_t g = (pfirst + (cc - cb) * CH) / kWinGroup + (threadIdx.x >> 6) +
                           (int64_t)(lane % PPT) * (B / kWinGroup);
-        if ((g + 1) * kWinGroup <= nseal) {
-          skip = !in_window(WSUM[g], step);
+        if (g * kWinGroup < n) {  // a group with photons (the last chunk may reach past them)
+          mrun = LM[g];
           ++uacc[5];
         }
       }
-      mskip = __ballot(skip);
     }
-    const unsigned live = ~(unsigned)(mskip >> ((c - m0) * PPT)) & kAll;  // wave-uniform
-    if (live == 0) continue;
-    // phase 1: the window, the record and the optical depth of every slot of the live groups,
+    uint64_t M[PPT];  // this chunk's masks of the wave's groups (wave-uniform: scalar registers)
+    bool any = false;
+#pragma unroll
+    for (int j = 0; j < PPT; ++j) {
+      const int src = (int)(c - m0) * PPT + j;
+      M[j] = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(mrun >> 32), src) << 32) |
+             (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)mrun, src);
+      any = any || M[j] != 0ull;
+    }
+    if (!any) continue;
+    // phase 1: the window, the record and the optical depth of every live slot of the chunk,
     // issued together, so that a chunk costs one memory round trip (loads past the chunk's live
-    // slots return zero).  The record and depth of a slot outside its window are read for
-    // nothing; where the partition keeps the in-window photons together that is a small share.
+    // slots return zero)
     uint32_t wv[PPT];
     uint32_t q[PPT][kRecDw];
     double tv[PPT];
@@ -1109,7 +1117,7 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
     for (int j = 0; j < PPT; ++j) {
       wv[j] = kWinEmpty;
       tv[j] = 0.0;
-      if ((live >> j) & 1u) {
+      if ((M[j] >> lane) & 1ull) {
         const unsigned off = threadIdx.x + j * B;
         wv[j] = (uint32_t)buf_ld<int32_t>(rwin, off * 4u);
         load_dwords<kRecDw>(rrec, off * (unsigned)sizeof(Rec), q[j]);
@@ -1120,33 +1128,42 @@ __global__ __launch_bounds__(256) void k_photon(StepArgs a) {
 #pragma unroll
     for (int j = 0; j < PPT; ++j) {
       const bool exists = (int64_t)(threadIdx.x + j * B) < rem;
-      if (exists && ((live >> j) & 1u)) ++uacc[4];
+      const bool bit = (M[j] >> lane) & 1ull;
+      if (exists && bit) ++uacc[4];
       if (exists && in_window(wv[j], step)) gmask |= 1u << j;
-    }
-    if (__ballot(gmask != 0) == 0ull) continue;
-    uacc[3] += __popc(gmask);
-    // one photon inside its window, from the dwords of its record and its optical depth
-    auto eval = [&](unsigned off, const uint32_t* w, double tau) -> bool {
-      auto dbl = [&](int i) { return __hiloint2double((int)w[i + 1], (int)w[i]); };
-      if constexpr (FK == QED_FIELD_LP_PULSE) {
-        if (MIXED) return infield_pw(off, dbl(0), (double)__uint_as_float(w[2]), (double)__uint_as_float(w[3]), tau);
-        else return infield_pw(off, dbl(0), dbl(2), dbl(4), tau);
-      } else if (MIXED) {
-        return infield(off, (Real)__uint_as_float(w[0]), (Real)__uint_as_float(w[1]), (Real)__uint_as_float(w[2]),
-                       NEED_X ? (Real)__uint_as_float(w[3]) : Real(0), NEED_Y ? (Real)__uint_as_float(w[4]) : Real(0),
-                       NEED_X ? (int32_t)w[5] : 0, tau);
-      } else {
-        return infield(off, (Real)dbl(0), (Real)dbl(2), (Real)dbl(4), NEED_X ? (Real)dbl(6) : Real(0),
-                       NEED_Y ? (Real)dbl(8) : Real(0), NEED_X ? (int32_t)w[10] : 0, tau);
+      // the mask for the next step loses the photons whose window is over then (a photon's
+      // window only ends; the slots past the step's photons keep their bits: the emission pass
+      // of this step may have set them)
+      if (M[j] != 0ull) {  // wave-uniform
+        const uint64_t nm = __ballot(bit && (!exists || !window_over(wv[j], step + 1)));
+        if (nm != M[j] && lane == 0) LM[(k0 + threadIdx.x + j * B) / kWinGroup] = nm;
       }
-    };
-    // phase 2: the photons inside their windows, in place
+    }
+    if (__ballot(gmask != 0) != 0ull) {
+      uacc[3] += __popc(gmask);
+      // one photon inside its window, from the dwords of its record and its optical depth
+      auto eval = [&](unsigned off, const uint32_t* w, double tau) -> bool {
+        auto dbl = [&](int i) { return __hiloint2double((int)w[i + 1], (int)w[i]); };
+        if constexpr (FK == QED_FIELD_LP_PULSE) {
+          if (MIXED) return infield_pw(off, dbl(0), (double)__uint_as_float(w[2]), (double)__uint_as_float(w[3]), tau);
+          else return infield_pw(off, dbl(0), dbl(2), dbl(4), tau);
+        } else if (MIXED) {
+          return infield(off, (Real)__uint_as_float(w[0]), (Real)__uint_as_float(w[1]), (Real)__uint_as_float(w[2]),
+                         NEED_X ? (Real)__uint_as_float(w[3]) : Real(0), NEED_Y ? (Real)__uint_as_float(w[4]) : Real(0),
+                         NEED_X ? (int32_t)w[5] : 0, tau);
+        } else {
+          return infield(off, (Real)dbl(0), (Real)dbl(2), (Real)dbl(4), NEED_X ? (Real)dbl(6) : Real(0),
+                         NEED_Y ? (Real)dbl(8) : Real(0), NEED_X ? (int32_t)w[10] : 0, tau);
+        }
+      };
+      // phase 2: the photons inside their windows, in place
 #pragma unroll
-    for (int j = 0; j < PPT; ++j) {
-      const unsigned off = threadIdx.x + j * B;
-      bool pend = false;
-      if ((gmask >> j) & 1u) pend = eval(off, q[j], tv[j]);
-      enqueue(off, pend);
+      for (int j = 0; j < PPT; ++j) {
+        const unsigned off = threadIdx.x + j * B;
+        bool pend = false;
+        if ((gmask >> j) & 1u) pend = eval(off, q[j], tv[j]);
+        enqueue(off, pend);
+      }
     }
   }
   if (cur >= 0) flush(cur);
@@ -1404,7 +1421,6 @@ __global__ __launch_bounds__(256) void k_ledger(const qed_instance* __restrict__
 // A photon leaves the arrays at compaction when it converted to a pair (tau < 0) or, with
 // retirement on, when its pair window is over (it can never convert: it only moves ballistically,
 // so it is booked into the ledger and the instance's photon spectrum and dropped).
-__device__ __forceinline__ bool window_over(uint32_t w, int64_t s);
 
 struct RetireArgs {
   int on;                       // retirement enabled
@@ -1572,14 +1588,10 @@ __global__ void k_compact_finish(const qed_instance* __restrict__ inst, int n_in
 // partition of the photons by pair window (after the compaction): the photons that can have no
 // pair rate from the next step on (an empty window, or one that ended before that step) go to
 // the front [0, D), the others to the back.  The photons the sweep evaluates in a step then sit
-// together, and the front's groups are skipped by their summaries.  Photons of the back that
+// together, and the sweep never reaches the front.  Photons of the back that
 // belong to the front swap places with front photons that belong to the back (per-uid results
 // do not depend on the order).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ bool window_over(uint32_t w, int64_t s) {
-  const uint32_t lo = w & 0xFFFFu, hi = w >> 16;
-  return lo > hi || (hi != 65535u && (int64_t)hi < s);
-}
 
 __global__ void k_part_prep(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
@@ -1700,47 +1712,43 @@ __global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restric
   }
 }
 
-// Window-group summaries of the full groups of every instance's photons (after a window build,
-// and after the partition at compaction, which moves photons across all groups).  One wave per
-// group; grid: x strides groups, y = instance.
-__global__ __launch_bounds__(256) void k_window_summary(const qed_instance* __restrict__ inst,
-                                                        const InstAcc* __restrict__ acc,
-                                                        const uint32_t* __restrict__ win, uint32_t* __restrict__ wsum) {
+// Live masks of every instance's photon slot groups from the windows (after a window build, and
+// after the partition at compaction, which moves photons across all groups): bit i of group g
+// set when slot 64 g + i holds a photon whose window is not over at the next step.  One wave per
+// group; grid: x strides groups, y = instance.  The groups past the photons keep their masks
+// (bits of slots that no photon holds cost the sweep a read that returns zero, nothing else).
+__global__ __launch_bounds__(256) void k_window_masks(const qed_instance* __restrict__ inst,
+                                                      const InstAcc* __restrict__ acc, const Glob* __restrict__ glob,
+                                                      const uint32_t* __restrict__ win, uint64_t* __restrict__ lmask) {
   const int ii = blockIdx.y;
   const qed_species& S = inst[ii].s[2];
   if (S.capacity == 0 || !S.count_dev) return;
   int64_t n = *S.count_dev;
   if (n > S.capacity) n = S.capacity;
   if (n < 0) n = 0;
-  const int64_t ng = n / kWinGroup;
+  const int64_t ng = (n + kWinGroup - 1) / kWinGroup, step = glob->step_next;
   const uint32_t* W = win + acc[ii].mover_off;
-  uint32_t* G = wsum + acc[ii].wsum_off;
+  uint64_t* L = lmask + acc[ii].lmask_off;
   const int lane = threadIdx.x & 63;
   const int64_t wstride = (int64_t)gridDim.x * (blockDim.x >> 6);
-  // the loop bound is wave-uniform, so every lane reaches the shuffles
+  // the loop bound is wave-uniform, so every lane reaches the ballot
   for (int64_t g = blockIdx.x * (int64_t)(blockDim.x >> 6) + (threadIdx.x >> 6); g < ng; g += wstride) {
-    const uint32_t w = W[g * kWinGroup + lane];
-    const bool any = (w & 0xFFFFu) <= (w >> 16);  // a non-empty window (pack_window)
-    uint32_t lo = any ? (w & 0xFFFFu) : 0xFFFFu, hi = any ? (w >> 16) : 0u;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-      lo = min(lo, (uint32_t)__shfl_xor((int)lo, o));
-      hi = max(hi, (uint32_t)__shfl_xor((int)hi, o));
-    }
-    if (lane == 0) G[g] = lo <= hi ? (lo | (hi << 16)) : kWinEmpty;
+    const int64_t k = g * kWinGroup + lane;
+    const bool live = k < n && !window_over(W[k], step);
+    const uint64_t m = __ballot(live);
+    if (lane == 0) L[g] = m;
   }
 }
 
-// the slots with a summary: every full group (after k_window_summary); the front is the
-// partition's (after_partition), else none (the windows were just rebuilt)
-__global__ void k_window_sealed(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
-                                int after_partition) {
+// The partition's front after a compaction (after_partition), else none (the windows were just
+// rebuilt)
+__global__ void k_window_front(const qed_instance* __restrict__ inst, int n_inst, InstAcc* __restrict__ acc,
+                               int after_partition) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) {
     const qed_species& S = inst[i].s[2];
     int64_t n = S.count_dev ? *S.count_dev : 0;
     if (n > S.capacity) n = S.capacity;
     if (n < 0) n = 0;
-    acc[i].n_sealed = n / kWinGroup * kWinGroup;
     const int64_t D = after_partition ? acc[i].n_live : 0;
     acc[i].n_front = D < 0 ? 0 : (D > n ? n : D);
   }
@@ -1856,8 +1864,11 @@ void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob*
                      chunk_lep, chunk_ph, advance, count_photons);
 }
 
-void launch_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step, hipStream_t s) {
+void launch_set_step(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, const uint32_t* win,
+                     uint64_t* lmask, int64_t step, hipStream_t s) {
   hipLaunchKernelGGL(k_set_step, dim3(1), dim3(256), 0, s, glob, acc, n_inst, step);
+  if (n_inst > 0 && win && lmask)
+    hipLaunchKernelGGL(k_window_masks, dim3(n_inst == 1 ? 2048 : 64, n_inst), dim3(256), 0, s, inst, acc, glob, win, lmask);
 }
 
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s) {
@@ -1989,8 +2000,8 @@ void launch_ledger(const qed_instance* inst, int n_inst, InstAcc* acc, bool mixe
   else hipLaunchKernelGGL(k_ledger<false>, dim3(128, 3 * n_inst), dim3(256), 0, s, inst, acc);
 }
 
-void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, uint32_t* win, void* rec,
-                           uint32_t* wsum, double t0, double dt, double cp_min, bool mixed, hipStream_t s) {
+void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, uint32_t* win,
+                           void* rec, uint64_t* lmask, double t0, double dt, double cp_min, bool mixed, hipStream_t s) {
   const dim3 g(n_inst == 1 ? 2048 : 64, n_inst);
   constexpr int LP = QED_FIELD_LP_PULSE, GEN = QED_FIELD_UNIFORM;  // record layouts: plane wave, general
   if (fk == LP) {
@@ -2000,12 +2011,12 @@ void launch_photon_windows(int fk, const qed_instance* inst, int n_inst, InstAcc
     if (mixed) hipLaunchKernelGGL((k_photon_windows<true, GEN>), g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
     else hipLaunchKernelGGL((k_photon_windows<false, GEN>), g, dim3(256), 0, s, inst, acc, win, rec, t0, dt, cp_min);
   }
-  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum);
-  hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 0);
+  hipLaunchKernelGGL(k_window_masks, g, dim3(256), 0, s, inst, acc, glob, win, lmask);
+  hipLaunchKernelGGL(k_window_front, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 0);
 }
 
 void launch_compact(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, const Glob* glob, int64_t* movers,
-                    uint32_t* win, void* rec, uint32_t* wsum, bool mixed, const RetireSpec& rs, hipStream_t s) {
+                    uint32_t* win, void* rec, uint64_t* lmask, bool mixed, const RetireSpec& rs, hipStream_t s) {
   const int rw = photon_rec_bytes(mixed, fk) / 8;
   RetireArgs r{};
   r.on = rs.on;
@@ -2030,8 +2041,8 @@ void launch_compact(int fk, const qed_instance* inst, int n_inst, InstAcc* acc, 
   hipLaunchKernelGGL(k_part_movers, g, dim3(256), 0, s, acc, glob, win, movers);
   if (mixed) hipLaunchKernelGGL(k_part_swap<true>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec, rw);
   else hipLaunchKernelGGL(k_part_swap<false>, g, dim3(256), 0, s, inst, acc, glob, movers, win, rec, rw);
-  hipLaunchKernelGGL(k_window_summary, g, dim3(256), 0, s, inst, acc, win, wsum);
-  hipLaunchKernelGGL(k_window_sealed, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 1);
+  hipLaunchKernelGGL(k_window_masks, g, dim3(256), 0, s, inst, acc, glob, win, lmask);
+  hipLaunchKernelGGL(k_window_front, dim3(1), dim3(256), 0, s, inst, n_inst, acc, 1);
 }
 
 }  // namespace qedk

@@ -163,10 +163,9 @@ def test_graph_replay_matches_plain_launches(shared_tables):
 @pytest.mark.parametrize("precision", [capi.QED_FP64, capi.QED_FP32_MIXED])
 @pytest.mark.parametrize("compact", [False, True])
 def test_batched_instances_equal_single_runs(compact, precision, shared_tables):
-    # compact=True: the batched run compacts every 100 steps, which also summarises each
-    # instance's photon slot groups (the sweep then skips groups outside their pair windows);
-    # the single runs never compact.  Both precisions: the FP32-mixed batched form of
-    # configuration 5 equals its single runs bit for bit
+    # compact=True: the batched run compacts every 100 steps, which also partitions each
+    # instance's photons and rebuilds its live masks; the single runs never compact.  Both
+    # precisions: the FP32-mixed batched form of configuration 5 equals its single runs bit for bit
     ws = [W.collision(n, a0=a0, gamma_mean=g0, n_steps=2400, meet_step=1200, seed=1, instance=i, uid0=0)
           for i, (n, a0, g0) in enumerate([(1000, 200.0, 2000.0), (17, 450.0, 800.0), (3001, 60.0, 4500.0),
                                            (1, 300.0, 1500.0), (650, 120.0, 3000.0)])]

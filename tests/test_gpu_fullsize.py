@@ -7,8 +7,8 @@ oracle run of that subset alone.  Every particle of the oracle's families must e
 GPU run with the same state (the strict FP64 bars of the parity tests); a family in which the two
 sides took different decisions shows up as a missing uid or a different state.  The full runs
 reach the paths small runs never take: photon chunk lists far above 8192 chunks (the sweep's
-multi-run deal), lepton sweeps whose blocks take several chunks, the partition and group
-summaries over ~1e8 photon slots, graph replay with compaction, and the grid sort."""
+multi-run deal), lepton sweeps whose blocks take several chunks, the partition and the live masks
+over ~1e8 photon slots, graph replay with compaction, and the grid sort."""
 import numpy as np
 import pytest
 

@@ -291,12 +291,12 @@ def test_photon_windows_parity(shared_tables, oracle_tables):
 
 @pytest.mark.parametrize("precision", [capi.QED_FP64, capi.QED_FP32_MIXED])
 def test_photon_window_groups_with_compaction(precision, shared_tables, oracle_tables):
-    # groups of 64 photon slots carry a summary window (made at each compaction and window
-    # build); a wave reads no window of a group whose summary excludes the step.  The collision
-    # of the test above, compacted every 100 steps as the production runs are: the photons born
-    # in the collision are summarised at the compactions and skipped once the pulse has passed
-    # them.  FP64 against the oracle per uid; FP32-mixed against its own run without summaries
-    # (no compaction: slots appended since the window build are read one by one).
+    # groups of 64 photon slots carry a live mask (a bit per photon whose pair window is not
+    # over: set at append, cleared by the sweep, rebuilt at each compaction and window build); a
+    # wave reads only the slots whose bit is set.  The collision of the test above, compacted
+    # every 100 steps as the production runs are (the partition also moves the photons whose
+    # window is over to the front, which the sweep never visits).  FP64 against the oracle per
+    # uid; FP32-mixed against its own run without compaction (same photons, other slots).
     w = W.collision(1500, a0=200.0, n_steps=2600, meet_step=1300, seed=11)
     r = Run(w, shared_tables, precision=precision)
     for _ in range(w.n_steps // 100):
@@ -324,7 +324,7 @@ def test_photon_window_groups_with_compaction(precision, shared_tables, oracle_t
         return
     ref = _gpu_run(w, shared_tables, precision=precision)
     lr = ref.ledger()[0]
-    assert lr["photon_window_reads"] == lr["particle_steps"][2]
+    assert lr["photon_steps_active"] <= lr["photon_window_reads"] < 0.9 * lr["particle_steps"][2]
     assert (led["n_pair"], led["n_emit"]) == (lr["n_pair"], lr["n_emit"])
     for name in ("electron", "positron", "photon"):
         a, b = r.species(0, name), ref.species(0, name)
