@@ -948,6 +948,8 @@ qed_status qed_sort(qed_workspace* ws, const qed_step_params* params, qed_stream
                                   (hipStream_t)stream));
     }
   }
+  launch_front_clear(ws->d_acc, ws->n_inst, (hipStream_t)stream);  // the photons moved: no front
+  HIP_TRY(hipGetLastError());
   ws->win_valid = false;  // the photons moved: their windows and records are set again by the next step
   return QED_OK;
 }
@@ -985,6 +987,8 @@ qed_status qed_sort_static(qed_workspace* ws, const qed_step_params* params, qed
                                   (hipStream_t)stream));
     }
   }
+  launch_front_clear(ws->d_acc, ws->n_inst, (hipStream_t)stream);  // the photons moved: no front
+  HIP_TRY(hipGetLastError());
   ws->win_valid = false;
   return QED_OK;
 }

@@ -523,20 +523,6 @@ __device__ inline void make_photon_rec(PhotonRecT<MIXED, FK>& R, const qed_field
   }
 }
 
-// Copies a record of `words8` 8-byte words (photon_rec_bytes / 8) from slot `src` to `dst`.
-__device__ __forceinline__ void move_rec(void* base, int words8, int64_t dst, int64_t src) {
-  uint2* b = (uint2*)base;
-  for (int w = 0; w < words8; ++w) b[dst * words8 + w] = b[src * words8 + w];
-}
-__device__ __forceinline__ void swap_rec(void* base, int words8, int64_t i, int64_t j) {
-  uint2* b = (uint2*)base;
-  for (int w = 0; w < words8; ++w) {
-    const uint2 t = b[i * words8 + w];
-    b[i * words8 + w] = b[j * words8 + w];
-    b[j * words8 + w] = t;
-  }
-}
-
 // A window is stored in 32 bits: first and last step as 16-bit fields (lo | hi << 16), saturated
 // so that the stored window always holds the exact one: lo at 65535 stands for "from 65535 or
 // later", hi at 65535 for "no last step".  An empty window is lo = 65535, hi = 0.  Past step

@@ -57,6 +57,7 @@ hipError_t launch_build_tables(const qed_table_params& p, double* h, double* lnc
 void launch_step_begin(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, EvCtl* evc, EvCtl* emc,
                        int64_t* base_lep, int64_t* base_ph, int chunk_lep, int chunk_ph, int advance,
                        int count_photons, hipStream_t s);
+void launch_front_clear(InstAcc* acc, int n_inst, hipStream_t s);
 void launch_set_step(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* glob, const uint32_t* win,
                      uint64_t* lmask, int64_t step, hipStream_t s);
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s);

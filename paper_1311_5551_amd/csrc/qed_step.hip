@@ -114,6 +114,12 @@ __global__ void k_set_step(Glob* glob, InstAcc* acc, int n_inst, int64_t step) {
   for (int i = threadIdx.x; i < n_inst; i += blockDim.x) acc[i].n_front = 0;
 }
 
+// Empties the partition's front (after the photons were reordered another way: the next
+// compaction sorts them all).
+__global__ void k_front_clear(InstAcc* acc, int n_inst) {
+  for (int i = threadIdx.x; i < n_inst; i += blockDim.x) acc[i].n_front = 0;
+}
+
 // largest idx with base[idx] <= c (lands on a non-empty entry; see the chunk-list layout)
 __device__ __forceinline__ int find_entry(const int64_t* __restrict__ base, int n, int64_t c) {
   int lo = 0, hi = n - 1;
@@ -1448,6 +1454,11 @@ __global__ void k_compact_prep(const qed_instance* __restrict__ inst, int n_inst
     acc[i].compact_skip = skip ? 1 : 0;
     acc[i].n_live = skip ? n : 0;
     acc[i].n_pair_compacted = acc[i].n_pair;
+    // The front [0, n_front) holds photons whose window was over at the last compaction: none of
+    // them has converted since (no pair rate), so the holes all lie behind it, it stays in place
+    // and the partition below only has to sort what lies behind it.  Retirement removes those
+    // photons: then there is no front to keep.
+    if (retire || acc[i].n_front > n) acc[i].n_front = retire ? 0 : n;
   }
 }
 
@@ -1469,13 +1480,15 @@ __global__ __launch_bounds__(256) void k_compact_count(const qed_instance* __res
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
   const uint32_t* W = win + acc[ii].mover_off;
-  const int64_t n = acc[ii].n_start[2];
+  const int64_t n = acc[ii].n_start[2], F = acc[ii].n_front;
   if (r.on)
     for (int b = threadIdx.x; b < r.n_bins + 2; b += blockDim.x) s_hist[b] = 0u;
   __syncthreads();
   unsigned u[2] = {0, 0};  // live, retired
   long long fe[4] = {0, 0, 0, 0};
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+  if (blockIdx.x == 0 && threadIdx.x == 0 && F > 0)
+    atomicAdd((unsigned long long*)&acc[ii].n_live, (unsigned long long)F);  // the front stays
+  for (int64_t k = F + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
     const double tau = S.tau_dev[k];
     if (tau < 0.0) continue;
     if (r.on && window_over(W[k], r.step)) {
@@ -1537,42 +1550,50 @@ __global__ __launch_bounds__(256) void k_compact_fill(const qed_instance* __rest
                                                       const Glob* __restrict__ glob, const int64_t* __restrict__ movers,
                                                       uint32_t* __restrict__ win, void* __restrict__ rec, int rec_words,
                                                       RetireArgs r) {
+  using Real = typename std::conditional<MIXED, float, double>::type;
   r.step = glob->step_next;
   const int ii = blockIdx.y;
   if (acc[ii].compact_skip) return;
   const qed_species& S = inst[ii].s[2];
-  const int64_t L = acc[ii].n_live, n = acc[ii].n_start[2];
+  const int64_t L = acc[ii].n_live, n = acc[ii].n_start[2], F = acc[ii].n_front;
   const long long n_movers = (long long)acc[ii].mover_ctr;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const bool d3 = inst[ii].dims == 3;
-  for (int64_t k0 = blockIdx.x * (int64_t)blockDim.x; k0 < L; k0 += stride) {
+  Real* const X = (Real*)S.x_dev;
+  Real* const Y = (Real*)S.y_dev;
+  Real* const Z = (Real*)S.z_dev;
+  Real* const UX = (Real*)S.ux_dev;
+  Real* const UY = (Real*)S.uy_dev;
+  Real* const UZ = (Real*)S.uz_dev;
+  uint32_t* const W = win + acc[ii].mover_off;
+  uint2* const R = (uint2*)rec + acc[ii].mover_off * rec_words;
+  for (int64_t k0 = F + blockIdx.x * (int64_t)blockDim.x; k0 < L; k0 += stride) {
     const int64_t k = k0 + threadIdx.x;
-    const bool hole = k < L && photon_leaves(S, win + acc[ii].mover_off, k, r);
+    const bool hole = k < L && photon_leaves(S, W, k, r);
     const long long slot = wave_reserve(hole, (int64_t*)&acc[ii].hole_ctr);
-    // every hole in [0, L) has a mover in [L, n); the bounds below only guard that invariant
+    // every hole in [F, L) has a mover in [L, n); the bounds below only guard that invariant
     if (hole && slot < n_movers) {
       const int64_t src = movers[acc[ii].mover_off + slot];
       if (src < L || src >= n) continue;
-      if (MIXED) {
-        ((float*)S.x_dev)[k] = ((const float*)S.x_dev)[src];
-        ((float*)S.y_dev)[k] = ((const float*)S.y_dev)[src];
-        if (d3) ((float*)S.z_dev)[k] = ((const float*)S.z_dev)[src];
-        ((float*)S.ux_dev)[k] = ((const float*)S.ux_dev)[src];
-        ((float*)S.uy_dev)[k] = ((const float*)S.uy_dev)[src];
-        ((float*)S.uz_dev)[k] = ((const float*)S.uz_dev)[src];
-      } else {
-        ((double*)S.x_dev)[k] = ((const double*)S.x_dev)[src];
-        ((double*)S.y_dev)[k] = ((const double*)S.y_dev)[src];
-        if (d3) ((double*)S.z_dev)[k] = ((const double*)S.z_dev)[src];
-        ((double*)S.ux_dev)[k] = ((const double*)S.ux_dev)[src];
-        ((double*)S.uy_dev)[k] = ((const double*)S.uy_dev)[src];
-        ((double*)S.uz_dev)[k] = ((const double*)S.uz_dev)[src];
-      }
-      S.tau_dev[k] = S.tau_dev[src];
-      S.uid_dev[k] = S.uid_dev[src];
-      S.birth_step_dev[k] = S.birth_step_dev[src];
-      win[acc[ii].mover_off + k] = win[acc[ii].mover_off + src];
-      move_rec(rec, rec_words, acc[ii].mover_off + k, acc[ii].mover_off + src);
+      // the mover's words, all loaded before the first store (one memory round trip)
+      const Real x = X[src], y = Y[src], z = d3 ? Z[src] : Real(0), ux = UX[src], uy = UY[src], uz = UZ[src];
+      const double tau = S.tau_dev[src];
+      const uint64_t uid = S.uid_dev[src];
+      const int32_t bs = S.birth_step_dev[src];
+      const uint32_t w = W[src];
+      uint2 rv[8];
+      for (int q = 0; q < rec_words; ++q) rv[q] = R[src * rec_words + q];
+      X[k] = x;
+      Y[k] = y;
+      if (d3) Z[k] = z;
+      UX[k] = ux;
+      UY[k] = uy;
+      UZ[k] = uz;
+      S.tau_dev[k] = tau;
+      S.uid_dev[k] = uid;
+      S.birth_step_dev[k] = bs;
+      W[k] = w;
+      for (int q = 0; q < rec_words; ++q) R[k * rec_words + q] = rv[q];
     }
   }
 }
@@ -1611,11 +1632,13 @@ __global__ __launch_bounds__(256) void k_part_count(InstAcc* __restrict__ acc, c
   __shared__ double sred[16];
   __shared__ unsigned sredu[16];
   const int ii = blockIdx.y;
-  const int64_t n = acc[ii].n_start[2], s = glob->step_next;
+  const int64_t n = acc[ii].n_start[2], s = glob->step_next, F = acc[ii].n_front;
   const uint32_t* W = win + acc[ii].mover_off;
   double d[1] = {0.0};
   unsigned u[1] = {0};
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+  if (blockIdx.x == 0 && threadIdx.x == 0 && F > 0)
+    atomicAdd((unsigned long long*)&acc[ii].n_live, (unsigned long long)F);  // the front: over before
+  for (int64_t k = F + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
     if (window_over(W[k], s)) ++u[0];
   block_sum(d, u, sred, sredu);
   if (threadIdx.x == 0 && u[0]) atomicAdd((unsigned long long*)&acc[ii].n_live, (unsigned long long)u[0]);
@@ -1652,15 +1675,8 @@ __global__ __launch_bounds__(256) void k_part_movers(InstAcc* __restrict__ acc, 
   }
 }
 
-template <class T>
-__device__ __forceinline__ void swap_at(void* a, int64_t i, int64_t j) {
-  T* p = (T*)a;
-  const T t = p[i];
-  p[i] = p[j];
-  p[j] = t;
-}
-
-// every photon of [0, D) whose window is not over swaps with one listed by k_part_movers
+// every photon of [F, D) whose window is not over swaps with one listed by k_part_movers (the
+// front [0, F) of the last compaction is in place)
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restrict__ inst, InstAcc* __restrict__ acc,
                                                    const Glob* __restrict__ glob, const int64_t* __restrict__ movers,
@@ -1668,16 +1684,22 @@ __global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restric
   using Real = typename std::conditional<MIXED, float, double>::type;
   const int ii = blockIdx.y;
   const qed_species& S = inst[ii].s[2];
-  const int64_t n = acc[ii].n_start[2], D = acc[ii].n_live, s = glob->step_next;
+  const int64_t n = acc[ii].n_start[2], D = acc[ii].n_live, s = glob->step_next, F = min(acc[ii].n_front, D);
   const long long n_movers = (long long)acc[ii].mover_ctr;
   uint32_t* W = win + acc[ii].mover_off;
-  const int64_t ro = acc[ii].mover_off;
   const bool d3 = inst[ii].dims == 3;
-  // a contiguous range of [0, D) per block, its holes' places reserved with one atomic
+  Real* const X = (Real*)S.x_dev;
+  Real* const Y = (Real*)S.y_dev;
+  Real* const Z = (Real*)S.z_dev;
+  Real* const UX = (Real*)S.ux_dev;
+  Real* const UY = (Real*)S.uy_dev;
+  Real* const UZ = (Real*)S.uz_dev;
+  uint2* const R = (uint2*)rec + acc[ii].mover_off * rec_words;
+  // a contiguous range of [F, D) per block, its holes' places reserved with one atomic
   __shared__ unsigned sredu[16];
   __shared__ long long s_base;
   int64_t b0, b1;
-  block_range(0, D, blockIdx.x, gridDim.x, &b0, &b1);
+  block_range(F, D, blockIdx.x, gridDim.x, &b0, &b1);
   if (b0 >= b1) return;  // the whole block
   unsigned u[1] = {0};
   for (int64_t k = b0 + threadIdx.x; k < b1; k += blockDim.x)
@@ -1697,17 +1719,33 @@ __global__ __launch_bounds__(256) void k_part_swap(const qed_instance* __restric
     if (sw && slot < n_movers) {
       const int64_t j = movers[acc[ii].mover_off + slot];
       if (j < D || j >= n) continue;
-      swap_at<Real>(S.x_dev, k, j);
-      swap_at<Real>(S.y_dev, k, j);
-      if (d3) swap_at<Real>(S.z_dev, k, j);
-      swap_at<Real>(S.ux_dev, k, j);
-      swap_at<Real>(S.uy_dev, k, j);
-      swap_at<Real>(S.uz_dev, k, j);
-      swap_at<double>(S.tau_dev, k, j);
-      swap_at<uint64_t>(S.uid_dev, k, j);
-      swap_at<int32_t>(S.birth_step_dev, k, j);
-      swap_at<uint32_t>(W, k, j);
-      swap_rec(rec, rec_words, ro + k, ro + j);
+      // both photons' words, all loaded before the first store (one memory round trip)
+      const Real xk = X[k], xj = X[j], yk = Y[k], yj = Y[j];
+      const Real zk = d3 ? Z[k] : Real(0), zj = d3 ? Z[j] : Real(0);
+      const Real uxk = UX[k], uxj = UX[j], uyk = UY[k], uyj = UY[j], uzk = UZ[k], uzj = UZ[j];
+      const double tk = S.tau_dev[k], tj = S.tau_dev[j];
+      const uint64_t ik = S.uid_dev[k], ij = S.uid_dev[j];
+      const int32_t bk = S.birth_step_dev[k], bj = S.birth_step_dev[j];
+      const uint32_t wk = W[k], wj = W[j];
+      uint2 rk[8], rj[8];
+      for (int q = 0; q < rec_words; ++q) {
+        rk[q] = R[k * rec_words + q];
+        rj[q] = R[j * rec_words + q];
+      }
+      X[k] = xj; X[j] = xk;
+      Y[k] = yj; Y[j] = yk;
+      if (d3) { Z[k] = zj; Z[j] = zk; }
+      UX[k] = uxj; UX[j] = uxk;
+      UY[k] = uyj; UY[j] = uyk;
+      UZ[k] = uzj; UZ[j] = uzk;
+      S.tau_dev[k] = tj; S.tau_dev[j] = tk;
+      S.uid_dev[k] = ij; S.uid_dev[j] = ik;
+      S.birth_step_dev[k] = bj; S.birth_step_dev[j] = bk;
+      W[k] = wj; W[j] = wk;
+      for (int q = 0; q < rec_words; ++q) {
+        R[k * rec_words + q] = rj[q];
+        R[j * rec_words + q] = rk[q];
+      }
     }
   }
 }
@@ -1869,6 +1907,10 @@ void launch_set_step(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* g
   hipLaunchKernelGGL(k_set_step, dim3(1), dim3(256), 0, s, glob, acc, n_inst, step);
   if (n_inst > 0 && win && lmask)
     hipLaunchKernelGGL(k_window_masks, dim3(n_inst == 1 ? 2048 : 64, n_inst), dim3(256), 0, s, inst, acc, glob, win, lmask);
+}
+
+void launch_front_clear(InstAcc* acc, int n_inst, hipStream_t s) {
+  if (n_inst > 0) hipLaunchKernelGGL(k_front_clear, dim3(1), dim3(256), 0, s, acc, n_inst);
 }
 
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s) {
