@@ -992,6 +992,24 @@ __device__ inline void wave_reserve2_grouped(bool want, int key, int64_t* ca, in
   }
 }
 
+// Sets bit `bit` of the 64-bit word `word` for every lane with a word (nullptr: none), with one
+// atomic per distinct word of the wave (consecutive slots share their group's word).  Every lane
+// of the wave must call it.
+__device__ inline void wave_or_bit(uint64_t* word, int bit) {
+  bool left = word != nullptr;
+  unsigned long long mask;
+  while ((mask = __ballot(left)) != 0ull) {
+    const int leader = __ffsll((long long)mask) - 1;
+    const long long lw = __shfl((long long)(uintptr_t)word, leader);
+    const bool mine = left && (long long)(uintptr_t)word == lw;
+    long long v = mine ? (long long)(1ull << bit) : 0ll;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+    if (__lane_id() == leader) atomicOr((unsigned long long*)(uintptr_t)lw, (unsigned long long)v);
+    if (mine) left = false;
+  }
+}
+
 // sums over the 64 lanes of a wave, every lane active; every lane gets the result
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

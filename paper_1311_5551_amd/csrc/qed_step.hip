@@ -831,6 +831,7 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
                                : wave_reserve_grouped(child, ii, G.count_dev);
     double dropped_e = 0.0;
     unsigned n_drop = 0;
+    uint64_t* lword = nullptr;  // the live mask word of a new photon that can still create a pair
     if (child) {
       if (slot < G.capacity) {
         if (MIXED) {
@@ -860,9 +861,7 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
         const uint32_t wn = pack_window(photon_window(F, pair_eps_min(F, a.tb.cp_min), a.tb.cp_min, a.sc.t0, a.sc.dt,
                                                       skx, sky, skz, sx, (int32_t)(step + 1)));
         a.win[pk] = wn;
-        // the live bit of a photon that can still create a pair (the masks' other bits belong to
-        // other slots, some of them set by other waves)
-        if (!window_over(wn, step + 1)) atomicOr((unsigned long long*)(a.lmask + lmoff + slot / kWinGroup), 1ull << (slot % kWinGroup));
+        if (!window_over(wn, step + 1)) lword = a.lmask + lmoff + slot / kWinGroup;
         make_photon_rec<MIXED, FK>(((PhotonRecT<MIXED, FK>*)a.rec)[pk], F, a.sc.t0, a.sc.dt, skx, sky, skz, sx, sy,
                                    (int32_t)(step + 1));
       } else {
@@ -870,6 +869,9 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
         dropped_e = sqrt(ckx * ckx + cky * cky + ckz * ckz);
       }
     }
+    // the new photons' live bits (the words' other bits belong to other slots, some of them set
+    // by other waves)
+    wave_or_bit(lword, (int)(slot % kWinGroup));
     if (uni) {
       if (bkey != bst.inst && threadIdx.x == 0) {
         bst.flush(0, a.acc);
