@@ -462,16 +462,30 @@ def cpu_baseline(args):
     w = W.subset(W.collision_config2(n=args.electrons), range(args.cpu_families))
     cfg = oracle.RunConfig(field_kind=w.field_kind, field=w.field, dt=w.dt, n_steps=w.n_steps, flags=w.flags,
                            seed=w.seed, instance=w.instance)
-    log("cpu baseline: oracle on %d families x %d steps, %d threads" % (w.n, w.n_steps, oracle.num_threads()))
+    threads = oracle.num_threads()
+    log("cpu baseline: oracle on %d families x %d steps, %d threads" % (w.n, w.n_steps, threads))
     t0 = time.perf_counter()
     _, led = oracle.run(cfg, tables, electrons=w.electrons)
     t1 = time.perf_counter()
-    return {"value": led["particle_steps"] / (t1 - t0), "unit": "particle-steps/s", "cores": oracle.num_threads(),
+    # the same on one core, over a smaller share of the families
+    w1 = W.subset(W.collision_config2(n=args.electrons), range(args.cpu_families_1core))
+    log("cpu baseline: oracle on %d families x %d steps, 1 thread" % (w1.n, w1.n_steps))
+    oracle.set_threads(1)
+    try:
+        t2 = time.perf_counter()
+        _, led1 = oracle.run(cfg, tables, electrons=w1.electrons)
+        t3 = time.perf_counter()
+    finally:
+        oracle.set_threads(threads)
+    return {"value": led["particle_steps"] / (t1 - t0), "unit": "particle-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": "first %d electrons of the 1e6-electron collision and all their descendants, all 20000 steps "
                       "(%d particle-steps, %.1f s; the oracle evaluates every live particle in every step, so every "
                       "one of its particle-steps is an evaluated one); oracle tables built beforehand"
-                      % (w.n, led["particle_steps"], t1 - t0)}
+                      % (w.n, led["particle_steps"], t1 - t0),
+            "one_core": {"value": led1["particle_steps"] / (t3 - t2), "unit": "particle-steps/s", "cores": 1,
+                         "sample": "first %d electrons and their descendants, all 20000 steps (%d particle-steps, "
+                                   "%.1f s)" % (w1.n, led1["particle_steps"], t3 - t2)}}
 
 
 def main():
@@ -488,6 +502,8 @@ def main():
     ap.add_argument("--no-full-run", dest="full_run", action="store_false",
                     help="skip the whole-schedule value of the collision forms")
     ap.add_argument("--cpu-families", type=int, default=1500)
+    ap.add_argument("--cpu-families-1core", type=int, default=40,
+                    help="families of the one-core oracle timing (a share of the --cpu-families sample)")
     ap.add_argument("--tune", choices=("auto", "replica", "none"), default="auto",
                     help="sweep launch shapes per form: auto = the tuned shapes cached in "
                          "paper_1311_5551_amd/tuned_launch.json for this device, form, workload and kernel sources, "

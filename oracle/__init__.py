@@ -126,6 +126,8 @@ def lib():
         L.oracle_fdtd_step.argtypes = [C.POINTER(_Config), _DP]
         L.oracle_fdtd_step.restype = None
         L.oracle_num_threads.restype = C.c_int
+        L.oracle_set_threads.argtypes = [C.c_int]
+        L.oracle_set_threads.restype = None
         _LIB = L
     return _LIB
 
@@ -454,3 +456,8 @@ def run(cfg: RunConfig, tables: dict, electrons=None, positrons=None, photons=No
 
 def num_threads() -> int:
     return int(lib().oracle_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the following oracle runs (results do not depend on it)."""
+    lib().oracle_set_threads(int(n))

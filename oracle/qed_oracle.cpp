@@ -1604,4 +1604,14 @@ int oracle_num_threads(void) {
 #endif
 }
 
+// threads of the following runs (the run's results do not depend on it: families are
+// independent and every sum is exact)
+void oracle_set_threads(int n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n > 0 ? n : 1);
+#else
+  (void)n;
+#endif
+}
+
 }  // extern "C"
