@@ -142,6 +142,8 @@ struct qed_workspace {
   // (field kind, particles per thread, block, precision, table rows)
   int fit[2] = {0, 0};
   int fit_key[2][5] = {{-1, -1, -1, -1, -1}, {-1, -1, -1, -1, -1}};
+  int emit_fit = 0;                         // emission-pass blocks per CU (occupancy query)
+  int emit_fit_key[3] = {-1, -1, -1};       // field kind, precision, lepton-sweep waves
   size_t win_len = 0;
   uint64_t* d_lmask = nullptr;  // live masks of the photon slot groups (kWinGroup slots each), at acc.lmask_off
   size_t lmask_len = 0;
@@ -386,6 +388,19 @@ int sweep_grid(qed_workspace* ws, int w, int n_tab) {
   return ws->cus * std::max(1, std::min(ws->fit[w], 2048 / ws->block[w]));
 }
 
+// Grid of the emission pass: as many blocks as fit the CUs at once (at most 4 per CU), so that a
+// step with many events keeps many of their latency chains in flight; the events are dealt to
+// the blocks in equal contiguous shares.
+int emit_grid(qed_workspace* ws, int lepton_waves) {
+  const bool mixed = ws->prec == QED_FP32_MIXED;
+  const int key[3] = {ws->field_kind, (int)mixed, lepton_waves};
+  if (std::memcmp(key, ws->emit_fit_key, sizeof(key)) != 0) {
+    ws->emit_fit = emit_blocks_per_cu(ws->field_kind, lepton_waves, mixed);
+    std::memcpy(ws->emit_fit_key, key, sizeof(key));
+  }
+  return ws->cus * std::max(1, std::min(ws->emit_fit, 4));
+}
+
 qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_params* p, hipStream_t s) {
   const int BL = ws->block[0], BP = ws->block[1];
   const StepConst sc = step_const(p);
@@ -428,7 +443,7 @@ qed_status enqueue_step(const qed_tables* tb, qed_workspace* ws, const qed_step_
   mark_end(ws, m, sl);
   if (p->flags & QED_EMIT) {
     m = mark_begin(ws, 4, sl);
-    launch_emit_events(ws->field_kind, a, ws->cus, 256, mixed, sl);
+    launch_emit_events(ws->field_kind, a, emit_grid(ws, a.qe.grid * a.qe.waves), 256, mixed, sl);
     mark_end(ws, m, sl);
   }
   if (p->flags & QED_PAIRS) {

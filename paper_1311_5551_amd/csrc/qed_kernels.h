@@ -63,6 +63,8 @@ void launch_set_step(const qed_instance* inst, int n_inst, InstAcc* acc, Glob* g
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s);
 void launch_lepton(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s);
 int photon_blocks_per_cu(int fk, int ppt, int block, int n_cp, bool mixed);
+// blocks of 256 threads of the emission pass that fit a CU, with the prefix of `lepton_waves` counts
+int emit_blocks_per_cu(int fk, int lepton_waves, bool mixed);
 // one step of the field solver of every QED_FIELD_GRID_FDTD instance; max_nodes_rows: the largest
 // instance's rows times its runs of 256 columns (the work items of one pass)
 void launch_fdtd(const qed_instance* inst, int n_inst, int max_nodes_rows, double dt, hipStream_t s);

@@ -737,7 +737,12 @@ __global__ __launch_bounds__(256) void k_emit_events(StepArgs a) {
     __syncthreads();
   }
   const int total = s_pref[NW];
-  const int per = (total + gridDim.x - 1) / gridDim.x;
+  // the blocks that take events: as many as one round of blockDim events each needs, up to the
+  // grid; the others leave now, so a step with few events pays no atomics on the shared
+  // counters for blocks without work
+  const int G = max(1, min((int)gridDim.x, (total + (int)blockDim.x - 1) / (int)blockDim.x));
+  if ((int)blockIdx.x >= G) return;
+  const int per = (total + G - 1) / G;
   const int eb = min(total, (int)blockIdx.x * per), ee = min(total, eb + per);
   BlockEventStats bst;
   bst.clear();
@@ -1917,6 +1922,25 @@ void launch_front_clear(InstAcc* acc, int n_inst, hipStream_t s) {
 
 void launch_grid_refresh(const qed_instance* inst, int n_inst, const Glob* glob, const StepConst& sc, hipStream_t s) {
   hipLaunchKernelGGL(k_grid_refresh, dim3(2048), dim3(256), 0, s, inst, n_inst, glob, sc);
+}
+
+template <int FK>
+static int emit_fit_fk(size_t shm, bool mixed) {
+  int n = 0;
+  const hipError_t e = mixed ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_emit_events<FK, true>, 256, shm)
+                             : hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_emit_events<FK, false>, 256, shm);
+  return e == hipSuccess ? n : 0;
+}
+int emit_blocks_per_cu(int fk, int lepton_waves, bool mixed) {
+  const size_t shm = ((size_t)lepton_waves + 1) * sizeof(int);
+  switch (fk) {
+    case QED_FIELD_UNIFORM: return emit_fit_fk<QED_FIELD_UNIFORM>(shm, mixed);
+    case QED_FIELD_LP_PULSE: return emit_fit_fk<QED_FIELD_LP_PULSE>(shm, mixed);
+    case QED_FIELD_CP_WAVE: return emit_fit_fk<QED_FIELD_CP_WAVE>(shm, mixed);
+    case QED_FIELD_CP_STANDING: return emit_fit_fk<QED_FIELD_CP_STANDING>(shm, mixed);
+    case QED_FIELD_GRID_FDTD: return emit_fit_fk<QED_FIELD_GRID_FDTD>(shm, mixed);
+    default: return emit_fit_fk<QED_FIELD_GRID_CP_STANDING>(shm, mixed);
+  }
 }
 
 void launch_emit_events(int fk, const StepArgs& a, int grid, int block, bool mixed, hipStream_t s) {
